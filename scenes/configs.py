@@ -1,0 +1,225 @@
+"""Seeded workload recipes: which gel, which indenter, which material and which
+pose schedule each environment gets.
+
+Every random draw for environment `e` of workload number `k` comes from
+numpy.random.default_rng(SeedSequence([k, e])), so any subset of
+environments can be regenerated on its own.
+
+A pose schedule holds S+1 poses: pose[0] is the starting pose (indenter lowest
+point 2*dhat above the gel top, i.e. press depth -2*dhat) and pose[s] is the
+target of load step s. Press depth delta is measured as the gel thickness
+minus the lowest world z of the indenter's vertices.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .indenters import (Indenter, end_on_peg, flat_plate, hex_nut, icosphere,
+                        quat_from_axis_angle, quat_mul, rotation_matrix)
+from .mesh import GelMesh, mesh_class
+
+DHAT = 0.05      # mm
+KAPPA = 1.0e3    # N/mm
+EPS_V = 1.0e-3   # mm per step
+NU = 0.45
+
+
+@dataclass
+class EnvSpec:
+    mesh: str
+    indenter: str
+    E: float
+    nu: float
+    mu_f: float
+    poses: np.ndarray                 # (S+1, 7)
+    eps_v: float = EPS_V
+    dhat: float = DHAT
+    kappa: float = KAPPA
+    extra: dict = field(default_factory=dict)
+
+    def material(self):
+        return (self.E, self.nu, self.mu_f, self.eps_v, self.dhat, self.kappa)
+
+
+@dataclass
+class Workload:
+    name: str
+    number: int
+    meshes: dict                      # name -> GelMesh
+    indenters: dict                   # name -> Indenter
+    envs: list                        # [EnvSpec]
+    precision: str = "f64"            # "f64" or "mixed"
+    tol: float = 1e-6                 # mm, on the preconditioned gradient
+    description: str = ""
+
+    @property
+    def n_steps(self) -> int:
+        return int(self.envs[0].poses.shape[0] - 1)
+
+
+INDENTERS = {
+    "sphere3": lambda: icosphere(3.0, 2),
+    "peg4": lambda: end_on_peg(4.0, 10.0, 64, 8),
+    "nut8": lambda: hex_nut(8.0, 4.7, 4.2),
+    "plate": lambda: flat_plate(2.0, 0.0, 3),
+    "sphere_small": lambda: icosphere(0.6, 1),
+    "sphere_sym": lambda: icosphere(0.6, 1, yaw=-np.pi / 4),
+}
+
+
+def pose_at_depth(ind: Indenter, q, xy, depth: float, thickness: float) -> np.ndarray:
+    """Pose with rotation q whose lowest indenter vertex sits `depth` below the gel top."""
+    R = rotation_matrix(q)
+    zmin = float((ind.Y @ R.T)[:, 2].min())
+    tz = thickness - depth - zmin
+    return np.array([xy[0], xy[1], tz, *q], dtype=np.float64)
+
+
+def press_schedule(ind, q, xy, depth, thickness, n_press, dhat=DHAT,
+                   shear=(0.0, 0.0), n_shear=0) -> np.ndarray:
+    poses = [pose_at_depth(ind, q, xy, -2.0 * dhat, thickness)]
+    for s in range(1, n_press + 1):
+        poses.append(pose_at_depth(ind, q, xy, depth * s / n_press, thickness))
+    last = poses[-1].copy()
+    for s in range(1, n_shear + 1):
+        p = last.copy()
+        p[0] += shear[0] * s / n_shear
+        p[1] += shear[1] * s / n_shear
+        poses.append(p)
+    return np.stack(poses)
+
+
+def _rng(k, e):
+    return np.random.default_rng(np.random.SeedSequence([k, e]))
+
+
+def _yaw_tilt(yaw, tilt):
+    return quat_mul(quat_from_axis_angle((0, 0, 1), yaw), quat_from_axis_angle((0, 1, 0), tilt))
+
+
+def sphere_press_484v(n_envs: int = 1, n_steps: int = 10) -> Workload:
+    """Plain single env: 8x8x2 mm gel (484 v, 1800 t), r=3 mm icosphere pressed
+    0.6 mm in 10 steps at a seeded xy offset in [-1,1]^2 mm; E=0.3, nu=0.45, no friction."""
+    g = mesh_class("c1")
+    ind = INDENTERS["sphere3"]()
+    envs = []
+    for e in range(n_envs):
+        r = _rng(1, e)
+        xy = r.uniform(-1.0, 1.0, 2)
+        poses = press_schedule(ind, (1.0, 0, 0, 0), xy, 0.6, g.thickness, n_steps)
+        envs.append(EnvSpec("c1", "sphere3", 0.3, NU, 0.0, poses))
+    return Workload("sphere_press_484v", 1, {"c1": g}, {"sphere3": ind}, envs, "f64", 1e-6,
+                    "1 env, 8x8x2 mm gel 10x10x3 hexes, icosphere r=3 pressed 0.6 mm in 10 steps")
+
+
+def peg_press_shear_12k(n_envs: int = 1) -> Workload:
+    """Single env, 20x16x4 mm gel with 40x32x8 hexes (12,177 v, 61,440 t), end-on peg
+    r=4 mm with tilt U[-5,5] deg and yaw U[0,360) deg; 20 press steps to 0.8 mm then
+    20 shear steps totalling +0.5 mm along x; E U[0.2,0.5] MPa, mu=0.5."""
+    g = mesh_class("12k")
+    ind = INDENTERS["peg4"]()
+    envs = []
+    for e in range(n_envs):
+        r = _rng(2, e)
+        tilt = np.deg2rad(r.uniform(-5.0, 5.0))
+        yaw = np.deg2rad(r.uniform(0.0, 360.0))
+        E = r.uniform(0.2, 0.5)
+        poses = press_schedule(ind, _yaw_tilt(yaw, tilt), (0.0, 0.0), 0.8, g.thickness, 20,
+                               shear=(0.5, 0.0), n_shear=20)
+        envs.append(EnvSpec("12k", "peg4", E, NU, 0.5, poses))
+    return Workload("peg_press_shear_12k", 2, {"12k": g}, {"peg4": ind}, envs, "f64", 1e-6,
+                    "1 env, 12k-vertex gel, tilted peg, 0.8 mm press + 0.5 mm shear, friction 0.5")
+
+
+def peg_batch_5k(n_envs: int = 2048, n_steps: int = 20, precision: str = "mixed") -> Workload:
+    """Uniform batch: n_envs x 5k-vertex gels (4,914 v, 24,000 t), peg at xy U[-2,2]^2 mm,
+    yaw U[0,360) deg, 20 press steps to depth U[0.3,1.0] mm, E U[0.2,0.5], mu U[0.3,0.8]."""
+    g = mesh_class("5k")
+    ind = INDENTERS["peg4"]()
+    envs = []
+    for e in range(n_envs):
+        r = _rng(3, e)
+        xy = r.uniform(-2.0, 2.0, 2)
+        yaw = np.deg2rad(r.uniform(0.0, 360.0))
+        depth = r.uniform(0.3, 1.0)
+        E = r.uniform(0.2, 0.5)
+        mu = r.uniform(0.3, 0.8)
+        poses = press_schedule(ind, _yaw_tilt(yaw, 0.0), xy, depth, g.thickness, n_steps)
+        envs.append(EnvSpec("5k", "peg4", E, NU, mu, poses))
+    return Workload(f"peg_batch_{n_envs}x5k", 3, {"5k": g}, {"peg4": ind}, envs, precision, 1e-6,
+                    f"{n_envs} envs, 5k-vertex gels, peg, {n_steps} press steps")
+
+
+def mixed_batch(n_envs: int = 512, n_steps: int = 20, precision: str = "mixed") -> Workload:
+    """Uneven batch: gel class uniform over {2k, 5k, 12k}, indenter uniform over
+    {sphere r=3, peg r=4, hex nut 8 mm across flats}; pose and press as the uniform batch."""
+    meshes = {k: mesh_class(k) for k in ("2k", "5k", "12k")}
+    inds = {k: INDENTERS[k]() for k in ("sphere3", "peg4", "nut8")}
+    envs = []
+    for e in range(n_envs):
+        r = _rng(4, e)
+        mk = ("2k", "5k", "12k")[int(r.integers(0, 3))]
+        ik = ("sphere3", "peg4", "nut8")[int(r.integers(0, 3))]
+        xy = r.uniform(-2.0, 2.0, 2)
+        yaw = np.deg2rad(r.uniform(0.0, 360.0))
+        depth = r.uniform(0.3, 1.0)
+        E = r.uniform(0.2, 0.5)
+        mu = r.uniform(0.3, 0.8)
+        poses = press_schedule(inds[ik], _yaw_tilt(yaw, 0.0), xy, depth,
+                               meshes[mk].thickness, n_steps)
+        envs.append(EnvSpec(mk, ik, E, NU, mu, poses))
+    return Workload(f"mixed_batch_{n_envs}", 4, meshes, inds, envs, precision, 1e-6,
+                    f"{n_envs} envs over 3 gel sizes and 3 indenters")
+
+
+def adjoint_peg_5k(n_envs: int = 64) -> Workload:
+    """64 x 5k-vertex gels, peg: 10 press steps to 0.6 mm then 10 shear steps of 0.5 mm
+    total. Hidden per-env parameters theta* (E, nu, mu, pose offset) are drawn here and
+    kept in EnvSpec.extra; the gradient is evaluated at a perturbed theta_0."""
+    g = mesh_class("5k")
+    ind = INDENTERS["peg4"]()
+    envs = []
+    for e in range(n_envs):
+        r = _rng(5, e)
+        E = r.uniform(0.2, 0.5)
+        nu = r.uniform(0.40, 0.48)
+        mu = r.uniform(0.3, 0.8)
+        dt = r.uniform(-0.2, 0.2, 3)
+        dw = np.deg2rad(r.uniform(-2.0, 2.0, 3))
+        poses = press_schedule(ind, (1.0, 0, 0, 0), (0.0, 0.0), 0.6, g.thickness, 10,
+                               shear=(0.5, 0.0), n_shear=10)
+        theta_star = dict(E=E, nu=nu, mu=mu, dt=dt, dw=dw)
+        theta0 = dict(E=1.2 * E, nu=nu - 0.02, mu=mu + 0.1, dt=dt + 0.1, dw=dw + np.deg2rad(1.0))
+        envs.append(EnvSpec("5k", "peg4", theta0["E"], theta0["nu"], theta0["mu"], poses,
+                            extra=dict(theta_star=theta_star, theta0=theta0)))
+    return Workload(f"adjoint_{n_envs}x5k", 5, {"5k": g}, {"peg4": ind}, envs, "f64", 1e-6,
+                    f"{n_envs} envs, adjoint of marker loss")
+
+
+def micro_press(mesh: str = "micro2", indenter: str = "sphere_small", depth: float = 0.15,
+                n_steps: int = 3, xy=(0.1, -0.05), E: float = 0.3, nu: float = NU,
+                mu_f: float = 0.0, shear=(0.0, 0.0), n_shear: int = 0, q=(1.0, 0, 0, 0)) -> Workload:
+    """Tiny scene for brute-force checks: a 1- to 9-hex gel and a small indenter."""
+    g = mesh_class(mesh)
+    ind = INDENTERS[indenter]()
+    poses = press_schedule(ind, q, xy, depth, g.thickness, n_steps, shear=shear, n_shear=n_shear)
+    env = EnvSpec(mesh, indenter, E, nu, mu_f, poses)
+    return Workload(f"micro_{mesh}_{indenter}", 0, {mesh: g}, {indenter: ind}, [env], "f64", 1e-10,
+                    "micro scene")
+
+
+WORKLOADS = {
+    "sphere_press_484v": sphere_press_484v,
+    "peg_press_shear_12k": peg_press_shear_12k,
+    "peg_batch_5k": peg_batch_5k,
+    "mixed_batch": mixed_batch,
+    "adjoint_peg_5k": adjoint_peg_5k,
+    "micro_press": micro_press,
+}
+
+
+def make_workload(name: str, **kw) -> Workload:
+    return WORKLOADS[name](**kw)
