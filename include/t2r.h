@@ -1,0 +1,230 @@
+/*
+ * t2r.h — C ABI of the MI355X PNCG-IPC visuotactile gel solver.
+ *
+ * The library computes, per environment and per load step, the quasi-static
+ * equilibrium of a tetrahedral neo-Hookean gel pad pressed by a rigid
+ * indenter, and the displacement of markers embedded in its top face.
+ *
+ *   Step energy (Tac2Real, Supp. A, eq. ipc_energy, without the inertia term):
+ *     Pi_s(x) = sum_e V_e psi(F_e) + kappa sum_{k in C(x)} b(d_k(x)) + D_s(x)
+ *   minimised by preconditioned Dai-Kou nonlinear CG (Supp. A,
+ *   eqs. dk_direction, step_size) with a Jacobi preconditioner, the
+ *   analytic step bound dhat / (2 |p|_inf), a conservative CCD bound and
+ *   backtracking. Markers follow Sec. 3.2 (interpolated from mesh nodes).
+ *
+ * Conventions
+ *   units      mm, N, MPa (N/mm^2), energy N*mm
+ *   floats     double (IEEE binary64) unless stated
+ *   indices    int32, zero-based
+ *   arrays     row-major; "[n][3]" means n consecutive xyz triples
+ *   poses      7 doubles (tx, ty, tz, qw, qx, qy, qz): indenter-local point y
+ *              maps to R(q) y + t; q need not be normalised
+ *   host ptr   readable by the CPU; borrowed for the duration of the call
+ *   device ptr HIP device memory on the context's device; borrowed until the
+ *              work enqueued on the context's stream has completed
+ *
+ * Errors
+ *   Every entry point returns t2r_status: T2R_OK (0) or a negative code. On a
+ *   negative code the call had no effect on the context; t2r_last_error()
+ *   describes it. Nothing is thrown across the ABI. Per-environment solve
+ *   outcomes are not call errors: they are written as T2R_ENV_* bit masks.
+ *   A context is not thread-safe: one host thread at a time.
+ *
+ * Lifetime
+ *   t2r_create performs no HIP call. Classes and environments are described
+ *   on the host; device memory is allocated and filled on the first call that
+ *   needs the GPU (t2r_step, t2r_eval, t2r_get_state, ...), after which no
+ *   more classes or environments can be added (T2R_E_STATE).
+ */
+#ifndef T2R_H
+#define T2R_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct t2r_ctx t2r_ctx;
+typedef int32_t t2r_status;
+
+enum {
+  T2R_OK = 0,
+  T2R_E_ARG = -1,          /* invalid argument, size or mesh */
+  T2R_E_NOMEM = -2,        /* device allocation failed */
+  T2R_E_HIP = -3,          /* HIP runtime error (no device, launch failure, ...) */
+  T2R_E_STATE = -4,        /* call not valid in the context's current state */
+  T2R_E_UNSUPPORTED = -5   /* feature not available in this build */
+};
+
+/* Per-environment outcome bits written by t2r_step (d_status). */
+enum {
+  T2R_ENV_CONVERGED = 1,      /* every solve of the step reached its tolerance */
+  T2R_ENV_MAXITER = 2,        /* some solve stopped at max_iters */
+  T2R_ENV_INFEASIBLE = 4,     /* the step started from an intersecting state */
+  T2R_ENV_NONFINITE = 8,      /* NaN/Inf pose or state; the env was not advanced */
+  T2R_ENV_PAIR_OVERFLOW = 16, /* contact pair list overflowed; env rolled back */
+  T2R_ENV_LINESEARCH = 32,    /* 30 halvings found no acceptable step */
+  T2R_ENV_SUBSTEPS = 64,      /* continuation hit max_substeps before the target */
+  T2R_ENV_SKIPPED = 128       /* masked out by the caller; state unchanged */
+};
+
+/* Material and contact parameters of one environment.
+ *   E, nu   Young's modulus (MPa) and Poisson ratio of the gel, 0 < nu < 0.5
+ *   mu_f    friction coefficient (0 disables friction)
+ *   eps_v   friction mollifier width, mm per step (Supp. A, eq. friction_mollifier)
+ *   dhat    barrier activation distance, mm
+ *   kappa   barrier stiffness, N/mm */
+typedef struct { double E, nu, mu_f, eps_v, dhat, kappa; } t2r_material;
+
+/* Solver options.
+ *   tol           stop a solve when |P g|_inf <= tol (mm), P = diag(H)^-1
+ *   substep_tol   tolerance of intermediate continuation solves (<= 0: use tol)
+ *   max_iters     PNCG iterations per solve
+ *   max_substeps  continuation solves per load step
+ *   precision     0: all FP64; 1: FP32 element terms, FP64 elsewhere
+ *   pair_capacity contact candidate pairs per env (0: automatic)
+ *   armijo        1: require sufficient decrease of Pi in the line search
+ *   block_size    threads per workgroup, 64..1024 multiple of 64 (0: default 256) */
+typedef struct {
+  double tol;
+  double substep_tol;
+  int32_t max_iters;
+  int32_t max_substeps;
+  int32_t precision;
+  int32_t pair_capacity;
+  int32_t armijo;
+  int32_t block_size;
+} t2r_solver_opts;
+
+/* Per-environment counters of the last t2r_step (t2r_get_stats). */
+typedef struct {
+  int32_t status;        /* T2R_ENV_* bits */
+  int32_t iters;         /* PNCG iterations, all solves of the step */
+  int32_t substeps;      /* continuation solves */
+  int32_t restarts;      /* direction resets to -P g */
+  int32_t halvings;      /* line-search halvings */
+  int32_t reculls;       /* broad-phase passes */
+  int32_t n_candidates;  /* candidate pairs at the last cull */
+  int32_t n_active;      /* pairs closer than dhat at the end */
+  int32_t n_friction;    /* lagged friction pairs */
+  int32_t max_solve_iters;
+  double d_min;          /* smallest gel/indenter distance at the end (mm), inf if none < dhat */
+  double residual;       /* final |P g|_inf (mm) */
+  double energy;         /* final Pi (N mm) */
+} t2r_env_stats;
+
+/* Fills *o with the defaults: tol 1e-6, substep_tol 1e-4, max_iters 20000,
+ * max_substeps 1000, precision 0, pair_capacity 0, armijo 1, block_size 0. */
+void t2r_default_opts(t2r_solver_opts* o);
+
+/* Creates a context bound to `hip_stream` (a hipStream_t, or NULL for the null
+ * stream) of the device current at the first GPU call. `opts` may be NULL for
+ * the defaults; it is copied. No HIP call is made. */
+t2r_status t2r_create(t2r_ctx** out, const t2r_solver_opts* opts, void* hip_stream);
+
+/* Releases every device allocation (synchronising the stream first) and the context. */
+void t2r_destroy(t2r_ctx* ctx);
+
+/* Message of the last failed call on ctx (empty if none); valid until the next call. */
+const char* t2r_last_error(const t2r_ctx* ctx);
+
+/* Optional device allocator used instead of hipMalloc/hipFree, e.g. a caching
+ * allocator owned by the caller. Must be set before the first GPU call. */
+typedef void* (*t2r_alloc_fn)(size_t bytes, void* user);
+typedef void (*t2r_free_fn)(void* ptr, void* user);
+t2r_status t2r_set_allocator(t2r_ctx* ctx, t2r_alloc_fn alloc, t2r_free_fn free_fn, void* user);
+
+/* Adds a gel mesh class (host copy; validated here, no GPU use).
+ *   n_v, X[n_v][3]     rest positions (mm)
+ *   n_t, tets[n_t][4]  vertex ids; every tet must have a positive rest volume
+ *                      and every vertex must belong to some tet
+ *   fixed[n_v]         1 = vertex held at rest (Dirichlet), 0 = free
+ *   n_m, markers[n_m][2] marker rest xy; each must lie inside the top face
+ *                      (boundary triangles at the maximal z), where it is
+ *                      embedded barycentrically (Sec. 3.2)
+ * Surface primitives (boundary triangles, their edges and vertices) are
+ * extracted; primitives whose vertices are all fixed are dropped.
+ * T2R_E_ARG on inverted/degenerate tets, out-of-range ids, unreferenced
+ * vertices, markers outside the top face, or sizes beyond 2^24 vertices. */
+t2r_status t2r_add_gel(t2r_ctx* ctx, int32_t n_v, const double* X, int32_t n_t,
+                       const int32_t* tets, const uint8_t* fixed, int32_t n_m,
+                       const double* markers, int32_t* gel_id);
+
+/* Counts of a gel class: out[0..8] = n_v, n_t, surface vertices, surface edges,
+ * surface triangles, markers, tiles, top-face triangles, fixed vertices. Host only. */
+t2r_status t2r_gel_info(const t2r_ctx* ctx, int32_t gel_id, int32_t* out9);
+
+/* Host copy of a gel class's embedding: marker_tri[n_m][3] vertex ids and
+ * marker_w[n_m][3] barycentric weights (either pointer may be NULL). */
+t2r_status t2r_gel_markers(const t2r_ctx* ctx, int32_t gel_id, int32_t* marker_tri,
+                           double* marker_w);
+
+/* Adds a rigid indenter class: n_v local vertices Y[n_v][3] (mm) and n_f
+ * triangles tris[n_f][3] of a closed surface. Edges are derived. Host only. */
+t2r_status t2r_add_indenter(t2r_ctx* ctx, int32_t n_v, const double* Y, int32_t n_f,
+                            const int32_t* tris, int32_t* ind_id);
+
+/* Adds n environments; env i uses gel_ids[i], ind_ids[i], mats[i] and starts
+ * at rest (x = X) with the indenter at pose0[i][7], which must leave every
+ * gel/indenter distance > 0 (checked at the first step). Ids of the new envs
+ * are first_env .. first_env + n - 1. Host only. */
+t2r_status t2r_add_envs(t2r_ctx* ctx, int32_t n, const int32_t* gel_ids,
+                        const int32_t* ind_ids, const t2r_material* mats,
+                        const double* pose0, int32_t* first_env);
+
+/* Number of environments and total vertices over all envs. */
+t2r_status t2r_env_count(const t2r_ctx* ctx, int32_t* n_env, int64_t* total_verts);
+
+/* Advances every environment by one load step: the indenter moves from the
+ * env's previous pose to d_pose[env][7] (device), with friction lagged at the
+ * previous equilibrium, and the new equilibrium is solved.
+ *   d_pose     device [n_env][7]
+ *   d_env_mask device [n_env] int32 or NULL; envs with 0 are skipped (status
+ *              T2R_ENV_SKIPPED, state unchanged)
+ *   d_markers  device [sum n_m][3] or NULL: marker displacements, envs in order
+ *   d_x        device [sum n_v][3] or NULL: equilibrium positions, envs in order
+ *   d_status   device [n_env] int32 or NULL: T2R_ENV_* bits
+ * All work is enqueued on the context's stream; the call does not wait. */
+t2r_status t2r_step(t2r_ctx* ctx, const double* d_pose, const int32_t* d_env_mask,
+                    double* d_markers, double* d_x, int32_t* d_status);
+
+/* Diagnostic evaluation of one env's step energy at given positions, without
+ * touching its state: the friction lag is taken at (d_x_lag, pose_lag) when
+ * d_x_lag is not NULL, and the energy is evaluated at (d_x, pose).
+ *   d_x, d_x_lag, d_p    device [n_v][3]; d_p may be NULL (curvature then 0)
+ *   pose, pose_lag       host [7]
+ *   d_grad, d_diag       device [n_v][3] or NULL: gradient and exact diagonal of
+ *                        the Hessian (fixed vertices: 0 and 1)
+ *   d_scalars            device [8] or NULL: Pi, p^T H p, d_min, active pairs,
+ *                        feasible (1/0), candidate pairs, friction pairs, Pi_elastic
+ * Synchronises the stream before returning. */
+t2r_status t2r_eval(t2r_ctx* ctx, int32_t env, const double* d_x, const double* d_p,
+                    const double* d_x_lag, const double* pose, const double* pose_lag,
+                    double* d_grad, double* d_diag, double* d_scalars);
+
+/* Copies the per-env counters of the last step into host_out (an array of
+ * n_env t2r_env_stats; bytes must be >= n_env * sizeof). Synchronises. */
+t2r_status t2r_get_stats(t2r_ctx* ctx, void* host_out, size_t bytes);
+
+/* Device copies of the resumable state: per env its positions [n_v][3]
+ * followed by its previous pose [7], envs in order (t2r_state_size doubles). */
+t2r_status t2r_state_size(const t2r_ctx* ctx, int64_t* n_doubles);
+t2r_status t2r_get_state(t2r_ctx* ctx, double* d_state);
+t2r_status t2r_set_state(t2r_ctx* ctx, const double* d_state);
+
+/* Puts the listed envs (host ids) back at rest with their initial pose. */
+t2r_status t2r_reset_envs(t2r_ctx* ctx, const int32_t* env_ids, int32_t n);
+
+/* Sets the contact pair capacity per env (reallocates; state is kept). */
+t2r_status t2r_set_pair_capacity(t2r_ctx* ctx, int32_t capacity);
+
+/* Adjoint of the marker loss over the steps since the last reset; not in this
+ * build (T2R_E_UNSUPPORTED). */
+t2r_status t2r_backward(t2r_ctx* ctx, const double* d_dL_du, double* d_grad);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* T2R_H */

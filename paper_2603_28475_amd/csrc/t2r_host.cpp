@@ -1,0 +1,1035 @@
+// Host side of the t2r C ABI: argument validation, mesh preprocessing (rest
+// shape, surface extraction, marker embedding, LDS tiles), indenter grids,
+// device memory and kernel launches. See include/t2r.h for the contract.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <array>
+#include <cstdint>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/t2r.h"
+#include "t2r_internal.h"
+
+using namespace t2r;
+
+
+namespace {
+
+constexpr int kMaxVerts = 1 << 24;
+
+struct GelHost {
+  int n_v = 0, n_t = 0, n_m = 0;
+  std::vector<double> X;          // [3][n_v]
+  std::vector<uint8_t> fixed;
+  // tiled tet data
+  std::vector<int> tet;           // [4][n_t]
+  std::vector<uint32_t> tet_local;
+  std::vector<double> Dinv;       // [9][n_t]
+  std::vector<double> vol;
+  std::vector<float> Dinv32, vol32;
+  std::vector<int> tile_tet, tile_vstart, tile_verts;
+  std::vector<uint8_t> tile_flags;
+  std::vector<int> surf_v, surf_e, surf_f;  // SoA
+  int n_sv = 0, n_se = 0, n_sf = 0, n_top = 0, n_fixed = 0;
+  std::vector<int> marker_tri;    // [3][n_m]
+  std::vector<double> marker_w;   // [3][n_m]
+  double vol_total = 0.0, diag_rest_max = 0.0;
+  GelDev dev{};
+};
+
+struct IndHost {
+  int n_v = 0, n_f = 0, n_e = 0;
+  std::vector<double> Y;          // [3][n_v]
+  std::vector<int> tri;           // [3][n_f]
+  std::vector<int> edge;          // [2][n_e]
+  double r_max = 0.0, lo[3], hi[3];
+  struct GridHost {
+    double origin[3], inv_cell;
+    int dims[3];
+    std::vector<int> start, items;
+    std::vector<double> box;      // [6][n]
+    int n = 0;
+  } gv, ge, gf;
+  IndDev dev{};
+};
+
+struct EnvHost {
+  int gel, ind;
+  t2r_material mat;
+  double pose0[7];
+};
+
+}  // namespace
+
+struct t2r_ctx {
+  t2r_solver_opts opts;
+  hipStream_t stream = nullptr;
+  t2r_alloc_fn alloc = nullptr;
+  t2r_free_fn free_fn = nullptr;
+  void* alloc_user = nullptr;
+  std::string err;
+  std::vector<GelHost> gels;
+  std::vector<IndHost> inds;
+  std::vector<EnvHost> envs;
+  bool committed = false;
+  std::vector<void*> allocs;
+  // device arrays
+  GelDev* d_gels = nullptr;
+  IndDev* d_inds = nullptr;
+  EnvDev* d_envs = nullptr;
+  std::vector<EnvDev> h_envs;
+  double *d_x = nullptr, *d_xprev = nullptr, *d_g0 = nullptr, *d_g1 = nullptr, *d_diag = nullptr,
+         *d_p = nullptr, *d_pose_prev = nullptr;
+  int2* d_pairs = nullptr;
+  FricPair* d_fric = nullptr;
+  EnvStats* d_stats = nullptr;
+  long long* d_xout_off = nullptr;
+  long long* d_state_off = nullptr;
+  long long total_dofs = 0, total_verts = 0, total_markers = 0, state_size = 0;
+  int pair_cap = 0;
+};
+
+namespace {
+
+t2r_status fail(t2r_ctx* c, t2r_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIP_TRY(ctx, call)                                                                 \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) return fail(ctx, T2R_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+void* dev_alloc(t2r_ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  void* p = nullptr;
+  if (c->alloc) {
+    p = c->alloc(bytes, c->alloc_user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) c->allocs.push_back(p);
+  return p;
+}
+
+void dev_free_all(t2r_ctx* c) {
+  for (void* p : c->allocs) {
+    if (c->free_fn) c->free_fn(p, c->alloc_user);
+    else (void)hipFree(p);
+  }
+  c->allocs.clear();
+}
+
+template <typename T>
+t2r_status upload(t2r_ctx* c, const std::vector<T>& v, const T** out) {
+  T* p = (T*)dev_alloc(c, v.size() * sizeof(T));
+  if (!p) return fail(c, T2R_E_NOMEM, "device allocation of %zu bytes failed", v.size() * sizeof(T));
+  if (!v.empty()) HIP_TRY(c, hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  *out = p;
+  return T2R_OK;
+}
+
+double det3(const double m[9]) {
+  return m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+         m[2] * (m[3] * m[7] - m[4] * m[6]);
+}
+
+void inv3(const double m[9], double out[9]) {
+  const double d = det3(m);
+  out[0] = (m[4] * m[8] - m[5] * m[7]) / d;
+  out[1] = (m[2] * m[7] - m[1] * m[8]) / d;
+  out[2] = (m[1] * m[5] - m[2] * m[4]) / d;
+  out[3] = (m[5] * m[6] - m[3] * m[8]) / d;
+  out[4] = (m[0] * m[8] - m[2] * m[6]) / d;
+  out[5] = (m[2] * m[3] - m[0] * m[5]) / d;
+  out[6] = (m[3] * m[7] - m[4] * m[6]) / d;
+  out[7] = (m[1] * m[6] - m[0] * m[7]) / d;
+  out[8] = (m[0] * m[4] - m[1] * m[3]) / d;
+}
+
+uint32_t spread10(uint32_t v) {
+  v &= 1023u;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+struct Key3 {
+  int a, b, c;
+  bool operator==(const Key3& o) const { return a == o.a && b == o.b && c == o.c; }
+};
+struct Key3Hash {
+  size_t operator()(const Key3& k) const {
+    return ((size_t)k.a * 73856093u) ^ ((size_t)k.b * 19349663u) ^ ((size_t)k.c * 83492791u);
+  }
+};
+
+// Builds the uniform grid of one primitive set (boxes given per primitive).
+void build_grid(IndHost::GridHost& G, const std::vector<std::array<double, 6>>& boxes, const double lo[3],
+                const double hi[3], double cell) {
+  G.n = (int)boxes.size();
+  for (int a = 0; a < 3; ++a) {
+    G.origin[a] = lo[a] - 1e-9 * (1.0 + fabs(lo[a]));
+    const double ext = hi[a] + 1e-9 * (1.0 + fabs(hi[a])) - G.origin[a];
+    G.dims[a] = std::max(1, std::min(64, (int)ceil(ext / cell)));
+  }
+  // one inverse cell size for all axes: cover the largest extent
+  double cmax = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const double ext = hi[a] + 1e-9 * (1.0 + fabs(hi[a])) - G.origin[a];
+    cmax = std::max(cmax, ext / G.dims[a]);
+  }
+  G.inv_cell = 1.0 / cmax;
+  for (int a = 0; a < 3; ++a) {
+    const double ext = hi[a] + 1e-9 * (1.0 + fabs(hi[a])) - G.origin[a];
+    G.dims[a] = std::max(1, (int)ceil(ext * G.inv_cell));
+  }
+  auto cell_of = [&](double v, int a) {
+    int c = (int)floor((v - G.origin[a]) * G.inv_cell);
+    return c < 0 ? 0 : (c >= G.dims[a] ? G.dims[a] - 1 : c);
+  };
+  const int ncell = G.dims[0] * G.dims[1] * G.dims[2];
+  std::vector<std::vector<int>> cells(ncell);
+  G.box.assign(6 * (size_t)G.n, 0.0);
+  for (int i = 0; i < G.n; ++i) {
+    for (int k = 0; k < 6; ++k) G.box[(size_t)k * G.n + i] = boxes[i][k];
+    int c0[3], c1[3];
+    for (int a = 0; a < 3; ++a) { c0[a] = cell_of(boxes[i][a], a); c1[a] = cell_of(boxes[i][3 + a], a); }
+    for (int z = c0[2]; z <= c1[2]; ++z)
+      for (int y = c0[1]; y <= c1[1]; ++y)
+        for (int x = c0[0]; x <= c1[0]; ++x) cells[(z * G.dims[1] + y) * G.dims[0] + x].push_back(i);
+  }
+  G.start.assign(ncell + 1, 0);
+  for (int k = 0; k < ncell; ++k) G.start[k + 1] = G.start[k] + (int)cells[k].size();
+  G.items.clear();
+  G.items.reserve(G.start[ncell]);
+  for (auto& v : cells) G.items.insert(G.items.end(), v.begin(), v.end());
+}
+
+t2r_status commit(t2r_ctx* c);
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+void t2r_default_opts(t2r_solver_opts* o) {
+  if (!o) return;
+  o->tol = 1e-6;
+  o->substep_tol = 1e-4;
+  o->max_iters = 20000;
+  o->max_substeps = 1000;
+  o->precision = 0;
+  o->pair_capacity = 0;
+  o->armijo = 1;
+  o->block_size = 0;
+}
+
+static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
+  if (!(o->tol > 0.0) || !isfinite(o->tol)) return fail(c, T2R_E_ARG, "tol must be positive");
+  if (!isfinite(o->substep_tol)) return fail(c, T2R_E_ARG, "substep_tol must be finite");
+  if (o->max_iters < 0 || o->max_substeps < 1) return fail(c, T2R_E_ARG, "max_iters >= 0 and max_substeps >= 1 required");
+  if (o->precision != 0 && o->precision != 1) return fail(c, T2R_E_ARG, "precision must be 0 or 1");
+  if (o->pair_capacity < 0) return fail(c, T2R_E_ARG, "pair_capacity must be >= 0");
+  if (o->block_size != 0 && (o->block_size < 64 || o->block_size > 256 || o->block_size % 64))
+    return fail(c, T2R_E_ARG, "block_size must be 0 or a multiple of 64 in [64, 256]");
+  return T2R_OK;
+}
+
+t2r_status t2r_create(t2r_ctx** out, const t2r_solver_opts* opts, void* hip_stream) {
+  if (!out) return T2R_E_ARG;
+  *out = nullptr;
+  t2r_ctx* c = new (std::nothrow) t2r_ctx();
+  if (!c) return T2R_E_NOMEM;
+  t2r_default_opts(&c->opts);
+  if (opts) {
+    t2r_status s = check_opts(c, opts);
+    if (s != T2R_OK) { delete c; return s; }
+    c->opts = *opts;
+  }
+  c->stream = (hipStream_t)hip_stream;
+  *out = c;
+  return T2R_OK;
+}
+
+void t2r_destroy(t2r_ctx* c) {
+  if (!c) return;
+  if (c->committed) (void)hipStreamSynchronize(c->stream);
+  dev_free_all(c);
+  delete c;
+}
+
+const char* t2r_last_error(const t2r_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+t2r_status t2r_set_allocator(t2r_ctx* c, t2r_alloc_fn a, t2r_free_fn f, void* user) {
+  if (!c) return T2R_E_ARG;
+  if (c->committed) return fail(c, T2R_E_STATE, "allocator must be set before the first GPU call");
+  if ((a == nullptr) != (f == nullptr)) return fail(c, T2R_E_ARG, "alloc and free must both be set or both NULL");
+  c->alloc = a;
+  c->free_fn = f;
+  c->alloc_user = user;
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_add_gel(t2r_ctx* c, int32_t n_v, const double* X, int32_t n_t, const int32_t* tets,
+                       const uint8_t* fixed, int32_t n_m, const double* markers, int32_t* gel_id) {
+  if (!c) return T2R_E_ARG;
+  if (c->committed) return fail(c, T2R_E_STATE, "cannot add a gel after the first GPU call");
+  if (n_v < 4 || n_v > kMaxVerts || n_t < 1 || n_t > 6 * kMaxVerts || n_m < 0)
+    return fail(c, T2R_E_ARG, "bad sizes n_v=%d n_t=%d n_m=%d", n_v, n_t, n_m);
+  if (!X || !tets || !fixed || (n_m > 0 && !markers) || !gel_id) return fail(c, T2R_E_ARG, "null pointer");
+  GelHost g;
+  g.n_v = n_v;
+  g.n_t = n_t;
+  g.n_m = n_m;
+  g.X.resize(3 * (size_t)n_v);
+  g.fixed.assign(fixed, fixed + n_v);
+  for (int v = 0; v < n_v; ++v) {
+    for (int a = 0; a < 3; ++a) {
+      const double xv = X[3 * (size_t)v + a];
+      if (!isfinite(xv)) return fail(c, T2R_E_ARG, "non-finite rest position at vertex %d", v);
+      g.X[(size_t)a * n_v + v] = xv;
+    }
+    g.n_fixed += fixed[v] ? 1 : 0;
+    if (fixed[v] > 1) return fail(c, T2R_E_ARG, "fixed flags must be 0 or 1");
+  }
+  std::vector<int> used(n_v, 0);
+  std::vector<double> Dinv(9 * (size_t)n_t), vol(n_t);
+  double xlo[3] = {1e300, 1e300, 1e300}, xhi[3] = {-1e300, -1e300, -1e300};
+  for (int v = 0; v < n_v; ++v)
+    for (int a = 0; a < 3; ++a) { xlo[a] = std::min(xlo[a], X[3 * v + a]); xhi[a] = std::max(xhi[a], X[3 * v + a]); }
+  const double scale = std::max({xhi[0] - xlo[0], xhi[1] - xlo[1], xhi[2] - xlo[2], 1e-300});
+  for (int e = 0; e < n_t; ++e) {
+    int id[4];
+    for (int k = 0; k < 4; ++k) {
+      id[k] = tets[4 * (size_t)e + k];
+      if (id[k] < 0 || id[k] >= n_v) return fail(c, T2R_E_ARG, "tet %d has vertex id %d out of range", e, id[k]);
+      used[id[k]] = 1;
+    }
+    double Dm[9];
+    for (int a = 0; a < 3; ++a)
+      for (int k = 0; k < 3; ++k) Dm[a * 3 + k] = X[3 * (size_t)id[k + 1] + a] - X[3 * (size_t)id[0] + a];
+    const double det = det3(Dm);
+    if (!(det > 1e-12 * scale * scale * scale * 1e-6))
+      return fail(c, T2R_E_ARG, "tet %d is inverted or degenerate (6V = %g)", e, det);
+    inv3(Dm, &Dinv[9 * (size_t)e]);
+    vol[e] = det / 6.0;
+    g.vol_total += vol[e];
+  }
+  for (int v = 0; v < n_v; ++v)
+    if (!used[v]) return fail(c, T2R_E_ARG, "vertex %d belongs to no tet", v);
+  // rest diagonal scale: max_v sum_e V_e |g_i|^2
+  {
+    std::vector<double> dsum(n_v, 0.0);
+    for (int e = 0; e < n_t; ++e) {
+      const double* D = &Dinv[9 * (size_t)e];
+      double g[4][3];
+      for (int b = 0; b < 3; ++b) {
+        g[1][b] = D[0 * 3 + b]; g[2][b] = D[1 * 3 + b]; g[3][b] = D[2 * 3 + b];
+        g[0][b] = -(g[1][b] + g[2][b] + g[3][b]);
+      }
+      for (int k = 0; k < 4; ++k)
+        dsum[tets[4 * (size_t)e + k]] += vol[e] * (g[k][0] * g[k][0] + g[k][1] * g[k][1] + g[k][2] * g[k][2]);
+    }
+    for (int v = 0; v < n_v; ++v)
+      if (!fixed[v]) g.diag_rest_max = std::max(g.diag_rest_max, dsum[v]);
+    if (g.diag_rest_max == 0.0) g.diag_rest_max = 1.0;
+  }
+  // surface: faces used by exactly one tet, outward by the opposite-vertex rule
+  std::vector<std::array<int, 3>> btris;
+  {
+    std::unordered_map<Key3, std::pair<int, std::array<int, 3>>, Key3Hash> faces;
+    faces.reserve(4 * (size_t)n_t);
+    static const int lf[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}};
+    for (int e = 0; e < n_t; ++e) {
+      for (int f = 0; f < 4; ++f) {
+        std::array<int, 3> t = {tets[4 * (size_t)e + lf[f][0]], tets[4 * (size_t)e + lf[f][1]],
+                                tets[4 * (size_t)e + lf[f][2]]};
+        std::array<int, 3> s = t;
+        std::sort(s.begin(), s.end());
+        Key3 k{s[0], s[1], s[2]};
+        auto it = faces.find(k);
+        if (it == faces.end()) faces.emplace(k, std::make_pair(1, t));
+        else it->second.first += 1;
+      }
+    }
+    for (auto& kv : faces)
+      if (kv.second.first == 1) btris.push_back(kv.second.second);
+    std::sort(btris.begin(), btris.end(), [](const std::array<int, 3>& a, const std::array<int, 3>& b) {
+      std::array<int, 3> sa = a, sb = b;
+      std::sort(sa.begin(), sa.end());
+      std::sort(sb.begin(), sb.end());
+      return sa < sb;
+    });
+  }
+  std::vector<std::array<int, 3>> stris;
+  std::vector<std::pair<int, int>> sedges;
+  std::vector<int> sverts;
+  {
+    std::vector<uint8_t> onb(n_v, 0);
+    std::vector<std::pair<int, int>> es;
+    for (auto& t : btris) {
+      for (int k = 0; k < 3; ++k) {
+        onb[t[k]] = 1;
+        int a = t[k], b = t[(k + 1) % 3];
+        es.push_back({std::min(a, b), std::max(a, b)});
+      }
+      if (!(fixed[t[0]] && fixed[t[1]] && fixed[t[2]])) stris.push_back(t);
+    }
+    std::sort(es.begin(), es.end());
+    es.erase(std::unique(es.begin(), es.end()), es.end());
+    for (auto& e : es)
+      if (!(fixed[e.first] && fixed[e.second])) sedges.push_back(e);
+    for (int v = 0; v < n_v; ++v)
+      if (onb[v] && !fixed[v]) sverts.push_back(v);
+  }
+  g.n_sv = (int)sverts.size();
+  g.n_se = (int)sedges.size();
+  g.n_sf = (int)stris.size();
+  g.surf_v = sverts;
+  g.surf_e.resize(2 * (size_t)g.n_se);
+  for (int i = 0; i < g.n_se; ++i) { g.surf_e[i] = sedges[i].first; g.surf_e[g.n_se + i] = sedges[i].second; }
+  g.surf_f.resize(3 * (size_t)g.n_sf);
+  for (int i = 0; i < g.n_sf; ++i)
+    for (int k = 0; k < 3; ++k) g.surf_f[(size_t)k * g.n_sf + i] = stris[i][k];
+  // markers: barycentric in the top-face triangle containing the rest xy
+  {
+    const double ztop = xhi[2];
+    const double ztol = 1e-9 * (1.0 + fabs(ztop));
+    std::vector<std::array<int, 3>> top;
+    for (auto& t : stris)
+      if (fabs(X[3 * (size_t)t[0] + 2] - ztop) <= ztol && fabs(X[3 * (size_t)t[1] + 2] - ztop) <= ztol &&
+          fabs(X[3 * (size_t)t[2] + 2] - ztop) <= ztol)
+        top.push_back(t);
+    g.n_top = (int)top.size();
+    g.marker_tri.resize(3 * (size_t)n_m);
+    g.marker_w.resize(3 * (size_t)n_m);
+    for (int m = 0; m < n_m; ++m) {
+      const double mx = markers[2 * (size_t)m], my = markers[2 * (size_t)m + 1];
+      if (!isfinite(mx) || !isfinite(my)) return fail(c, T2R_E_ARG, "non-finite marker %d", m);
+      bool found = false;
+      for (auto& t : top) {
+        const double ax = X[3 * (size_t)t[0]], ay = X[3 * (size_t)t[0] + 1];
+        const double e1x = X[3 * (size_t)t[1]] - ax, e1y = X[3 * (size_t)t[1] + 1] - ay;
+        const double e2x = X[3 * (size_t)t[2]] - ax, e2y = X[3 * (size_t)t[2] + 1] - ay;
+        const double den = e1x * e2y - e1y * e2x;
+        if (den == 0.0) continue;
+        const double px = mx - ax, py = my - ay;
+        const double s = (px * e2y - py * e2x) / den;
+        const double r = (e1x * py - e1y * px) / den;
+        const double w0 = 1.0 - s - r;
+        if (w0 >= -1e-12 && s >= -1e-12 && r >= -1e-12) {
+          for (int k = 0; k < 3; ++k) g.marker_tri[(size_t)k * n_m + m] = t[k];
+          g.marker_w[m] = w0;
+          g.marker_w[n_m + m] = s;
+          g.marker_w[2 * (size_t)n_m + m] = r;
+          found = true;
+          break;
+        }
+      }
+      if (!found) return fail(c, T2R_E_ARG, "marker %d (%g, %g) is outside the top face", m, mx, my);
+    }
+  }
+  // tiles: Morton order of tet centroids, then greedy cuts at kTileTets tets / kTileVerts verts
+  {
+    std::vector<std::pair<uint32_t, int>> order(n_t);
+    for (int e = 0; e < n_t; ++e) {
+      uint32_t q[3];
+      for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (int k = 0; k < 4; ++k) s += X[3 * (size_t)tets[4 * (size_t)e + k] + a];
+        s *= 0.25;
+        const double u = (s - xlo[a]) / std::max(xhi[a] - xlo[a], 1e-300);
+        q[a] = (uint32_t)std::min(1023.0, std::max(0.0, floor(u * 1024.0)));
+      }
+      order[e] = {spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2), e};
+    }
+    std::stable_sort(order.begin(), order.end());
+    g.tet.resize(4 * (size_t)n_t);
+    g.tet_local.resize(n_t);
+    g.Dinv.resize(9 * (size_t)n_t);
+    g.vol.resize(n_t);
+    g.Dinv32.resize(9 * (size_t)n_t);
+    g.vol32.resize(n_t);
+    g.tile_tet.push_back(0);
+    g.tile_vstart.push_back(0);
+    std::unordered_map<int, int> local;
+    std::vector<int> tile_v;
+    int in_tile = 0;
+    auto close_tile = [&](int next_e) {
+      g.tile_tet.push_back(next_e);
+      g.tile_verts.insert(g.tile_verts.end(), tile_v.begin(), tile_v.end());
+      g.tile_vstart.push_back((int)g.tile_verts.size());
+      local.clear();
+      tile_v.clear();
+      in_tile = 0;
+    };
+    for (int i = 0; i < n_t; ++i) {
+      const int e = order[i].second;
+      int newv = 0;
+      for (int k = 0; k < 4; ++k)
+        if (!local.count(tets[4 * (size_t)e + k])) ++newv;
+      if (in_tile == kTileTets || (int)tile_v.size() + newv > kTileVerts) close_tile(i);
+      uint32_t loc = 0;
+      for (int k = 0; k < 4; ++k) {
+        const int v = tets[4 * (size_t)e + k];
+        auto it = local.find(v);
+        int l;
+        if (it == local.end()) {
+          l = (int)tile_v.size();
+          local.emplace(v, l);
+          tile_v.push_back(v);
+        } else {
+          l = it->second;
+        }
+        loc |= (uint32_t)l << (8 * k);
+        g.tet[(size_t)k * n_t + i] = v;
+      }
+      g.tet_local[i] = loc;
+      for (int k = 0; k < 9; ++k) {
+        g.Dinv[(size_t)k * n_t + i] = Dinv[9 * (size_t)e + k];
+        g.Dinv32[(size_t)k * n_t + i] = (float)Dinv[9 * (size_t)e + k];
+      }
+      g.vol[i] = vol[e];
+      g.vol32[i] = (float)vol[e];
+      ++in_tile;
+    }
+    close_tile(n_t);
+    const int ntiles = (int)g.tile_tet.size() - 1;
+    std::vector<int> first(n_v, -1), last(n_v, -1);
+    for (int t = 0; t < ntiles; ++t)
+      for (int j = g.tile_vstart[t]; j < g.tile_vstart[t + 1]; ++j) {
+        const int v = g.tile_verts[j];
+        if (first[v] < 0) first[v] = t;
+        last[v] = t;
+      }
+    g.tile_flags.resize(g.tile_verts.size());
+    for (int t = 0; t < ntiles; ++t)
+      for (int j = g.tile_vstart[t]; j < g.tile_vstart[t + 1]; ++j) {
+        const int v = g.tile_verts[j];
+        g.tile_flags[j] = (first[v] == t ? kFirstTouch : 0) | (last[v] == t ? kLastTouch : 0);
+      }
+  }
+  c->gels.push_back(std::move(g));
+  *gel_id = (int32_t)c->gels.size() - 1;
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_gel_info(const t2r_ctx* c, int32_t id, int32_t* out) {
+  if (!c || !out || id < 0 || id >= (int)c->gels.size()) return T2R_E_ARG;
+  const GelHost& g = c->gels[id];
+  out[0] = g.n_v; out[1] = g.n_t; out[2] = g.n_sv; out[3] = g.n_se; out[4] = g.n_sf;
+  out[5] = g.n_m; out[6] = (int)g.tile_tet.size() - 1; out[7] = g.n_top; out[8] = g.n_fixed;
+  return T2R_OK;
+}
+
+t2r_status t2r_gel_markers(const t2r_ctx* c, int32_t id, int32_t* tri, double* w) {
+  if (!c || id < 0 || id >= (int)c->gels.size()) return T2R_E_ARG;
+  const GelHost& g = c->gels[id];
+  for (int m = 0; m < g.n_m; ++m)
+    for (int k = 0; k < 3; ++k) {
+      if (tri) tri[3 * m + k] = g.marker_tri[(size_t)k * g.n_m + m];
+      if (w) w[3 * m + k] = g.marker_w[(size_t)k * g.n_m + m];
+    }
+  return T2R_OK;
+}
+
+t2r_status t2r_add_indenter(t2r_ctx* c, int32_t n_v, const double* Y, int32_t n_f, const int32_t* tris,
+                            int32_t* ind_id) {
+  if (!c) return T2R_E_ARG;
+  if (c->committed) return fail(c, T2R_E_STATE, "cannot add an indenter after the first GPU call");
+  if (n_v < 3 || n_v > kMaxVerts || n_f < 1 || n_f > 2 * kMaxVerts) return fail(c, T2R_E_ARG, "bad indenter sizes");
+  if (!Y || !tris || !ind_id) return fail(c, T2R_E_ARG, "null pointer");
+  IndHost I;
+  I.n_v = n_v;
+  I.n_f = n_f;
+  I.Y.resize(3 * (size_t)n_v);
+  for (int a = 0; a < 3; ++a) { I.lo[a] = 1e300; I.hi[a] = -1e300; }
+  for (int v = 0; v < n_v; ++v) {
+    double r2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double y = Y[3 * (size_t)v + a];
+      if (!isfinite(y)) return fail(c, T2R_E_ARG, "non-finite indenter vertex %d", v);
+      I.Y[(size_t)a * n_v + v] = y;
+      I.lo[a] = std::min(I.lo[a], y);
+      I.hi[a] = std::max(I.hi[a], y);
+      r2 += y * y;
+    }
+    I.r_max = std::max(I.r_max, sqrt(r2));
+  }
+  I.tri.resize(3 * (size_t)n_f);
+  std::vector<std::pair<int, int>> es;
+  for (int f = 0; f < n_f; ++f) {
+    for (int k = 0; k < 3; ++k) {
+      const int v = tris[3 * (size_t)f + k];
+      if (v < 0 || v >= n_v) return fail(c, T2R_E_ARG, "indenter triangle %d has vertex id %d out of range", f, v);
+      I.tri[(size_t)k * n_f + f] = v;
+    }
+    for (int k = 0; k < 3; ++k) {
+      const int a = tris[3 * (size_t)f + k], b = tris[3 * (size_t)f + (k + 1) % 3];
+      if (a == b) return fail(c, T2R_E_ARG, "indenter triangle %d is degenerate", f);
+      es.push_back({std::min(a, b), std::max(a, b)});
+    }
+  }
+  std::sort(es.begin(), es.end());
+  es.erase(std::unique(es.begin(), es.end()), es.end());
+  I.n_e = (int)es.size();
+  I.edge.resize(2 * (size_t)I.n_e);
+  for (int i = 0; i < I.n_e; ++i) { I.edge[i] = es[i].first; I.edge[I.n_e + i] = es[i].second; }
+  // grids: cell ~ mean edge length, at most 64 cells per axis
+  double mean_e = 0.0;
+  for (int i = 0; i < I.n_e; ++i) {
+    double s = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double d = Y[3 * (size_t)es[i].first + a] - Y[3 * (size_t)es[i].second + a];
+      s += d * d;
+    }
+    mean_e += sqrt(s);
+  }
+  mean_e /= std::max(1, I.n_e);
+  const double ext = std::max({I.hi[0] - I.lo[0], I.hi[1] - I.lo[1], I.hi[2] - I.lo[2]});
+  const double cell = std::max(mean_e, ext / 64.0);
+  auto box_of = [&](const int* ids, int k) {
+    std::array<double, 6> b;
+    for (int a = 0; a < 3; ++a) { b[a] = 1e300; b[3 + a] = -1e300; }
+    for (int j = 0; j < k; ++j)
+      for (int a = 0; a < 3; ++a) {
+        const double y = Y[3 * (size_t)ids[j] + a];
+        b[a] = std::min(b[a], y);
+        b[3 + a] = std::max(b[3 + a], y);
+      }
+    return b;
+  };
+  std::vector<std::array<double, 6>> bv(n_v), be(I.n_e), bf(n_f);
+  for (int v = 0; v < n_v; ++v) bv[v] = box_of(&v, 1);
+  for (int i = 0; i < I.n_e; ++i) { int ids[2] = {es[i].first, es[i].second}; be[i] = box_of(ids, 2); }
+  for (int f = 0; f < n_f; ++f) bf[f] = box_of(&tris[3 * (size_t)f], 3);
+  build_grid(I.gv, bv, I.lo, I.hi, cell);
+  build_grid(I.ge, be, I.lo, I.hi, cell);
+  build_grid(I.gf, bf, I.lo, I.hi, cell);
+  c->inds.push_back(std::move(I));
+  *ind_id = (int32_t)c->inds.size() - 1;
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_add_envs(t2r_ctx* c, int32_t n, const int32_t* gel_ids, const int32_t* ind_ids,
+                        const t2r_material* mats, const double* pose0, int32_t* first_env) {
+  if (!c) return T2R_E_ARG;
+  if (c->committed) return fail(c, T2R_E_STATE, "cannot add environments after the first GPU call");
+  if (n < 1 || !gel_ids || !ind_ids || !mats || !pose0) return fail(c, T2R_E_ARG, "bad arguments");
+  std::vector<EnvHost> add;
+  for (int i = 0; i < n; ++i) {
+    EnvHost e;
+    e.gel = gel_ids[i];
+    e.ind = ind_ids[i];
+    if (e.gel < 0 || e.gel >= (int)c->gels.size()) return fail(c, T2R_E_ARG, "env %d: bad gel id %d", i, e.gel);
+    if (e.ind < 0 || e.ind >= (int)c->inds.size()) return fail(c, T2R_E_ARG, "env %d: bad indenter id %d", i, e.ind);
+    const t2r_material& m = mats[i];
+    if (!(m.E > 0) || !(m.nu > 0 && m.nu < 0.5) || !(m.mu_f >= 0) || !(m.eps_v > 0) || !(m.dhat > 0) ||
+        !(m.kappa > 0) || !isfinite(m.E) || !isfinite(m.mu_f) || !isfinite(m.eps_v) || !isfinite(m.dhat) ||
+        !isfinite(m.kappa))
+      return fail(c, T2R_E_ARG, "env %d: invalid material", i);
+    e.mat = m;
+    double qn = 0.0;
+    for (int k = 0; k < 7; ++k) {
+      e.pose0[k] = pose0[7 * (size_t)i + k];
+      if (!isfinite(e.pose0[k])) return fail(c, T2R_E_ARG, "env %d: non-finite pose", i);
+      if (k >= 3) qn += e.pose0[k] * e.pose0[k];
+    }
+    if (!(qn > 0)) return fail(c, T2R_E_ARG, "env %d: zero quaternion", i);
+    add.push_back(e);
+  }
+  if (first_env) *first_env = (int32_t)c->envs.size();
+  c->envs.insert(c->envs.end(), add.begin(), add.end());
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_env_count(const t2r_ctx* c, int32_t* n_env, int64_t* total_verts) {
+  if (!c) return T2R_E_ARG;
+  if (n_env) *n_env = (int32_t)c->envs.size();
+  if (total_verts) {
+    int64_t s = 0;
+    for (auto& e : c->envs) s += c->gels[e.gel].n_v;
+    *total_verts = s;
+  }
+  return T2R_OK;
+}
+
+static int block_of(const t2r_ctx* c) { return c->opts.block_size ? c->opts.block_size : 256; }
+
+static StepParams step_params(t2r_ctx* c) {
+  StepParams P{};
+  P.gels = c->d_gels;
+  P.inds = c->d_inds;
+  P.envs = c->d_envs;
+  P.n_env = (int)c->envs.size();
+  P.x = c->d_x;
+  P.xprev = c->d_xprev;
+  P.g0 = c->d_g0;
+  P.g1 = c->d_g1;
+  P.diag = c->d_diag;
+  P.p = c->d_p;
+  P.pose_prev = c->d_pose_prev;
+  P.pairs = c->d_pairs;
+  P.fric = c->d_fric;
+  P.stats = c->d_stats;
+  P.x_out_off = c->d_xout_off;
+  P.tol = c->opts.tol;
+  P.substep_tol = c->opts.substep_tol;
+  P.max_iters = c->opts.max_iters;
+  P.max_substeps = c->opts.max_substeps;
+  P.precision = c->opts.precision;
+  P.armijo = c->opts.armijo;
+  return P;
+}
+
+t2r_status t2r_step(t2r_ctx* c, const double* d_pose, const int32_t* d_mask, double* d_markers, double* d_x,
+                    int32_t* d_status) {
+  if (!c) return T2R_E_ARG;
+  if (!d_pose) return fail(c, T2R_E_ARG, "d_pose is NULL");
+  if (c->envs.empty()) return fail(c, T2R_E_STATE, "no environments");
+  t2r_status s = commit(c);
+  if (s != T2R_OK) return s;
+  StepParams P = step_params(c);
+  P.pose_in = d_pose;
+  P.env_mask = d_mask;
+  P.markers_out = d_markers;
+  P.x_out = d_x;
+  P.status_out = d_status;
+  HIP_TRY(c, t2r_launch_step(&P, block_of(c), c->stream));
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_eval(t2r_ctx* c, int32_t env, const double* d_x, const double* d_p, const double* d_x_lag,
+                    const double* pose, const double* pose_lag, double* d_grad, double* d_diag,
+                    double* d_scalars) {
+  if (!c) return T2R_E_ARG;
+  if (env < 0 || env >= (int)c->envs.size()) return fail(c, T2R_E_ARG, "bad env id %d", env);
+  if (!d_x || !pose || (d_x_lag && !pose_lag)) return fail(c, T2R_E_ARG, "null pointer");
+  for (int k = 0; k < 7; ++k)
+    if (!isfinite(pose[k]) || (pose_lag && d_x_lag && !isfinite(pose_lag[k])))
+      return fail(c, T2R_E_ARG, "non-finite pose");
+  t2r_status s = commit(c);
+  if (s != T2R_OK) return s;
+  const EnvHost& E = c->envs[env];
+  const GelHost& G = c->gels[E.gel];
+  const int nv = G.n_v;
+  EnvDev ed = c->h_envs[env];
+  ed.voff = 0;
+  ed.poff = 0;
+  ed.foff = 0;
+  ed.moff = 0;
+  // scratch (freed before returning)
+  std::vector<void*> tmp;
+  auto talloc = [&](size_t b) -> void* {
+    void* p = nullptr;
+    if (c->alloc) p = c->alloc(b, c->alloc_user);
+    else if (hipMalloc(&p, b) != hipSuccess) p = nullptr;
+    if (p) tmp.push_back(p);
+    return p;
+  };
+  auto tfree = [&]() {
+    (void)hipStreamSynchronize(c->stream);
+    for (void* p : tmp) {
+      if (c->free_fn) c->free_fn(p, c->alloc_user);
+      else (void)hipFree(p);
+    }
+  };
+  const size_t vb = 3 * (size_t)nv * sizeof(double);
+  double* sx = (double*)talloc(vb);
+  double* sxp = (double*)talloc(vb);
+  double* sg0 = (double*)talloc(vb);
+  double* sg1 = (double*)talloc(vb);
+  double* sd = (double*)talloc(vb);
+  double* sp = (double*)talloc(vb);
+  int2* spairs = (int2*)talloc((size_t)ed.pair_cap * sizeof(int2));
+  FricPair* sfric = (FricPair*)talloc((size_t)ed.fric_cap * sizeof(FricPair));
+  EnvDev* senv = (EnvDev*)talloc(sizeof(EnvDev));
+  double* sposes = (double*)talloc(14 * sizeof(double));
+  EnvStats* sstats = (EnvStats*)talloc(sizeof(EnvStats));
+  if (tmp.size() != 11) { tfree(); return fail(c, T2R_E_NOMEM, "scratch allocation failed"); }
+  double hp[14];
+  for (int k = 0; k < 7; ++k) { hp[k] = pose[k]; hp[7 + k] = (pose_lag ? pose_lag[k] : pose[k]); }
+  hipError_t he = hipSuccess;
+  he = hipMemcpyAsync(senv, &ed, sizeof(EnvDev), hipMemcpyHostToDevice, c->stream);
+  if (he == hipSuccess) he = hipMemcpyAsync(sposes, hp, sizeof hp, hipMemcpyHostToDevice, c->stream);
+  if (he == hipSuccess) he = t2r_launch_aos_to_soa(d_x, sx, nv, c->stream);
+  if (he == hipSuccess && d_p) he = t2r_launch_aos_to_soa(d_p, sp, nv, c->stream);
+  if (he == hipSuccess && !d_p) he = hipMemsetAsync(sp, 0, vb, c->stream);
+  if (he == hipSuccess && d_x_lag) he = t2r_launch_aos_to_soa(d_x_lag, sxp, nv, c->stream);
+  if (he != hipSuccess) { tfree(); return fail(c, T2R_E_HIP, "eval setup: %s", hipGetErrorString(he)); }
+  EvalParams Q{};
+  Q.sp = step_params(c);
+  Q.sp.envs = senv;
+  Q.sp.n_env = 1;
+  Q.sp.x = sx;
+  Q.sp.xprev = sxp;
+  Q.sp.g0 = sg0;
+  Q.sp.g1 = sg1;
+  Q.sp.diag = sd;
+  Q.sp.p = sp;
+  Q.sp.pairs = spairs;
+  Q.sp.fric = sfric;
+  Q.sp.stats = sstats;
+  Q.env = 0;
+  Q.pose = sposes;
+  Q.pose_lag = sposes + 7;
+  Q.has_lag = d_x_lag ? 1 : 0;
+  Q.has_p = d_p ? 1 : 0;
+  Q.grad_out = d_grad;
+  Q.diag_out = d_diag;
+  Q.scalars_out = d_scalars;
+  he = t2r_launch_eval(&Q, block_of(c), c->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+  tfree();
+  if (he != hipSuccess) return fail(c, T2R_E_HIP, "eval: %s", hipGetErrorString(he));
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_get_stats(t2r_ctx* c, void* out, size_t bytes) {
+  if (!c || !out) return T2R_E_ARG;
+  if (!c->committed) return fail(c, T2R_E_STATE, "no step has run");
+  const size_t need = c->envs.size() * sizeof(t2r_env_stats);
+  if (bytes < need) return fail(c, T2R_E_ARG, "buffer too small: %zu < %zu", bytes, need);
+  static_assert(sizeof(t2r_env_stats) == sizeof(EnvStats), "stats layout");
+  HIP_TRY(c, hipMemcpyAsync(out, c->d_stats, need, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_state_size(const t2r_ctx* c, int64_t* n) {
+  if (!c || !n) return T2R_E_ARG;
+  int64_t s = 0;
+  for (auto& e : c->envs) s += 3 * (int64_t)c->gels[e.gel].n_v + 7;
+  *n = s;
+  return T2R_OK;
+}
+
+t2r_status t2r_get_state(t2r_ctx* c, double* d_state) {
+  if (!c || !d_state) return T2R_E_ARG;
+  t2r_status s = commit(c);
+  if (s != T2R_OK) return s;
+  StepParams P = step_params(c);
+  HIP_TRY(c, t2r_launch_pack_state(&P, nullptr, d_state, c->d_state_off, 1, c->stream));
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_set_state(t2r_ctx* c, const double* d_state) {
+  if (!c || !d_state) return T2R_E_ARG;
+  t2r_status s = commit(c);
+  if (s != T2R_OK) return s;
+  StepParams P = step_params(c);
+  HIP_TRY(c, t2r_launch_pack_state(&P, d_state, nullptr, c->d_state_off, 0, c->stream));
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_reset_envs(t2r_ctx* c, const int32_t* ids, int32_t n) {
+  if (!c || (n > 0 && !ids) || n < 0) return T2R_E_ARG;
+  for (int i = 0; i < n; ++i)
+    if (ids[i] < 0 || ids[i] >= (int)c->envs.size()) return fail(c, T2R_E_ARG, "bad env id %d", ids[i]);
+  t2r_status s = commit(c);
+  if (s != T2R_OK) return s;
+  for (int i = 0; i < n; ++i) {
+    const EnvHost& e = c->envs[ids[i]];
+    const GelHost& g = c->gels[e.gel];
+    const EnvDev& ed = c->h_envs[ids[i]];
+    HIP_TRY(c, hipMemcpyAsync(c->d_x + ed.voff, g.dev.X, 3 * (size_t)g.n_v * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_pose_prev + 7 * (size_t)ids[i], e.pose0, 7 * sizeof(double),
+                              hipMemcpyHostToDevice, c->stream));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));  // host pose0 copies are pageable
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_set_pair_capacity(t2r_ctx* c, int32_t cap) {
+  if (!c || cap < 0) return T2R_E_ARG;
+  if (cap > (1 << 24)) return fail(c, T2R_E_ARG, "pair capacity too large");
+  if (c->committed) return fail(c, T2R_E_STATE, "pair capacity must be set before the first GPU call");
+  c->opts.pair_capacity = cap;
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_backward(t2r_ctx* c, const double*, double*) {
+  return fail(c, T2R_E_UNSUPPORTED, "the adjoint is not part of this build");
+}
+
+}  // extern "C"
+
+// ===========================================================================
+namespace {
+
+t2r_status upload_gel(t2r_ctx* c, GelHost& g) {
+  GelDev& d = g.dev;
+  d.n_v = g.n_v; d.n_t = g.n_t; d.n_tiles = (int)g.tile_tet.size() - 1;
+  d.n_sv = g.n_sv; d.n_se = g.n_se; d.n_sf = g.n_sf; d.n_m = g.n_m;
+  d.vol_total = g.vol_total;
+  d.diag_rest_max = g.diag_rest_max;
+  t2r_status s;
+#define UP(field, vec) if ((s = upload(c, vec, &d.field)) != T2R_OK) return s
+  UP(X, g.X); UP(fixed, g.fixed); UP(tet, g.tet); UP(tet_local, g.tet_local); UP(Dinv, g.Dinv);
+  UP(vol, g.vol); UP(Dinv32, g.Dinv32); UP(vol32, g.vol32); UP(tile_tet, g.tile_tet);
+  UP(tile_vstart, g.tile_vstart); UP(tile_verts, g.tile_verts); UP(tile_flags, g.tile_flags);
+  UP(surf_v, g.surf_v); UP(surf_e, g.surf_e); UP(surf_f, g.surf_f); UP(marker_tri, g.marker_tri);
+  UP(marker_w, g.marker_w);
+#undef UP
+  return T2R_OK;
+}
+
+t2r_status upload_grid(t2r_ctx* c, IndHost::GridHost& h, Grid& d) {
+  for (int a = 0; a < 3; ++a) { d.origin[a] = h.origin[a]; d.dims[a] = h.dims[a]; }
+  d.inv_cell = h.inv_cell;
+  d.n_prim = h.n;
+  t2r_status s;
+  if ((s = upload(c, h.start, &d.start)) != T2R_OK) return s;
+  if ((s = upload(c, h.items, &d.items)) != T2R_OK) return s;
+  return upload(c, h.box, &d.box);
+}
+
+t2r_status upload_ind(t2r_ctx* c, IndHost& I) {
+  IndDev& d = I.dev;
+  d.n_v = I.n_v; d.n_f = I.n_f; d.n_e = I.n_e; d.r_max = I.r_max;
+  for (int a = 0; a < 3; ++a) { d.box_lo[a] = I.lo[a]; d.box_hi[a] = I.hi[a]; }
+  t2r_status s;
+  if ((s = upload(c, I.Y, &d.Y)) != T2R_OK) return s;
+  if ((s = upload(c, I.tri, &d.tri)) != T2R_OK) return s;
+  if ((s = upload(c, I.edge, &d.edge)) != T2R_OK) return s;
+  if ((s = upload_grid(c, I.gv, d.gv)) != T2R_OK) return s;
+  if ((s = upload_grid(c, I.ge, d.ge)) != T2R_OK) return s;
+  return upload_grid(c, I.gf, d.gf);
+}
+
+template <typename T>
+T* alloc_n(t2r_ctx* c, size_t n) {
+  return (T*)dev_alloc(c, n * sizeof(T));
+}
+
+t2r_status commit(t2r_ctx* c) {
+  if (c->committed) return T2R_OK;
+  int dev_count = 0;
+  if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count == 0)
+    return fail(c, T2R_E_HIP, "no HIP device available");
+  t2r_status s;
+  for (auto& g : c->gels)
+    if ((s = upload_gel(c, g)) != T2R_OK) { dev_free_all(c); return s; }
+  for (auto& I : c->inds)
+    if ((s = upload_ind(c, I)) != T2R_OK) { dev_free_all(c); return s; }
+  std::vector<GelDev> hg;
+  for (auto& g : c->gels) hg.push_back(g.dev);
+  std::vector<IndDev> hi;
+  for (auto& I : c->inds) hi.push_back(I.dev);
+  const GelDev* dg;
+  const IndDev* di;
+  if ((s = upload(c, hg, &dg)) != T2R_OK) { dev_free_all(c); return s; }
+  if ((s = upload(c, hi, &di)) != T2R_OK) { dev_free_all(c); return s; }
+  c->d_gels = (GelDev*)dg;
+  c->d_inds = (IndDev*)di;
+  // per-env layout
+  c->h_envs.clear();
+  long long voff = 0, poff = 0, foff = 0, moff = 0, vtot = 0, soff = 0;
+  std::vector<long long> xoff, sofs;
+  for (auto& e : c->envs) {
+    const GelHost& g = c->gels[e.gel];
+    EnvDev d{};
+    d.gel = e.gel;
+    d.ind = e.ind;
+    d.mu = e.mat.E / (2.0 * (1.0 + e.mat.nu));
+    d.lam = e.mat.E * e.mat.nu / ((1.0 + e.mat.nu) * (1.0 - 2.0 * e.mat.nu));
+    d.mu_f = e.mat.mu_f;
+    d.eps_v = e.mat.eps_v;
+    d.dhat = e.mat.dhat;
+    d.kappa = e.mat.kappa;
+    int cap = c->opts.pair_capacity;
+    if (cap == 0) cap = std::max(4096, 2 * (g.n_sv + g.n_se + g.n_sf));
+    d.pair_cap = cap;
+    d.fric_cap = std::max(1024, cap / 2);
+    d.voff = voff;
+    d.poff = poff;
+    d.foff = foff;
+    d.moff = moff;
+    xoff.push_back(vtot);
+    sofs.push_back(soff);
+    voff += 3 * (long long)g.n_v;
+    poff += cap;
+    foff += d.fric_cap;
+    moff += g.n_m;
+    vtot += g.n_v;
+    soff += 3 * (long long)g.n_v + 7;
+    c->h_envs.push_back(d);
+  }
+  c->total_dofs = voff;
+  c->total_verts = vtot;
+  c->total_markers = moff;
+  c->state_size = soff;
+  const GelDev* dummy;
+  (void)dummy;
+  const EnvDev* de;
+  if ((s = upload(c, c->h_envs, &de)) != T2R_OK) { dev_free_all(c); return s; }
+  c->d_envs = (EnvDev*)de;
+  const long long* dx;
+  if ((s = upload(c, xoff, &dx)) != T2R_OK) { dev_free_all(c); return s; }
+  c->d_xout_off = (long long*)dx;
+  if ((s = upload(c, sofs, &dx)) != T2R_OK) { dev_free_all(c); return s; }
+  c->d_state_off = (long long*)dx;
+  const size_t nd = (size_t)voff;
+  c->d_x = alloc_n<double>(c, nd);
+  c->d_xprev = alloc_n<double>(c, nd);
+  c->d_g0 = alloc_n<double>(c, nd);
+  c->d_g1 = alloc_n<double>(c, nd);
+  c->d_diag = alloc_n<double>(c, nd);
+  c->d_p = alloc_n<double>(c, nd);
+  c->d_pose_prev = alloc_n<double>(c, 7 * c->envs.size());
+  c->d_pairs = alloc_n<int2>(c, (size_t)poff);
+  c->d_fric = alloc_n<FricPair>(c, (size_t)foff);
+  c->d_stats = alloc_n<EnvStats>(c, c->envs.size());
+  if (!c->d_x || !c->d_xprev || !c->d_g0 || !c->d_g1 || !c->d_diag || !c->d_p || !c->d_pose_prev ||
+      !c->d_pairs || !c->d_fric || !c->d_stats) {
+    dev_free_all(c);
+    return fail(c, T2R_E_NOMEM, "state allocation failed (%lld DOFs)", voff);
+  }
+  // initial state: x = X, p = 0, pose_prev = pose0
+  std::vector<double> pose(7 * c->envs.size());
+  for (size_t i = 0; i < c->envs.size(); ++i) {
+    const GelHost& g = c->gels[c->envs[i].gel];
+    HIP_TRY(c, hipMemcpyAsync(c->d_x + c->h_envs[i].voff, g.dev.X, 3 * (size_t)g.n_v * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+    for (int k = 0; k < 7; ++k) pose[7 * i + k] = c->envs[i].pose0[k];
+  }
+  HIP_TRY(c, hipMemsetAsync(c->d_p, 0, nd * sizeof(double), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_stats, 0, c->envs.size() * sizeof(EnvStats), c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_pose_prev, pose.data(), pose.size() * sizeof(double), hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));  // host staging vectors go out of scope
+  c->committed = true;
+  return T2R_OK;
+}
+
+}  // namespace

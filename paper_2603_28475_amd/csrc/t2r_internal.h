@@ -1,0 +1,145 @@
+// Internal descriptors shared by the host library and the gfx950 kernels.
+// All device arrays are structure-of-arrays: a [k][n] array stores component c
+// of item i at c*n + i, so that consecutive threads read consecutive words.
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace t2r {
+
+// Tet tiles: a workgroup stages one tile's vertices in LDS, evaluates its tets
+// and accumulates per-vertex sums with LDS atomics before one global flush.
+constexpr int kTileTets = 512;
+constexpr int kTileVerts = 256;   // local vertex ids fit in one byte
+constexpr int kMaxBlock = 1024;
+
+// Pair kinds of the contact list (top three bits of the first word).
+constexpr int kVF = 0;   // gel surface vertex  vs indenter triangle
+constexpr int kFV = 1;   // indenter vertex     vs gel surface triangle
+constexpr int kEE = 2;   // gel surface edge    vs indenter edge
+constexpr int kKindShift = 29;
+constexpr int kPrimMask = (1 << kKindShift) - 1;
+
+// Tile vertex flags.
+constexpr uint8_t kFirstTouch = 1;  // this tile writes the vertex first (store, not add)
+constexpr uint8_t kLastTouch = 2;   // this tile writes it last (fixed vertices reset here)
+
+struct Grid {              // uniform grid over an indenter's local bounding box
+  double origin[3];
+  double inv_cell;         // 1 / cell edge (cells are cubes)
+  int dims[3];
+  const int* start;        // [ncell+1] CSR offsets
+  const int* items;        // primitive ids per cell
+  const double* box;       // [6][n_prim]: lo xyz, hi xyz of each primitive (local frame)
+  int n_prim;
+};
+
+struct GelDev {
+  int n_v, n_t, n_tiles, n_sv, n_se, n_sf, n_m;
+  double vol_total;        // sum of rest volumes
+  double diag_rest_max;    // largest rest elastic diagonal entry for mu = 1, lam = 0
+  const double* X;         // [3][n_v]
+  const uint8_t* fixed;    // [n_v]
+  const int* tet;          // [4][n_t] global vertex ids, tiled order
+  const uint32_t* tet_local;  // [n_t] four local ids (bytes 0..3)
+  const double* Dinv;      // [9][n_t] Dm^-1 row-major entries
+  const double* vol;       // [n_t]
+  const float* Dinv32;     // [9][n_t] FP32 copy (mixed precision)
+  const float* vol32;      // [n_t]
+  const int* tile_tet;     // [n_tiles+1]
+  const int* tile_vstart;  // [n_tiles+1]
+  const int* tile_verts;   // global vertex ids of each tile
+  const uint8_t* tile_flags;  // kFirstTouch | kLastTouch per tile vertex
+  const int* surf_v;       // [n_sv]
+  const int* surf_e;       // [2][n_se]
+  const int* surf_f;       // [3][n_sf]
+  const int* marker_tri;   // [3][n_m]
+  const double* marker_w;  // [3][n_m]
+};
+
+struct IndDev {
+  int n_v, n_f, n_e;
+  double r_max;            // largest |y| over local vertices
+  double box_lo[3], box_hi[3];  // local bounding box
+  const double* Y;         // [3][n_v]
+  const int* tri;          // [3][n_f]
+  const int* edge;         // [2][n_e]
+  Grid gv, ge, gf;         // grids of vertices, edges and triangles
+};
+
+struct EnvDev {
+  int gel, ind;
+  double mu, lam, mu_f, eps_v, dhat, kappa;
+  long long voff;          // offset (doubles) of this env's [3][n_v] block in each state array
+  long long poff;          // offset of its pair list
+  long long foff;          // offset of its friction list
+  long long moff;          // offset (markers) in the marker output
+  int pair_cap, fric_cap;
+};
+
+struct FricPair {          // lagged friction data of one pair (Supp. A, eq. friction_energy)
+  int gv[3];               // gel vertex ids (-1 unused)
+  int iv[3];               // indenter vertex ids (-1 unused)
+  double a[3];             // gel-side closest-point weights
+  double c[3];             // indenter-side closest-point weights
+  double n[3];             // unit normal, indenter closest point -> gel closest point
+  double base[3];          // sum a x_prev - sum c y(q_prev)
+  double mulam;            // mu_f * lambda = -mu_f kappa b'(d) at the lag
+};
+
+struct EnvStats {
+  int status, iters, substeps, restarts, halvings, reculls, n_candidates, n_active,
+      n_friction, max_solve_iters;
+  double d_min, residual, energy;
+};
+
+struct StepParams {
+  const GelDev* gels;
+  const IndDev* inds;
+  const EnvDev* envs;
+  int n_env;
+  // state
+  double* x;               // [sum 3 n_v]
+  double* xprev;
+  double* g0;
+  double* g1;
+  double* diag;
+  double* p;
+  double* pose_prev;       // [n_env][7]
+  int2* pairs;             // [sum pair_cap]
+  FricPair* fric;          // [sum fric_cap]
+  EnvStats* stats;         // [n_env]
+  // inputs / outputs
+  const double* pose_in;   // [n_env][7]
+  const int* env_mask;     // [n_env] or null
+  double* markers_out;     // [sum n_m][3] or null
+  double* x_out;           // [sum n_v][3] or null
+  int* status_out;         // [n_env] or null
+  long long* x_out_off;    // [n_env] vertex offsets into x_out
+  // options
+  double tol, substep_tol;
+  int max_iters, max_substeps, precision, armijo;
+};
+
+struct EvalParams {
+  StepParams sp;           // state pointers point at scratch copies
+  int env;
+  const double* pose;      // device [7]
+  const double* pose_lag;  // device [7]
+  int has_lag, has_p;
+  double* grad_out;        // [n_v][3] or null
+  double* diag_out;
+  double* scalars_out;     // [8]
+};
+
+}  // namespace t2r
+
+extern "C" {
+hipError_t t2r_launch_step(const t2r::StepParams* p, int block, hipStream_t stream);
+hipError_t t2r_launch_eval(const t2r::EvalParams* p, int block, hipStream_t stream);
+hipError_t t2r_launch_pack_state(const t2r::StepParams* p, const double* in, double* out,
+                                 const long long* state_off, int direction, hipStream_t stream);
+hipError_t t2r_launch_aos_to_soa(const double* in, double* out, int nv, hipStream_t stream);
+}

@@ -1,0 +1,1209 @@
+// gfx950 kernels of the PNCG-IPC gel solver.
+//
+// One workgroup owns one environment for a whole load step: continuation over
+// the indenter motion, broad phase, every PNCG iteration and the marker output
+// run in one launch with only workgroup barriers, so the iteration loop stays
+// on the device and an env's vectors are touched by a single CU (its L1 and the
+// XCD's L2). Thousands of environments fill the 256 CUs.
+//
+// Per PNCG iteration (Supp. A, eqs. dk_direction, step_size):
+//   curvature pass   p^T H p over tets (LDS-staged tiles) and contact pairs
+//   CCD pass         conservative step bound over candidate pairs
+//   eval pass        Pi, grad, diag(H) at x + alpha p (tiles + pairs + friction),
+//                    repeated with alpha/2 until feasible and decreasing
+//   dots pass        x += alpha p, P = diag^-1, DK dot products, |P g|_inf
+//   direction pass   p = -P g + beta p
+#include <float.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "t2r_internal.h"
+#include "t2r_math.h"
+
+namespace t2r {
+
+constexpr double kInf = 1.0e300;
+constexpr double kArmijoC = 1e-4;
+constexpr double kEnergyGuard64 = 1e-13;   // x mu * total volume
+constexpr double kEnergyGuard32 = 1e-6;
+constexpr double kDiagFloor = 1e-12;       // x mu * largest rest diagonal (mu = 1 part)
+constexpr double kYpMin = 1e-30;
+constexpr int kMaxHalvings = 30;
+constexpr double kCcdGap = 0.1;            // keep every pair at >= 10% of its gap
+constexpr int kCcdMaxAdvance = 64;
+constexpr double kSqrt3 = 1.7320508075688772;
+
+// Status bits (mirror T2R_ENV_* in t2r.h).
+constexpr int kConverged = 1, kMaxIter = 2, kInfeasible = 4, kNonFinite = 8, kOverflow = 16,
+              kLineSearch = 32, kSubsteps = 64, kSkipped = 128;
+
+// ---------------------------------------------------------------------------
+// Workgroup shared state
+// ---------------------------------------------------------------------------
+struct Shared {
+  double R[9], t[3];          // current indenter pose
+  double iw_lo[3], iw_hi[3];  // indenter world bounding box
+  double red[16 * 8];         // per-wave partials
+  double bc[8];               // broadcast results
+  int count, overflow, flag;
+  int pad;
+};
+
+struct Tile {
+  double x[3][kTileVerts];
+  double p[3][kTileVerts];
+  double g[3][kTileVerts];
+  double d[3][kTileVerts];
+};
+
+// Block-wide reduction of NS sums followed by NM maxima (values in v[0..NS+NM)).
+// Every thread receives the results in v.
+template <int NS, int NM>
+__device__ inline void block_reduce(double* v, Shared& S) {
+  constexpr int N = NS + NM;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double a = v[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double b = __shfl_xor(a, o, 64);
+      a = (i < NS) ? a + b : fmax(a, b);
+    }
+    v[i] = a;
+  }
+  __syncthreads();  // previous readers of S.red / S.bc are done
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) S.red[wave * 8 + i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    const int i = threadIdx.x;
+    double a = S.red[i];
+    for (int w = 1; w < nw; ++w) a = (i < NS) ? a + S.red[w * 8 + i] : fmax(a, S.red[w * 8 + i]);
+    S.bc[i] = a;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = S.bc[i];
+}
+
+__device__ inline double block_min(double v, Shared& S) {
+  double a = -v;
+  block_reduce<0, 1>(&a, S);
+  return -a;
+}
+
+// ---------------------------------------------------------------------------
+// Pose helpers (thread 0 writes S)
+// ---------------------------------------------------------------------------
+__device__ inline void quat_to_R(const double q_in[4], double R[9]) {
+  const double n = sqrt(q_in[0] * q_in[0] + q_in[1] * q_in[1] + q_in[2] * q_in[2] + q_in[3] * q_in[3]);
+  const double w = q_in[0] / n, x = q_in[1] / n, y = q_in[2] / n, z = q_in[3] / n;
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z); R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
+}
+
+// Pose at tau between p0 and p1: translation linear, rotation by slerp.
+__device__ inline void interp_pose(const double p0[7], const double p1[7], double tau, double out[7]) {
+  for (int i = 0; i < 3; ++i) out[i] = (1.0 - tau) * p0[i] + tau * p1[i];
+  double q0[4], q1[4];
+  double n0 = 0, n1 = 0;
+  for (int i = 0; i < 4; ++i) { q0[i] = p0[3 + i]; q1[i] = p1[3 + i]; n0 += q0[i] * q0[i]; n1 += q1[i] * q1[i]; }
+  n0 = sqrt(n0); n1 = sqrt(n1);
+  double c = 0;
+  for (int i = 0; i < 4; ++i) { q0[i] /= n0; q1[i] /= n1; c += q0[i] * q1[i]; }
+  if (c < 0) { for (int i = 0; i < 4; ++i) q1[i] = -q1[i]; c = -c; }
+  c = fmin(c, 1.0);
+  const double th = acos(c);
+  double a, b;
+  if (th < 1e-12) { a = 1.0 - tau; b = tau; }
+  else { const double s = sin(th); a = sin((1.0 - tau) * th) / s; b = sin(tau * th) / s; }
+  double n = 0;
+  for (int i = 0; i < 4; ++i) { out[3 + i] = a * q0[i] + b * q1[i]; n += out[3 + i] * out[3 + i]; }
+  n = sqrt(n);
+  for (int i = 0; i < 4; ++i) out[3 + i] /= n;
+}
+
+__device__ inline void set_pose(Shared& S, const IndDev& I, const double pose[7]) {
+  quat_to_R(pose + 3, S.R);
+  for (int i = 0; i < 3; ++i) S.t[i] = pose[i];
+  // world box of the local box
+  double c[3], h[3];
+  for (int i = 0; i < 3; ++i) { c[i] = 0.5 * (I.box_lo[i] + I.box_hi[i]); h[i] = 0.5 * (I.box_hi[i] - I.box_lo[i]); }
+  for (int a = 0; a < 3; ++a) {
+    const double cw = S.R[a * 3 + 0] * c[0] + S.R[a * 3 + 1] * c[1] + S.R[a * 3 + 2] * c[2] + S.t[a];
+    const double hw = fabs(S.R[a * 3 + 0]) * h[0] + fabs(S.R[a * 3 + 1]) * h[1] + fabs(S.R[a * 3 + 2]) * h[2];
+    S.iw_lo[a] = cw - hw;
+    S.iw_hi[a] = cw + hw;
+  }
+}
+
+__device__ inline void ind_world(const Shared& S, const IndDev& I, int j, double y[3]) {
+  const double a = I.Y[j], b = I.Y[I.n_v + j], c = I.Y[2 * I.n_v + j];
+  for (int r = 0; r < 3; ++r) y[r] = S.R[r * 3 + 0] * a + S.R[r * 3 + 1] * b + S.R[r * 3 + 2] * c + S.t[r];
+}
+
+// ---------------------------------------------------------------------------
+// Env view: pointers of one env's state
+// ---------------------------------------------------------------------------
+struct View {
+  const GelDev* G;
+  const IndDev* I;
+  const EnvDev* E;
+  double* x;
+  double* xprev;
+  double* g0;
+  double* g1;
+  double* diag;
+  double* p;
+  int2* pairs;
+  FricPair* fric;
+  int npairs, nfric;
+  int mixed;
+};
+
+// ---------------------------------------------------------------------------
+// Element passes over LDS-staged tiles
+// ---------------------------------------------------------------------------
+__device__ inline void load_Dm(const GelDev& G, int e, double Dm[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Dm[k] = G.Dinv[k * G.n_t + e];
+}
+
+// Evaluates sum V psi, the gradient and diag(H) of the elastic term at
+// x + alpha p into gout/dout ([3][n_v]). Returns energy (thread partial) and
+// clears `feasible` on an inverted tet.
+__device__ double elem_eval(const View& V, const double* x, const double* p, double alpha,
+                            double* gout, double* dout, Tile& T, int& feasible) {
+  const GelDev& G = *V.G;
+  const EnvDev& E = *V.E;
+  const int nv = G.n_v;
+  double energy = 0.0;
+  for (int tile = 0; tile < G.n_tiles; ++tile) {
+    const int t0 = G.tile_tet[tile], t1 = G.tile_tet[tile + 1];
+    const int v0 = G.tile_vstart[tile], ntv = G.tile_vstart[tile + 1] - v0;
+    for (int i = threadIdx.x; i < ntv; i += blockDim.x) {
+      const int v = G.tile_verts[v0 + i];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T.x[c][i] = fma(alpha, p[c * nv + v], x[c * nv + v]);
+        T.g[c][i] = 0.0;
+        T.d[c][i] = 0.0;
+      }
+    }
+    __syncthreads();
+    for (int e = t0 + threadIdx.x; e < t1; e += blockDim.x) {
+      const uint32_t loc = G.tet_local[e];
+      int l[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) l[k] = (loc >> (8 * k)) & 0xff;
+      bool ok;
+      if (V.mixed) {
+        float Ds[9], Dm[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) Ds[a * 3 + k] = (float)(T.x[a][l[k + 1]] - T.x[a][l[0]]);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Dm[k] = G.Dinv32[k * G.n_t + e];
+        TetDer<float> r;
+        ok = tet_grad_diag<float>(Ds, Dm, G.vol32[e], (float)E.mu, (float)E.lam, r);
+        if (ok) {
+          energy += (double)r.E;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              atomicAdd(&T.g[c][l[k]], (double)r.g[k][c]);
+              atomicAdd(&T.d[c][l[k]], (double)r.d[k][c]);
+            }
+        }
+      } else {
+        double Ds[9], Dm[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) Ds[a * 3 + k] = T.x[a][l[k + 1]] - T.x[a][l[0]];
+        load_Dm(G, e, Dm);
+        TetDer<double> r;
+        ok = tet_grad_diag<double>(Ds, Dm, G.vol[e], E.mu, E.lam, r);
+        if (ok) {
+          energy += r.E;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              atomicAdd(&T.g[c][l[k]], r.g[k][c]);
+              atomicAdd(&T.d[c][l[k]], r.d[k][c]);
+            }
+        }
+      }
+      if (!ok) feasible = 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ntv; i += blockDim.x) {
+      const int v = G.tile_verts[v0 + i];
+      const uint8_t fl = G.tile_flags[v0 + i];
+      const bool fixed = (fl & kLastTouch) && G.fixed[v];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double gv = T.g[c][i], dv = T.d[c][i];
+        if (!(fl & kFirstTouch)) {
+          gv += gout[c * nv + v];
+          dv += dout[c * nv + v];
+        }
+        if (fixed) { gv = 0.0; dv = 1.0; }
+        gout[c * nv + v] = gv;
+        dout[c * nv + v] = dv;
+      }
+    }
+    __syncthreads();
+  }
+  return energy;
+}
+
+// p^T H_elastic p at x (thread partial).
+__device__ double elem_curv(const View& V, const double* x, const double* p, Tile& T) {
+  const GelDev& G = *V.G;
+  const EnvDev& E = *V.E;
+  const int nv = G.n_v;
+  double curv = 0.0;
+  for (int tile = 0; tile < G.n_tiles; ++tile) {
+    const int t0 = G.tile_tet[tile], t1 = G.tile_tet[tile + 1];
+    const int v0 = G.tile_vstart[tile], ntv = G.tile_vstart[tile + 1] - v0;
+    for (int i = threadIdx.x; i < ntv; i += blockDim.x) {
+      const int v = G.tile_verts[v0 + i];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T.x[c][i] = x[c * nv + v];
+        T.p[c][i] = p[c * nv + v];
+      }
+    }
+    __syncthreads();
+    for (int e = t0 + threadIdx.x; e < t1; e += blockDim.x) {
+      const uint32_t loc = G.tet_local[e];
+      int l[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) l[k] = (loc >> (8 * k)) & 0xff;
+      if (V.mixed) {
+        float Ds[9], dDs[9], Dm[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            Ds[a * 3 + k] = (float)(T.x[a][l[k + 1]] - T.x[a][l[0]]);
+            dDs[a * 3 + k] = (float)(T.p[a][l[k + 1]] - T.p[a][l[0]]);
+          }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Dm[k] = G.Dinv32[k * G.n_t + e];
+        curv += (double)tet_curvature<float>(Ds, dDs, Dm, G.vol32[e], (float)E.mu, (float)E.lam);
+      } else {
+        double Ds[9], dDs[9], Dm[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            Ds[a * 3 + k] = T.x[a][l[k + 1]] - T.x[a][l[0]];
+            dDs[a * 3 + k] = T.p[a][l[k + 1]] - T.p[a][l[0]];
+          }
+        load_Dm(G, e, Dm);
+        curv += tet_curvature<double>(Ds, dDs, Dm, G.vol[e], E.mu, E.lam);
+      }
+    }
+    __syncthreads();
+  }
+  return curv;
+}
+
+// ---------------------------------------------------------------------------
+// Contact pairs
+// ---------------------------------------------------------------------------
+struct PairPts {
+  double z[4][3];
+  int gid[4];      // gel vertex id or -1 for indenter points
+  int kind;
+};
+
+// Gathers the four points of pair `pr`; gel points at x + alpha p.
+__device__ inline void load_pair(const View& V, const Shared& S, int2 pr, const double* x,
+                                 const double* p, double alpha, PairPts& P) {
+  const GelDev& G = *V.G;
+  const IndDev& I = *V.I;
+  const int nv = G.n_v;
+  const int kind = (int)((unsigned)pr.x >> kKindShift);
+  const int gp = pr.x & kPrimMask, ip = pr.y;
+  P.kind = kind;
+  int gv[4] = {-1, -1, -1, -1}, iv[4] = {-1, -1, -1, -1};
+  if (kind == kVF) {
+    gv[0] = gp;
+    iv[1] = I.tri[ip]; iv[2] = I.tri[I.n_f + ip]; iv[3] = I.tri[2 * I.n_f + ip];
+  } else if (kind == kFV) {
+    iv[0] = ip;
+    gv[1] = G.surf_f[gp]; gv[2] = G.surf_f[G.n_sf + gp]; gv[3] = G.surf_f[2 * G.n_sf + gp];
+  } else {
+    gv[0] = G.surf_e[gp]; gv[1] = G.surf_e[G.n_se + gp];
+    iv[2] = I.edge[ip]; iv[3] = I.edge[I.n_e + ip];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    P.gid[k] = gv[k];
+    if (gv[k] >= 0) {
+      for (int c = 0; c < 3; ++c) {
+        const double xv = x[c * nv + gv[k]];
+        P.z[k][c] = p ? fma(alpha, p[c * nv + gv[k]], xv) : xv;
+      }
+    } else {
+      ind_world(S, I, iv[k], P.z[k]);
+    }
+  }
+}
+
+__device__ inline void classify(const PairPts& P, Feature& f) {
+  if (P.kind == kEE) classify_ee(P.z[0], P.z[1], P.z[2], P.z[3], f);
+  else classify_pt(P.z[0], P.z[1], P.z[2], P.z[3], f);
+}
+
+__device__ inline double pair_distance(const PairPts& P, const Feature& f, double r[3]) {
+  for (int c = 0; c < 3; ++c) r[c] = f.c[0] * P.z[0][c] + f.c[1] * P.z[1][c] + f.c[2] * P.z[2][c] + f.c[3] * P.z[3][c];
+  return sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+}
+
+// Barrier energy, gradient and diag of every candidate pair at x + alpha p.
+__device__ double pairs_eval(const View& V, const Shared& S, const double* x, const double* p,
+                             double alpha, double* gout, double* dout, int& feasible, int& nactive) {
+  const GelDev& G = *V.G;
+  const EnvDev& E = *V.E;
+  const int nv = G.n_v;
+  const double dh = E.dhat, kap = E.kappa;
+  double energy = 0.0;
+  for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
+    PairPts P;
+    load_pair(V, S, V.pairs[i], x, p, alpha, P);
+    Feature f;
+    classify(P, f);
+    double r[3];
+    const double d = pair_distance(P, f, r);
+    if (!(d > 0.0)) { feasible = 0; continue; }
+    if (d >= dh) continue;
+    ++nactive;
+    double b, b1, b2;
+    barrier3(d, dh, b, b1, b2);
+    energy += kap * b;
+    const double invd = 1.0 / d;
+    double n[3] = {r[0] * invd, r[1] * invd, r[2] * invd};
+    double D[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    for (int w = 0; w < f.k; ++w)
+      for (int c = 0; c < 3; ++c)
+        D[w][c] = f.cw[0][w] * P.z[0][c] + f.cw[1][w] * P.z[1][c] + f.cw[2][w] * P.z[2][c] + f.cw[3][w] * P.z[3][c];
+    double Mi[2][2];
+    gram_inverse(D, f.k, Mi);
+    for (int k = 0; k < 4; ++k) {
+      const int v = P.gid[k];
+      if (v < 0 || G.fixed[v]) continue;
+      const double ci = f.c[k];
+      for (int c = 0; c < 3; ++c) {
+        const double gi = ci * n[c];
+        double u0 = 0.0, u1 = 0.0;
+        if (f.k > 0) u0 = f.cw[k][0] * r[c] + ci * D[0][c];
+        if (f.k > 1) u1 = f.cw[k][1] * r[c] + ci * D[1][c];
+        const double uMu = u0 * (Mi[0][0] * u0 + Mi[0][1] * u1) + u1 * (Mi[1][0] * u0 + Mi[1][1] * u1);
+        const double hdd = (ci * ci - uMu) * invd - gi * gi * invd;
+        atomicAdd(&gout[c * nv + v], kap * b1 * gi);
+        atomicAdd(&dout[c * nv + v], kap * (b2 * gi * gi + b1 * hdd));
+      }
+    }
+  }
+  return energy;
+}
+
+// p^T H_barrier p at x (thread partial).
+__device__ double pairs_curv(const View& V, const Shared& S, const double* x, const double* p) {
+  const GelDev& G = *V.G;
+  const EnvDev& E = *V.E;
+  const int nv = G.n_v;
+  const double dh = E.dhat, kap = E.kappa;
+  double curv = 0.0;
+  for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
+    PairPts P;
+    load_pair(V, S, V.pairs[i], x, nullptr, 0.0, P);
+    Feature f;
+    classify(P, f);
+    double r[3];
+    const double d = pair_distance(P, f, r);
+    if (!(d > 0.0) || d >= dh) continue;
+    double b, b1, b2;
+    barrier3(d, dh, b, b1, b2);
+    const double invd = 1.0 / d;
+    double n[3] = {r[0] * invd, r[1] * invd, r[2] * invd};
+    double D[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    for (int w = 0; w < f.k; ++w)
+      for (int c = 0; c < 3; ++c)
+        D[w][c] = f.cw[0][w] * P.z[0][c] + f.cw[1][w] * P.z[1][c] + f.cw[2][w] * P.z[2][c] + f.cw[3][w] * P.z[3][c];
+    double Mi[2][2];
+    gram_inverse(D, f.k, Mi);
+    double q[3] = {0, 0, 0}, vv[2] = {0, 0};
+    for (int k = 0; k < 4; ++k) {
+      const int v = P.gid[k];
+      if (v < 0 || G.fixed[v]) continue;
+      double pk[3];
+      for (int c = 0; c < 3; ++c) pk[c] = p[c * nv + v];
+      for (int c = 0; c < 3; ++c) q[c] += f.c[k] * pk[c];
+      const double rp = dot3(r, pk);
+      for (int w = 0; w < f.k; ++w) vv[w] += f.cw[k][w] * rp + f.c[k] * dot3(D[w], pk);
+    }
+    const double nq = dot3(n, q);
+    const double vMv = vv[0] * (Mi[0][0] * vv[0] + Mi[0][1] * vv[1]) + vv[1] * (Mi[1][0] * vv[0] + Mi[1][1] * vv[1]);
+    const double pHp = (dot3(q, q) - vMv) * invd - nq * nq * invd;
+    curv += kap * (b2 * nq * nq + b1 * pHp);
+  }
+  return curv;
+}
+
+// Smallest distance over candidate pairs at x (thread partial; kInf if none).
+__device__ double pairs_dmin(const View& V, const Shared& S, const double* x, int& nactive) {
+  double dmin = kInf;
+  for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
+    PairPts P;
+    load_pair(V, S, V.pairs[i], x, nullptr, 0.0, P);
+    Feature f;
+    classify(P, f);
+    double r[3];
+    const double d = pair_distance(P, f, r);
+    dmin = fmin(dmin, d);
+    if (d < V.E->dhat) ++nactive;
+  }
+  return dmin;
+}
+
+// Conservative advancement: largest t <= amax keeping each pair at >= kCcdGap of its
+// start distance, gel points moving along p, indenter static (thread partial min).
+__device__ double pairs_ccd(const View& V, const Shared& S, const double* x, const double* p, double amax) {
+  const int nv = V.G->n_v;
+  double tmin = amax;
+  for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
+    PairPts P;
+    load_pair(V, S, V.pairs[i], x, nullptr, 0.0, P);
+    double l = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      const int v = P.gid[k];
+      if (v < 0) continue;
+      double s = 0.0;
+      for (int c = 0; c < 3; ++c) { const double pc = p[c * nv + v]; s += pc * pc; }
+      l = fmax(l, sqrt(s));
+    }
+    if (l == 0.0) continue;
+    Feature f;
+    classify(P, f);
+    double r[3];
+    const double d0 = pair_distance(P, f, r);
+    if (!(d0 > 0.0)) { tmin = 0.0; continue; }
+    const double gap = kCcdGap * d0;
+    if (l * amax <= d0 - gap) continue;
+    double t = 0.0, d = d0;
+    for (int it = 0; it < kCcdMaxAdvance; ++it) {
+      if (l * (amax - t) <= d - gap) { t = amax; break; }
+      t += (d - gap) / l;
+      PairPts Q;
+      load_pair(V, S, V.pairs[i], x, p, t, Q);
+      Feature g;
+      classify(Q, g);
+      d = pair_distance(Q, g, r);
+      if (d - gap <= 1e-3 * (d0 - gap)) break;
+    }
+    tmin = fmin(tmin, fmin(t, amax));
+  }
+  return tmin;
+}
+
+// ---------------------------------------------------------------------------
+// Lagged friction (Supp. A, eqs. friction_energy, friction_mollifier)
+// ---------------------------------------------------------------------------
+__device__ inline void fric_delta(const View& V, const Shared& S, const FricPair& F, const double* x,
+                                  const double* p, double alpha, double Dl[3]) {
+  const int nv = V.G->n_v;
+  const IndDev& I = *V.I;
+  for (int c = 0; c < 3; ++c) Dl[c] = -F.base[c];
+  for (int k = 0; k < 3; ++k) {
+    const int v = F.gv[k];
+    if (v < 0) continue;
+    for (int c = 0; c < 3; ++c) {
+      const double xv = x[c * nv + v];
+      Dl[c] += F.a[k] * (p ? fma(alpha, p[c * nv + v], xv) : xv);
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    const int j = F.iv[k];
+    if (j < 0) continue;
+    double y[3];
+    ind_world(S, I, j, y);
+    for (int c = 0; c < 3; ++c) Dl[c] -= F.c[k] * y[c];
+  }
+}
+
+__device__ double fric_eval(const View& V, const Shared& S, const double* x, const double* p, double alpha,
+                            double* gout, double* dout) {
+  const GelDev& G = *V.G;
+  const int nv = G.n_v;
+  const double eps = V.E->eps_v;
+  double energy = 0.0;
+  for (int i = threadIdx.x; i < V.nfric; i += blockDim.x) {
+    const FricPair F = V.fric[i];
+    double Dl[3];
+    fric_delta(V, S, F, x, p, alpha, Dl);
+    const double nD = dot3(F.n, Dl);
+    double TD[3];
+    for (int c = 0; c < 3; ++c) TD[c] = Dl[c] - nD * F.n[c];
+    const double s = sqrt(dot3(TD, TD));
+    double f, fos, corr;
+    mollifier3(s, eps, f, fos, corr);
+    energy += F.mulam * f;
+    double uh[3] = {0, 0, 0};
+    if (s > 0) for (int c = 0; c < 3; ++c) uh[c] = TD[c] / s;
+    for (int k = 0; k < 3; ++k) {
+      const int v = F.gv[k];
+      if (v < 0 || G.fixed[v]) continue;
+      const double a = F.a[k];
+      for (int c = 0; c < 3; ++c) {
+        atomicAdd(&gout[c * nv + v], F.mulam * a * fos * TD[c]);
+        const double h = fos * (1.0 - F.n[c] * F.n[c]) + corr * uh[c] * uh[c];
+        atomicAdd(&dout[c * nv + v], F.mulam * a * a * h);
+      }
+    }
+  }
+  return energy;
+}
+
+__device__ double fric_curv(const View& V, const Shared& S, const double* x, const double* p) {
+  const GelDev& G = *V.G;
+  const int nv = G.n_v;
+  const double eps = V.E->eps_v;
+  double curv = 0.0;
+  for (int i = threadIdx.x; i < V.nfric; i += blockDim.x) {
+    const FricPair F = V.fric[i];
+    double Dl[3];
+    fric_delta(V, S, F, x, nullptr, 0.0, Dl);
+    const double nD = dot3(F.n, Dl);
+    double TD[3];
+    for (int c = 0; c < 3; ++c) TD[c] = Dl[c] - nD * F.n[c];
+    const double s = sqrt(dot3(TD, TD));
+    double f, fos, corr;
+    mollifier3(s, eps, f, fos, corr);
+    double q[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k) {
+      const int v = F.gv[k];
+      if (v < 0 || G.fixed[v]) continue;
+      for (int c = 0; c < 3; ++c) q[c] += F.a[k] * p[c * nv + v];
+    }
+    const double nq = dot3(F.n, q);
+    double uq = 0.0;
+    if (s > 0) uq = dot3(TD, q) / s;
+    curv += F.mulam * (fos * (dot3(q, q) - nq * nq) + corr * uq * uq);
+  }
+  return curv;
+}
+
+// ---------------------------------------------------------------------------
+// Broad phase: each gel surface primitive queries a uniform grid of the
+// indenter's primitives in the indenter's local frame. A pair is reported from
+// the single cell holding the lowest corner of the two boxes' overlap.
+// ---------------------------------------------------------------------------
+__device__ inline int cell_of(double v, double o, double inv, int dim) {
+  int c = (int)floor((v - o) * inv);
+  return c < 0 ? 0 : (c >= dim ? dim - 1 : c);
+}
+
+// Writes the friction record of a pair closer than dhat at the lag state.
+__device__ inline void make_fric(const View& V, const PairPts& P, const Feature& f, const double r[3],
+                                 double d, int2 pr, FricPair& F) {
+  const IndDev& I = *V.I;
+  const EnvDev& E = *V.E;
+  const int kind = P.kind;
+  const double sgn = (kind == kFV) ? -1.0 : 1.0;  // r = gel - indenter for VF and EE
+  for (int c = 0; c < 3; ++c) F.n[c] = sgn * r[c] / d;
+  const int gp = pr.x & kPrimMask, ip = pr.y;
+  for (int k = 0; k < 3; ++k) { F.gv[k] = -1; F.iv[k] = -1; F.a[k] = 0.0; F.c[k] = 0.0; }
+  int ng = 0, ni = 0;
+  for (int k = 0; k < 4; ++k) {
+    if (P.gid[k] >= 0) { F.gv[ng] = P.gid[k]; F.a[ng] = sgn * f.c[k]; ++ng; }
+  }
+  int ids[3] = {-1, -1, -1};
+  if (kind == kVF) { ids[0] = I.tri[ip]; ids[1] = I.tri[I.n_f + ip]; ids[2] = I.tri[2 * I.n_f + ip]; }
+  else if (kind == kFV) { ids[0] = ip; }
+  else { ids[0] = I.edge[ip]; ids[1] = I.edge[I.n_e + ip]; }
+  for (int k = 0; k < 4; ++k) {
+    if (P.gid[k] < 0) { F.iv[ni] = ids[ni]; F.c[ni] = -sgn * f.c[k]; ++ni; }
+  }
+  for (int c = 0; c < 3; ++c) {
+    double s = 0.0;
+    for (int k = 0; k < 4; ++k) s += sgn * f.c[k] * P.z[k][c];  // gel cp - indenter cp
+    F.base[c] = s;
+  }
+  double b, b1, b2;
+  barrier3(d, E.dhat, b, b1, b2);
+  F.mulam = -E.mu_f * E.kappa * b1;
+  (void)gp;
+}
+
+// mode 0: candidate pairs (d < thr) into V.pairs; mode 1: friction records for
+// pairs with d < dhat; mode 2: distances only. Returns the thread's smallest d.
+__device__ double cull(View& V, Shared& S, const double* x, double thr, int mode, int cap) {
+  const GelDev& G = *V.G;
+  const IndDev& I = *V.I;
+  const int nv = G.n_v;
+  if (threadIdx.x == 0) { S.count = 0; S.overflow = 0; }
+  __syncthreads();
+  double dmin = kInf;
+  const int ntot = G.n_sv + G.n_se + G.n_sf;
+  for (int i = threadIdx.x; i < ntot; i += blockDim.x) {
+    int kind, gp, gvid[3], ngv;
+    if (i < G.n_sv) { kind = kVF; gp = i; gvid[0] = G.surf_v[i]; ngv = 1; }
+    else if (i < G.n_sv + G.n_se) {
+      kind = kEE; gp = i - G.n_sv; gvid[0] = G.surf_e[gp]; gvid[1] = G.surf_e[G.n_se + gp]; ngv = 2;
+    } else {
+      kind = kFV; gp = i - G.n_sv - G.n_se;
+      gvid[0] = G.surf_f[gp]; gvid[1] = G.surf_f[G.n_sf + gp]; gvid[2] = G.surf_f[2 * G.n_sf + gp]; ngv = 3;
+    }
+    double lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
+    for (int k = 0; k < ngv; ++k)
+      for (int c = 0; c < 3; ++c) {
+        const double xv = x[c * nv + gvid[k]];
+        lo[c] = fmin(lo[c], xv);
+        hi[c] = fmax(hi[c], xv);
+      }
+    bool away = false;
+    for (int c = 0; c < 3; ++c) {
+      lo[c] -= thr; hi[c] += thr;
+      if (lo[c] > S.iw_hi[c] || hi[c] < S.iw_lo[c]) away = true;
+    }
+    if (away) continue;
+    // query box in the indenter frame
+    double ql[3], qh[3];
+    {
+      double c[3], h[3];
+      for (int k = 0; k < 3; ++k) { c[k] = 0.5 * (lo[k] + hi[k]) - S.t[k]; h[k] = 0.5 * (hi[k] - lo[k]); }
+      for (int a = 0; a < 3; ++a) {
+        const double cl = S.R[0 * 3 + a] * c[0] + S.R[1 * 3 + a] * c[1] + S.R[2 * 3 + a] * c[2];
+        const double hl = fabs(S.R[0 * 3 + a]) * h[0] + fabs(S.R[1 * 3 + a]) * h[1] + fabs(S.R[2 * 3 + a]) * h[2];
+        ql[a] = cl - hl;
+        qh[a] = cl + hl;
+      }
+    }
+    const Grid& Gr = (kind == kVF) ? I.gf : ((kind == kFV) ? I.gv : I.ge);
+    bool outside = false;
+    int c0[3], c1[3];
+    for (int a = 0; a < 3; ++a) {
+      const double gmax = Gr.origin[a] + Gr.dims[a] / Gr.inv_cell;
+      if (qh[a] < Gr.origin[a] || ql[a] > gmax) outside = true;
+      c0[a] = cell_of(ql[a], Gr.origin[a], Gr.inv_cell, Gr.dims[a]);
+      c1[a] = cell_of(qh[a], Gr.origin[a], Gr.inv_cell, Gr.dims[a]);
+    }
+    if (outside) continue;
+    for (int cz = c0[2]; cz <= c1[2]; ++cz)
+      for (int cy = c0[1]; cy <= c1[1]; ++cy)
+        for (int cx = c0[0]; cx <= c1[0]; ++cx) {
+          const int cell = (cz * Gr.dims[1] + cy) * Gr.dims[0] + cx;
+          const int j0 = Gr.start[cell], j1 = Gr.start[cell + 1];
+          for (int j = j0; j < j1; ++j) {
+            const int it = Gr.items[j];
+            double il[3], ih[3];
+            bool ov = true;
+            for (int a = 0; a < 3; ++a) {
+              il[a] = Gr.box[a * Gr.n_prim + it];
+              ih[a] = Gr.box[(3 + a) * Gr.n_prim + it];
+              if (il[a] > qh[a] || ih[a] < ql[a]) ov = false;
+            }
+            if (!ov) continue;
+            // report from the cell of the overlap's lowest corner only
+            const int rx = cell_of(fmax(ql[0], il[0]), Gr.origin[0], Gr.inv_cell, Gr.dims[0]);
+            const int ry = cell_of(fmax(ql[1], il[1]), Gr.origin[1], Gr.inv_cell, Gr.dims[1]);
+            const int rz = cell_of(fmax(ql[2], il[2]), Gr.origin[2], Gr.inv_cell, Gr.dims[2]);
+            if (rx != cx || ry != cy || rz != cz) continue;
+            int2 pr;
+            pr.x = (kind << kKindShift) | gp;
+            pr.y = it;
+            PairPts P;
+            load_pair(V, S, pr, x, nullptr, 0.0, P);
+            Feature f;
+            classify(P, f);
+            double r[3];
+            const double d = pair_distance(P, f, r);
+            dmin = fmin(dmin, d);
+            if (mode == 0 && d < thr) {
+              const int slot = atomicAdd(&S.count, 1);
+              if (slot < cap) V.pairs[slot] = pr;
+              else S.overflow = 1;
+            } else if (mode == 1 && d < V.E->dhat && d > 0.0) {
+              const int slot = atomicAdd(&S.count, 1);
+              if (slot < cap) make_fric(V, P, f, r, d, pr, V.fric[slot]);
+              else S.overflow = 1;
+            }
+          }
+        }
+  }
+  __syncthreads();
+  return dmin;
+}
+
+// ---------------------------------------------------------------------------
+// Vector passes over the 3 n_v DOFs of an env
+// ---------------------------------------------------------------------------
+struct Solver {
+  View V;
+  Shared* S;
+  Tile* T;
+  double floor_d;     // preconditioner floor
+  double guard;       // energy rounding guard
+  double buffer;      // cull buffer beyond dhat
+  int armijo;
+  int pair_cap, fric_cap;
+  // stats
+  int reculls, restarts, halvings, ncand;
+};
+
+__device__ bool recull(Solver& s, const double* x) {
+  View& V = s.V;
+  cull(V, *s.S, x, V.E->dhat + s.buffer, 0, s.pair_cap);
+  const int ov = s.S->overflow;
+  const int cnt = s.S->count;
+  __syncthreads();
+  V.npairs = min(cnt, s.pair_cap);
+  s.ncand = V.npairs;
+  ++s.reculls;
+  return ov == 0;
+}
+
+// Evaluates Pi, grad (-> g) and diag at x + alpha p. Returns energy; feasible in flag.
+__device__ double eval_all(Solver& s, const double* x, const double* p, double alpha, double* g,
+                           double* dg, int& feasible, int& nactive, double* e_el = nullptr) {
+  View& V = s.V;
+  int feas = 1, nact = 0;
+  double v[3];
+  v[0] = elem_eval(V, x, p, alpha, g, dg, *s.T, feas);
+  double eel = v[0];
+  v[0] += pairs_eval(V, *s.S, x, p, alpha, g, dg, feas, nact);
+  if (V.nfric > 0) v[0] += fric_eval(V, *s.S, x, p, alpha, g, dg);
+  v[1] = (double)nact;
+  v[2] = feas ? 0.0 : 1.0;  // max -> any infeasible
+  double w[4] = {v[0], v[1], eel, v[2]};
+  block_reduce<3, 1>(w, *s.S);
+  feasible = (w[3] == 0.0);
+  nactive = (int)w[1];
+  if (e_el) *e_el = w[2];
+  return w[0];
+}
+
+__device__ double curvature_all(Solver& s, const double* x, const double* p) {
+  View& V = s.V;
+  double c = elem_curv(V, x, p, *s.T);
+  c += pairs_curv(V, *s.S, x, p);
+  if (V.nfric > 0) c += fric_curv(V, *s.S, x, p);
+  double w[1] = {c};
+  block_reduce<1, 0>(w, *s.S);
+  return w[0];
+}
+
+// P = 1/max(diag, floor) stored in place; p = -P g; returns |Pg|_inf, |p|_inf, g.p
+__device__ void init_direction(Solver& s, const double* g, double& res, double& pinf, double& gp) {
+  View& V = s.V;
+  const int n = 3 * V.G->n_v;
+  double a[3] = {0.0, 0.0, 0.0};  // sum g.p ; max |Pg| ; (pinf = res)
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const double P = 1.0 / fmax(V.diag[j], s.floor_d);
+    V.diag[j] = P;
+    const double pj = -P * g[j];
+    V.p[j] = pj;
+    a[0] += g[j] * pj;
+    a[1] = fmax(a[1], fabs(pj));
+  }
+  double w[2] = {a[0], a[1]};
+  block_reduce<1, 1>(w, *s.S);
+  gp = w[0];
+  res = w[1];
+  pinf = w[1];
+}
+
+// Runs PNCG at the current pose from x. Returns status bits (kConverged etc.).
+__device__ int pncg(Solver& s, double tol, int max_iters, int& iters, double& res_out, double& e_out,
+                    int& nactive_out) {
+  View& V = s.V;
+  const int n = 3 * V.G->n_v;
+  const double dh = V.E->dhat;
+  double* x = V.x;
+  double* g0 = V.g0;
+  double* g1 = V.g1;
+  if (!recull(s, x)) return kOverflow;
+  double macc = 0.0;
+  int feas, nact;
+  double E0 = eval_all(s, x, V.p, 0.0, g0, V.diag, feas, nact);
+  nactive_out = nact;
+  if (!feas) { iters = 0; return kInfeasible; }
+  double res, pinf, gp;
+  init_direction(s, g0, res, pinf, gp);
+  int status = 0;
+  int k = 0;
+  for (;; ++k) {
+    if (res <= tol) { status = kConverged; break; }
+    if (k >= max_iters) { status = kMaxIter; break; }
+    const double a_up = dh / (2.0 * pinf);
+    const double curv = curvature_all(s, x, V.p);
+    const double a_bar = (curv > 0.0) ? -gp / curv : kInf;
+    double alpha = fmin(a_up, a_bar);
+    if (macc + alpha * kSqrt3 * pinf > s.buffer) {
+      if (!recull(s, x)) { status = kOverflow; break; }
+      macc = 0.0;
+    }
+    {
+      double w = pairs_ccd(V, *s.S, x, V.p, alpha);
+      alpha = block_min(w, *s.S);
+    }
+    bool ok = false;
+    double E1 = E0;
+    for (int h = 0; h <= kMaxHalvings; ++h) {
+      E1 = eval_all(s, x, V.p, alpha, g1, V.diag, feas, nact);
+      if (feas && (!s.armijo || E1 <= E0 + kArmijoC * alpha * gp + s.guard)) { ok = true; break; }
+      alpha *= 0.5;
+      ++s.halvings;
+    }
+    if (!ok) { status = kLineSearch; break; }
+    nactive_out = nact;
+    macc += alpha * kSqrt3 * pinf;
+    // dots: x += alpha p ; P1 ; y = g1 - g0
+    double a[6] = {0, 0, 0, 0, 0, 0};  // gPy, yPy, yp, pg1, gPg | max|Pg1|
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const double pj = V.p[j];
+      x[j] = fma(alpha, pj, x[j]);
+      const double P = 1.0 / fmax(V.diag[j], s.floor_d);
+      V.diag[j] = P;
+      const double gj = g1[j];
+      const double y = gj - g0[j];
+      const double Py = P * y;
+      a[0] += gj * Py;
+      a[1] += y * Py;
+      a[2] += y * pj;
+      a[3] += pj * gj;
+      a[4] += gj * P * gj;
+      a[5] = fmax(a[5], fabs(P * gj));
+    }
+    block_reduce<5, 1>(a, *s.S);
+    const double yp = a[2];
+    double beta = 0.0;
+    if (yp > kYpMin) beta = a[0] / yp - (a[1] / yp) * (a[3] / yp);
+    double b2[2] = {0.0, 0.0};  // g.p_new | max |p_new|
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const double pn = -V.diag[j] * g1[j] + beta * V.p[j];
+      V.p[j] = pn;
+      b2[0] += g1[j] * pn;
+      b2[1] = fmax(b2[1], fabs(pn));
+    }
+    block_reduce<1, 1>(b2, *s.S);
+    gp = b2[0];
+    pinf = b2[1];
+    res = a[5];
+    if (gp >= 0.0) {  // not a descent direction: restart with -P g
+      for (int j = threadIdx.x; j < n; j += blockDim.x) V.p[j] = -V.diag[j] * g1[j];
+      __syncthreads();
+      gp = -a[4];
+      pinf = a[5];
+      ++s.restarts;
+    }
+    E0 = E1;
+    double* tmp = g0; g0 = g1; g1 = tmp;
+  }
+  iters = k;
+  res_out = res;
+  e_out = E0;
+  // keep the latest gradient in V.g0 for callers
+  if (g0 != V.g0) {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) V.g0[j] = g0[j];
+    __syncthreads();
+  }
+  return status;
+}
+
+__device__ void make_view(const StepParams& P, int e, View& V) {
+  const EnvDev& E = P.envs[e];
+  V.E = &E;
+  V.G = &P.gels[E.gel];
+  V.I = &P.inds[E.ind];
+  V.x = P.x + E.voff;
+  V.xprev = P.xprev + E.voff;
+  V.g0 = P.g0 + E.voff;
+  V.g1 = P.g1 + E.voff;
+  V.diag = P.diag + E.voff;
+  V.p = P.p + E.voff;
+  V.pairs = P.pairs + E.poff;
+  V.fric = P.fric + E.foff;
+  V.npairs = 0;
+  V.nfric = 0;
+  V.mixed = P.precision;
+}
+
+__device__ void init_solver(Solver& s, const StepParams& P, Shared& S, Tile& T) {
+  const EnvDev& E = *s.V.E;
+  const GelDev& G = *s.V.G;
+  s.S = &S;
+  s.T = &T;
+  s.floor_d = kDiagFloor * E.mu * G.diag_rest_max;
+  s.guard = (P.precision ? kEnergyGuard32 : kEnergyGuard64) * E.mu * G.vol_total;
+  s.buffer = E.dhat;
+  s.armijo = P.armijo;
+  s.pair_cap = E.pair_cap;
+  s.fric_cap = E.fric_cap;
+  s.reculls = s.restarts = s.halvings = s.ncand = 0;
+}
+
+__device__ void write_outputs(const StepParams& P, int e, const View& V) {
+  const GelDev& G = *V.G;
+  const int nv = G.n_v;
+  if (P.markers_out) {
+    double* mo = P.markers_out + 3 * V.E->moff;
+    for (int m = threadIdx.x; m < G.n_m; m += blockDim.x) {
+      for (int c = 0; c < 3; ++c) {
+        double u = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          const int v = G.marker_tri[k * G.n_m + m];
+          u += G.marker_w[k * G.n_m + m] * (V.x[c * nv + v] - G.X[c * nv + v]);
+        }
+        mo[3 * m + c] = u;
+      }
+    }
+  }
+  if (P.x_out) {
+    double* xo = P.x_out + 3 * P.x_out_off[e];
+    for (int j = threadIdx.x; j < 3 * nv; j += blockDim.x) {
+      const int v = j / 3, c = j - 3 * v;
+      xo[j] = V.x[c * nv + v];
+    }
+  }
+}
+
+}  // namespace t2r
+
+using namespace t2r;
+
+__global__ void __launch_bounds__(256) t2r_step_kernel(StepParams P) {
+  __shared__ Shared S;
+  __shared__ Tile T;
+  const int e = blockIdx.x;
+  if (e >= P.n_env) return;
+  Solver s;
+  make_view(P, e, s.V);
+  View& V = s.V;
+  init_solver(s, P, S, T);
+  const GelDev& G = *V.G;
+  const IndDev& I = *V.I;
+  const EnvDev& E = *V.E;
+  const int n = 3 * G.n_v;
+  EnvStats st;
+  st.status = 0; st.iters = 0; st.substeps = 0; st.restarts = 0; st.halvings = 0; st.reculls = 0;
+  st.n_candidates = 0; st.n_active = 0; st.n_friction = 0; st.max_solve_iters = 0;
+  st.d_min = kInf; st.residual = 0.0; st.energy = 0.0;
+
+  double* pose_prev = P.pose_prev + 7 * e;
+  double q0[7], q1[7];
+  for (int i = 0; i < 7; ++i) { q0[i] = pose_prev[i]; q1[i] = P.pose_in[7 * e + i]; }
+  bool skip = P.env_mask && P.env_mask[e] == 0;
+  bool bad = false;
+  for (int i = 0; i < 7; ++i) bad |= !isfinite(q1[i]);
+  if (skip || bad) {
+    st.status = skip ? kSkipped : kNonFinite;
+    write_outputs(P, e, V);
+    if (threadIdx.x == 0) { P.stats[e] = st; if (P.status_out) P.status_out[e] = st.status; }
+    return;
+  }
+  // keep x_{s-1} for the friction lag and for rollback
+  for (int j = threadIdx.x; j < n; j += blockDim.x) V.xprev[j] = V.x[j];
+  // friction lag and starting distance at (x_{s-1}, q_{s-1})
+  if (threadIdx.x == 0) set_pose(S, I, q0);
+  __syncthreads();
+  double dmin_start;
+  {
+    const int mode = (E.mu_f > 0.0) ? 1 : 2;
+    double dm = cull(V, S, V.x, E.dhat, mode, s.fric_cap);
+    const int cnt = S.count, ov = S.overflow;
+    dmin_start = block_min(dm, S);
+    V.nfric = (mode == 1) ? min(cnt, s.fric_cap) : 0;
+    if (ov) st.status |= kOverflow;
+  }
+  st.n_friction = V.nfric;
+  int status_acc = kConverged;
+  double tau = 0.0, dmin = dmin_start;
+  int sub = 0;
+  double res = 0.0, energy = 0.0;
+  int nact = 0;
+  const bool rollback_needed = false;
+  (void)rollback_needed;
+  if (!(dmin_start > 0.0)) {
+    status_acc = kInfeasible;
+  } else {
+    // continuation rate |dt| + theta r_max of the indenter's points
+    double dt = 0.0;
+    for (int i = 0; i < 3; ++i) dt += (q1[i] - q0[i]) * (q1[i] - q0[i]);
+    dt = sqrt(dt);
+    double qa = 0.0, na = 0.0, nb = 0.0;
+    for (int i = 3; i < 7; ++i) { qa += q0[i] * q1[i]; na += q0[i] * q0[i]; nb += q1[i] * q1[i]; }
+    const double cth = fmin(1.0, fabs(qa) / sqrt(na * nb));
+    const double theta = 2.0 * acos(cth);
+    const double rate = dt + theta * I.r_max;
+    while (tau < 1.0 && sub < P.max_substeps) {
+      const double dtau = (rate > 0.0) ? 0.5 * fmin(E.dhat, dmin) / rate : 1.0 - tau;
+      const double tau_new = fmin(1.0, tau + dtau);
+      if (threadIdx.x == 0) {
+        double q[7];
+        interp_pose(q0, q1, tau_new, q);
+        set_pose(S, I, q);
+      }
+      __syncthreads();
+      const bool last = tau_new >= 1.0;
+      const double tol = (last || P.substep_tol <= 0.0) ? P.tol : fmax(P.tol, P.substep_tol);
+      int iters = 0;
+      const int stt = pncg(s, tol, P.max_iters, iters, res, energy, nact);
+      st.iters += iters;
+      st.max_solve_iters = max(st.max_solve_iters, iters);
+      ++sub;
+      tau = tau_new;
+      if (stt & (kOverflow | kInfeasible)) { status_acc = stt; break; }
+      if (!(stt & kConverged)) status_acc = (status_acc & ~kConverged) | stt;
+      int na2 = 0;
+      double dm = pairs_dmin(V, S, V.x, na2);
+      dmin = block_min(dm, S);
+    }
+    if (tau < 1.0 && !(status_acc & (kOverflow | kInfeasible))) status_acc = (status_acc & ~kConverged) | kSubsteps;
+  }
+  st.status |= status_acc;
+  if (st.status & (kOverflow | kInfeasible)) {
+    // roll back to x_{s-1}; the previous pose is kept
+    for (int j = threadIdx.x; j < n; j += blockDim.x) V.x[j] = V.xprev[j];
+    __syncthreads();
+  } else if (threadIdx.x == 0) {
+    for (int i = 0; i < 7; ++i) pose_prev[i] = q1[i];
+  }
+  {
+    int na2 = 0;
+    double dm = pairs_dmin(V, S, V.x, na2);
+    double w[2] = {(double)na2, -dm};
+    block_reduce<1, 1>(w, S);
+    st.d_min = -w[1];
+    st.n_active = (int)w[0];
+  }
+  st.substeps = sub;
+  st.restarts = s.restarts;
+  st.halvings = s.halvings;
+  st.reculls = s.reculls;
+  st.n_candidates = s.ncand;
+  st.residual = res;
+  st.energy = energy;
+  write_outputs(P, e, V);
+  if (threadIdx.x == 0) {
+    P.stats[e] = st;
+    if (P.status_out) P.status_out[e] = st.status;
+  }
+}
+
+// Diagnostic evaluation of one env (state arrays are scratch copies).
+__global__ void __launch_bounds__(256) t2r_eval_kernel(EvalParams Q) {
+  __shared__ Shared S;
+  __shared__ Tile T;
+  const StepParams& P = Q.sp;
+  Solver s;
+  make_view(P, Q.env, s.V);
+  View& V = s.V;
+  init_solver(s, P, S, T);
+  const GelDev& G = *V.G;
+  const IndDev& I = *V.I;
+  const EnvDev& E = *V.E;
+  const int nv = G.n_v;
+  if (Q.has_lag && E.mu_f > 0.0) {
+    if (threadIdx.x == 0) set_pose(S, I, Q.pose_lag);
+    __syncthreads();
+    cull(V, S, V.xprev, E.dhat, 1, s.fric_cap);
+    V.nfric = min(S.count, s.fric_cap);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) set_pose(S, I, Q.pose);
+  __syncthreads();
+  recull(s, V.x);
+  int feas, nact;
+  double eel = 0.0;
+  const double Etot = eval_all(s, V.x, V.p, 0.0, V.g0, V.diag, feas, nact, &eel);
+  double curv = 0.0;
+  if (Q.has_p) curv = curvature_all(s, V.x, V.p);
+  int na2 = 0;
+  double dm = pairs_dmin(V, S, V.x, na2);
+  dm = block_min(dm, S);
+  for (int j = threadIdx.x; j < 3 * nv; j += blockDim.x) {
+    const int v = j / 3, c = j - 3 * v;
+    if (Q.grad_out) Q.grad_out[j] = V.g0[c * nv + v];
+    if (Q.diag_out) Q.diag_out[j] = V.diag[c * nv + v];
+  }
+  if (threadIdx.x == 0 && Q.scalars_out) {
+    Q.scalars_out[0] = Etot;
+    Q.scalars_out[1] = curv;
+    Q.scalars_out[2] = dm;
+    Q.scalars_out[3] = (double)nact;
+    Q.scalars_out[4] = feas ? 1.0 : 0.0;
+    Q.scalars_out[5] = (double)V.npairs;
+    Q.scalars_out[6] = (double)V.nfric;
+    Q.scalars_out[7] = eel;
+  }
+}
+
+// Converts between the ABI layout [n_v][3] and the state's [3][n_v] for every env.
+// direction 0: in ([sum n_v][3] + 7 pose per env) -> state ; 1: state -> out.
+__global__ void t2r_pack_kernel(StepParams P, const double* in, double* out, const long long* state_off,
+                                int direction) {
+  const int e = blockIdx.x;
+  if (e >= P.n_env) return;
+  const EnvDev& E = P.envs[e];
+  const GelDev& G = P.gels[E.gel];
+  const int nv = G.n_v;
+  const long long base = state_off[e];
+  if (direction == 0) {
+    for (int j = threadIdx.x; j < 3 * nv; j += blockDim.x) {
+      const int v = j / 3, c = j - 3 * v;
+      P.x[E.voff + c * nv + v] = in[base + j];
+    }
+    if (threadIdx.x < 7) P.pose_prev[7 * e + threadIdx.x] = in[base + 3 * nv + threadIdx.x];
+  } else {
+    for (int j = threadIdx.x; j < 3 * nv; j += blockDim.x) {
+      const int v = j / 3, c = j - 3 * v;
+      out[base + j] = P.x[E.voff + c * nv + v];
+    }
+    if (threadIdx.x < 7) out[base + 3 * nv + threadIdx.x] = P.pose_prev[7 * e + threadIdx.x];
+  }
+}
+
+// Copies [n_v][3] (ABI layout) into [3][n_v] for one env's scratch slot.
+__global__ void t2r_aos_to_soa_kernel(const double* in, double* out, int nv) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < 3 * nv; j += gridDim.x * blockDim.x) {
+    const int v = j / 3, c = j - 3 * v;
+    out[c * nv + v] = in[j];
+  }
+}
+
+extern "C" hipError_t t2r_launch_step(const StepParams* p, int block, hipStream_t stream) {
+  hipLaunchKernelGGL(t2r_step_kernel, dim3(p->n_env), dim3(block), 0, stream, *p);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t t2r_launch_eval(const EvalParams* q, int block, hipStream_t stream) {
+  hipLaunchKernelGGL(t2r_eval_kernel, dim3(1), dim3(block), 0, stream, *q);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t t2r_launch_pack_state(const StepParams* p, const double* in, double* out,
+                                            const long long* state_off, int direction, hipStream_t stream) {
+  hipLaunchKernelGGL(t2r_pack_kernel, dim3(p->n_env), dim3(256), 0, stream, *p, in, out, state_off, direction);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t t2r_launch_aos_to_soa(const double* in, double* out, int nv, hipStream_t stream) {
+  const int blocks = (3 * nv + 255) / 256;
+  hipLaunchKernelGGL(t2r_aos_to_soa_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, stream, in, out, nv);
+  return hipGetLastError();
+}

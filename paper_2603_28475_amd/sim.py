@@ -1,0 +1,71 @@
+"""Sim: a batch of gel/indenter environments stepped on the GPU through libt2r.
+
+Torch provides the device buffers and the stream; all compute is in the HIP
+library. Typical use:
+
+    sim = Sim.from_workload(workload, opts)
+    for s in range(1, S + 1):
+        markers, status = sim.step(poses[:, s])   # poses as a (n_env, 7) tensor
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import t2r
+
+
+class Sim:
+    def __init__(self, opts: t2r.SolverOpts | None = None, device: str | int = "cuda:0"):
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = t2r.Context(opts, self.stream.cuda_stream)
+        self.gel_ids = {}
+        self.ind_ids = {}
+        self.env_gel = []
+        self.n_m = []
+        self.n_v = []
+
+    @classmethod
+    def from_workload(cls, workload, opts: t2r.SolverOpts | None = None, device="cuda:0",
+                      envs=None):
+        """Builds every gel and indenter class of a scenes.Workload and its envs
+        (all of them, or the listed indices)."""
+        sim = cls(opts, device)
+        for name, g in workload.meshes.items():
+            sim.gel_ids[name] = sim.ctx.add_gel(g.X, g.tets, g.fixed, g.markers)
+        for name, ind in workload.indenters.items():
+            sim.ind_ids[name] = sim.ctx.add_indenter(ind.Y, ind.tris)
+        sel = workload.envs if envs is None else [workload.envs[i] for i in envs]
+        sim.ctx.add_envs([sim.gel_ids[e.mesh] for e in sel], [sim.ind_ids[e.indenter] for e in sel],
+                         [e.material() for e in sel], np.stack([e.poses[0] for e in sel]))
+        for e in sel:
+            info = sim.ctx.gel_info(sim.gel_ids[e.mesh])
+            sim.n_m.append(info["n_m"])
+            sim.n_v.append(info["n_v"])
+        sim.n_env = len(sel)
+        sim.markers = torch.zeros((sum(sim.n_m), 3), dtype=torch.float64, device=sim.device)
+        sim.x = torch.zeros((sum(sim.n_v), 3), dtype=torch.float64, device=sim.device)
+        sim.status = torch.zeros(sim.n_env, dtype=torch.int32, device=sim.device)
+        return sim
+
+    def step(self, poses, mask=None, want_x=False):
+        """One load step of every env to `poses` ((n_env, 7), any float array).
+        Returns (markers tensor (sum n_m, 3), status tensor (n_env,)), not synchronised."""
+        p = torch.as_tensor(np.asarray(poses, dtype=np.float64) if not torch.is_tensor(poses) else poses,
+                            dtype=torch.float64, device=self.device).contiguous()
+        m = None if mask is None else torch.as_tensor(mask, dtype=torch.int32, device=self.device)
+        self.ctx.step(p, m, self.markers, self.x if want_x else None, self.status)
+        return self.markers, self.status
+
+    def split_markers(self, markers=None):
+        markers = self.markers if markers is None else markers
+        return torch.split(markers, self.n_m)
+
+    def split_x(self, x=None):
+        x = self.x if x is None else x
+        return torch.split(x, self.n_v)
+
+    def stats(self):
+        return self.ctx.get_stats()

@@ -1,0 +1,49 @@
+"""Writes the stored expected values used by the GPU parity tests.
+
+Calls only the CPU oracle (oracle/) on the seeded scenes (scenes/); nothing
+here comes from the HIP path. The paper prints no worked numeric example, so
+these values are pinned by the oracle's own tests (finite differences, closed
+forms, brute force, invariants), not by the paper.
+
+    python tests/golden/make_golden.py
+"""
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle.sim import simulate  # noqa: E402
+from scenes.configs import micro_press, sphere_press_484v  # noqa: E402
+
+
+def sphere_press():
+    w = sphere_press_484v()
+    env = w.envs[0]
+    t = time.time()
+    r = simulate(w.meshes["c1"], w.indenters["sphere3"], env, mode="newton")
+    np.savez_compressed(os.path.join(HERE, "sphere_press_484v_newton.npz"),
+                        x=np.array(r.x), markers=np.array(r.markers), poses=env.poses,
+                        n_active=np.array(r.n_active), d_min=np.array(r.d_min))
+    print(f"sphere_press_484v: {time.time() - t:.1f}s, active {r.n_active}")
+
+
+def micro_friction():
+    w = micro_press(mesh="micro3", indenter="sphere_small", depth=0.12, n_steps=3, mu_f=0.5,
+                    shear=(0.06, 0.03), n_shear=3)
+    env = w.envs[0]
+    t = time.time()
+    r = simulate(w.meshes["micro3"], w.indenters["sphere_small"], env, mode="newton")
+    np.savez_compressed(os.path.join(HERE, "micro3_friction_newton.npz"),
+                        x=np.array(r.x), markers=np.array(r.markers), poses=env.poses,
+                        n_active=np.array(r.n_active))
+    print(f"micro3_friction: {time.time() - t:.1f}s, active {r.n_active}")
+
+
+if __name__ == "__main__":
+    micro_friction()
+    sphere_press()

@@ -1,0 +1,114 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point of
+include/t2r.h, and its host-side preprocessing (validation, surface
+extraction, marker embedding) agrees with the oracle. No GPU call is made."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.geometry import GelGeometry
+from scenes.configs import INDENTERS, sphere_press_484v
+from scenes.mesh import mesh_class
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _t2r():
+    from paper_2603_28475_amd import t2r
+    return t2r
+
+
+def test_library_exports_every_declared_symbol():
+    t2r = _t2r()
+    header = open(os.path.join(ROOT, "include", "t2r.h")).read()
+    names = set(re.findall(r"\b(t2r_[a-z_]+)\s*\(", header))
+    names -= {"t2r_alloc_fn", "t2r_free_fn"}
+    assert len(names) >= 20
+    lib = ctypes.CDLL(t2r.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert {s[0] for s in t2r.SIGNATURES} == names
+
+
+@pytest.mark.parametrize("name", ["c1", "5k"])
+def test_surface_and_markers_agree_with_oracle(name):
+    t2r = _t2r()
+    g = mesh_class(name)
+    ctx = t2r.Context()
+    gid = ctx.add_gel(g.X, g.tets, g.fixed, g.markers)
+    info = ctx.gel_info(gid)
+    geo = GelGeometry(g.X, g.tets, g.fixed, g.markers)
+    assert info["n_v"] == g.n_verts and info["n_t"] == g.n_tets
+    assert info["n_sv"] == len(geo.surf_verts)
+    assert info["n_se"] == len(geo.surf_edges)
+    assert info["n_sf"] == len(geo.surf_tris)
+    assert info["n_fixed"] == int(g.fixed.sum())
+    tri, w = ctx.gel_markers(gid)
+    # the interpolated rest positions must coincide (triangles may differ on ties)
+    ref_lib = np.einsum("mk,mkd->md", w, g.X[tri])
+    assert np.allclose(ref_lib, geo.marker_ref, atol=1e-12)
+    assert np.all(w >= -1e-12) and np.allclose(w.sum(axis=1), 1.0)
+    # every tet lands in exactly one tile, tiles respect the LDS limits
+    assert info["n_tiles"] >= g.n_tets // 512
+
+
+def test_invalid_inputs_are_rejected_on_the_host():
+    t2r = _t2r()
+    g = mesh_class("micro2")
+    ctx = t2r.Context()
+    bad = g.tets.copy()
+    bad[0] = bad[0][[0, 2, 1, 3]]
+    with pytest.raises(t2r.T2RError) as e:
+        ctx.add_gel(g.X, bad, g.fixed, g.markers)
+    assert e.value.code == t2r.T2R_E_ARG and "inverted" in str(e.value)
+    bad = g.tets.copy()
+    bad[3, 2] = g.n_verts
+    with pytest.raises(t2r.T2RError):
+        ctx.add_gel(g.X, bad, g.fixed, g.markers)
+    X = np.concatenate([g.X, [[9.0, 9.0, 9.0]]])
+    with pytest.raises(t2r.T2RError) as e:
+        ctx.add_gel(X, g.tets, np.concatenate([g.fixed, [0]]), g.markers)
+    assert "belongs to no tet" in str(e.value)
+    with pytest.raises(t2r.T2RError) as e:
+        ctx.add_gel(g.X, g.tets, g.fixed, np.array([[50.0, 0.0]]))
+    assert "outside the top face" in str(e.value)
+    gid = ctx.add_gel(g.X, g.tets, g.fixed, g.markers)
+    ind = INDENTERS["sphere_small"]()
+    iid = ctx.add_indenter(ind.Y, ind.tris)
+    pose = np.array([[0, 0, 2.0, 1, 0, 0, 0]])
+    with pytest.raises(t2r.T2RError):
+        ctx.add_envs([gid], [iid], [(0.3, 0.7, 0, 1e-3, 0.05, 1e3)], pose)   # nu >= 0.5
+    with pytest.raises(t2r.T2RError):
+        ctx.add_envs([gid], [iid + 1], [(0.3, 0.45, 0, 1e-3, 0.05, 1e3)], pose)
+    with pytest.raises(t2r.T2RError):
+        ctx.add_envs([gid], [iid], [(0.3, 0.45, 0, 1e-3, 0.05, 1e3)], pose * np.nan)
+    assert ctx.add_envs([gid], [iid], [(0.3, 0.45, 0, 1e-3, 0.05, 1e3)], pose) == 0
+    assert ctx.env_count() == (1, g.n_verts)
+    assert ctx.state_size() == 3 * g.n_verts + 7
+    with pytest.raises(t2r.T2RError) as e:
+        ctx.backward(None, None)
+    assert e.value.code == t2r.T2R_E_UNSUPPORTED
+
+
+def test_invalid_options_are_rejected():
+    t2r = _t2r()
+    for kw in ({"tol": 0.0}, {"precision": 3}, {"block_size": 100}, {"max_substeps": 0}):
+        with pytest.raises(t2r.T2RError):
+            t2r.Context(t2r.default_opts(**kw))
+    o = t2r.default_opts()
+    assert o.tol == 1e-6 and o.armijo == 1 and o.max_iters > 0
+
+
+def test_workload_classes_build_on_the_host():
+    t2r = _t2r()
+    w = sphere_press_484v(n_envs=3)
+    ctx = t2r.Context()
+    gid = ctx.add_gel(*(getattr(w.meshes["c1"], k) for k in ("X", "tets", "fixed", "markers")))
+    ind = w.indenters["sphere3"]
+    iid = ctx.add_indenter(ind.Y, ind.tris)
+    first = ctx.add_envs([gid] * 3, [iid] * 3, [e.material() for e in w.envs],
+                         np.stack([e.poses[0] for e in w.envs]))
+    assert first == 0 and ctx.env_count()[0] == 3

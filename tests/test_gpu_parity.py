@@ -1,0 +1,213 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Kernel rows: the element terms, contact pairs and lagged friction (energy,
+gradient, diagonal Hessian, curvature) at given states via t2r_eval. Solve
+rows: whole load-step sequences via t2r_step against the oracle's Newton
+minimiser (stored under tests/golden by an oracle-only script), batching and
+the failure paths.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_28475_amd import t2r
+    return t2r
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda:0")
+
+
+def _build(t2r, workload, envs=None, **opts):
+    from paper_2603_28475_amd.sim import Sim
+    o = t2r.default_opts(**opts)
+    return Sim.from_workload(workload, o, envs=envs)
+
+
+def _oracle_problem(workload, env):
+    from oracle.sim import build
+    return build(workload.meshes[env.mesh], workload.indenters[env.indenter], env)
+
+
+def _eval_both(t2r, w, env_idx, x, pose, p=None, x_lag=None, pose_lag=None):
+    sim = _build(t2r, w, envs=[env_idx])
+    nv = x.shape[0]
+    g = torch.zeros((nv, 3), dtype=torch.float64, device="cuda:0")
+    d = torch.zeros_like(g)
+    sc = torch.zeros(8, dtype=torch.float64, device="cuda:0")
+    sim.ctx.eval(0, _dev(x), pose, d_p=None if p is None else _dev(p),
+                 d_x_lag=None if x_lag is None else _dev(x_lag), pose_lag=pose_lag,
+                 d_grad=g, d_diag=d, d_scalars=sc)
+    torch.cuda.synchronize()
+    env = w.envs[env_idx]
+    gel, ind, prob = _oracle_problem(w, env)
+    if x_lag is not None:
+        prob.set_lag(x_lag, pose_lag)
+    prob.set_pose(pose)
+    return g.cpu().numpy(), d.cpu().numpy(), sc.cpu().numpy(), prob
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def test_eval_elastic_barrier_matches_oracle():
+    t2r = _gpu()
+    from scenes.configs import sphere_press_484v
+    w = sphere_press_484v()
+    gold = np.load(os.path.join(HERE, "golden", "sphere_press_484v_newton.npz"))
+    rng = np.random.default_rng(7)
+    for s in (3, 9):
+        x = gold["x"][s].copy()
+        free = w.meshes["c1"].fixed == 0
+        x[free] += 2e-4 * rng.standard_normal((free.sum(), 3))
+        p = np.zeros_like(x)
+        p[free] = rng.standard_normal((free.sum(), 3))
+        pose = gold["poses"][s + 1]
+        g, d, sc, prob = _eval_both(t2r, w, 0, x, pose, p=p)
+        assert sc[4] == 1.0
+        E = prob.energy(x)
+        assert sc[0] == pytest.approx(E, rel=1e-12)
+        assert sc[7] == pytest.approx(prob.energy_parts(x)[0], rel=1e-12)
+        pairs, geo = prob.active(x)
+        assert int(sc[3]) == len(pairs["idx"]) and len(pairs["idx"]) > 0
+        assert sc[2] == pytest.approx(geo["d"].min(), rel=1e-13)
+        assert _rel(g, prob.gradient(x)) < 1e-11
+        # fixed vertices carry no DOF: the library reports diag 1 there
+        assert _rel(d[free], prob.diag(x)[free]) < 1e-11
+        assert np.all(d[~free] == 1.0)
+        assert sc[1] == pytest.approx(prob.curvature(x, p), rel=1e-11)
+
+
+def test_eval_friction_matches_oracle():
+    t2r = _gpu()
+    from scenes.configs import micro_press
+    w = micro_press(mesh="micro3", indenter="sphere_small", depth=0.12, n_steps=3, mu_f=0.5,
+                    shear=(0.06, 0.03), n_shear=3)
+    gold = np.load(os.path.join(HERE, "golden", "micro3_friction_newton.npz"))
+    rng = np.random.default_rng(8)
+    x_lag = gold["x"][3]
+    x = x_lag.copy()
+    free = w.meshes["micro3"].fixed == 0
+    x[free] += 3e-4 * rng.standard_normal((free.sum(), 3))
+    p = np.zeros_like(x)
+    p[free] = rng.standard_normal((free.sum(), 3))
+    g, d, sc, prob = _eval_both(t2r, w, 0, x, gold["poses"][5], p=p, x_lag=x_lag,
+                                pose_lag=gold["poses"][4])
+    assert int(sc[6]) == len(prob.lag["lam"]) > 0
+    assert sc[0] == pytest.approx(prob.energy(x), rel=1e-12)
+    assert _rel(g, prob.gradient(x)) < 1e-11
+    assert _rel(d[free], prob.diag(x)[free]) < 1e-11
+    assert sc[1] == pytest.approx(prob.curvature(x, p), rel=1e-11)
+
+
+def _run_steps(sim, poses, want_x=False):
+    out_m, out_x, st = [], [], []
+    for s in range(1, poses.shape[1]):
+        m, status = sim.step(poses[:, s], want_x=want_x)
+        torch.cuda.synchronize()
+        out_m.append(m.cpu().numpy().copy())
+        if want_x:
+            out_x.append(sim.x.cpu().numpy().copy())
+        st.append(status.cpu().numpy().copy())
+    return np.array(out_m), np.array(out_x), np.array(st)
+
+
+def test_sphere_press_sequence_matches_newton_oracle():
+    t2r = _gpu()
+    from scenes.configs import sphere_press_484v
+    w = sphere_press_484v()
+    gold = np.load(os.path.join(HERE, "golden", "sphere_press_484v_newton.npz"))
+    sim = _build(t2r, w, tol=1e-10, substep_tol=1e-6, max_iters=200000)
+    poses = np.stack([e.poses for e in w.envs])
+    m, x, st = _run_steps(sim, poses, want_x=True)
+    assert np.all(st & 1), st
+    err_m = np.abs(m - gold["markers"]).max()
+    err_x = np.abs(x - gold["x"]).max()
+    assert err_m <= 1e-6, err_m
+    assert err_x <= 1e-6, err_x
+
+
+def test_friction_sequence_matches_newton_oracle():
+    t2r = _gpu()
+    from scenes.configs import micro_press
+    w = micro_press(mesh="micro3", indenter="sphere_small", depth=0.12, n_steps=3, mu_f=0.5,
+                    shear=(0.06, 0.03), n_shear=3)
+    gold = np.load(os.path.join(HERE, "golden", "micro3_friction_newton.npz"))
+    sim = _build(t2r, w, tol=1e-11, substep_tol=1e-8, max_iters=200000)
+    poses = np.stack([e.poses for e in w.envs])
+    m, x, st = _run_steps(sim, poses, want_x=True)
+    assert np.all(st & 1), st
+    assert np.abs(x - gold["x"]).max() <= 1e-6
+    assert np.abs(m - gold["markers"]).max() <= 1e-6
+
+
+def test_batched_launch_equals_single_env_launches():
+    t2r = _gpu()
+    from scenes.configs import sphere_press_484v
+    w = sphere_press_484v(n_envs=4, n_steps=4)
+    poses = np.stack([e.poses for e in w.envs])
+    sim = _build(t2r, w, tol=1e-9)
+    mb, _, stb = _run_steps(sim, poses)
+    assert np.all(stb & 1)
+    for k in range(4):
+        s1 = _build(t2r, w, envs=[k], tol=1e-9)
+        m1, _, st1 = _run_steps(s1, poses[k:k + 1])
+        assert np.all(st1 & 1)
+        # FP64 atomics accumulate in a launch-dependent order, so two runs converged
+        # to |P g| <= 1e-9 agree to about ten times that, not bit for bit
+        assert np.abs(mb[:, 49 * k:49 * (k + 1)] - m1).max() <= 1e-7
+
+
+def test_nonfinite_pose_and_mask_leave_state_unchanged():
+    t2r = _gpu()
+    from scenes.configs import sphere_press_484v
+    w = sphere_press_484v(n_envs=3, n_steps=3)
+    poses = np.stack([e.poses for e in w.envs])
+    sim = _build(t2r, w, tol=1e-8)
+    sim.step(poses[:, 1])
+    torch.cuda.synchronize()
+    st0 = torch.zeros(sim.ctx.state_size(), dtype=torch.float64, device="cuda:0")
+    sim.ctx.get_state(st0)
+    bad = poses[:, 2].copy()
+    bad[0, 2] = np.nan
+    _, status = sim.step(bad, mask=[1, 0, 1])
+    torch.cuda.synchronize()
+    s = status.cpu().numpy()
+    assert s[0] & t2r.ENV_NONFINITE and s[1] & t2r.ENV_SKIPPED and s[2] & t2r.ENV_CONVERGED
+    st1 = torch.zeros_like(st0)
+    sim.ctx.get_state(st1)
+    n0 = 3 * 484 + 7
+    assert torch.equal(st0[:2 * n0], st1[:2 * n0])
+    assert not torch.equal(st0[2 * n0:], st1[2 * n0:])
+
+
+def test_pair_overflow_rolls_back():
+    t2r = _gpu()
+    from scenes.configs import sphere_press_484v
+    w = sphere_press_484v(n_envs=1, n_steps=10)
+    poses = np.stack([e.poses for e in w.envs])
+    sim = _build(t2r, w, tol=1e-8, pair_capacity=2)
+    st0 = torch.zeros(sim.ctx.state_size(), dtype=torch.float64, device="cuda:0")
+    for s in range(1, 6):
+        _, status = sim.step(poses[:, s])
+    torch.cuda.synchronize()
+    assert status.cpu().numpy()[0] & t2r.ENV_PAIR_OVERFLOW
+    sim.ctx.get_state(st0)
+    torch.cuda.synchronize()
+    st = st0.cpu().numpy()
+    # every step overflowed, so the env is still at rest with its starting pose
+    assert np.array_equal(st[:3 * 484].reshape(-1, 3), w.meshes["c1"].X)
+    assert np.array_equal(st[3 * 484:], poses[0, 0])
