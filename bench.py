@@ -1,0 +1,213 @@
+#!/usr/bin/env python
+"""Benchmark of the batched PNCG-IPC load step on one MI355X.
+
+Workload (default): 2048 environments, each a 20x16x4 mm gel meshed with
+25x20x8 hexes (4,914 vertices, 24,000 tets) pressed by an end-on peg
+(r = 4 mm, 2,048 triangles) at a seeded pose, 20 press steps to a seeded
+depth; all envs advance one load step per launch of the persistent kernel.
+A "step" is one such load step of every env: continuation, culling, every
+PNCG iteration to tolerance and the marker output.
+
+Prints one JSON line: env-steps/s of the batched launch, the roofline of the
+step kernel from HIP-event timings, the unbatched ("plain") solver on the
+same GPU for a sample of envs, and the CPU oracle on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
+BYTES_PER_VERT_ITER = 384  # 16 vector passes x 3 coords x 8 B per PNCG iteration
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--envs", type=int, default=2048)
+    ap.add_argument("--precision", choices=["f64", "mixed"], default="f64")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--plain-envs", type=int, default=8, help="envs timed one launch each (0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle budget (0: skip)")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2603_28475_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(args, *a):
+    if not args.quiet:
+        print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(args, workload, iters_per_env_step):
+    """The oracle's PNCG reference (one thread) on env 0, timed per iteration.
+
+    A full load step takes the numpy oracle tens of minutes at this mesh size,
+    so it runs as many iterations of the first solve of load step 1 as fit in
+    the budget, and the per-iteration time is scaled by the GPU run's mean
+    PNCG iterations per env-step (same algorithm and tolerance)."""
+    from oracle.geometry import slerp_pose  # noqa: F401
+    from oracle.pncg import pncg_solve
+    from oracle.sim import build
+    env = workload.envs[0]
+    gel, ind, prob = build(workload.meshes[env.mesh], workload.indenters[env.indenter], env)
+    prob.set_lag(gel.X, env.poses[0])
+    prob.set_pose(env.poses[1])
+    t0 = time.perf_counter()
+    pncg_solve(prob, gel.X, tol=args.tol, max_iters=1)
+    t1 = time.perf_counter() - t0
+    n = max(2, int(args.cpu_seconds / max(t1, 1e-3)))
+    t0 = time.perf_counter()
+    _, info = pncg_solve(prob, gel.X, tol=args.tol, max_iters=n)
+    dt = time.perf_counter() - t0
+    done = max(1, info["iters"])
+    per_iter = dt / done
+    return {"value": 1.0 / (per_iter * iters_per_env_step), "unit": "env-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"env 0, first solve of load step 1: {done} PNCG iterations of the numpy FP64 "
+                      f"oracle in {dt:.1f} s ({per_iter:.2f} s/iteration, one thread), scaled by "
+                      f"{iters_per_env_step:.0f} iterations per env-step (GPU run mean)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the batched step shards "
+              "environments across GPUs with no exchange inside a step; see DESIGN.md.",
+              file=sys.stderr)
+        sys.exit(2)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    import numpy as np
+    import torch
+
+    from paper_2603_28475_amd import t2r
+    from paper_2603_28475_amd.sim import Sim
+    from scenes.configs import peg_batch_5k
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    W, K = args.warmup, args.steps
+    n_steps = W + K
+    workload = peg_batch_5k(n_envs=args.envs, n_steps=20, precision=args.precision)
+    if n_steps > workload.n_steps:
+        print(f"warmup + steps must be <= {workload.n_steps}", file=sys.stderr)
+        sys.exit(1)
+    prec = 0 if args.precision == "f64" else 1
+    opts = t2r.default_opts(tol=args.tol, precision=prec, block_size=args.block)
+    t_build = time.perf_counter()
+    sim = Sim.from_workload(workload, opts)
+    poses = torch.as_tensor(np.stack([e.poses for e in workload.envs]), dtype=torch.float64,
+                            device="cuda:0")
+    pose_steps = [poses[:, s].contiguous() for s in range(n_steps + 1)]
+    log(args, f"built {args.envs} envs in {time.perf_counter() - t_build:.1f}s")
+    stream = torch.cuda.current_stream()
+    nv = sim.n_v[0]
+
+    for s in range(1, W + 1):
+        sim.step(pose_steps[s])
+        torch.cuda.synchronize()
+        st = sim.stats()
+        log(args, f"warmup step {s}: iters/env {np.mean([x['iters'] for x in st]):.0f}")
+
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    iters = []
+    status_ok = True
+    t0 = time.perf_counter()
+    for k in range(K):
+        s = W + 1 + k
+        starts[k].record(stream)
+        sim.step(pose_steps[s])
+        ends[k].record(stream)
+        st = sim.stats()  # synchronises; needed for the per-launch iteration counts
+        iters.append(np.array([x["iters"] for x in st], dtype=np.int64))
+        status_ok &= all(x["status"] & t2r.ENV_CONVERGED for x in st)
+        log(args, f"step {s}: {starts[k].elapsed_time(ends[k]):.1f} ms, iters/env mean "
+                  f"{iters[-1].mean():.0f} max {iters[-1].max()}, substeps "
+                  f"{np.mean([x['substeps'] for x in st]):.1f}, cand {np.mean([x['n_candidates'] for x in st]):.0f}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [starts[k].elapsed_time(ends[k]) for k in range(K)]
+    value = args.envs * K / wall
+    # roofline of the step kernel: algorithmic vector bytes per launch / launch time
+    bytes_per_launch = [float(it.sum()) * BYTES_PER_VERT_ITER * nv for it in iters]
+    achieved = float(np.mean([b / (t * 1e-3) for b, t in zip(bytes_per_launch, launch_ms)]))
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            tr = json.load(fh)
+        if tr.get("source_hash") == source_hash() and tr.get("envs") == args.envs:
+            traffic = tr.get("bytes_per_launch")
+
+    plain = None
+    if args.plain_envs > 0:
+        # unbatched: the same solver, one env per launch, on a sample of envs
+        n = min(args.plain_envs, args.envs)
+        sims = [Sim.from_workload(workload, opts, envs=[i]) for i in range(n)]
+        # advance each plain env through the warmup steps, then time one step each
+        for i_, sm in enumerate(sims):
+            for s in range(1, W + 1):
+                sm.step(poses[i_:i_ + 1, s].contiguous())
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for i_, sm in enumerate(sims):
+            sm.step(poses[i_:i_ + 1, W + 1].contiguous())
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - tp
+        plain = {"value": n / dtp, "unit": "env-steps/s", "sample": f"envs 0..{n - 1}, step {W + 1}, "
+                 "one launch per env", "batched_over_plain": value / (n / dtp)}
+
+    iters_mean = float(np.mean([it.mean() for it in iters]))
+    cpu = cpu_baseline(args, workload, iters_mean) if args.cpu_seconds > 0 else None
+    line = {
+        "metric": "env-steps/s at fixed PNCG tol (batched)",
+        "value": value,
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * wall / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": workload.name, "envs": args.envs, "gel_verts": nv,
+                   "gel_tets": workload.meshes["5k"].n_tets, "indenter": "peg r=4 mm, 2048 tris",
+                   "load_steps_timed": f"{W + 1}..{W + K} of 20", "tol_mm": args.tol,
+                   "precision": args.precision, "all_converged": bool(status_ok),
+                   "pncg_iters_per_env_step": float(np.mean([it.mean() for it in iters]))},
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK, "traffic": traffic,
+                     "kernel": "t2r_step_kernel", "launch_ms": launch_ms},
+        "plain": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

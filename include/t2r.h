@@ -113,6 +113,8 @@ typedef struct {
   double d_min;          /* smallest gel/indenter distance at the end (mm), inf if none < dhat */
   double residual;       /* final |P g|_inf (mm) */
   double energy;         /* final Pi (N mm) */
+  double phase_ms[6];    /* time in: culling, curvature, CCD, energy/gradient evaluation,
+                            vector passes, and the whole step (ms, this env's workgroup) */
 } t2r_env_stats;
 
 /* Fills *o with the defaults: tol 1e-6, substep_tol 1e-4, max_iters 20000,

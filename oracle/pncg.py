@@ -3,8 +3,10 @@ Test infrastructure only.
 
 From Supp. A (eqs. dk_direction and step_size) with these readings:
   * P_k = diag(H(x_k))^-1, re-evaluated at every iterate, from the exact
-    (unprojected) diagonal; entries are floored at 1e-12 * max(diag) over the
-    free DOFs so the inverse exists.
+    (unprojected) diagonal; entries are floored at 1e-12 mu max_v sum_e V_e |g_i|^2
+    (a fixed fraction of the largest rest-state stiffness of a free vertex) so
+    the inverse exists; the floor is per env, not per iterate, so the kernels
+    can apply P in the same pass that finishes diag.
   * p_0 = -P_0 g_0;  p_{k+1} = -P_{k+1} g_{k+1} + beta_k p_k with
         beta_k = g_{k+1}^T P_{k+1} y_k / (y_k^T p_k)
                  - (y_k^T P_{k+1} y_k / y_k^T p_k) (p_k^T g_{k+1} / y_k^T p_k),
@@ -37,7 +39,7 @@ MAX_HALVINGS = 30
 
 def _precond(prob, x, free):
     dg = prob.diag(x)
-    floor = DIAG_FLOOR * dg[free].max()
+    floor = DIAG_FLOOR * prob.diag_scale
     P = 1.0 / np.maximum(dg, floor)
     P[~free] = 0.0
     return P

@@ -63,6 +63,12 @@ class StepProblem:
         # natural energy scale mu * total volume: the rounding guard of the
         # line-search energy test is a fixed multiple of it
         self.energy_ref = float(self.mu * gel.vol.sum())
+        # preconditioner floor: a fixed fraction of the largest rest-state
+        # stiffness mu * sum_e V_e |g_i|^2 over free vertices
+        G = np.concatenate([-gel.Dm_inv.sum(axis=1, keepdims=True), gel.Dm_inv], axis=1)
+        s = np.zeros(gel.n_v)
+        np.add.at(s, gel.tets, gel.vol[:, None] * np.einsum("nid,nid->ni", G, G))
+        self.diag_scale = float(self.mu * s[~gel.fixed].max())
         self.pose = None
         self.Yw = None
         self.lag = None

@@ -95,6 +95,7 @@ struct t2r_ctx {
   long long* d_state_off = nullptr;
   long long total_dofs = 0, total_verts = 0, total_markers = 0, state_size = 0;
   int pair_cap = 0;
+  double clock_khz = 1.0;
 };
 
 namespace {
@@ -695,6 +696,7 @@ static StepParams step_params(t2r_ctx* c) {
   P.fric = c->d_fric;
   P.stats = c->d_stats;
   P.x_out_off = c->d_xout_off;
+  P.clock_khz = c->clock_khz;
   P.tol = c->opts.tol;
   P.substep_tol = c->opts.substep_tol;
   P.max_iters = c->opts.max_iters;
@@ -937,6 +939,12 @@ t2r_status commit(t2r_ctx* c) {
   int dev_count = 0;
   if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count == 0)
     return fail(c, T2R_E_HIP, "no HIP device available");
+  {
+    int dev = 0, khz = 0;
+    HIP_TRY(c, hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+      c->clock_khz = (double)khz;
+  }
   t2r_status s;
   for (auto& g : c->gels)
     if ((s = upload_gel(c, g)) != T2R_OK) { dev_free_all(c); return s; }

@@ -93,6 +93,7 @@ struct EnvStats {
   int status, iters, substeps, restarts, halvings, reculls, n_candidates, n_active,
       n_friction, max_solve_iters;
   double d_min, residual, energy;
+  double phase_ms[6];      // cull, curvature, ccd, eval, vector passes, whole step
 };
 
 struct StepParams {
@@ -119,6 +120,7 @@ struct StepParams {
   int* status_out;         // [n_env] or null
   long long* x_out_off;    // [n_env] vertex offsets into x_out
   // options
+  double clock_khz;        // wall-clock counter rate (phase timers)
   double tol, substep_tol;
   int max_iters, max_substeps, precision, armijo;
 };

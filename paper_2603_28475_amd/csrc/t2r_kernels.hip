@@ -48,7 +48,14 @@ struct Shared {
   double bc[8];               // broadcast results
   int count, overflow, flag;
   int pad;
+  unsigned long long tacc[6];  // wall-clock ticks per phase (thread 0)
 };
+
+// Phase timers: thread 0 accumulates wall-clock ticks into S.tacc[k].
+__device__ inline unsigned long long tick() { return wall_clock64(); }
+__device__ inline void tock(Shared& S, int k, unsigned long long t0) {
+  if (threadIdx.x == 0) S.tacc[k] += wall_clock64() - t0;
+}
 
 struct Tile {
   double x[3][kTileVerts];
@@ -110,12 +117,15 @@ __device__ inline void quat_to_R(const double q_in[4], double R[9]) {
 
 // Pose at tau between p0 and p1: translation linear, rotation by slerp.
 __device__ inline void interp_pose(const double p0[7], const double p1[7], double tau, double out[7]) {
+  #pragma unroll
   for (int i = 0; i < 3; ++i) out[i] = (1.0 - tau) * p0[i] + tau * p1[i];
   double q0[4], q1[4];
   double n0 = 0, n1 = 0;
+  #pragma unroll
   for (int i = 0; i < 4; ++i) { q0[i] = p0[3 + i]; q1[i] = p1[3 + i]; n0 += q0[i] * q0[i]; n1 += q1[i] * q1[i]; }
   n0 = sqrt(n0); n1 = sqrt(n1);
   double c = 0;
+  #pragma unroll
   for (int i = 0; i < 4; ++i) { q0[i] /= n0; q1[i] /= n1; c += q0[i] * q1[i]; }
   if (c < 0) { for (int i = 0; i < 4; ++i) q1[i] = -q1[i]; c = -c; }
   c = fmin(c, 1.0);
@@ -124,17 +134,22 @@ __device__ inline void interp_pose(const double p0[7], const double p1[7], doubl
   if (th < 1e-12) { a = 1.0 - tau; b = tau; }
   else { const double s = sin(th); a = sin((1.0 - tau) * th) / s; b = sin(tau * th) / s; }
   double n = 0;
+  #pragma unroll
   for (int i = 0; i < 4; ++i) { out[3 + i] = a * q0[i] + b * q1[i]; n += out[3 + i] * out[3 + i]; }
   n = sqrt(n);
+  #pragma unroll
   for (int i = 0; i < 4; ++i) out[3 + i] /= n;
 }
 
 __device__ inline void set_pose(Shared& S, const IndDev& I, const double pose[7]) {
   quat_to_R(pose + 3, S.R);
+  #pragma unroll
   for (int i = 0; i < 3; ++i) S.t[i] = pose[i];
   // world box of the local box
   double c[3], h[3];
+  #pragma unroll
   for (int i = 0; i < 3; ++i) { c[i] = 0.5 * (I.box_lo[i] + I.box_hi[i]); h[i] = 0.5 * (I.box_hi[i] - I.box_lo[i]); }
+  #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double cw = S.R[a * 3 + 0] * c[0] + S.R[a * 3 + 1] * c[1] + S.R[a * 3 + 2] * c[2] + S.t[a];
     const double hw = fabs(S.R[a * 3 + 0]) * h[0] + fabs(S.R[a * 3 + 1]) * h[1] + fabs(S.R[a * 3 + 2]) * h[2];
@@ -145,6 +160,7 @@ __device__ inline void set_pose(Shared& S, const IndDev& I, const double pose[7]
 
 __device__ inline void ind_world(const Shared& S, const IndDev& I, int j, double y[3]) {
   const double a = I.Y[j], b = I.Y[I.n_v + j], c = I.Y[2 * I.n_v + j];
+  #pragma unroll
   for (int r = 0; r < 3; ++r) y[r] = S.R[r * 3 + 0] * a + S.R[r * 3 + 1] * b + S.R[r * 3 + 2] * c + S.t[r];
 }
 
@@ -178,7 +194,7 @@ __device__ inline void load_Dm(const GelDev& G, int e, double Dm[9]) {
 // Evaluates sum V psi, the gradient and diag(H) of the elastic term at
 // x + alpha p into gout/dout ([3][n_v]). Returns energy (thread partial) and
 // clears `feasible` on an inverted tet.
-__device__ double elem_eval(const View& V, const double* x, const double* p, double alpha,
+__device__ __noinline__ double elem_eval(const View& V, const double* x, const double* p, double alpha,
                             double* gout, double* dout, Tile& T, int& feasible) {
   const GelDev& G = *V.G;
   const EnvDev& E = *V.E;
@@ -211,18 +227,13 @@ __device__ double elem_eval(const View& V, const double* x, const double* p, dou
           for (int k = 0; k < 3; ++k) Ds[a * 3 + k] = (float)(T.x[a][l[k + 1]] - T.x[a][l[0]]);
 #pragma unroll
         for (int k = 0; k < 9; ++k) Dm[k] = G.Dinv32[k * G.n_t + e];
-        TetDer<float> r;
-        ok = tet_grad_diag<float>(Ds, Dm, G.vol32[e], (float)E.mu, (float)E.lam, r);
-        if (ok) {
-          energy += (double)r.E;
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              atomicAdd(&T.g[c][l[k]], (double)r.g[k][c]);
-              atomicAdd(&T.d[c][l[k]], (double)r.d[k][c]);
-            }
-        }
+        float ef = 0.0f;
+        ok = tet_grad_diag<float>(Ds, Dm, G.vol32[e], (float)E.mu, (float)E.lam, ef,
+                                  [&](int k, int c, float gv, float dv) {
+                                    atomicAdd(&T.g[c][l[k]], (double)gv);
+                                    atomicAdd(&T.d[c][l[k]], (double)dv);
+                                  });
+        if (ok) energy += (double)ef;
       } else {
         double Ds[9], Dm[9];
 #pragma unroll
@@ -230,18 +241,13 @@ __device__ double elem_eval(const View& V, const double* x, const double* p, dou
 #pragma unroll
           for (int k = 0; k < 3; ++k) Ds[a * 3 + k] = T.x[a][l[k + 1]] - T.x[a][l[0]];
         load_Dm(G, e, Dm);
-        TetDer<double> r;
-        ok = tet_grad_diag<double>(Ds, Dm, G.vol[e], E.mu, E.lam, r);
-        if (ok) {
-          energy += r.E;
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              atomicAdd(&T.g[c][l[k]], r.g[k][c]);
-              atomicAdd(&T.d[c][l[k]], r.d[k][c]);
-            }
-        }
+        double ed = 0.0;
+        ok = tet_grad_diag<double>(Ds, Dm, G.vol[e], E.mu, E.lam, ed,
+                                   [&](int k, int c, double gv, double dv) {
+                                     atomicAdd(&T.g[c][l[k]], gv);
+                                     atomicAdd(&T.d[c][l[k]], dv);
+                                   });
+        if (ok) energy += ed;
       }
       if (!ok) feasible = 0;
     }
@@ -268,7 +274,7 @@ __device__ double elem_eval(const View& V, const double* x, const double* p, dou
 }
 
 // p^T H_elastic p at x (thread partial).
-__device__ double elem_curv(const View& V, const double* x, const double* p, Tile& T) {
+__device__ __noinline__ double elem_curv(const View& V, const double* x, const double* p, Tile& T) {
   const GelDev& G = *V.G;
   const EnvDev& E = *V.E;
   const int nv = G.n_v;
@@ -353,6 +359,7 @@ __device__ inline void load_pair(const View& V, const Shared& S, int2 pr, const 
   for (int k = 0; k < 4; ++k) {
     P.gid[k] = gv[k];
     if (gv[k] >= 0) {
+      #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const double xv = x[c * nv + gv[k]];
         P.z[k][c] = p ? fma(alpha, p[c * nv + gv[k]], xv) : xv;
@@ -369,12 +376,13 @@ __device__ inline void classify(const PairPts& P, Feature& f) {
 }
 
 __device__ inline double pair_distance(const PairPts& P, const Feature& f, double r[3]) {
+  #pragma unroll
   for (int c = 0; c < 3; ++c) r[c] = f.c[0] * P.z[0][c] + f.c[1] * P.z[1][c] + f.c[2] * P.z[2][c] + f.c[3] * P.z[3][c];
   return sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
 }
 
 // Barrier energy, gradient and diag of every candidate pair at x + alpha p.
-__device__ double pairs_eval(const View& V, const Shared& S, const double* x, const double* p,
+__device__ __noinline__ double pairs_eval(const View& V, const Shared& S, const double* x, const double* p,
                              double alpha, double* gout, double* dout, int& feasible, int& nactive) {
   const GelDev& G = *V.G;
   const EnvDev& E = *V.E;
@@ -397,15 +405,19 @@ __device__ double pairs_eval(const View& V, const Shared& S, const double* x, co
     const double invd = 1.0 / d;
     double n[3] = {r[0] * invd, r[1] * invd, r[2] * invd};
     double D[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    for (int w = 0; w < f.k; ++w)
+    #pragma unroll
+    for (int w = 0; w < 2; ++w)
+      #pragma unroll
       for (int c = 0; c < 3; ++c)
         D[w][c] = f.cw[0][w] * P.z[0][c] + f.cw[1][w] * P.z[1][c] + f.cw[2][w] * P.z[2][c] + f.cw[3][w] * P.z[3][c];
     double Mi[2][2];
     gram_inverse(D, f.k, Mi);
+    #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = P.gid[k];
       if (v < 0 || G.fixed[v]) continue;
       const double ci = f.c[k];
+      #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const double gi = ci * n[c];
         double u0 = 0.0, u1 = 0.0;
@@ -422,7 +434,7 @@ __device__ double pairs_eval(const View& V, const Shared& S, const double* x, co
 }
 
 // p^T H_barrier p at x (thread partial).
-__device__ double pairs_curv(const View& V, const Shared& S, const double* x, const double* p) {
+__device__ __noinline__ double pairs_curv(const View& V, const Shared& S, const double* x, const double* p) {
   const GelDev& G = *V.G;
   const EnvDev& E = *V.E;
   const int nv = G.n_v;
@@ -441,20 +453,26 @@ __device__ double pairs_curv(const View& V, const Shared& S, const double* x, co
     const double invd = 1.0 / d;
     double n[3] = {r[0] * invd, r[1] * invd, r[2] * invd};
     double D[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    for (int w = 0; w < f.k; ++w)
+    #pragma unroll
+    for (int w = 0; w < 2; ++w)
+      #pragma unroll
       for (int c = 0; c < 3; ++c)
         D[w][c] = f.cw[0][w] * P.z[0][c] + f.cw[1][w] * P.z[1][c] + f.cw[2][w] * P.z[2][c] + f.cw[3][w] * P.z[3][c];
     double Mi[2][2];
     gram_inverse(D, f.k, Mi);
     double q[3] = {0, 0, 0}, vv[2] = {0, 0};
+    #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = P.gid[k];
       if (v < 0 || G.fixed[v]) continue;
       double pk[3];
+      #pragma unroll
       for (int c = 0; c < 3; ++c) pk[c] = p[c * nv + v];
+      #pragma unroll
       for (int c = 0; c < 3; ++c) q[c] += f.c[k] * pk[c];
       const double rp = dot3(r, pk);
-      for (int w = 0; w < f.k; ++w) vv[w] += f.cw[k][w] * rp + f.c[k] * dot3(D[w], pk);
+      #pragma unroll
+      for (int w = 0; w < 2; ++w) if (w < f.k) vv[w] += f.cw[k][w] * rp + f.c[k] * dot3(D[w], pk);
     }
     const double nq = dot3(n, q);
     const double vMv = vv[0] * (Mi[0][0] * vv[0] + Mi[0][1] * vv[1]) + vv[1] * (Mi[1][0] * vv[0] + Mi[1][1] * vv[1]);
@@ -465,7 +483,7 @@ __device__ double pairs_curv(const View& V, const Shared& S, const double* x, co
 }
 
 // Smallest distance over candidate pairs at x (thread partial; kInf if none).
-__device__ double pairs_dmin(const View& V, const Shared& S, const double* x, int& nactive) {
+__device__ __noinline__ double pairs_dmin(const View& V, const Shared& S, const double* x, int& nactive) {
   double dmin = kInf;
   for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
     PairPts P;
@@ -482,17 +500,19 @@ __device__ double pairs_dmin(const View& V, const Shared& S, const double* x, in
 
 // Conservative advancement: largest t <= amax keeping each pair at >= kCcdGap of its
 // start distance, gel points moving along p, indenter static (thread partial min).
-__device__ double pairs_ccd(const View& V, const Shared& S, const double* x, const double* p, double amax) {
+__device__ __noinline__ double pairs_ccd(const View& V, const Shared& S, const double* x, const double* p, double amax) {
   const int nv = V.G->n_v;
   double tmin = amax;
   for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
     PairPts P;
     load_pair(V, S, V.pairs[i], x, nullptr, 0.0, P);
     double l = 0.0;
+    #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = P.gid[k];
       if (v < 0) continue;
       double s = 0.0;
+      #pragma unroll
       for (int c = 0; c < 3; ++c) { const double pc = p[c * nv + v]; s += pc * pc; }
       l = fmax(l, sqrt(s));
     }
@@ -527,25 +547,30 @@ __device__ inline void fric_delta(const View& V, const Shared& S, const FricPair
                                   const double* p, double alpha, double Dl[3]) {
   const int nv = V.G->n_v;
   const IndDev& I = *V.I;
+  #pragma unroll
   for (int c = 0; c < 3; ++c) Dl[c] = -F.base[c];
+  #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int v = F.gv[k];
     if (v < 0) continue;
+    #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const double xv = x[c * nv + v];
       Dl[c] += F.a[k] * (p ? fma(alpha, p[c * nv + v], xv) : xv);
     }
   }
+  #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int j = F.iv[k];
     if (j < 0) continue;
     double y[3];
     ind_world(S, I, j, y);
+    #pragma unroll
     for (int c = 0; c < 3; ++c) Dl[c] -= F.c[k] * y[c];
   }
 }
 
-__device__ double fric_eval(const View& V, const Shared& S, const double* x, const double* p, double alpha,
+__device__ __noinline__ double fric_eval(const View& V, const Shared& S, const double* x, const double* p, double alpha,
                             double* gout, double* dout) {
   const GelDev& G = *V.G;
   const int nv = G.n_v;
@@ -557,6 +582,7 @@ __device__ double fric_eval(const View& V, const Shared& S, const double* x, con
     fric_delta(V, S, F, x, p, alpha, Dl);
     const double nD = dot3(F.n, Dl);
     double TD[3];
+    #pragma unroll
     for (int c = 0; c < 3; ++c) TD[c] = Dl[c] - nD * F.n[c];
     const double s = sqrt(dot3(TD, TD));
     double f, fos, corr;
@@ -564,10 +590,12 @@ __device__ double fric_eval(const View& V, const Shared& S, const double* x, con
     energy += F.mulam * f;
     double uh[3] = {0, 0, 0};
     if (s > 0) for (int c = 0; c < 3; ++c) uh[c] = TD[c] / s;
+    #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int v = F.gv[k];
       if (v < 0 || G.fixed[v]) continue;
       const double a = F.a[k];
+      #pragma unroll
       for (int c = 0; c < 3; ++c) {
         atomicAdd(&gout[c * nv + v], F.mulam * a * fos * TD[c]);
         const double h = fos * (1.0 - F.n[c] * F.n[c]) + corr * uh[c] * uh[c];
@@ -578,7 +606,7 @@ __device__ double fric_eval(const View& V, const Shared& S, const double* x, con
   return energy;
 }
 
-__device__ double fric_curv(const View& V, const Shared& S, const double* x, const double* p) {
+__device__ __noinline__ double fric_curv(const View& V, const Shared& S, const double* x, const double* p) {
   const GelDev& G = *V.G;
   const int nv = G.n_v;
   const double eps = V.E->eps_v;
@@ -589,14 +617,17 @@ __device__ double fric_curv(const View& V, const Shared& S, const double* x, con
     fric_delta(V, S, F, x, nullptr, 0.0, Dl);
     const double nD = dot3(F.n, Dl);
     double TD[3];
+    #pragma unroll
     for (int c = 0; c < 3; ++c) TD[c] = Dl[c] - nD * F.n[c];
     const double s = sqrt(dot3(TD, TD));
     double f, fos, corr;
     mollifier3(s, eps, f, fos, corr);
     double q[3] = {0, 0, 0};
+    #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int v = F.gv[k];
       if (v < 0 || G.fixed[v]) continue;
+      #pragma unroll
       for (int c = 0; c < 3; ++c) q[c] += F.a[k] * p[c * nv + v];
     }
     const double nq = dot3(F.n, q);
@@ -624,10 +655,13 @@ __device__ inline void make_fric(const View& V, const PairPts& P, const Feature&
   const EnvDev& E = *V.E;
   const int kind = P.kind;
   const double sgn = (kind == kFV) ? -1.0 : 1.0;  // r = gel - indenter for VF and EE
+  #pragma unroll
   for (int c = 0; c < 3; ++c) F.n[c] = sgn * r[c] / d;
   const int gp = pr.x & kPrimMask, ip = pr.y;
+  #pragma unroll
   for (int k = 0; k < 3; ++k) { F.gv[k] = -1; F.iv[k] = -1; F.a[k] = 0.0; F.c[k] = 0.0; }
   int ng = 0, ni = 0;
+  #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (P.gid[k] >= 0) { F.gv[ng] = P.gid[k]; F.a[ng] = sgn * f.c[k]; ++ng; }
   }
@@ -635,11 +669,14 @@ __device__ inline void make_fric(const View& V, const PairPts& P, const Feature&
   if (kind == kVF) { ids[0] = I.tri[ip]; ids[1] = I.tri[I.n_f + ip]; ids[2] = I.tri[2 * I.n_f + ip]; }
   else if (kind == kFV) { ids[0] = ip; }
   else { ids[0] = I.edge[ip]; ids[1] = I.edge[I.n_e + ip]; }
+  #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (P.gid[k] < 0) { F.iv[ni] = ids[ni]; F.c[ni] = -sgn * f.c[k]; ++ni; }
   }
+  #pragma unroll
   for (int c = 0; c < 3; ++c) {
     double s = 0.0;
+    #pragma unroll
     for (int k = 0; k < 4; ++k) s += sgn * f.c[k] * P.z[k][c];  // gel cp - indenter cp
     F.base[c] = s;
   }
@@ -651,7 +688,7 @@ __device__ inline void make_fric(const View& V, const PairPts& P, const Feature&
 
 // mode 0: candidate pairs (d < thr) into V.pairs; mode 1: friction records for
 // pairs with d < dhat; mode 2: distances only. Returns the thread's smallest d.
-__device__ double cull(View& V, Shared& S, const double* x, double thr, int mode, int cap) {
+__device__ __noinline__ double cull(View& V, Shared& S, const double* x, double thr, int mode, int cap) {
   const GelDev& G = *V.G;
   const IndDev& I = *V.I;
   const int nv = G.n_v;
@@ -670,12 +707,14 @@ __device__ double cull(View& V, Shared& S, const double* x, double thr, int mode
     }
     double lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
     for (int k = 0; k < ngv; ++k)
+      #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const double xv = x[c * nv + gvid[k]];
         lo[c] = fmin(lo[c], xv);
         hi[c] = fmax(hi[c], xv);
       }
     bool away = false;
+    #pragma unroll
     for (int c = 0; c < 3; ++c) {
       lo[c] -= thr; hi[c] += thr;
       if (lo[c] > S.iw_hi[c] || hi[c] < S.iw_lo[c]) away = true;
@@ -685,7 +724,9 @@ __device__ double cull(View& V, Shared& S, const double* x, double thr, int mode
     double ql[3], qh[3];
     {
       double c[3], h[3];
+      #pragma unroll
       for (int k = 0; k < 3; ++k) { c[k] = 0.5 * (lo[k] + hi[k]) - S.t[k]; h[k] = 0.5 * (hi[k] - lo[k]); }
+      #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const double cl = S.R[0 * 3 + a] * c[0] + S.R[1 * 3 + a] * c[1] + S.R[2 * 3 + a] * c[2];
         const double hl = fabs(S.R[0 * 3 + a]) * h[0] + fabs(S.R[1 * 3 + a]) * h[1] + fabs(S.R[2 * 3 + a]) * h[2];
@@ -696,6 +737,7 @@ __device__ double cull(View& V, Shared& S, const double* x, double thr, int mode
     const Grid& Gr = (kind == kVF) ? I.gf : ((kind == kFV) ? I.gv : I.ge);
     bool outside = false;
     int c0[3], c1[3];
+    #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const double gmax = Gr.origin[a] + Gr.dims[a] / Gr.inv_cell;
       if (qh[a] < Gr.origin[a] || ql[a] > gmax) outside = true;
@@ -712,6 +754,7 @@ __device__ double cull(View& V, Shared& S, const double* x, double thr, int mode
             const int it = Gr.items[j];
             double il[3], ih[3];
             bool ov = true;
+            #pragma unroll
             for (int a = 0; a < 3; ++a) {
               il[a] = Gr.box[a * Gr.n_prim + it];
               ih[a] = Gr.box[(3 + a) * Gr.n_prim + it];
@@ -767,7 +810,9 @@ struct Solver {
 
 __device__ bool recull(Solver& s, const double* x) {
   View& V = s.V;
+  const unsigned long long t0 = tick();
   cull(V, *s.S, x, V.E->dhat + s.buffer, 0, s.pair_cap);
+  tock(*s.S, 0, t0);
   const int ov = s.S->overflow;
   const int cnt = s.S->count;
   __syncthreads();
@@ -839,36 +884,47 @@ __device__ int pncg(Solver& s, double tol, int max_iters, int& iters, double& re
   if (!recull(s, x)) return kOverflow;
   double macc = 0.0;
   int feas, nact;
+  unsigned long long t0 = tick();
   double E0 = eval_all(s, x, V.p, 0.0, g0, V.diag, feas, nact);
+  tock(*s.S, 3, t0);
   nactive_out = nact;
   if (!feas) { iters = 0; return kInfeasible; }
   double res, pinf, gp;
+  t0 = tick();
   init_direction(s, g0, res, pinf, gp);
+  tock(*s.S, 4, t0);
   int status = 0;
   int k = 0;
   for (;; ++k) {
     if (res <= tol) { status = kConverged; break; }
     if (k >= max_iters) { status = kMaxIter; break; }
     const double a_up = dh / (2.0 * pinf);
+    t0 = tick();
     const double curv = curvature_all(s, x, V.p);
+    tock(*s.S, 1, t0);
     const double a_bar = (curv > 0.0) ? -gp / curv : kInf;
     double alpha = fmin(a_up, a_bar);
     if (macc + alpha * kSqrt3 * pinf > s.buffer) {
       if (!recull(s, x)) { status = kOverflow; break; }
       macc = 0.0;
     }
+    t0 = tick();
     {
       double w = pairs_ccd(V, *s.S, x, V.p, alpha);
       alpha = block_min(w, *s.S);
     }
+    tock(*s.S, 2, t0);
     bool ok = false;
     double E1 = E0;
+    t0 = tick();
     for (int h = 0; h <= kMaxHalvings; ++h) {
       E1 = eval_all(s, x, V.p, alpha, g1, V.diag, feas, nact);
       if (feas && (!s.armijo || E1 <= E0 + kArmijoC * alpha * gp + s.guard)) { ok = true; break; }
       alpha *= 0.5;
       ++s.halvings;
     }
+    tock(*s.S, 3, t0);
+    t0 = tick();
     if (!ok) { status = kLineSearch; break; }
     nactive_out = nact;
     macc += alpha * kSqrt3 * pinf;
@@ -913,6 +969,7 @@ __device__ int pncg(Solver& s, double tol, int max_iters, int& iters, double& re
     }
     E0 = E1;
     double* tmp = g0; g0 = g1; g1 = tmp;
+    tock(*s.S, 4, t0);
   }
   iters = k;
   res_out = res;
@@ -963,8 +1020,10 @@ __device__ void write_outputs(const StepParams& P, int e, const View& V) {
   if (P.markers_out) {
     double* mo = P.markers_out + 3 * V.E->moff;
     for (int m = threadIdx.x; m < G.n_m; m += blockDim.x) {
+      #pragma unroll
       for (int c = 0; c < 3; ++c) {
         double u = 0.0;
+        #pragma unroll
         for (int k = 0; k < 3; ++k) {
           const int v = G.marker_tri[k * G.n_m + m];
           u += G.marker_w[k * G.n_m + m] * (V.x[c * nv + v] - G.X[c * nv + v]);
@@ -999,16 +1058,22 @@ __global__ void __launch_bounds__(256) t2r_step_kernel(StepParams P) {
   const IndDev& I = *V.I;
   const EnvDev& E = *V.E;
   const int n = 3 * G.n_v;
+  const unsigned long long t_start = tick();
+  if (threadIdx.x < 6) S.tacc[threadIdx.x] = 0ull;
+  __syncthreads();
   EnvStats st;
   st.status = 0; st.iters = 0; st.substeps = 0; st.restarts = 0; st.halvings = 0; st.reculls = 0;
   st.n_candidates = 0; st.n_active = 0; st.n_friction = 0; st.max_solve_iters = 0;
   st.d_min = kInf; st.residual = 0.0; st.energy = 0.0;
+  for (int k = 0; k < 6; ++k) st.phase_ms[k] = 0.0;
 
   double* pose_prev = P.pose_prev + 7 * e;
   double q0[7], q1[7];
+  #pragma unroll
   for (int i = 0; i < 7; ++i) { q0[i] = pose_prev[i]; q1[i] = P.pose_in[7 * e + i]; }
   bool skip = P.env_mask && P.env_mask[e] == 0;
   bool bad = false;
+  #pragma unroll
   for (int i = 0; i < 7; ++i) bad |= !isfinite(q1[i]);
   if (skip || bad) {
     st.status = skip ? kSkipped : kNonFinite;
@@ -1043,6 +1108,7 @@ __global__ void __launch_bounds__(256) t2r_step_kernel(StepParams P) {
   } else {
     // continuation rate |dt| + theta r_max of the indenter's points
     double dt = 0.0;
+    #pragma unroll
     for (int i = 0; i < 3; ++i) dt += (q1[i] - q0[i]) * (q1[i] - q0[i]);
     dt = sqrt(dt);
     double qa = 0.0, na = 0.0, nb = 0.0;
@@ -1081,6 +1147,7 @@ __global__ void __launch_bounds__(256) t2r_step_kernel(StepParams P) {
     for (int j = threadIdx.x; j < n; j += blockDim.x) V.x[j] = V.xprev[j];
     __syncthreads();
   } else if (threadIdx.x == 0) {
+    #pragma unroll
     for (int i = 0; i < 7; ++i) pose_prev[i] = q1[i];
   }
   {
@@ -1100,6 +1167,8 @@ __global__ void __launch_bounds__(256) t2r_step_kernel(StepParams P) {
   st.energy = energy;
   write_outputs(P, e, V);
   if (threadIdx.x == 0) {
+    S.tacc[5] = wall_clock64() - t_start;
+    for (int k = 0; k < 6; ++k) st.phase_ms[k] = (double)S.tacc[k] / P.clock_khz;
     P.stats[e] = st;
     if (P.status_out) P.status_out[e] = st.status;
   }

@@ -17,15 +17,12 @@ namespace t2r {
 //   p^T H_e p   = V [mu |dF|^2 + (mu - lam ln J) tr((F^-1 dF)^2) + lam (tr F^-1 dF)^2]
 // ---------------------------------------------------------------------------
 
-template <typename T>
-struct TetDer {
-  T E;          // V psi
-  T g[4][3];    // gradient blocks
-  T d[4][3];    // diagonal Hessian blocks
-};
-
-template <typename T>
-__device__ inline bool tet_grad_diag(const T Ds[9], const T Dm[9], T V, T mu, T lam, TetDer<T>& out) {
+// Evaluates one tet and hands each (vertex i, axis a) gradient and diagonal
+// entry to emit(i, a, grad, diag) as soon as it is known, so that no per-tet
+// array of 24 results stays live in registers. Returns false for J <= 0.
+template <typename T, typename Emit>
+__device__ inline bool tet_grad_diag(const T Ds[9], const T Dm[9], T V, T mu, T lam, T& energy,
+                                     Emit&& emit) {
   // Ds[a*3+k] = (x_{k+1} - x_0)_a ; F = Ds Dm
   T F[9];
 #pragma unroll
@@ -52,41 +49,39 @@ __device__ inline bool tet_grad_diag(const T Ds[9], const T Dm[9], T V, T mu, T 
   T I1 = T(0);
 #pragma unroll
   for (int k = 0; k < 9; ++k) I1 += F[k] * F[k];
-  out.E = V * (T(0.5) * mu * (I1 - T(3)) - mu * lnJ + T(0.5) * lam * lnJ * lnJ);
-  T Pm[9], FiT[9];
+  energy = V * (T(0.5) * mu * (I1 - T(3)) - mu * lnJ + T(0.5) * lam * lnJ * lnJ);
+  // reuse F for V P and C for F^-T
   const T cP = lam * lnJ - mu;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    FiT[k] = C[k] * invJ;
-    Pm[k] = mu * F[k] + cP * FiT[k];
+    C[k] *= invJ;
+    F[k] = V * (mu * F[k] + cP * C[k]);
   }
-  const T cd = mu + lam * (T(1) - lnJ);
-  T gs[3] = {T(0), T(0), T(0)}, ds[3] = {T(0), T(0), T(0)};
+  const T cd = V * (mu + lam * (T(1) - lnJ));
+  const T Vmu = V * mu;
+  T gs0 = T(0), gs1 = T(0), gs2 = T(0);
 #pragma unroll
   for (int i = 1; i < 4; ++i) {
     const T gi0 = Dm[(i - 1) * 3 + 0], gi1 = Dm[(i - 1) * 3 + 1], gi2 = Dm[(i - 1) * 3 + 2];
-    const T gg = gi0 * gi0 + gi1 * gi1 + gi2 * gi2;
+    const T gg = Vmu * (gi0 * gi0 + gi1 * gi1 + gi2 * gi2);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const T ga = V * (Pm[a * 3 + 0] * gi0 + Pm[a * 3 + 1] * gi1 + Pm[a * 3 + 2] * gi2);
-      const T w = FiT[a * 3 + 0] * gi0 + FiT[a * 3 + 1] * gi1 + FiT[a * 3 + 2] * gi2;
-      out.g[i][a] = ga;
-      out.d[i][a] = V * (mu * gg + cd * w * w);
-      gs[a] += ga;
+      const T ga = F[a * 3 + 0] * gi0 + F[a * 3 + 1] * gi1 + F[a * 3 + 2] * gi2;
+      const T w = C[a * 3 + 0] * gi0 + C[a * 3 + 1] * gi1 + C[a * 3 + 2] * gi2;
+      emit(i, a, ga, gg + cd * w * w);
+      if (a == 0) gs0 += ga; else if (a == 1) gs1 += ga; else gs2 += ga;
     }
   }
   {
     const T g00 = -(Dm[0] + Dm[3] + Dm[6]), g01 = -(Dm[1] + Dm[4] + Dm[7]),
             g02 = -(Dm[2] + Dm[5] + Dm[8]);
-    const T gg = g00 * g00 + g01 * g01 + g02 * g02;
+    const T gg = Vmu * (g00 * g00 + g01 * g01 + g02 * g02);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const T w = FiT[a * 3 + 0] * g00 + FiT[a * 3 + 1] * g01 + FiT[a * 3 + 2] * g02;
-      out.g[0][a] = -gs[a];
-      out.d[0][a] = V * (mu * gg + cd * w * w);
+      const T w = C[a * 3 + 0] * g00 + C[a * 3 + 1] * g01 + C[a * 3 + 2] * g02;
+      emit(0, a, -(a == 0 ? gs0 : (a == 1 ? gs1 : gs2)), gg + cd * w * w);
     }
   }
-  (void)ds;
   return true;
 }
 

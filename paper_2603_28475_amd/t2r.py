@@ -36,7 +36,7 @@ class EnvStats(C.Structure):
                 ("restarts", C.c_int32), ("halvings", C.c_int32), ("reculls", C.c_int32),
                 ("n_candidates", C.c_int32), ("n_active", C.c_int32), ("n_friction", C.c_int32),
                 ("max_solve_iters", C.c_int32), ("d_min", C.c_double), ("residual", C.c_double),
-                ("energy", C.c_double)]
+                ("energy", C.c_double), ("phase_ms", C.c_double * 6)]
 
 
 class T2RError(RuntimeError):
@@ -213,7 +213,12 @@ class Context:
         n, _ = self.env_count()
         arr = (EnvStats * n)()
         self.check(lib.t2r_get_stats(self.handle, C.cast(arr, C.c_void_p), C.sizeof(arr)))
-        return [{f: getattr(s, f) for f, _ in EnvStats._fields_} for s in arr]
+        out = []
+        for s in arr:
+            d = {f: getattr(s, f) for f, _ in EnvStats._fields_}
+            d["phase_ms"] = list(s.phase_ms)
+            out.append(d)
+        return out
 
     def get_state(self, d_state):
         self.check(lib.t2r_get_state(self.handle, _tptr(d_state)))
