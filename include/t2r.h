@@ -86,7 +86,8 @@ typedef struct { double E, nu, mu_f, eps_v, dhat, kappa; } t2r_material;
  *   precision     0: all FP64; 1: FP32 element terms, FP64 elsewhere
  *   pair_capacity contact candidate pairs per env (0: automatic)
  *   armijo        1: require sufficient decrease of Pi in the line search
- *   block_size    threads per workgroup, 64..1024 multiple of 64 (0: default 256) */
+ *   block_size    threads per env workgroup: 256 (two envs per CU) or 512 (one env
+ *                 per CU, for few large envs); 0 = 256 */
 typedef struct {
   double tol;
   double substep_tol;
@@ -105,16 +106,20 @@ typedef struct {
   int32_t substeps;      /* continuation solves */
   int32_t restarts;      /* direction resets to -P g */
   int32_t halvings;      /* line-search halvings */
-  int32_t reculls;       /* broad-phase passes */
+  int32_t reculls;       /* candidate-list refreshes (filter of the outer list) */
   int32_t n_candidates;  /* candidate pairs at the last cull */
   int32_t n_active;      /* pairs closer than dhat at the end */
   int32_t n_friction;    /* lagged friction pairs */
   int32_t max_solve_iters;
+  int32_t outer_builds;  /* grid traversals building the outer candidate list */
+  int32_t reserved;
   double d_min;          /* smallest gel/indenter distance at the end (mm), inf if none < dhat */
   double residual;       /* final |P g|_inf (mm) */
   double energy;         /* final Pi (N mm) */
-  double phase_ms[6];    /* time in: culling, curvature, CCD, energy/gradient evaluation,
-                            vector passes, and the whole step (ms, this env's workgroup) */
+  double phase_ms[10];   /* ms spent by this env's workgroup in: [0] coarse (grid) culls,
+                            [1] candidate filtering, [2] curvature elements, [3] curvature
+                            pairs, [4] CCD, [5] evaluation elements, [6] evaluation pairs
+                            and friction, [7] vector passes, [8] the whole step, [9] friction lag */
 } t2r_env_stats;
 
 /* Fills *o with the defaults: tol 1e-6, substep_tol 1e-4, max_iters 20000,

@@ -31,7 +31,7 @@ struct GelHost {
   std::vector<uint8_t> fixed;
   // tiled tet data
   std::vector<int> tet;           // [4][n_t]
-  std::vector<uint32_t> tet_local;
+  std::vector<uint64_t> tet_local;
   std::vector<double> Dinv;       // [9][n_t]
   std::vector<double> vol;
   std::vector<float> Dinv32, vol32;
@@ -89,6 +89,10 @@ struct t2r_ctx {
   double *d_x = nullptr, *d_xprev = nullptr, *d_g0 = nullptr, *d_g1 = nullptr, *d_diag = nullptr,
          *d_p = nullptr, *d_pose_prev = nullptr;
   int2* d_pairs = nullptr;
+  double* d_pair_d = nullptr;
+  int2* d_outer = nullptr;
+  ListState* d_lists = nullptr;
+  double* d_xsnap = nullptr;
   FricPair* d_fric = nullptr;
   EnvStats* d_stats = nullptr;
   long long* d_xout_off = nullptr;
@@ -249,8 +253,8 @@ static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
   if (o->max_iters < 0 || o->max_substeps < 1) return fail(c, T2R_E_ARG, "max_iters >= 0 and max_substeps >= 1 required");
   if (o->precision != 0 && o->precision != 1) return fail(c, T2R_E_ARG, "precision must be 0 or 1");
   if (o->pair_capacity < 0) return fail(c, T2R_E_ARG, "pair_capacity must be >= 0");
-  if (o->block_size != 0 && (o->block_size < 64 || o->block_size > 256 || o->block_size % 64))
-    return fail(c, T2R_E_ARG, "block_size must be 0 or a multiple of 64 in [64, 256]");
+  if (o->block_size != 0 && o->block_size != 256 && o->block_size != 512)
+    return fail(c, T2R_E_ARG, "block_size must be 0 (256), 256 or 512");
   return T2R_OK;
 }
 
@@ -489,7 +493,7 @@ t2r_status t2r_add_gel(t2r_ctx* c, int32_t n_v, const double* X, int32_t n_t, co
       for (int k = 0; k < 4; ++k)
         if (!local.count(tets[4 * (size_t)e + k])) ++newv;
       if (in_tile == kTileTets || (int)tile_v.size() + newv > kTileVerts) close_tile(i);
-      uint32_t loc = 0;
+      uint64_t loc = 0;
       for (int k = 0; k < 4; ++k) {
         const int v = tets[4 * (size_t)e + k];
         auto it = local.find(v);
@@ -501,7 +505,7 @@ t2r_status t2r_add_gel(t2r_ctx* c, int32_t n_v, const double* X, int32_t n_t, co
         } else {
           l = it->second;
         }
-        loc |= (uint32_t)l << (8 * k);
+        loc |= (uint64_t)l << (16 * k);
         g.tet[(size_t)k * n_t + i] = v;
       }
       g.tet_local[i] = loc;
@@ -693,6 +697,10 @@ static StepParams step_params(t2r_ctx* c) {
   P.p = c->d_p;
   P.pose_prev = c->d_pose_prev;
   P.pairs = c->d_pairs;
+  P.pair_d = c->d_pair_d;
+  P.outer = c->d_outer;
+  P.lists = c->d_lists;
+  P.xsnap = c->d_xsnap;
   P.fric = c->d_fric;
   P.stats = c->d_stats;
   P.x_out_off = c->d_xout_off;
@@ -743,6 +751,8 @@ t2r_status t2r_eval(t2r_ctx* c, int32_t env, const double* d_x, const double* d_
   ed.poff = 0;
   ed.foff = 0;
   ed.moff = 0;
+  ed.ooff = 0;
+  ed.snoff = 0;
   // scratch (freed before returning)
   std::vector<void*> tmp;
   auto talloc = [&](size_t b) -> void* {
@@ -767,16 +777,21 @@ t2r_status t2r_eval(t2r_ctx* c, int32_t env, const double* d_x, const double* d_
   double* sd = (double*)talloc(vb);
   double* sp = (double*)talloc(vb);
   int2* spairs = (int2*)talloc((size_t)ed.pair_cap * sizeof(int2));
+  double* spd = (double*)talloc((size_t)ed.pair_cap * sizeof(double));
+  int2* souter = (int2*)talloc((size_t)ed.outer_cap * sizeof(int2));
+  ListState* slists = (ListState*)talloc(sizeof(ListState));
+  double* ssnap = (double*)talloc(6 * (size_t)std::max(G.n_sv, 1) * sizeof(double));
   FricPair* sfric = (FricPair*)talloc((size_t)ed.fric_cap * sizeof(FricPair));
   EnvDev* senv = (EnvDev*)talloc(sizeof(EnvDev));
   double* sposes = (double*)talloc(14 * sizeof(double));
   EnvStats* sstats = (EnvStats*)talloc(sizeof(EnvStats));
-  if (tmp.size() != 11) { tfree(); return fail(c, T2R_E_NOMEM, "scratch allocation failed"); }
+  if (tmp.size() != 15) { tfree(); return fail(c, T2R_E_NOMEM, "scratch allocation failed"); }
   double hp[14];
   for (int k = 0; k < 7; ++k) { hp[k] = pose[k]; hp[7 + k] = (pose_lag ? pose_lag[k] : pose[k]); }
   hipError_t he = hipSuccess;
   he = hipMemcpyAsync(senv, &ed, sizeof(EnvDev), hipMemcpyHostToDevice, c->stream);
   if (he == hipSuccess) he = hipMemcpyAsync(sposes, hp, sizeof hp, hipMemcpyHostToDevice, c->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(slists, 0, sizeof(ListState), c->stream);
   if (he == hipSuccess) he = t2r_launch_aos_to_soa(d_x, sx, nv, c->stream);
   if (he == hipSuccess && d_p) he = t2r_launch_aos_to_soa(d_p, sp, nv, c->stream);
   if (he == hipSuccess && !d_p) he = hipMemsetAsync(sp, 0, vb, c->stream);
@@ -793,6 +808,10 @@ t2r_status t2r_eval(t2r_ctx* c, int32_t env, const double* d_x, const double* d_
   Q.sp.diag = sd;
   Q.sp.p = sp;
   Q.sp.pairs = spairs;
+  Q.sp.pair_d = spd;
+  Q.sp.outer = souter;
+  Q.sp.lists = slists;
+  Q.sp.xsnap = ssnap;
   Q.sp.fric = sfric;
   Q.sp.stats = sstats;
   Q.env = 0;
@@ -803,7 +822,7 @@ t2r_status t2r_eval(t2r_ctx* c, int32_t env, const double* d_x, const double* d_
   Q.grad_out = d_grad;
   Q.diag_out = d_diag;
   Q.scalars_out = d_scalars;
-  he = t2r_launch_eval(&Q, block_of(c), c->stream);
+  he = t2r_launch_eval(&Q, 256, c->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
   tfree();
   if (he != hipSuccess) return fail(c, T2R_E_HIP, "eval: %s", hipGetErrorString(he));
@@ -847,6 +866,8 @@ t2r_status t2r_set_state(t2r_ctx* c, const double* d_state) {
   if (s != T2R_OK) return s;
   StepParams P = step_params(c);
   HIP_TRY(c, t2r_launch_pack_state(&P, d_state, nullptr, c->d_state_off, 0, c->stream));
+  // positions changed arbitrarily: every neighbour list must be rebuilt
+  HIP_TRY(c, hipMemsetAsync(c->d_lists, 0, c->envs.size() * sizeof(ListState), c->stream));
   c->err.clear();
   return T2R_OK;
 }
@@ -865,6 +886,7 @@ t2r_status t2r_reset_envs(t2r_ctx* c, const int32_t* ids, int32_t n) {
                               hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->d_pose_prev + 7 * (size_t)ids[i], e.pose0, 7 * sizeof(double),
                               hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d_lists + ids[i], 0, sizeof(ListState), c->stream));
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));  // host pose0 copies are pageable
   c->err.clear();
@@ -962,7 +984,7 @@ t2r_status commit(t2r_ctx* c) {
   c->d_inds = (IndDev*)di;
   // per-env layout
   c->h_envs.clear();
-  long long voff = 0, poff = 0, foff = 0, moff = 0, vtot = 0, soff = 0;
+  long long voff = 0, poff = 0, foff = 0, moff = 0, vtot = 0, soff = 0, ooff = 0, snoff = 0;
   std::vector<long long> xoff, sofs;
   for (auto& e : c->envs) {
     const GelHost& g = c->gels[e.gel];
@@ -979,6 +1001,9 @@ t2r_status commit(t2r_ctx* c) {
     if (cap == 0) cap = std::max(4096, 2 * (g.n_sv + g.n_se + g.n_sf));
     d.pair_cap = cap;
     d.fric_cap = std::max(1024, cap / 2);
+    d.outer_cap = 3 * cap;
+    d.ooff = ooff;
+    d.snoff = snoff;
     d.voff = voff;
     d.poff = poff;
     d.foff = foff;
@@ -988,6 +1013,8 @@ t2r_status commit(t2r_ctx* c) {
     voff += 3 * (long long)g.n_v;
     poff += cap;
     foff += d.fric_cap;
+    ooff += d.outer_cap;
+    snoff += 6 * (long long)g.n_sv;
     moff += g.n_m;
     vtot += g.n_v;
     soff += 3 * (long long)g.n_v + 7;
@@ -1016,10 +1043,15 @@ t2r_status commit(t2r_ctx* c) {
   c->d_p = alloc_n<double>(c, nd);
   c->d_pose_prev = alloc_n<double>(c, 7 * c->envs.size());
   c->d_pairs = alloc_n<int2>(c, (size_t)poff);
+  c->d_pair_d = alloc_n<double>(c, (size_t)poff);
+  c->d_outer = alloc_n<int2>(c, (size_t)ooff);
+  c->d_lists = alloc_n<ListState>(c, c->envs.size());
+  c->d_xsnap = alloc_n<double>(c, (size_t)std::max(snoff, 1LL));
   c->d_fric = alloc_n<FricPair>(c, (size_t)foff);
   c->d_stats = alloc_n<EnvStats>(c, c->envs.size());
   if (!c->d_x || !c->d_xprev || !c->d_g0 || !c->d_g1 || !c->d_diag || !c->d_p || !c->d_pose_prev ||
-      !c->d_pairs || !c->d_fric || !c->d_stats) {
+      !c->d_pairs || !c->d_pair_d || !c->d_outer || !c->d_lists || !c->d_xsnap || !c->d_fric ||
+      !c->d_stats) {
     dev_free_all(c);
     return fail(c, T2R_E_NOMEM, "state allocation failed (%lld DOFs)", voff);
   }
@@ -1033,6 +1065,7 @@ t2r_status commit(t2r_ctx* c) {
   }
   HIP_TRY(c, hipMemsetAsync(c->d_p, 0, nd * sizeof(double), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_stats, 0, c->envs.size() * sizeof(EnvStats), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_lists, 0, c->envs.size() * sizeof(ListState), c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->d_pose_prev, pose.data(), pose.size() * sizeof(double), hipMemcpyHostToDevice,
                             c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));  // host staging vectors go out of scope

@@ -11,8 +11,8 @@ namespace t2r {
 
 // Tet tiles: a workgroup stages one tile's vertices in LDS, evaluates its tets
 // and accumulates per-vertex sums with LDS atomics before one global flush.
-constexpr int kTileTets = 512;
-constexpr int kTileVerts = 256;   // local vertex ids fit in one byte
+constexpr int kTileTets = 1024;
+constexpr int kTileVerts = 512;   // local vertex ids are 16-bit
 constexpr int kMaxBlock = 1024;
 
 // Pair kinds of the contact list (top three bits of the first word).
@@ -43,7 +43,7 @@ struct GelDev {
   const double* X;         // [3][n_v]
   const uint8_t* fixed;    // [n_v]
   const int* tet;          // [4][n_t] global vertex ids, tiled order
-  const uint32_t* tet_local;  // [n_t] four local ids (bytes 0..3)
+  const uint64_t* tet_local;  // [n_t] four 16-bit local ids
   const double* Dinv;      // [9][n_t] Dm^-1 row-major entries
   const double* vol;       // [n_t]
   const float* Dinv32;     // [9][n_t] FP32 copy (mixed precision)
@@ -76,7 +76,9 @@ struct EnvDev {
   long long poff;          // offset of its pair list
   long long foff;          // offset of its friction list
   long long moff;          // offset (markers) in the marker output
-  int pair_cap, fric_cap;
+  long long ooff;          // offset of its outer (coarse) candidate list
+  long long snoff;         // offset of its two surface-vertex snapshots (6 n_sv doubles)
+  int pair_cap, fric_cap, outer_cap;
 };
 
 struct FricPair {          // lagged friction data of one pair (Supp. A, eq. friction_energy)
@@ -89,11 +91,17 @@ struct FricPair {          // lagged friction data of one pair (Supp. A, eq. fri
   double mulam;            // mu_f * lambda = -mu_f kappa b'(d) at the lag
 };
 
+struct ListState {         // neighbour lists kept across load steps
+  double pose_o[7];        // indenter pose when the outer list was built
+  double pose_i[7];        // ... and when the inner list was built
+  int n_outer, n_inner, valid_o, valid_i;
+};
+
 struct EnvStats {
   int status, iters, substeps, restarts, halvings, reculls, n_candidates, n_active,
-      n_friction, max_solve_iters;
+      n_friction, max_solve_iters, outer_builds, pad;
   double d_min, residual, energy;
-  double phase_ms[6];      // cull, curvature, ccd, eval, vector passes, whole step
+  double phase_ms[10];     // see t2r_env_stats
 };
 
 struct StepParams {
@@ -110,6 +118,10 @@ struct StepParams {
   double* p;
   double* pose_prev;       // [n_env][7]
   int2* pairs;             // [sum pair_cap]
+  double* pair_d;          // [sum pair_cap] distance of each candidate at the current x
+  int2* outer;             // [sum outer_cap] coarse candidates (wider radius, rebuilt rarely)
+  ListState* lists;        // [n_env]
+  double* xsnap;           // [sum 6 n_sv] surface positions when the lists were built
   FricPair* fric;          // [sum fric_cap]
   EnvStats* stats;         // [n_env]
   // inputs / outputs

@@ -43,17 +43,18 @@ constexpr int kConverged = 1, kMaxIter = 2, kInfeasible = 4, kNonFinite = 8, kOv
 // ---------------------------------------------------------------------------
 struct Shared {
   double R[9], t[3];          // current indenter pose
+  double pose[7];             // ... as (t, q)
   double iw_lo[3], iw_hi[3];  // indenter world bounding box
   double red[16 * 8];         // per-wave partials
   double bc[8];               // broadcast results
   int count, overflow, flag;
   int pad;
-  unsigned long long tacc[6];  // wall-clock ticks per phase (thread 0)
+  unsigned long long tacc[10];  // wall-clock ticks per phase (thread 0)
 };
 
 // Phase timers: thread 0 accumulates wall-clock ticks into S.tacc[k].
-__device__ inline unsigned long long tick() { return wall_clock64(); }
-__device__ inline void tock(Shared& S, int k, unsigned long long t0) {
+__device__ __forceinline__ unsigned long long tick() { return wall_clock64(); }
+__device__ __forceinline__ void tock(Shared& S, int k, unsigned long long t0) {
   if (threadIdx.x == 0) S.tacc[k] += wall_clock64() - t0;
 }
 
@@ -67,7 +68,7 @@ struct Tile {
 // Block-wide reduction of NS sums followed by NM maxima (values in v[0..NS+NM)).
 // Every thread receives the results in v.
 template <int NS, int NM>
-__device__ inline void block_reduce(double* v, Shared& S) {
+__device__ __forceinline__ void block_reduce(double* v, Shared& S) {
   constexpr int N = NS + NM;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
@@ -98,7 +99,7 @@ __device__ inline void block_reduce(double* v, Shared& S) {
   for (int i = 0; i < N; ++i) v[i] = S.bc[i];
 }
 
-__device__ inline double block_min(double v, Shared& S) {
+__device__ __forceinline__ double block_min(double v, Shared& S) {
   double a = -v;
   block_reduce<0, 1>(&a, S);
   return -a;
@@ -107,7 +108,7 @@ __device__ inline double block_min(double v, Shared& S) {
 // ---------------------------------------------------------------------------
 // Pose helpers (thread 0 writes S)
 // ---------------------------------------------------------------------------
-__device__ inline void quat_to_R(const double q_in[4], double R[9]) {
+__device__ __forceinline__ void quat_to_R(const double q_in[4], double R[9]) {
   const double n = sqrt(q_in[0] * q_in[0] + q_in[1] * q_in[1] + q_in[2] * q_in[2] + q_in[3] * q_in[3]);
   const double w = q_in[0] / n, x = q_in[1] / n, y = q_in[2] / n, z = q_in[3] / n;
   R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
@@ -116,7 +117,7 @@ __device__ inline void quat_to_R(const double q_in[4], double R[9]) {
 }
 
 // Pose at tau between p0 and p1: translation linear, rotation by slerp.
-__device__ inline void interp_pose(const double p0[7], const double p1[7], double tau, double out[7]) {
+__device__ __forceinline__ void interp_pose(const double p0[7], const double p1[7], double tau, double out[7]) {
   #pragma unroll
   for (int i = 0; i < 3; ++i) out[i] = (1.0 - tau) * p0[i] + tau * p1[i];
   double q0[4], q1[4];
@@ -141,7 +142,8 @@ __device__ inline void interp_pose(const double p0[7], const double p1[7], doubl
   for (int i = 0; i < 4; ++i) out[3 + i] /= n;
 }
 
-__device__ inline void set_pose(Shared& S, const IndDev& I, const double pose[7]) {
+__device__ __forceinline__ void set_pose(Shared& S, const IndDev& I, const double pose[7]) {
+  for (int i = 0; i < 7; ++i) S.pose[i] = pose[i];
   quat_to_R(pose + 3, S.R);
   #pragma unroll
   for (int i = 0; i < 3; ++i) S.t[i] = pose[i];
@@ -158,7 +160,7 @@ __device__ inline void set_pose(Shared& S, const IndDev& I, const double pose[7]
   }
 }
 
-__device__ inline void ind_world(const Shared& S, const IndDev& I, int j, double y[3]) {
+__device__ __forceinline__ void ind_world(const Shared& S, const IndDev& I, int j, double y[3]) {
   const double a = I.Y[j], b = I.Y[I.n_v + j], c = I.Y[2 * I.n_v + j];
   #pragma unroll
   for (int r = 0; r < 3; ++r) y[r] = S.R[r * 3 + 0] * a + S.R[r * 3 + 1] * b + S.R[r * 3 + 2] * c + S.t[r];
@@ -178,15 +180,17 @@ struct View {
   double* diag;
   double* p;
   int2* pairs;
+  double* pd;      // distance of each candidate pair at the current x
+  int2* outer;     // coarse candidates within the outer radius
   FricPair* fric;
-  int npairs, nfric;
+  int npairs, nfric, nouter;
   int mixed;
 };
 
 // ---------------------------------------------------------------------------
 // Element passes over LDS-staged tiles
 // ---------------------------------------------------------------------------
-__device__ inline void load_Dm(const GelDev& G, int e, double Dm[9]) {
+__device__ __forceinline__ void load_Dm(const GelDev& G, int e, double Dm[9]) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) Dm[k] = G.Dinv[k * G.n_t + e];
 }
@@ -194,7 +198,7 @@ __device__ inline void load_Dm(const GelDev& G, int e, double Dm[9]) {
 // Evaluates sum V psi, the gradient and diag(H) of the elastic term at
 // x + alpha p into gout/dout ([3][n_v]). Returns energy (thread partial) and
 // clears `feasible` on an inverted tet.
-__device__ __noinline__ double elem_eval(const View& V, const double* x, const double* p, double alpha,
+__device__ __forceinline__ double elem_eval(const View& V, const double* x, const double* p, double alpha,
                             double* gout, double* dout, Tile& T, int& feasible) {
   const GelDev& G = *V.G;
   const EnvDev& E = *V.E;
@@ -214,10 +218,10 @@ __device__ __noinline__ double elem_eval(const View& V, const double* x, const d
     }
     __syncthreads();
     for (int e = t0 + threadIdx.x; e < t1; e += blockDim.x) {
-      const uint32_t loc = G.tet_local[e];
+      const uint64_t loc = G.tet_local[e];
       int l[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) l[k] = (loc >> (8 * k)) & 0xff;
+      for (int k = 0; k < 4; ++k) l[k] = (int)((loc >> (16 * k)) & 0xffff);
       bool ok;
       if (V.mixed) {
         float Ds[9], Dm[9];
@@ -274,7 +278,7 @@ __device__ __noinline__ double elem_eval(const View& V, const double* x, const d
 }
 
 // p^T H_elastic p at x (thread partial).
-__device__ __noinline__ double elem_curv(const View& V, const double* x, const double* p, Tile& T) {
+__device__ __forceinline__ double elem_curv(const View& V, const double* x, const double* p, Tile& T) {
   const GelDev& G = *V.G;
   const EnvDev& E = *V.E;
   const int nv = G.n_v;
@@ -292,10 +296,10 @@ __device__ __noinline__ double elem_curv(const View& V, const double* x, const d
     }
     __syncthreads();
     for (int e = t0 + threadIdx.x; e < t1; e += blockDim.x) {
-      const uint32_t loc = G.tet_local[e];
+      const uint64_t loc = G.tet_local[e];
       int l[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) l[k] = (loc >> (8 * k)) & 0xff;
+      for (int k = 0; k < 4; ++k) l[k] = (int)((loc >> (16 * k)) & 0xffff);
       if (V.mixed) {
         float Ds[9], dDs[9], Dm[9];
 #pragma unroll
@@ -336,7 +340,7 @@ struct PairPts {
 };
 
 // Gathers the four points of pair `pr`; gel points at x + alpha p.
-__device__ inline void load_pair(const View& V, const Shared& S, int2 pr, const double* x,
+__device__ __forceinline__ void load_pair(const View& V, const Shared& S, int2 pr, const double* x,
                                  const double* p, double alpha, PairPts& P) {
   const GelDev& G = *V.G;
   const IndDev& I = *V.I;
@@ -370,19 +374,36 @@ __device__ inline void load_pair(const View& V, const Shared& S, int2 pr, const 
   }
 }
 
-__device__ inline void classify(const PairPts& P, Feature& f) {
+__device__ __forceinline__ void classify(const PairPts& P, Feature& f) {
   if (P.kind == kEE) classify_ee(P.z[0], P.z[1], P.z[2], P.z[3], f);
   else classify_pt(P.z[0], P.z[1], P.z[2], P.z[3], f);
 }
 
-__device__ inline double pair_distance(const PairPts& P, const Feature& f, double r[3]) {
+__device__ __forceinline__ double pair_distance(const PairPts& P, const Feature& f, double r[3]) {
   #pragma unroll
   for (int c = 0; c < 3; ++c) r[c] = f.c[0] * P.z[0][c] + f.c[1] * P.z[1][c] + f.c[2] * P.z[2][c] + f.c[3] * P.z[3][c];
   return sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
 }
 
+// Gel vertex ids of a pair (-1 where unused), without touching positions.
+__device__ __forceinline__ void pair_gel_ids(const GelDev& G, int2 pr, int gv[3]) {
+  const int kind = (int)((unsigned)pr.x >> kKindShift);
+  const int gp = pr.x & kPrimMask;
+  gv[1] = gv[2] = -1;
+  if (kind == kVF) {
+    gv[0] = gp;
+  } else if (kind == kFV) {
+    gv[0] = G.surf_f[gp]; gv[1] = G.surf_f[G.n_sf + gp]; gv[2] = G.surf_f[2 * G.n_sf + gp];
+  } else {
+    gv[0] = G.surf_e[gp]; gv[1] = G.surf_e[G.n_se + gp];
+  }
+}
+
 // Barrier energy, gradient and diag of every candidate pair at x + alpha p.
-__device__ __noinline__ double pairs_eval(const View& V, const Shared& S, const double* x, const double* p,
+// For a trial step, a pair whose cached distance minus the largest motion of
+// its gel vertices stays >= dhat is inactive (and positive) at the trial point:
+// its cache keeps that lower bound and no exact distance is computed.
+__device__ __forceinline__ double pairs_eval(const View& V, const Shared& S, const double* x, const double* p,
                              double alpha, double* gout, double* dout, int& feasible, int& nactive) {
   const GelDev& G = *V.G;
   const EnvDev& E = *V.E;
@@ -390,12 +411,29 @@ __device__ __noinline__ double pairs_eval(const View& V, const Shared& S, const 
   const double dh = E.dhat, kap = E.kappa;
   double energy = 0.0;
   for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
+    const int2 pr = V.pairs[i];
+    if (alpha > 0.0) {
+      int gv[3];
+      pair_gel_ids(G, pr, gv);
+      double l2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (gv[k] < 0) continue;
+        double sq = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { const double pc = p[c * nv + gv[k]]; sq += pc * pc; }
+        l2 = fmax(l2, sq);
+      }
+      const double lb = V.pd[i] - alpha * sqrt(l2);
+      if (lb >= dh) { V.pd[i] = lb; continue; }
+    }
     PairPts P;
-    load_pair(V, S, V.pairs[i], x, p, alpha, P);
+    load_pair(V, S, pr, x, p, alpha, P);
     Feature f;
     classify(P, f);
     double r[3];
     const double d = pair_distance(P, f, r);
+    V.pd[i] = d;
     if (!(d > 0.0)) { feasible = 0; continue; }
     if (d >= dh) continue;
     ++nactive;
@@ -434,13 +472,14 @@ __device__ __noinline__ double pairs_eval(const View& V, const Shared& S, const 
 }
 
 // p^T H_barrier p at x (thread partial).
-__device__ __noinline__ double pairs_curv(const View& V, const Shared& S, const double* x, const double* p) {
+__device__ __forceinline__ double pairs_curv(const View& V, const Shared& S, const double* x, const double* p) {
   const GelDev& G = *V.G;
   const EnvDev& E = *V.E;
   const int nv = G.n_v;
   const double dh = E.dhat, kap = E.kappa;
   double curv = 0.0;
   for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
+    if (!(V.pd[i] < dh)) continue;  // inactive at x: no barrier curvature
     PairPts P;
     load_pair(V, S, V.pairs[i], x, nullptr, 0.0, P);
     Feature f;
@@ -483,7 +522,7 @@ __device__ __noinline__ double pairs_curv(const View& V, const Shared& S, const 
 }
 
 // Smallest distance over candidate pairs at x (thread partial; kInf if none).
-__device__ __noinline__ double pairs_dmin(const View& V, const Shared& S, const double* x, int& nactive) {
+__device__ __forceinline__ double pairs_dmin(const View& V, const Shared& S, const double* x, int& nactive) {
   double dmin = kInf;
   for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
     PairPts P;
@@ -498,30 +537,32 @@ __device__ __noinline__ double pairs_dmin(const View& V, const Shared& S, const 
   return dmin;
 }
 
+
 // Conservative advancement: largest t <= amax keeping each pair at >= kCcdGap of its
-// start distance, gel points moving along p, indenter static (thread partial min).
-__device__ __noinline__ double pairs_ccd(const View& V, const Shared& S, const double* x, const double* p, double amax) {
-  const int nv = V.G->n_v;
+// distance at x, gel points moving along p, indenter static (thread partial min).
+// The distance at x comes from the per-pair cache, so pairs that cannot close
+// their gap within amax cost only the gather of p at their gel vertices.
+__device__ __forceinline__ double pairs_ccd(const View& V, const Shared& S, const double* x, const double* p, double amax) {
+  const GelDev& G = *V.G;
+  const int nv = G.n_v;
   double tmin = amax;
   for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
-    PairPts P;
-    load_pair(V, S, V.pairs[i], x, nullptr, 0.0, P);
-    double l = 0.0;
-    #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int v = P.gid[k];
+    const int2 pr = V.pairs[i];
+    const double d0 = V.pd[i];
+    if (!(d0 > 0.0)) { tmin = 0.0; continue; }
+    int gv[3];
+    pair_gel_ids(G, pr, gv);
+    double l2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int v = gv[k];
       if (v < 0) continue;
       double s = 0.0;
-      #pragma unroll
+#pragma unroll
       for (int c = 0; c < 3; ++c) { const double pc = p[c * nv + v]; s += pc * pc; }
-      l = fmax(l, sqrt(s));
+      l2 = fmax(l2, s);
     }
-    if (l == 0.0) continue;
-    Feature f;
-    classify(P, f);
-    double r[3];
-    const double d0 = pair_distance(P, f, r);
-    if (!(d0 > 0.0)) { tmin = 0.0; continue; }
+    const double l = sqrt(l2);
     const double gap = kCcdGap * d0;
     if (l * amax <= d0 - gap) continue;
     double t = 0.0, d = d0;
@@ -529,9 +570,10 @@ __device__ __noinline__ double pairs_ccd(const View& V, const Shared& S, const d
       if (l * (amax - t) <= d - gap) { t = amax; break; }
       t += (d - gap) / l;
       PairPts Q;
-      load_pair(V, S, V.pairs[i], x, p, t, Q);
+      load_pair(V, S, pr, x, p, t, Q);
       Feature g;
       classify(Q, g);
+      double r[3];
       d = pair_distance(Q, g, r);
       if (d - gap <= 1e-3 * (d0 - gap)) break;
     }
@@ -543,7 +585,7 @@ __device__ __noinline__ double pairs_ccd(const View& V, const Shared& S, const d
 // ---------------------------------------------------------------------------
 // Lagged friction (Supp. A, eqs. friction_energy, friction_mollifier)
 // ---------------------------------------------------------------------------
-__device__ inline void fric_delta(const View& V, const Shared& S, const FricPair& F, const double* x,
+__device__ __forceinline__ void fric_delta(const View& V, const Shared& S, const FricPair& F, const double* x,
                                   const double* p, double alpha, double Dl[3]) {
   const int nv = V.G->n_v;
   const IndDev& I = *V.I;
@@ -570,7 +612,7 @@ __device__ inline void fric_delta(const View& V, const Shared& S, const FricPair
   }
 }
 
-__device__ __noinline__ double fric_eval(const View& V, const Shared& S, const double* x, const double* p, double alpha,
+__device__ __forceinline__ double fric_eval(const View& V, const Shared& S, const double* x, const double* p, double alpha,
                             double* gout, double* dout) {
   const GelDev& G = *V.G;
   const int nv = G.n_v;
@@ -606,7 +648,7 @@ __device__ __noinline__ double fric_eval(const View& V, const Shared& S, const d
   return energy;
 }
 
-__device__ __noinline__ double fric_curv(const View& V, const Shared& S, const double* x, const double* p) {
+__device__ __forceinline__ double fric_curv(const View& V, const Shared& S, const double* x, const double* p) {
   const GelDev& G = *V.G;
   const int nv = G.n_v;
   const double eps = V.E->eps_v;
@@ -643,13 +685,13 @@ __device__ __noinline__ double fric_curv(const View& V, const Shared& S, const d
 // indenter's primitives in the indenter's local frame. A pair is reported from
 // the single cell holding the lowest corner of the two boxes' overlap.
 // ---------------------------------------------------------------------------
-__device__ inline int cell_of(double v, double o, double inv, int dim) {
+__device__ __forceinline__ int cell_of(double v, double o, double inv, int dim) {
   int c = (int)floor((v - o) * inv);
   return c < 0 ? 0 : (c >= dim ? dim - 1 : c);
 }
 
 // Writes the friction record of a pair closer than dhat at the lag state.
-__device__ inline void make_fric(const View& V, const PairPts& P, const Feature& f, const double r[3],
+__device__ __forceinline__ void make_fric(const View& V, const PairPts& P, const Feature& f, const double r[3],
                                  double d, int2 pr, FricPair& F) {
   const IndDev& I = *V.I;
   const EnvDev& E = *V.E;
@@ -687,8 +729,9 @@ __device__ inline void make_fric(const View& V, const PairPts& P, const Feature&
 }
 
 // mode 0: candidate pairs (d < thr) into V.pairs; mode 1: friction records for
-// pairs with d < dhat; mode 2: distances only. Returns the thread's smallest d.
-__device__ __noinline__ double cull(View& V, Shared& S, const double* x, double thr, int mode, int cap) {
+// pairs with d < dhat; mode 2: distances only; mode 3: coarse candidates
+// (d < thr) into V.outer. Returns the thread's smallest d.
+__device__ __forceinline__ double cull(View& V, Shared& S, const double* x, double thr, int mode, int cap) {
   const GelDev& G = *V.G;
   const IndDev& I = *V.I;
   const int nv = G.n_v;
@@ -778,7 +821,11 @@ __device__ __noinline__ double cull(View& V, Shared& S, const double* x, double 
             dmin = fmin(dmin, d);
             if (mode == 0 && d < thr) {
               const int slot = atomicAdd(&S.count, 1);
-              if (slot < cap) V.pairs[slot] = pr;
+              if (slot < cap) { V.pairs[slot] = pr; V.pd[slot] = d; }
+              else S.overflow = 1;
+            } else if (mode == 3 && d < thr) {
+              const int slot = atomicAdd(&S.count, 1);
+              if (slot < cap) V.outer[slot] = pr;
               else S.overflow = 1;
             } else if (mode == 1 && d < V.E->dhat && d > 0.0) {
               const int slot = atomicAdd(&S.count, 1);
@@ -801,59 +848,231 @@ struct Solver {
   Tile* T;
   double floor_d;     // preconditioner floor
   double guard;       // energy rounding guard
-  double buffer;      // cull buffer beyond dhat
+  double buffer;      // inner list radius beyond dhat
+  double buffer_out;  // outer list radius beyond dhat
   int armijo;
-  int pair_cap, fric_cap;
+  int pair_cap, fric_cap, outer_cap;
+  ListState* L;       // persistent list state of this env
+  double* xs_o;       // [3][n_sv] surface positions at the outer build
+  double* xs_i;       // [3][n_sv] ... at the inner build
   // stats
-  int reculls, restarts, halvings, ncand;
+  int reculls, restarts, halvings, ncand, outer_builds;
 };
 
-__device__ bool recull(Solver& s, const double* x) {
+// Inner candidate list from the outer one: exact distance of every coarse pair,
+// keep those below thr. Work is one pair per thread, so it stays balanced.
+__device__ __forceinline__ void filter_pairs(View& V, Shared& S, const double* x, double thr, int cap) {
+  if (threadIdx.x == 0) { S.count = 0; S.overflow = 0; }
+  __syncthreads();
+  for (int i = threadIdx.x; i < V.nouter; i += blockDim.x) {
+    const int2 pr = V.outer[i];
+    PairPts P;
+    load_pair(V, S, pr, x, nullptr, 0.0, P);
+    Feature f;
+    classify(P, f);
+    double r[3];
+    const double d = pair_distance(P, f, r);
+    if (d < thr) {
+      const int slot = atomicAdd(&S.count, 1);
+      if (slot < cap) { V.pairs[slot] = pr; V.pd[slot] = d; }
+      else S.overflow = 1;
+    }
+  }
+  __syncthreads();
+}
+
+// Largest displacement of any indenter point between two poses: |dt| + theta r_max.
+__device__ __forceinline__ double ind_motion(const double a[7], const double b[7], double r_max) {
+  double dt = 0.0, qa = 0.0, na = 0.0, nb = 0.0;
+  for (int i = 0; i < 3; ++i) dt += (a[i] - b[i]) * (a[i] - b[i]);
+  for (int i = 3; i < 7; ++i) { qa += a[i] * b[i]; na += a[i] * a[i]; nb += b[i] * b[i]; }
+  const double c = fmin(1.0, fabs(qa) / sqrt(na * nb));
+  return sqrt(dt) + 2.0 * acos(c) * r_max;
+}
+
+// Largest surface-vertex displacement since each snapshot and largest |p| on the
+// surface (p may be null): out = {outer, inner, p}.
+__device__ __forceinline__ void surf_motion(Solver& s, const double* x, const double* p, double out[3]) {
+  const GelDev& G = *s.V.G;
+  const int nv = G.n_v, ns = G.n_sv;
+  double m[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+    const int v = G.surf_v[i];
+    double a = 0.0, b = 0.0, c2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double xv = x[c * nv + v];
+      const double da = xv - s.xs_o[c * ns + i], db = xv - s.xs_i[c * ns + i];
+      a += da * da;
+      b += db * db;
+      if (p) { const double pv = p[c * nv + v]; c2 += pv * pv; }
+    }
+    m[0] = fmax(m[0], a);
+    m[1] = fmax(m[1], b);
+    m[2] = fmax(m[2], c2);
+  }
+  block_reduce<0, 3>(m, *s.S);
+  for (int k = 0; k < 3; ++k) out[k] = sqrt(m[k]);
+}
+
+__device__ __forceinline__ void snapshot(Solver& s, const double* x, double* dst) {
+  const GelDev& G = *s.V.G;
+  const int nv = G.n_v, ns = G.n_sv;
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+    const int v = G.surf_v[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dst[c * ns + i] = x[c * nv + v];
+  }
+  __syncthreads();
+}
+
+// Two-level neighbour list. The outer list (radius dhat + buffer_out) comes from
+// the grid traversal; the inner list (radius dhat + buffer) filters it. Each
+// list remembers the surface positions and the indenter pose it was built at.
+// A pair's distance changes by at most the motion of its gel points plus that of
+// the indenter, so a pair missing from the inner list is still inactive and
+// cannot be hit as long as (surface motion + indenter motion + the coming step)
+// stays below buffer; for the outer list the margin is buffer_out - buffer,
+// which also keeps every pair within the inner radius inside the outer list.
+__device__ __forceinline__ bool rebuild_outer(Solver& s, const double* x) {
   View& V = s.V;
   const unsigned long long t0 = tick();
-  cull(V, *s.S, x, V.E->dhat + s.buffer, 0, s.pair_cap);
+  cull(V, *s.S, x, V.E->dhat + s.buffer_out, 3, s.outer_cap);
+  const int ov = s.S->overflow;
+  const int cnt = s.S->count;
+  __syncthreads();
+  V.nouter = min(cnt, s.outer_cap);
+  snapshot(s, x, s.xs_o);
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < 7; ++i) s.L->pose_o[i] = s.S->pose[i];
+    s.L->n_outer = V.nouter;
+    s.L->valid_o = ov ? 0 : 1;
+    s.L->valid_i = 0;
+  }
+  ++s.outer_builds;
+  __syncthreads();
   tock(*s.S, 0, t0);
+  return ov == 0;
+}
+
+__device__ __forceinline__ bool refilter(Solver& s, const double* x) {
+  View& V = s.V;
+  const unsigned long long t0 = tick();
+  filter_pairs(V, *s.S, x, V.E->dhat + s.buffer, s.pair_cap);
   const int ov = s.S->overflow;
   const int cnt = s.S->count;
   __syncthreads();
   V.npairs = min(cnt, s.pair_cap);
   s.ncand = V.npairs;
   ++s.reculls;
+  snapshot(s, x, s.xs_i);
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < 7; ++i) s.L->pose_i[i] = s.S->pose[i];
+    s.L->n_inner = V.npairs;
+    s.L->valid_i = ov ? 0 : 1;
+  }
+  __syncthreads();
+  tock(*s.S, 1, t0);
   return ov == 0;
 }
 
+// Makes both lists valid at (x, current pose) for a coming motion of at most
+// `step` of any surface point. Returns false on a list overflow.
+__device__ __forceinline__ bool ensure_lists(Solver& s, const double* x, double step, const double m[2]) {
+  View& V = s.V;
+  const double r_max = V.I->r_max;
+  const int vo = s.L->valid_o, vi = s.L->valid_i;
+  const double mo = vo ? m[0] + ind_motion(s.L->pose_o, s.S->pose, r_max) : kInf;
+  const double mi = vi ? m[1] + ind_motion(s.L->pose_i, s.S->pose, r_max) : kInf;
+  __syncthreads();
+  if (!(mo + step <= s.buffer_out - s.buffer)) {
+    if (!rebuild_outer(s, x)) return false;
+    return refilter(s, x);
+  }
+  if (!(mi + step <= s.buffer)) return refilter(s, x);
+  return true;
+}
+
+__device__ __forceinline__ bool ensure_lists(Solver& s, const double* x, double step) {
+  double m[3];
+  surf_motion(s, x, nullptr, m);
+  return ensure_lists(s, x, step, m);
+}
+
+// Restores the list sizes kept from the previous launch.
+__device__ __forceinline__ void load_lists(Solver& s) {
+  s.V.nouter = s.L->valid_o ? s.L->n_outer : 0;
+  s.V.npairs = s.L->valid_i ? s.L->n_inner : 0;
+}
+
+// Friction lag and smallest distance at (x, current pose) from the outer list:
+// exact distance of every coarse pair; pairs closer than dhat get a friction
+// record when mode == 1. Requires a valid outer list. Returns the thread's min d.
+__device__ __forceinline__ double lag_from_outer(Solver& s, const double* x, int mode) {
+  View& V = s.V;
+  Shared& S = *s.S;
+  if (threadIdx.x == 0) { S.count = 0; S.overflow = 0; }
+  __syncthreads();
+  double dmin = kInf;
+  for (int i = threadIdx.x; i < V.nouter; i += blockDim.x) {
+    const int2 pr = V.outer[i];
+    PairPts P;
+    load_pair(V, S, pr, x, nullptr, 0.0, P);
+    Feature f;
+    classify(P, f);
+    double r[3];
+    const double d = pair_distance(P, f, r);
+    dmin = fmin(dmin, d);
+    if (mode == 1 && d < V.E->dhat && d > 0.0) {
+      const int slot = atomicAdd(&S.count, 1);
+      if (slot < s.fric_cap) make_fric(V, P, f, r, d, pr, V.fric[slot]);
+      else S.overflow = 1;
+    }
+  }
+  __syncthreads();
+  return dmin;
+}
+
 // Evaluates Pi, grad (-> g) and diag at x + alpha p. Returns energy; feasible in flag.
-__device__ double eval_all(Solver& s, const double* x, const double* p, double alpha, double* g,
+__device__ __forceinline__ double eval_all(Solver& s, const double* x, const double* p, double alpha, double* g,
                            double* dg, int& feasible, int& nactive, double* e_el = nullptr) {
   View& V = s.V;
   int feas = 1, nact = 0;
   double v[3];
+  unsigned long long t0 = tick();
   v[0] = elem_eval(V, x, p, alpha, g, dg, *s.T, feas);
+  tock(*s.S, 5, t0);
   double eel = v[0];
+  t0 = tick();
   v[0] += pairs_eval(V, *s.S, x, p, alpha, g, dg, feas, nact);
   if (V.nfric > 0) v[0] += fric_eval(V, *s.S, x, p, alpha, g, dg);
   v[1] = (double)nact;
   v[2] = feas ? 0.0 : 1.0;  // max -> any infeasible
   double w[4] = {v[0], v[1], eel, v[2]};
   block_reduce<3, 1>(w, *s.S);
+  tock(*s.S, 6, t0);
   feasible = (w[3] == 0.0);
   nactive = (int)w[1];
   if (e_el) *e_el = w[2];
   return w[0];
 }
 
-__device__ double curvature_all(Solver& s, const double* x, const double* p) {
+__device__ __forceinline__ double curvature_all(Solver& s, const double* x, const double* p) {
   View& V = s.V;
+  unsigned long long t0 = tick();
   double c = elem_curv(V, x, p, *s.T);
+  tock(*s.S, 2, t0);
+  t0 = tick();
   c += pairs_curv(V, *s.S, x, p);
   if (V.nfric > 0) c += fric_curv(V, *s.S, x, p);
   double w[1] = {c};
   block_reduce<1, 0>(w, *s.S);
+  tock(*s.S, 3, t0);
   return w[0];
 }
 
 // P = 1/max(diag, floor) stored in place; p = -P g; returns |Pg|_inf, |p|_inf, g.p
-__device__ void init_direction(Solver& s, const double* g, double& res, double& pinf, double& gp) {
+__device__ __forceinline__ void init_direction(Solver& s, const double* g, double& res, double& pinf, double& gp) {
   View& V = s.V;
   const int n = 3 * V.G->n_v;
   double a[3] = {0.0, 0.0, 0.0};  // sum g.p ; max |Pg| ; (pinf = res)
@@ -873,7 +1092,7 @@ __device__ void init_direction(Solver& s, const double* g, double& res, double& 
 }
 
 // Runs PNCG at the current pose from x. Returns status bits (kConverged etc.).
-__device__ int pncg(Solver& s, double tol, int max_iters, int& iters, double& res_out, double& e_out,
+__device__ __forceinline__ int pncg(Solver& s, double tol, int max_iters, int& iters, double& res_out, double& e_out,
                     int& nactive_out) {
   View& V = s.V;
   const int n = 3 * V.G->n_v;
@@ -881,53 +1100,47 @@ __device__ int pncg(Solver& s, double tol, int max_iters, int& iters, double& re
   double* x = V.x;
   double* g0 = V.g0;
   double* g1 = V.g1;
-  if (!recull(s, x)) return kOverflow;
-  double macc = 0.0;
+  if (!ensure_lists(s, x, 0.0)) return kOverflow;
   int feas, nact;
-  unsigned long long t0 = tick();
+  unsigned long long t0;
   double E0 = eval_all(s, x, V.p, 0.0, g0, V.diag, feas, nact);
-  tock(*s.S, 3, t0);
   nactive_out = nact;
   if (!feas) { iters = 0; return kInfeasible; }
   double res, pinf, gp;
   t0 = tick();
   init_direction(s, g0, res, pinf, gp);
-  tock(*s.S, 4, t0);
+  tock(*s.S, 7, t0);
   int status = 0;
   int k = 0;
   for (;; ++k) {
     if (res <= tol) { status = kConverged; break; }
     if (k >= max_iters) { status = kMaxIter; break; }
     const double a_up = dh / (2.0 * pinf);
-    t0 = tick();
     const double curv = curvature_all(s, x, V.p);
-    tock(*s.S, 1, t0);
     const double a_bar = (curv > 0.0) ? -gp / curv : kInf;
     double alpha = fmin(a_up, a_bar);
-    if (macc + alpha * kSqrt3 * pinf > s.buffer) {
-      if (!recull(s, x)) { status = kOverflow; break; }
-      macc = 0.0;
+    {
+      double m[3];
+      surf_motion(s, x, V.p, m);
+      if (!ensure_lists(s, x, alpha * m[2], m)) { status = kOverflow; break; }
     }
     t0 = tick();
     {
       double w = pairs_ccd(V, *s.S, x, V.p, alpha);
       alpha = block_min(w, *s.S);
     }
-    tock(*s.S, 2, t0);
+    tock(*s.S, 4, t0);
     bool ok = false;
     double E1 = E0;
-    t0 = tick();
     for (int h = 0; h <= kMaxHalvings; ++h) {
       E1 = eval_all(s, x, V.p, alpha, g1, V.diag, feas, nact);
       if (feas && (!s.armijo || E1 <= E0 + kArmijoC * alpha * gp + s.guard)) { ok = true; break; }
       alpha *= 0.5;
       ++s.halvings;
     }
-    tock(*s.S, 3, t0);
     t0 = tick();
     if (!ok) { status = kLineSearch; break; }
     nactive_out = nact;
-    macc += alpha * kSqrt3 * pinf;
     // dots: x += alpha p ; P1 ; y = g1 - g0
     double a[6] = {0, 0, 0, 0, 0, 0};  // gPy, yPy, yp, pg1, gPg | max|Pg1|
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
@@ -969,7 +1182,7 @@ __device__ int pncg(Solver& s, double tol, int max_iters, int& iters, double& re
     }
     E0 = E1;
     double* tmp = g0; g0 = g1; g1 = tmp;
-    tock(*s.S, 4, t0);
+    tock(*s.S, 7, t0);
   }
   iters = k;
   res_out = res;
@@ -982,7 +1195,7 @@ __device__ int pncg(Solver& s, double tol, int max_iters, int& iters, double& re
   return status;
 }
 
-__device__ void make_view(const StepParams& P, int e, View& V) {
+__device__ __forceinline__ void make_view(const StepParams& P, int e, View& V) {
   const EnvDev& E = P.envs[e];
   V.E = &E;
   V.G = &P.gels[E.gel];
@@ -994,13 +1207,16 @@ __device__ void make_view(const StepParams& P, int e, View& V) {
   V.diag = P.diag + E.voff;
   V.p = P.p + E.voff;
   V.pairs = P.pairs + E.poff;
+  V.pd = P.pair_d + E.poff;
+  V.outer = P.outer + E.ooff;
+  V.nouter = 0;
   V.fric = P.fric + E.foff;
   V.npairs = 0;
   V.nfric = 0;
   V.mixed = P.precision;
 }
 
-__device__ void init_solver(Solver& s, const StepParams& P, Shared& S, Tile& T) {
+__device__ __forceinline__ void init_solver(Solver& s, const StepParams& P, Shared& S, Tile& T) {
   const EnvDev& E = *s.V.E;
   const GelDev& G = *s.V.G;
   s.S = &S;
@@ -1008,13 +1224,18 @@ __device__ void init_solver(Solver& s, const StepParams& P, Shared& S, Tile& T) 
   s.floor_d = kDiagFloor * E.mu * G.diag_rest_max;
   s.guard = (P.precision ? kEnergyGuard32 : kEnergyGuard64) * E.mu * G.vol_total;
   s.buffer = E.dhat;
+  s.buffer_out = 4.0 * E.dhat;
   s.armijo = P.armijo;
   s.pair_cap = E.pair_cap;
   s.fric_cap = E.fric_cap;
-  s.reculls = s.restarts = s.halvings = s.ncand = 0;
+  s.outer_cap = E.outer_cap;
+  s.L = P.lists + (&E - P.envs);
+  s.xs_o = P.xsnap + E.snoff;
+  s.xs_i = P.xsnap + E.snoff + 3 * (long long)G.n_sv;
+  s.reculls = s.restarts = s.halvings = s.ncand = s.outer_builds = 0;
 }
 
-__device__ void write_outputs(const StepParams& P, int e, const View& V) {
+__device__ __forceinline__ void write_outputs(const StepParams& P, int e, const View& V) {
   const GelDev& G = *V.G;
   const int nv = G.n_v;
   if (P.markers_out) {
@@ -1045,7 +1266,10 @@ __device__ void write_outputs(const StepParams& P, int e, const View& V) {
 
 using namespace t2r;
 
-__global__ void __launch_bounds__(256) t2r_step_kernel(StepParams P) {
+// Two workgroups of 256 threads (or one of 512) per CU: 2 waves per SIMD, which
+// the register budget of the fully inlined step allows without spilling.
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel(StepParams P) {
   __shared__ Shared S;
   __shared__ Tile T;
   const int e = blockIdx.x;
@@ -1059,13 +1283,14 @@ __global__ void __launch_bounds__(256) t2r_step_kernel(StepParams P) {
   const EnvDev& E = *V.E;
   const int n = 3 * G.n_v;
   const unsigned long long t_start = tick();
-  if (threadIdx.x < 6) S.tacc[threadIdx.x] = 0ull;
+  if (threadIdx.x < 10) S.tacc[threadIdx.x] = 0ull;
   __syncthreads();
   EnvStats st;
   st.status = 0; st.iters = 0; st.substeps = 0; st.restarts = 0; st.halvings = 0; st.reculls = 0;
   st.n_candidates = 0; st.n_active = 0; st.n_friction = 0; st.max_solve_iters = 0;
+  st.outer_builds = 0; st.pad = 0;
   st.d_min = kInf; st.residual = 0.0; st.energy = 0.0;
-  for (int k = 0; k < 6; ++k) st.phase_ms[k] = 0.0;
+  for (int k = 0; k < 10; ++k) st.phase_ms[k] = 0.0;
 
   double* pose_prev = P.pose_prev + 7 * e;
   double q0[7], q1[7];
@@ -1083,15 +1308,23 @@ __global__ void __launch_bounds__(256) t2r_step_kernel(StepParams P) {
   }
   // keep x_{s-1} for the friction lag and for rollback
   for (int j = threadIdx.x; j < n; j += blockDim.x) V.xprev[j] = V.x[j];
-  // friction lag and starting distance at (x_{s-1}, q_{s-1})
+  // friction lag and starting distance at (x_{s-1}, q_{s-1}), from the outer
+  // list kept since the last step (rebuilt here if the motion since it was
+  // built exceeds its margin)
   if (threadIdx.x == 0) set_pose(S, I, q0);
   __syncthreads();
+  load_lists(s);
   double dmin_start;
-  {
+  if (!ensure_lists(s, V.x, 0.0)) {
+    st.status |= kOverflow;
+    dmin_start = 0.0;
+  } else {
     const int mode = (E.mu_f > 0.0) ? 1 : 2;
-    double dm = cull(V, S, V.x, E.dhat, mode, s.fric_cap);
+    const unsigned long long t0 = tick();
+    double dm = lag_from_outer(s, V.x, mode);
     const int cnt = S.count, ov = S.overflow;
     dmin_start = block_min(dm, S);
+    tock(S, 9, t0);
     V.nfric = (mode == 1) ? min(cnt, s.fric_cap) : 0;
     if (ov) st.status |= kOverflow;
   }
@@ -1162,13 +1395,14 @@ __global__ void __launch_bounds__(256) t2r_step_kernel(StepParams P) {
   st.restarts = s.restarts;
   st.halvings = s.halvings;
   st.reculls = s.reculls;
+  st.outer_builds = s.outer_builds;
   st.n_candidates = s.ncand;
   st.residual = res;
   st.energy = energy;
   write_outputs(P, e, V);
   if (threadIdx.x == 0) {
-    S.tacc[5] = wall_clock64() - t_start;
-    for (int k = 0; k < 6; ++k) st.phase_ms[k] = (double)S.tacc[k] / P.clock_khz;
+    S.tacc[8] = wall_clock64() - t_start;
+    for (int k = 0; k < 10; ++k) st.phase_ms[k] = (double)S.tacc[k] / P.clock_khz;
     P.stats[e] = st;
     if (P.status_out) P.status_out[e] = st.status;
   }
@@ -1187,16 +1421,18 @@ __global__ void __launch_bounds__(256) t2r_eval_kernel(EvalParams Q) {
   const IndDev& I = *V.I;
   const EnvDev& E = *V.E;
   const int nv = G.n_v;
+  load_lists(s);
   if (Q.has_lag && E.mu_f > 0.0) {
     if (threadIdx.x == 0) set_pose(S, I, Q.pose_lag);
     __syncthreads();
-    cull(V, S, V.xprev, E.dhat, 1, s.fric_cap);
+    ensure_lists(s, V.xprev, 0.0);
+    lag_from_outer(s, V.xprev, 1);
     V.nfric = min(S.count, s.fric_cap);
     __syncthreads();
   }
   if (threadIdx.x == 0) set_pose(S, I, Q.pose);
   __syncthreads();
-  recull(s, V.x);
+  ensure_lists(s, V.x, 0.0);
   int feas, nact;
   double eel = 0.0;
   const double Etot = eval_all(s, V.x, V.p, 0.0, V.g0, V.diag, feas, nact, &eel);
@@ -1256,7 +1492,12 @@ __global__ void t2r_aos_to_soa_kernel(const double* in, double* out, int nv) {
 }
 
 extern "C" hipError_t t2r_launch_step(const StepParams* p, int block, hipStream_t stream) {
-  hipLaunchKernelGGL(t2r_step_kernel, dim3(p->n_env), dim3(block), 0, stream, *p);
+  if (block == 512)
+    hipLaunchKernelGGL(t2r_step_kernel<512>, dim3(p->n_env), dim3(512), 0, stream, *p);
+  else if (block == 256)
+    hipLaunchKernelGGL(t2r_step_kernel<256>, dim3(p->n_env), dim3(256), 0, stream, *p);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ namespace t2r {
 // entry to emit(i, a, grad, diag) as soon as it is known, so that no per-tet
 // array of 24 results stays live in registers. Returns false for J <= 0.
 template <typename T, typename Emit>
-__device__ inline bool tet_grad_diag(const T Ds[9], const T Dm[9], T V, T mu, T lam, T& energy,
+__device__ __forceinline__ bool tet_grad_diag(const T Ds[9], const T Dm[9], T V, T mu, T lam, T& energy,
                                      Emit&& emit) {
   // Ds[a*3+k] = (x_{k+1} - x_0)_a ; F = Ds Dm
   T F[9];
@@ -86,7 +86,7 @@ __device__ inline bool tet_grad_diag(const T Ds[9], const T Dm[9], T V, T mu, T 
 }
 
 template <typename T>
-__device__ inline T tet_curvature(const T Ds[9], const T dDs[9], const T Dm[9], T V, T mu, T lam) {
+__device__ __forceinline__ T tet_curvature(const T Ds[9], const T dDs[9], const T Dm[9], T V, T mu, T lam) {
   T F[9], dF[9];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -134,7 +134,7 @@ __device__ inline T tet_curvature(const T Ds[9], const T dDs[9], const T Dm[9], 
 // IPC log barrier on the unsquared distance (Supp. A, eq. ipc_energy):
 //   b(d) = -(d - dh)^2 ln(d / dh) on (0, dh), 0 beyond.
 // ---------------------------------------------------------------------------
-__device__ inline void barrier3(double d, double dh, double& b, double& b1, double& b2) {
+__device__ __forceinline__ void barrier3(double d, double dh, double& b, double& b1, double& b2) {
   const double e = d - dh;
   const double l = log(d / dh);
   b = -e * e * l;
@@ -145,7 +145,7 @@ __device__ inline void barrier3(double d, double dh, double& b, double& b1, doub
 // Friction mollifier (Supp. A, eq. friction_mollifier) pieces at s >= 0:
 //   f(s), f'(s)/s, and (f''(s) - f'(s)/s)/s^2 * s^2 / s  written as `corr` so that
 //   Hess_Delta = mulam [ fos T + corr uhat uhat^T ] with uhat = T Delta / s.
-__device__ inline void mollifier3(double s, double eps, double& f, double& fos, double& corr) {
+__device__ __forceinline__ void mollifier3(double s, double eps, double& f, double& fos, double& corr) {
   if (s < eps) {
     f = -s * s * s / (3.0 * eps * eps) + s * s / eps + eps / 3.0;
     fos = -s / (eps * eps) + 2.0 / eps;
@@ -176,14 +176,14 @@ struct Feature {
   int k;
 };
 
-__device__ inline double dot3(const double a[3], const double b[3]) {
+__device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
 // Point p against triangle (a, b, c) by Voronoi-region tests of the closest
 // point (Ericson, Real-Time Collision Detection, 2005, Sec. 5.1.5).
 // Point order: z0 = p, z1 = a, z2 = b, z3 = c; r = p - closest.
-__device__ inline void classify_pt(const double p[3], const double a[3], const double b[3],
+__device__ __forceinline__ void classify_pt(const double p[3], const double a[3], const double b[3],
                                    const double c[3], Feature& f) {
   double ab[3], ac[3], ap[3], bp[3], cp[3];
 #pragma unroll
@@ -245,7 +245,7 @@ constexpr double kParallelSin2 = 1e-14;
 
 // Segments [a0,a1] and [b0,b1]: clamped closest points (Ericson 2005, Sec. 5.1.9).
 // Point order: z0 = a0, z1 = a1, z2 = b0, z3 = b1; r = (a0 + s e_a) - (b0 + t e_b).
-__device__ inline void classify_ee(const double a0[3], const double a1[3], const double b0[3],
+__device__ __forceinline__ void classify_ee(const double a0[3], const double a1[3], const double b0[3],
                                    const double b1[3], Feature& f) {
   double d1[3], d2[3], r[3];
 #pragma unroll
@@ -275,14 +275,17 @@ __device__ inline void classify_ee(const double a0[3], const double a1[3], const
   for (int i = 0; i < 4; ++i) f.cw[i][0] = f.cw[i][1] = 0.0;
   const bool si = (s > 0.0) && (s < 1.0);
   const bool ti = (t > 0.0) && (t < 1.0);
-  int k = 0;
-  if (si) { f.cw[0][k] = -1.0; f.cw[1][k] = 1.0; ++k; }
-  if (ti) { f.cw[2][k] = 1.0; f.cw[3][k] = -1.0; ++k; }
-  f.k = k;
+  // free parameters in order (s first): constant indices only, no dynamic indexing
+  if (si) { f.cw[0][0] = -1.0; f.cw[1][0] = 1.0; }
+  if (ti) {
+    if (si) { f.cw[2][1] = 1.0; f.cw[3][1] = -1.0; }
+    else { f.cw[2][0] = 1.0; f.cw[3][0] = -1.0; }
+  }
+  f.k = (si ? 1 : 0) + (ti ? 1 : 0);
 }
 
 // Inverse of the k x k Gram matrix M (k <= 2); returns false if singular.
-__device__ inline bool gram_inverse(const double D[2][3], int k, double Mi[2][2]) {
+__device__ __forceinline__ bool gram_inverse(const double D[2][3], int k, double Mi[2][2]) {
   Mi[0][0] = Mi[0][1] = Mi[1][0] = Mi[1][1] = 0.0;
   if (k == 0) return true;
   const double m00 = dot3(D[0], D[0]);

@@ -35,8 +35,9 @@ class EnvStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("substeps", C.c_int32),
                 ("restarts", C.c_int32), ("halvings", C.c_int32), ("reculls", C.c_int32),
                 ("n_candidates", C.c_int32), ("n_active", C.c_int32), ("n_friction", C.c_int32),
-                ("max_solve_iters", C.c_int32), ("d_min", C.c_double), ("residual", C.c_double),
-                ("energy", C.c_double), ("phase_ms", C.c_double * 6)]
+                ("max_solve_iters", C.c_int32), ("outer_builds", C.c_int32),
+                ("reserved", C.c_int32), ("d_min", C.c_double), ("residual", C.c_double),
+                ("energy", C.c_double), ("phase_ms", C.c_double * 10)]
 
 
 class T2RError(RuntimeError):

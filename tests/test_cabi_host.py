@@ -95,7 +95,7 @@ def test_invalid_inputs_are_rejected_on_the_host():
 
 def test_invalid_options_are_rejected():
     t2r = _t2r()
-    for kw in ({"tol": 0.0}, {"precision": 3}, {"block_size": 100}, {"max_substeps": 0}):
+    for kw in ({"tol": 0.0}, {"precision": 3}, {"block_size": 100}, {"block_size": 1024}, {"max_substeps": 0}):
         with pytest.raises(t2r.T2RError):
             t2r.Context(t2r.default_opts(**kw))
     o = t2r.default_opts()

@@ -211,3 +211,17 @@ def test_pair_overflow_rolls_back():
     # every step overflowed, so the env is still at rest with its starting pose
     assert np.array_equal(st[:3 * 484].reshape(-1, 3), w.meshes["c1"].X)
     assert np.array_equal(st[3 * 484:], poses[0, 0])
+
+
+def test_mixed_precision_sequence_within_1e3_mm_of_oracle():
+    # FP32 element terms, FP64 accumulation, distances, CCD and dot products
+    t2r = _gpu()
+    from scenes.configs import sphere_press_484v
+    w = sphere_press_484v()
+    gold = np.load(os.path.join(HERE, "golden", "sphere_press_484v_newton.npz"))
+    sim = _build(t2r, w, tol=1e-6, precision=1)
+    poses = np.stack([e.poses for e in w.envs])
+    m, x, st = _run_steps(sim, poses, want_x=True)
+    assert np.all(st & 1), st
+    assert np.abs(m - gold["markers"]).max() <= 1e-3
+    assert np.abs(x - gold["x"]).max() <= 1e-3
