@@ -52,7 +52,7 @@ def test_surface_and_markers_agree_with_oracle(name):
     assert np.allclose(ref_lib, geo.marker_ref, atol=1e-12)
     assert np.all(w >= -1e-12) and np.allclose(w.sum(axis=1), 1.0)
     # every tet lands in exactly one tile, tiles respect the LDS limits
-    assert info["n_tiles"] >= g.n_tets // 512
+    assert info["n_tiles"] >= -(-g.n_tets // 1024)  # at most 1024 tets per tile
 
 
 def test_invalid_inputs_are_rejected_on_the_host():
