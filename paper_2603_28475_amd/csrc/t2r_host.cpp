@@ -468,6 +468,67 @@ t2r_status t2r_add_gel(t2r_ctx* c, int32_t n_v, const double* X, int32_t n_t, co
       order[e] = {spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2), e};
     }
     std::stable_sort(order.begin(), order.end());
+    // tile boundaries: greedy cuts along the Morton order
+    std::vector<int> bounds(1, 0);
+    {
+      std::unordered_map<int, int> seen;
+      int cnt = 0;
+      for (int i = 0; i < n_t; ++i) {
+        const int e = order[i].second;
+        int newv = 0;
+        for (int k = 0; k < 4; ++k)
+          if (!seen.count(tets[4 * (size_t)e + k])) ++newv;
+        if (cnt == kTileTets || (int)seen.size() + newv > kTileVerts) {
+          bounds.push_back(i);
+          seen.clear();
+          cnt = 0;
+        }
+        for (int k = 0; k < 4; ++k) seen.emplace(tets[4 * (size_t)e + k], 0);
+        ++cnt;
+      }
+      bounds.push_back(n_t);
+    }
+    // inside each tile, deal tets into groups of 64 (one wavefront's lanes) so that
+    // no vertex appears twice at the same tet-vertex slot within a group: the LDS
+    // atomics of one instruction then never collide on an address
+    {
+      std::vector<std::pair<uint32_t, int>> reordered;
+      reordered.reserve(n_t);
+      for (size_t t = 0; t + 1 < bounds.size(); ++t) {
+        const int b0 = bounds[t], b1 = bounds[t + 1];
+        std::vector<int> rest;
+        for (int i = b0; i < b1; ++i) rest.push_back(i);
+        // fill each group of 64 in turn with the earliest tets that do not clash
+        // with it; full groups keep every wavefront aligned with a group
+        while (!rest.empty()) {
+          std::array<std::vector<int>, 4> used;
+          std::vector<int> take, keep;
+          for (int i : rest) {
+            const int e = order[i].second;
+            bool ok = (int)take.size() < 64;
+            for (int k = 0; k < 4 && ok; ++k) {
+              const int v = tets[4 * (size_t)e + k];
+              for (int u : used[k])
+                if (u == v) { ok = false; break; }
+            }
+            if (ok) {
+              take.push_back(i);
+              for (int k = 0; k < 4; ++k) used[k].push_back(tets[4 * (size_t)e + k]);
+            } else {
+              keep.push_back(i);
+            }
+          }
+          // not enough clash-free tets left: top the group up in order
+          while ((int)take.size() < 64 && !keep.empty()) {
+            take.push_back(keep.front());
+            keep.erase(keep.begin());
+          }
+          for (int i : take) reordered.push_back(order[i]);
+          rest.swap(keep);
+        }
+      }
+      order.swap(reordered);
+    }
     g.tet.resize(4 * (size_t)n_t);
     g.tet_local.resize(n_t);
     g.Dinv.resize(9 * (size_t)n_t);
@@ -487,12 +548,13 @@ t2r_status t2r_add_gel(t2r_ctx* c, int32_t n_v, const double* X, int32_t n_t, co
       tile_v.clear();
       in_tile = 0;
     };
+    size_t next_bound = 1;
     for (int i = 0; i < n_t; ++i) {
       const int e = order[i].second;
-      int newv = 0;
-      for (int k = 0; k < 4; ++k)
-        if (!local.count(tets[4 * (size_t)e + k])) ++newv;
-      if (in_tile == kTileTets || (int)tile_v.size() + newv > kTileVerts) close_tile(i);
+      if (i == bounds[next_bound] && i > 0) {
+        close_tile(i);
+        ++next_bound;
+      }
       uint64_t loc = 0;
       for (int k = 0; k < 4; ++k) {
         const int v = tets[4 * (size_t)e + k];
