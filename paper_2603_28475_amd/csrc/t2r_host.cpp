@@ -193,7 +193,7 @@ void build_grid(IndHost::GridHost& G, const std::vector<std::array<double, 6>>& 
   for (int a = 0; a < 3; ++a) {
     G.origin[a] = lo[a] - 1e-9 * (1.0 + fabs(lo[a]));
     const double ext = hi[a] + 1e-9 * (1.0 + fabs(hi[a])) - G.origin[a];
-    G.dims[a] = std::max(1, std::min(64, (int)ceil(ext / cell)));
+    G.dims[a] = std::max(1, std::min(96, (int)ceil(ext / cell)));
   }
   // one inverse cell size for all axes: cover the largest extent
   double cmax = 0.0;
@@ -674,7 +674,9 @@ t2r_status t2r_add_indenter(t2r_ctx* c, int32_t n_v, const double* Y, int32_t n_
   }
   mean_e /= std::max(1, I.n_e);
   const double ext = std::max({I.hi[0] - I.lo[0], I.hi[1] - I.lo[1], I.hi[2] - I.lo[2]});
-  const double cell = std::max(mean_e, ext / 64.0);
+  // cells of about half the mean edge: a query then tests few primitives beyond
+  // its own box; at most 96 cells per axis
+  const double cell = std::max(0.5 * mean_e, ext / 96.0);
   auto box_of = [&](const int* ids, int k) {
     std::array<double, 6> b;
     for (int a = 0; a < 3; ++a) { b[a] = 1e300; b[3 + a] = -1e300; }

@@ -25,8 +25,7 @@ namespace t2r {
 
 constexpr double kInf = 1.0e300;
 constexpr double kArmijoC = 1e-4;
-constexpr double kEnergyGuard64 = 1e-13;   // x mu * total volume
-constexpr double kEnergyGuard32 = 1e-6;
+constexpr double kEnergyGuard = 1e-13;     // x mu * total volume (energies are FP64 in both modes)
 constexpr double kDiagFloor = 1e-12;       // x mu * largest rest diagonal (mu = 1 part)
 constexpr double kYpMin = 1e-30;
 constexpr int kMaxHalvings = 30;
@@ -223,36 +222,31 @@ __device__ __forceinline__ double elem_eval(const View& V, const double* x, cons
 #pragma unroll
       for (int k = 0; k < 4; ++k) l[k] = (int)((loc >> (16 * k)) & 0xffff);
       bool ok;
+      double Ds[9];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Ds[a * 3 + k] = T.x[a][l[k + 1]] - T.x[a][l[0]];
+      double ed = 0.0;
       if (V.mixed) {
-        float Ds[9], Dm[9];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int k = 0; k < 3; ++k) Ds[a * 3 + k] = (float)(T.x[a][l[k + 1]] - T.x[a][l[0]]);
+        float Dm[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) Dm[k] = G.Dinv32[k * G.n_t + e];
-        float ef = 0.0f;
-        ok = tet_grad_diag<float>(Ds, Dm, G.vol32[e], (float)E.mu, (float)E.lam, ef,
-                                  [&](int k, int c, float gv, float dv) {
-                                    atomicAdd(&T.g[c][l[k]], (double)gv);
-                                    atomicAdd(&T.d[c][l[k]], (double)dv);
-                                  });
-        if (ok) energy += (double)ef;
+        ok = tet_grad_diag_mixed(Ds, Dm, G.vol32[e], E.mu, E.lam, ed,
+                                 [&](int k, int c, float gv, float dv) {
+                                   atomicAdd(&T.g[c][l[k]], (double)gv);
+                                   atomicAdd(&T.d[c][l[k]], (double)dv);
+                                 });
       } else {
-        double Ds[9], Dm[9];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int k = 0; k < 3; ++k) Ds[a * 3 + k] = T.x[a][l[k + 1]] - T.x[a][l[0]];
+        double Dm[9];
         load_Dm(G, e, Dm);
-        double ed = 0.0;
-        ok = tet_grad_diag<double>(Ds, Dm, G.vol[e], E.mu, E.lam, ed,
-                                   [&](int k, int c, double gv, double dv) {
-                                     atomicAdd(&T.g[c][l[k]], gv);
-                                     atomicAdd(&T.d[c][l[k]], dv);
-                                   });
-        if (ok) energy += ed;
+        ok = tet_grad_diag64(Ds, Dm, G.vol[e], E.mu, E.lam, ed,
+                             [&](int k, int c, double gv, double dv) {
+                               atomicAdd(&T.g[c][l[k]], gv);
+                               atomicAdd(&T.d[c][l[k]], dv);
+                             });
       }
+      if (ok) energy += ed;
       if (!ok) feasible = 0;
     }
     __syncthreads();
@@ -1222,9 +1216,9 @@ __device__ __forceinline__ void init_solver(Solver& s, const StepParams& P, Shar
   s.S = &S;
   s.T = &T;
   s.floor_d = kDiagFloor * E.mu * G.diag_rest_max;
-  s.guard = (P.precision ? kEnergyGuard32 : kEnergyGuard64) * E.mu * G.vol_total;
+  s.guard = kEnergyGuard * E.mu * G.vol_total;
   s.buffer = E.dhat;
-  s.buffer_out = 4.0 * E.dhat;
+  s.buffer_out = 6.0 * E.dhat;
   s.armijo = P.armijo;
   s.pair_cap = E.pair_cap;
   s.fric_cap = E.fric_cap;

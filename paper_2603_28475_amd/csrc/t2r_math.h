@@ -17,22 +17,14 @@ namespace t2r {
 //   p^T H_e p   = V [mu |dF|^2 + (mu - lam ln J) tr((F^-1 dF)^2) + lam (tr F^-1 dF)^2]
 // ---------------------------------------------------------------------------
 
-// Evaluates one tet and hands each (vertex i, axis a) gradient and diagonal
-// entry to emit(i, a, grad, diag) as soon as it is known, so that no per-tet
-// array of 24 results stays live in registers. Returns false for J <= 0.
+// Gradient and diagonal of one tet from its deformation gradient F (with
+// ln J given), handed to emit(i, a, grad, diag) per (vertex i, axis a) as soon
+// as each is known, so no per-tet array of 24 results stays live. F is
+// overwritten.
 template <typename T, typename Emit>
-__device__ __forceinline__ bool tet_grad_diag(const T Ds[9], const T Dm[9], T V, T mu, T lam, T& energy,
-                                     Emit&& emit) {
-  // Ds[a*3+k] = (x_{k+1} - x_0)_a ; F = Ds Dm
-  T F[9];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-      F[a * 3 + b] = Ds[a * 3 + 0] * Dm[0 * 3 + b] + Ds[a * 3 + 1] * Dm[1 * 3 + b] +
-                     Ds[a * 3 + 2] * Dm[2 * 3 + b];
-  // cofactor matrix C (C = J F^-T)
-  T C[9];
+__device__ __forceinline__ void tet_grad_diag_from_F(T F[9], const T Dm[9], T V, T mu, T lam, T lnJ,
+                                                     Emit&& emit) {
+  T C[9];  // cofactor matrix, J F^-T
   C[0] = F[4] * F[8] - F[5] * F[7];
   C[1] = F[5] * F[6] - F[3] * F[8];
   C[2] = F[3] * F[7] - F[4] * F[6];
@@ -42,14 +34,7 @@ __device__ __forceinline__ bool tet_grad_diag(const T Ds[9], const T Dm[9], T V,
   C[6] = F[1] * F[5] - F[2] * F[4];
   C[7] = F[2] * F[3] - F[0] * F[5];
   C[8] = F[0] * F[4] - F[1] * F[3];
-  const T J = F[0] * C[0] + F[1] * C[1] + F[2] * C[2];
-  if (!(J > T(0))) return false;
-  const T invJ = T(1) / J;
-  const T lnJ = log(J);
-  T I1 = T(0);
-#pragma unroll
-  for (int k = 0; k < 9; ++k) I1 += F[k] * F[k];
-  energy = V * (T(0.5) * mu * (I1 - T(3)) - mu * lnJ + T(0.5) * lam * lnJ * lnJ);
+  const T invJ = T(1) / (F[0] * C[0] + F[1] * C[1] + F[2] * C[2]);
   // reuse F for V P and C for F^-T
   const T cP = lam * lnJ - mu;
 #pragma unroll
@@ -82,6 +67,51 @@ __device__ __forceinline__ bool tet_grad_diag(const T Ds[9], const T Dm[9], T V,
       emit(0, a, -(a == 0 ? gs0 : (a == 1 ? gs1 : gs2)), gg + cd * w * w);
     }
   }
+}
+
+// FP64 deformation gradient F = Ds Dm, J = det F and ln J; false for J <= 0.
+// Returns the FP64 energy V psi(F) in `energy`.
+template <typename TD>
+__device__ __forceinline__ bool tet_F_energy(const double Ds[9], const TD Dm[9], double V, double mu,
+                                             double lam, double F[9], double& lnJ, double& energy) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      F[a * 3 + b] = Ds[a * 3 + 0] * (double)Dm[0 * 3 + b] + Ds[a * 3 + 1] * (double)Dm[1 * 3 + b] +
+                     Ds[a * 3 + 2] * (double)Dm[2 * 3 + b];
+  const double J = F[0] * (F[4] * F[8] - F[5] * F[7]) + F[1] * (F[5] * F[6] - F[3] * F[8]) +
+                   F[2] * (F[3] * F[7] - F[4] * F[6]);
+  if (!(J > 0.0)) return false;
+  lnJ = log(J);
+  double I1 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) I1 += F[k] * F[k];
+  energy = V * (0.5 * mu * (I1 - 3.0) - mu * lnJ + 0.5 * lam * lnJ * lnJ);
+  return true;
+}
+
+// FP64 tet: energy, gradient and diagonal all in double.
+template <typename Emit>
+__device__ __forceinline__ bool tet_grad_diag64(const double Ds[9], const double Dm[9], double V, double mu,
+                                                double lam, double& energy, Emit&& emit) {
+  double F[9], lnJ;
+  if (!tet_F_energy(Ds, Dm, V, mu, lam, F, lnJ, energy)) return false;
+  tet_grad_diag_from_F<double>(F, Dm, V, mu, lam, lnJ, emit);
+  return true;
+}
+
+// Mixed tet: F, J, ln J and the energy in double (the line search compares
+// energies), gradient and diagonal in float from the rounded F.
+template <typename Emit>
+__device__ __forceinline__ bool tet_grad_diag_mixed(const double Ds[9], const float Dm[9], float V, double mu,
+                                                    double lam, double& energy, Emit&& emit) {
+  double F[9], lnJ;
+  if (!tet_F_energy(Ds, Dm, (double)V, mu, lam, F, lnJ, energy)) return false;
+  float F32[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) F32[k] = (float)F[k];
+  tet_grad_diag_from_F<float>(F32, Dm, V, (float)mu, (float)lam, (float)lnJ, emit);
   return true;
 }
 
