@@ -32,15 +32,17 @@ BYTES_PER_VERT_ITER = 384  # 16 vector passes x 3 coords x 8 B per PNCG iteratio
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=19)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--envs", type=int, default=2048)
-    ap.add_argument("--precision", choices=["f64", "mixed"], default="f64")
+    ap.add_argument("--precision", choices=["f64", "mixed"], default="mixed")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--plain-envs", type=int, default=8, help="envs timed one launch each (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle budget (0: skip)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -107,6 +109,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        # a plain copy kernel of known size: 1 GiB read + 1 GiB written per launch
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8}))
+        return
     W, K = args.warmup, args.steps
     n_steps = W + K
     workload = peg_batch_5k(n_envs=args.envs, n_steps=20, precision=args.precision)
