@@ -84,7 +84,9 @@ typedef struct { double E, nu, mu_f, eps_v, dhat, kappa; } t2r_material;
  *   max_iters     PNCG iterations per solve
  *   max_substeps  continuation solves per load step
  *   precision     0: all FP64; 1: FP32 element terms, FP64 elsewhere
- *   pair_capacity contact candidate pairs per env (0: automatic)
+ *   pair_capacity contact candidate pairs per env (0: automatic, 3x the gel's
+ *                 surface vertices + edges + faces, at least 8192); the coarse
+ *                 list holds 4x and the friction list 1/2 of it
  *   armijo        1: require sufficient decrease of Pi in the line search
  *   block_size    threads per env workgroup: 256 (two envs per CU) or 512 (one env
  *                 per CU, for few large envs); 0 = 256 */
@@ -206,7 +208,8 @@ t2r_status t2r_step(t2r_ctx* ctx, const double* d_pose, const int32_t* d_env_mas
  *                        the Hessian (fixed vertices: 0 and 1)
  *   d_scalars            device [8] or NULL: Pi, p^T H p, d_min, active pairs,
  *                        feasible (1/0), candidate pairs, friction pairs, Pi_elastic
- * Synchronises the stream before returning. */
+ * Synchronises the stream before returning. Returns T2R_E_NOMEM (outputs not
+ * written) when the env's contact pair lists exceed their capacity. */
 t2r_status t2r_eval(t2r_ctx* ctx, int32_t env, const double* d_x, const double* d_p,
                     const double* d_x_lag, const double* pose, const double* pose_lag,
                     double* d_grad, double* d_diag, double* d_scalars);

@@ -94,6 +94,10 @@ struct t2r_ctx {
   ListState* d_lists = nullptr;
   double* d_xsnap = nullptr;
   FricPair* d_fric = nullptr;
+  int* d_vmap = nullptr;
+  uint64_t* d_oslot = nullptr;
+  uint64_t* d_pslot = nullptr;
+  int* d_slot_v = nullptr;
   EnvStats* d_stats = nullptr;
   long long* d_xout_off = nullptr;
   long long* d_state_off = nullptr;
@@ -592,7 +596,8 @@ t2r_status t2r_add_gel(t2r_ctx* c, int32_t n_v, const double* X, int32_t n_t, co
     for (int t = 0; t < ntiles; ++t)
       for (int j = g.tile_vstart[t]; j < g.tile_vstart[t + 1]; ++j) {
         const int v = g.tile_verts[j];
-        g.tile_flags[j] = (first[v] == t ? kFirstTouch : 0) | (last[v] == t ? kLastTouch : 0);
+        g.tile_flags[j] = (first[v] == t ? kFirstTouch : 0) | (last[v] == t ? kLastTouch : 0) |
+                         (last[v] == t && g.fixed[v] ? kFixedLast : 0);
       }
   }
   c->gels.push_back(std::move(g));
@@ -766,6 +771,10 @@ static StepParams step_params(t2r_ctx* c) {
   P.lists = c->d_lists;
   P.xsnap = c->d_xsnap;
   P.fric = c->d_fric;
+  P.vmap = c->d_vmap;
+  P.oslot = c->d_oslot;
+  P.pslot = c->d_pslot;
+  P.slot_v = c->d_slot_v;
   P.stats = c->d_stats;
   P.x_out_off = c->d_xout_off;
   P.clock_khz = c->clock_khz;
@@ -817,6 +826,7 @@ t2r_status t2r_eval(t2r_ctx* c, int32_t env, const double* d_x, const double* d_
   ed.moff = 0;
   ed.ooff = 0;
   ed.snoff = 0;
+  ed.vtxoff = 0;
   // scratch (freed before returning)
   std::vector<void*> tmp;
   auto talloc = [&](size_t b) -> void* {
@@ -849,13 +859,18 @@ t2r_status t2r_eval(t2r_ctx* c, int32_t env, const double* d_x, const double* d_
   EnvDev* senv = (EnvDev*)talloc(sizeof(EnvDev));
   double* sposes = (double*)talloc(14 * sizeof(double));
   EnvStats* sstats = (EnvStats*)talloc(sizeof(EnvStats));
-  if (tmp.size() != 15) { tfree(); return fail(c, T2R_E_NOMEM, "scratch allocation failed"); }
+  int* svmap = (int*)talloc((size_t)nv * sizeof(int));
+  uint64_t* soslot = (uint64_t*)talloc((size_t)ed.outer_cap * sizeof(uint64_t));
+  uint64_t* spslot = (uint64_t*)talloc((size_t)ed.pair_cap * sizeof(uint64_t));
+  int* sslot_v = (int*)talloc((size_t)kContactSlots * sizeof(int));
+  if (tmp.size() != 19) { tfree(); return fail(c, T2R_E_NOMEM, "scratch allocation failed"); }
   double hp[14];
   for (int k = 0; k < 7; ++k) { hp[k] = pose[k]; hp[7 + k] = (pose_lag ? pose_lag[k] : pose[k]); }
   hipError_t he = hipSuccess;
   he = hipMemcpyAsync(senv, &ed, sizeof(EnvDev), hipMemcpyHostToDevice, c->stream);
   if (he == hipSuccess) he = hipMemcpyAsync(sposes, hp, sizeof hp, hipMemcpyHostToDevice, c->stream);
   if (he == hipSuccess) he = hipMemsetAsync(slists, 0, sizeof(ListState), c->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(svmap, 0, (size_t)nv * sizeof(int), c->stream);
   if (he == hipSuccess) he = t2r_launch_aos_to_soa(d_x, sx, nv, c->stream);
   if (he == hipSuccess && d_p) he = t2r_launch_aos_to_soa(d_p, sp, nv, c->stream);
   if (he == hipSuccess && !d_p) he = hipMemsetAsync(sp, 0, vb, c->stream);
@@ -877,6 +892,10 @@ t2r_status t2r_eval(t2r_ctx* c, int32_t env, const double* d_x, const double* d_
   Q.sp.lists = slists;
   Q.sp.xsnap = ssnap;
   Q.sp.fric = sfric;
+  Q.sp.vmap = svmap;
+  Q.sp.oslot = soslot;
+  Q.sp.pslot = spslot;
+  Q.sp.slot_v = sslot_v;
   Q.sp.stats = sstats;
   Q.env = 0;
   Q.pose = sposes;
@@ -887,9 +906,14 @@ t2r_status t2r_eval(t2r_ctx* c, int32_t env, const double* d_x, const double* d_
   Q.diag_out = d_diag;
   Q.scalars_out = d_scalars;
   he = t2r_launch_eval(&Q, 256, c->stream);
+  int32_t est = 0;
+  if (he == hipSuccess) he = hipMemcpyAsync(&est, &sstats->status, sizeof est, hipMemcpyDeviceToHost, c->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
   tfree();
   if (he != hipSuccess) return fail(c, T2R_E_HIP, "eval: %s", hipGetErrorString(he));
+  if (est & T2R_ENV_PAIR_OVERFLOW)
+    return fail(c, T2R_E_NOMEM, "contact pair list capacity %d exceeded (raise it with t2r_set_pair_capacity)",
+                ed.pair_cap);
   c->err.clear();
   return T2R_OK;
 }
@@ -1062,12 +1086,13 @@ t2r_status commit(t2r_ctx* c) {
     d.dhat = e.mat.dhat;
     d.kappa = e.mat.kappa;
     int cap = c->opts.pair_capacity;
-    if (cap == 0) cap = std::max(4096, 2 * (g.n_sv + g.n_se + g.n_sf));
+    if (cap == 0) cap = std::max(8192, 3 * (g.n_sv + g.n_se + g.n_sf));
     d.pair_cap = cap;
     d.fric_cap = std::max(1024, cap / 2);
-    d.outer_cap = 3 * cap;
+    d.outer_cap = 4 * cap;
     d.ooff = ooff;
     d.snoff = snoff;
+    d.vtxoff = vtot;
     d.voff = voff;
     d.poff = poff;
     d.foff = foff;
@@ -1112,10 +1137,14 @@ t2r_status commit(t2r_ctx* c) {
   c->d_lists = alloc_n<ListState>(c, c->envs.size());
   c->d_xsnap = alloc_n<double>(c, (size_t)std::max(snoff, 1LL));
   c->d_fric = alloc_n<FricPair>(c, (size_t)foff);
+  c->d_vmap = alloc_n<int>(c, (size_t)vtot);
+  c->d_oslot = alloc_n<uint64_t>(c, (size_t)ooff);
+  c->d_pslot = alloc_n<uint64_t>(c, (size_t)poff);
+  c->d_slot_v = alloc_n<int>(c, c->envs.size() * (size_t)kContactSlots);
   c->d_stats = alloc_n<EnvStats>(c, c->envs.size());
   if (!c->d_x || !c->d_xprev || !c->d_g0 || !c->d_g1 || !c->d_diag || !c->d_p || !c->d_pose_prev ||
       !c->d_pairs || !c->d_pair_d || !c->d_outer || !c->d_lists || !c->d_xsnap || !c->d_fric ||
-      !c->d_stats) {
+      !c->d_vmap || !c->d_oslot || !c->d_pslot || !c->d_slot_v || !c->d_stats) {
     dev_free_all(c);
     return fail(c, T2R_E_NOMEM, "state allocation failed (%lld DOFs)", voff);
   }
@@ -1130,6 +1159,7 @@ t2r_status commit(t2r_ctx* c) {
   HIP_TRY(c, hipMemsetAsync(c->d_p, 0, nd * sizeof(double), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_stats, 0, c->envs.size() * sizeof(EnvStats), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_lists, 0, c->envs.size() * sizeof(ListState), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_vmap, 0, (size_t)vtot * sizeof(int), c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->d_pose_prev, pose.data(), pose.size() * sizeof(double), hipMemcpyHostToDevice,
                             c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));  // host staging vectors go out of scope

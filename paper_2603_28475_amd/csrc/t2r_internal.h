@@ -15,6 +15,13 @@ constexpr int kTileTets = 1024;
 constexpr int kTileVerts = 512;   // local vertex ids are 16-bit
 constexpr int kMaxBlock = 1024;
 
+// Contact slots: the gel vertices touched by an env's coarse pair list get
+// dense ids below kContactSlots, so pair passes accumulate in LDS (in the
+// tile's storage) and write each vertex once per pass. Three 16-bit slot ids
+// are packed per pair; kNoSlot marks an absent or fixed vertex.
+constexpr int kContactSlots = 1024;
+constexpr uint32_t kNoSlot = 0xffff;
+
 // Pair kinds of the contact list (top three bits of the first word).
 constexpr int kVF = 0;   // gel surface vertex  vs indenter triangle
 constexpr int kFV = 1;   // indenter vertex     vs gel surface triangle
@@ -24,7 +31,8 @@ constexpr int kPrimMask = (1 << kKindShift) - 1;
 
 // Tile vertex flags.
 constexpr uint8_t kFirstTouch = 1;  // this tile writes the vertex first (store, not add)
-constexpr uint8_t kLastTouch = 2;   // this tile writes it last (fixed vertices reset here)
+constexpr uint8_t kLastTouch = 2;   // this tile writes it last
+constexpr uint8_t kFixedLast = 4;   // last touch of a fixed vertex: gradient 0, diagonal 1
 
 struct Grid {              // uniform grid over an indenter's local bounding box
   double origin[3];
@@ -51,7 +59,7 @@ struct GelDev {
   const int* tile_tet;     // [n_tiles+1]
   const int* tile_vstart;  // [n_tiles+1]
   const int* tile_verts;   // global vertex ids of each tile
-  const uint8_t* tile_flags;  // kFirstTouch | kLastTouch per tile vertex
+  const uint8_t* tile_flags;  // kFirstTouch | kLastTouch | kFixedLast per tile vertex
   const int* surf_v;       // [n_sv]
   const int* surf_e;       // [2][n_se]
   const int* surf_f;       // [3][n_sf]
@@ -78,6 +86,7 @@ struct EnvDev {
   long long moff;          // offset (markers) in the marker output
   long long ooff;          // offset of its outer (coarse) candidate list
   long long snoff;         // offset of its two surface-vertex snapshots (6 n_sv doubles)
+  long long vtxoff;        // vertex offset (voff / 3) of its vertex map
   int pair_cap, fric_cap, outer_cap;
 };
 
@@ -89,12 +98,14 @@ struct FricPair {          // lagged friction data of one pair (Supp. A, eq. fri
   double n[3];             // unit normal, indenter closest point -> gel closest point
   double base[3];          // sum a x_prev - sum c y(q_prev)
   double mulam;            // mu_f * lambda = -mu_f kappa b'(d) at the lag
+  uint64_t slot;           // contact slots of gv[0..2] (kNoSlot where none)
 };
 
 struct ListState {         // neighbour lists kept across load steps
   double pose_o[7];        // indenter pose when the outer list was built
   double pose_i[7];        // ... and when the inner list was built
   int n_outer, n_inner, valid_o, valid_i;
+  int n_slots, slots_ok;   // contact slots of the outer list (slots_ok = 0: global atomics)
 };
 
 struct EnvStats {
@@ -123,6 +134,10 @@ struct StepParams {
   ListState* lists;        // [n_env]
   double* xsnap;           // [sum 6 n_sv] surface positions when the lists were built
   FricPair* fric;          // [sum fric_cap]
+  int* vmap;               // [sum n_v] vertex -> contact slot + 1 while slots are built, else 0
+  uint64_t* oslot;         // [sum outer_cap] packed contact slots of each outer pair
+  uint64_t* pslot;         // [sum pair_cap] ... of each inner pair
+  int* slot_v;             // [n_env][kContactSlots] gel vertex of each contact slot
   EnvStats* stats;         // [n_env]
   // inputs / outputs
   const double* pose_in;   // [n_env][7]

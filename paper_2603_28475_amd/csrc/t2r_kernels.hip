@@ -16,6 +16,8 @@
 #include <float.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include "t2r_internal.h"
@@ -57,11 +59,19 @@ __device__ __forceinline__ void tock(Shared& S, int k, unsigned long long t0) {
   if (threadIdx.x == 0) S.tacc[k] += wall_clock64() - t0;
 }
 
-struct Tile {
-  double x[3][kTileVerts];
-  double p[3][kTileVerts];
-  double g[3][kTileVerts];
-  double d[3][kTileVerts];
+// LDS of the element passes (staged tile) and, between them, of the pair
+// passes (per contact slot accumulators).
+union Tile {
+  struct {
+    double x[3][kTileVerts];
+    double p[3][kTileVerts];
+    double g[3][kTileVerts];
+    double d[3][kTileVerts];
+  };
+  struct {
+    double cg[3][kContactSlots];
+    double cd[3][kContactSlots];
+  };
 };
 
 // Block-wide reduction of NS sums followed by NM maxima (values in v[0..NS+NM)).
@@ -182,88 +192,193 @@ struct View {
   double* pd;      // distance of each candidate pair at the current x
   int2* outer;     // coarse candidates within the outer radius
   FricPair* fric;
+  int* vmap;
+  uint64_t* oslot;
+  uint64_t* pslot;
+  int* slot_v;
   int npairs, nfric, nouter;
+  int nslots, slots_ok;
   int mixed;
 };
 
 // ---------------------------------------------------------------------------
 // Element passes over LDS-staged tiles
+//
+// A tile is a contiguous run of tets whose vertices (<= kTileVerts, local ids
+// in tet_local) are staged in LDS. Each thread owns up to kSlots vertex slots
+// of every tile; the global loads for the next tile's slots are issued into
+// registers before the current tile's tets are computed, so HBM/L2 latency
+// overlaps the arithmetic, and the per-tet inputs (local ids, Dm^-1, volume)
+// are likewise loaded one tet ahead.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void load_Dm(const GelDev& G, int e, double Dm[9]) {
+constexpr int kSlots = kTileVerts / 256;  // vertex slots per thread (blocks of >= 256 threads)
+
+template <bool MIXED>
+struct TetIn {
+  using R = typename std::conditional<MIXED, float, double>::type;
+  uint64_t loc;
+  R Dm[9];
+  R vol;
+};
+
+template <bool MIXED>
+__device__ __forceinline__ void load_tet(const GelDev& G, int e, TetIn<MIXED>& t) {
+  t.loc = G.tet_local[e];
+  if constexpr (MIXED) {
 #pragma unroll
-  for (int k = 0; k < 9; ++k) Dm[k] = G.Dinv[k * G.n_t + e];
+    for (int k = 0; k < 9; ++k) t.Dm[k] = G.Dinv32[k * G.n_t + e];
+    t.vol = G.vol32[e];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) t.Dm[k] = G.Dinv[k * G.n_t + e];
+    t.vol = G.vol[e];
+  }
+}
+
+__device__ __forceinline__ void tet_ids(uint64_t loc, int l[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) l[k] = (int)((loc >> (16 * k)) & 0xffff);
+}
+
+// Registers of one thread's vertex slots of one tile.
+struct SlotRegs {
+  int v[kSlots];     // global vertex id (-1: slot unused)
+  int fl[kSlots];    // tile flags
+  double a[kSlots][3];
+  double b[kSlots][3];
+};
+
+// Loads slot vertices of `tile`: a = x + alpha p (and b = p when WANT_P).
+template <bool WANT_P>
+__device__ __forceinline__ void fetch_slots(const GelDev& G, int tile, const double* x, const double* p,
+                                            double alpha, SlotRegs& R) {
+  const int nv = G.n_v;
+  const int v0 = G.tile_vstart[tile], ntv = G.tile_vstart[tile + 1] - v0;
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    const int i = threadIdx.x + s * blockDim.x;
+    R.v[s] = -1;
+    if (i < ntv) {
+      const int v = G.tile_verts[v0 + i];
+      R.v[s] = v;
+      R.fl[s] = G.tile_flags[v0 + i];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double xv = x[c * nv + v];
+        if (WANT_P) {
+          R.a[s][c] = xv;
+          R.b[s][c] = p[c * nv + v];
+        } else {
+          R.a[s][c] = p ? fma(alpha, p[c * nv + v], xv) : xv;
+        }
+      }
+    }
+  }
 }
 
 // Evaluates sum V psi, the gradient and diag(H) of the elastic term at
 // x + alpha p into gout/dout ([3][n_v]). Returns energy (thread partial) and
-// clears `feasible` on an inverted tet.
-__device__ __forceinline__ double elem_eval(const View& V, const double* x, const double* p, double alpha,
-                            double* gout, double* dout, Tile& T, int& feasible) {
+// clears `feasible` on an inverted tet. Fixed vertices get g = 0, diag = 1.
+template <bool MIXED>
+__device__ __forceinline__ double elem_eval_impl(const View& V, const double* x, const double* p, double alpha,
+                                                 double* gout, double* dout, Tile& T, int& feasible) {
   const GelDev& G = *V.G;
   const EnvDev& E = *V.E;
   const int nv = G.n_v;
+  const int B = blockDim.x;
   double energy = 0.0;
+  if (G.n_tiles == 0) return energy;
+  SlotRegs R;
+  // every g/d slot is zero between tiles: each flush clears what it read
+  for (int i = threadIdx.x; i < kTileVerts; i += B) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { T.g[c][i] = 0.0; T.d[c][i] = 0.0; }
+  }
+  fetch_slots<false>(G, 0, x, p, alpha, R);
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s)
+    if (R.v[s] >= 0)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) T.x[c][threadIdx.x + s * B] = R.a[s][c];
+  __syncthreads();
   for (int tile = 0; tile < G.n_tiles; ++tile) {
     const int t0 = G.tile_tet[tile], t1 = G.tile_tet[tile + 1];
-    const int v0 = G.tile_vstart[tile], ntv = G.tile_vstart[tile + 1] - v0;
-    for (int i = threadIdx.x; i < ntv; i += blockDim.x) {
-      const int v = G.tile_verts[v0 + i];
+    // this tile's slots: earlier partial sums of vertices shared with earlier tiles
+    int cur_v[kSlots], cur_fl[kSlots];
+    double og[kSlots][3], od[kSlots][3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        T.x[c][i] = fma(alpha, p[c * nv + v], x[c * nv + v]);
-        T.g[c][i] = 0.0;
-        T.d[c][i] = 0.0;
+    for (int s = 0; s < kSlots; ++s) {
+      cur_v[s] = R.v[s];
+      cur_fl[s] = R.fl[s];
+      if (cur_v[s] >= 0 && !(cur_fl[s] & kFirstTouch)) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          og[s][c] = gout[c * nv + cur_v[s]];
+          od[s][c] = dout[c * nv + cur_v[s]];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { og[s][c] = 0.0; od[s][c] = 0.0; }
       }
     }
-    __syncthreads();
-    for (int e = t0 + threadIdx.x; e < t1; e += blockDim.x) {
-      const uint64_t loc = G.tet_local[e];
-      int l[4];
+    if (tile + 1 < G.n_tiles) fetch_slots<false>(G, tile + 1, x, p, alpha, R);
+    else {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) l[k] = (int)((loc >> (16 * k)) & 0xffff);
-      bool ok;
+      for (int s = 0; s < kSlots; ++s) R.v[s] = -1;
+    }
+    int e = t0 + threadIdx.x;
+    TetIn<MIXED> tc;
+    if (e < t1) load_tet<MIXED>(G, e, tc);
+    for (; e < t1; e += B) {
+      TetIn<MIXED> tn;
+      if (e + B < t1) load_tet<MIXED>(G, e + B, tn);
+      int l[4];
+      tet_ids(tc.loc, l);
       double Ds[9];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int k = 0; k < 3; ++k) Ds[a * 3 + k] = T.x[a][l[k + 1]] - T.x[a][l[0]];
       double ed = 0.0;
-      if (V.mixed) {
-        float Dm[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Dm[k] = G.Dinv32[k * G.n_t + e];
-        ok = tet_grad_diag_mixed(Ds, Dm, G.vol32[e], E.mu, E.lam, ed,
+      bool ok;
+      if constexpr (MIXED) {
+        ok = tet_grad_diag_mixed(Ds, tc.Dm, tc.vol, E.mu, E.lam, ed,
                                  [&](int k, int c, float gv, float dv) {
                                    atomicAdd(&T.g[c][l[k]], (double)gv);
                                    atomicAdd(&T.d[c][l[k]], (double)dv);
                                  });
       } else {
-        double Dm[9];
-        load_Dm(G, e, Dm);
-        ok = tet_grad_diag64(Ds, Dm, G.vol[e], E.mu, E.lam, ed,
+        ok = tet_grad_diag64(Ds, tc.Dm, tc.vol, E.mu, E.lam, ed,
                              [&](int k, int c, double gv, double dv) {
                                atomicAdd(&T.g[c][l[k]], gv);
                                atomicAdd(&T.d[c][l[k]], dv);
                              });
       }
       if (ok) energy += ed;
-      if (!ok) feasible = 0;
+      else feasible = 0;
+      tc = tn;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < ntv; i += blockDim.x) {
-      const int v = G.tile_verts[v0 + i];
-      const uint8_t fl = G.tile_flags[v0 + i];
-      const bool fixed = (fl & kLastTouch) && G.fixed[v];
+    // flush this tile's slots, clear them, stage the next tile's positions
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        double gv = T.g[c][i], dv = T.d[c][i];
-        if (!(fl & kFirstTouch)) {
-          gv += gout[c * nv + v];
-          dv += dout[c * nv + v];
+    for (int s = 0; s < kSlots; ++s) {
+      const int i = threadIdx.x + s * B;
+      if (cur_v[s] >= 0) {
+        const int v = cur_v[s];
+        const bool fixed = cur_fl[s] & kFixedLast;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          double gv = T.g[c][i] + og[s][c], dv = T.d[c][i] + od[s][c];
+          T.g[c][i] = 0.0;
+          T.d[c][i] = 0.0;
+          if (fixed) { gv = 0.0; dv = 1.0; }
+          gout[c * nv + v] = gv;
+          dout[c * nv + v] = dv;
         }
-        if (fixed) { gv = 0.0; dv = 1.0; }
-        gout[c * nv + v] = gv;
-        dout[c * nv + v] = dv;
+      }
+      if (R.v[s] >= 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) T.x[c][i] = R.a[s][c];
       }
     }
     __syncthreads();
@@ -271,57 +386,72 @@ __device__ __forceinline__ double elem_eval(const View& V, const double* x, cons
   return energy;
 }
 
+__device__ __forceinline__ double elem_eval(const View& V, const double* x, const double* p, double alpha,
+                                            double* gout, double* dout, Tile& T, int& feasible) {
+  return V.mixed ? elem_eval_impl<true>(V, x, p, alpha, gout, dout, T, feasible)
+                 : elem_eval_impl<false>(V, x, p, alpha, gout, dout, T, feasible);
+}
+
 // p^T H_elastic p at x (thread partial).
-__device__ __forceinline__ double elem_curv(const View& V, const double* x, const double* p, Tile& T) {
+template <bool MIXED>
+__device__ __forceinline__ double elem_curv_impl(const View& V, const double* x, const double* p, Tile& T) {
   const GelDev& G = *V.G;
   const EnvDev& E = *V.E;
-  const int nv = G.n_v;
+  const int B = blockDim.x;
+  using Rl = typename TetIn<MIXED>::R;
   double curv = 0.0;
-  for (int tile = 0; tile < G.n_tiles; ++tile) {
-    const int t0 = G.tile_tet[tile], t1 = G.tile_tet[tile + 1];
-    const int v0 = G.tile_vstart[tile], ntv = G.tile_vstart[tile + 1] - v0;
-    for (int i = threadIdx.x; i < ntv; i += blockDim.x) {
-      const int v = G.tile_verts[v0 + i];
+  if (G.n_tiles == 0) return curv;
+  SlotRegs R;
+  fetch_slots<true>(G, 0, x, p, 0.0, R);
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s)
+    if (R.v[s] >= 0)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        T.x[c][i] = x[c * nv + v];
-        T.p[c][i] = p[c * nv + v];
+        T.x[c][threadIdx.x + s * B] = R.a[s][c];
+        T.p[c][threadIdx.x + s * B] = R.b[s][c];
       }
-    }
-    __syncthreads();
-    for (int e = t0 + threadIdx.x; e < t1; e += blockDim.x) {
-      const uint64_t loc = G.tet_local[e];
+  __syncthreads();
+  for (int tile = 0; tile < G.n_tiles; ++tile) {
+    const int t0 = G.tile_tet[tile], t1 = G.tile_tet[tile + 1];
+    if (tile + 1 < G.n_tiles) fetch_slots<true>(G, tile + 1, x, p, 0.0, R);
+    int e = t0 + threadIdx.x;
+    TetIn<MIXED> tc;
+    if (e < t1) load_tet<MIXED>(G, e, tc);
+    for (; e < t1; e += B) {
+      TetIn<MIXED> tn;
+      if (e + B < t1) load_tet<MIXED>(G, e + B, tn);
       int l[4];
+      tet_ids(tc.loc, l);
+      Rl Ds[9], dDs[9];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) l[k] = (int)((loc >> (16 * k)) & 0xffff);
-      if (V.mixed) {
-        float Ds[9], dDs[9], Dm[9];
+      for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            Ds[a * 3 + k] = (float)(T.x[a][l[k + 1]] - T.x[a][l[0]]);
-            dDs[a * 3 + k] = (float)(T.p[a][l[k + 1]] - T.p[a][l[0]]);
-          }
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Dm[k] = G.Dinv32[k * G.n_t + e];
-        curv += (double)tet_curvature<float>(Ds, dDs, Dm, G.vol32[e], (float)E.mu, (float)E.lam);
-      } else {
-        double Ds[9], dDs[9], Dm[9];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            Ds[a * 3 + k] = T.x[a][l[k + 1]] - T.x[a][l[0]];
-            dDs[a * 3 + k] = T.p[a][l[k + 1]] - T.p[a][l[0]];
-          }
-        load_Dm(G, e, Dm);
-        curv += tet_curvature<double>(Ds, dDs, Dm, G.vol[e], E.mu, E.lam);
-      }
+        for (int k = 0; k < 3; ++k) {
+          Ds[a * 3 + k] = (Rl)(T.x[a][l[k + 1]] - T.x[a][l[0]]);
+          dDs[a * 3 + k] = (Rl)(T.p[a][l[k + 1]] - T.p[a][l[0]]);
+        }
+      curv += (double)tet_curvature<Rl>(Ds, dDs, tc.Dm, tc.vol, (Rl)E.mu, (Rl)E.lam);
+      tc = tn;
     }
     __syncthreads();
+    if (tile + 1 < G.n_tiles) {
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s)
+        if (R.v[s] >= 0)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            T.x[c][threadIdx.x + s * B] = R.a[s][c];
+            T.p[c][threadIdx.x + s * B] = R.b[s][c];
+          }
+      __syncthreads();
+    }
   }
   return curv;
+}
+
+__device__ __forceinline__ double elem_curv(const View& V, const double* x, const double* p, Tile& T) {
+  return V.mixed ? elem_curv_impl<true>(V, x, p, T) : elem_curv_impl<false>(V, x, p, T);
 }
 
 // ---------------------------------------------------------------------------
@@ -393,12 +523,32 @@ __device__ __forceinline__ void pair_gel_ids(const GelDev& G, int2 pr, int gv[3]
   }
 }
 
+// Adds (gval, dval) to component c of a pair vertex: into its LDS contact slot
+// q, or with a global atomic when the env has no slots (q < 0).
+__device__ __forceinline__ void pair_add(Tile& T, int q, double* gout, double* dout, int idx, int c,
+                                         double gval, double dval) {
+  if (q >= 0) {
+    atomicAdd(&T.cg[c][q], gval);
+    atomicAdd(&T.cd[c][q], dval);
+  } else {
+    atomicAdd(&gout[idx], gval);
+    atomicAdd(&dout[idx], dval);
+  }
+}
+
+// Slot of the j-th gel vertex of a pair (pair_gel_ids order); -1: use global
+// atomics; kNoSlot: fixed vertex (no contribution).
+__device__ __forceinline__ int pair_slot(const View& V, uint64_t sl, int j, int v) {
+  if (V.slots_ok) return (int)((sl >> (16 * j)) & 0xffff);
+  return V.G->fixed[v] ? (int)kNoSlot : -1;
+}
+
 // Barrier energy, gradient and diag of every candidate pair at x + alpha p.
 // For a trial step, a pair whose cached distance minus the largest motion of
 // its gel vertices stays >= dhat is inactive (and positive) at the trial point:
 // its cache keeps that lower bound and no exact distance is computed.
 __device__ __forceinline__ double pairs_eval(const View& V, const Shared& S, const double* x, const double* p,
-                             double alpha, double* gout, double* dout, int& feasible, int& nactive) {
+                             double alpha, double* gout, double* dout, Tile& T, int& feasible, int& nactive) {
   const GelDev& G = *V.G;
   const EnvDev& E = *V.E;
   const int nv = G.n_v;
@@ -406,6 +556,7 @@ __device__ __forceinline__ double pairs_eval(const View& V, const Shared& S, con
   double energy = 0.0;
   for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
     const int2 pr = V.pairs[i];
+    const uint64_t sl = V.slots_ok ? V.pslot[i] : 0ull;
     if (alpha > 0.0) {
       int gv[3];
       pair_gel_ids(G, pr, gv);
@@ -447,7 +598,9 @@ __device__ __forceinline__ double pairs_eval(const View& V, const Shared& S, con
     #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = P.gid[k];
-      if (v < 0 || G.fixed[v]) continue;
+      if (v < 0) continue;
+      const int q = pair_slot(V, sl, (P.kind == kFV) ? k - 1 : k, v);
+      if (q == (int)kNoSlot) continue;
       const double ci = f.c[k];
       #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -457,8 +610,7 @@ __device__ __forceinline__ double pairs_eval(const View& V, const Shared& S, con
         if (f.k > 1) u1 = f.cw[k][1] * r[c] + ci * D[1][c];
         const double uMu = u0 * (Mi[0][0] * u0 + Mi[0][1] * u1) + u1 * (Mi[1][0] * u0 + Mi[1][1] * u1);
         const double hdd = (ci * ci - uMu) * invd - gi * gi * invd;
-        atomicAdd(&gout[c * nv + v], kap * b1 * gi);
-        atomicAdd(&dout[c * nv + v], kap * (b2 * gi * gi + b1 * hdd));
+        pair_add(T, q, gout, dout, c * nv + v, c, kap * b1 * gi, kap * (b2 * gi * gi + b1 * hdd));
       }
     }
   }
@@ -607,7 +759,7 @@ __device__ __forceinline__ void fric_delta(const View& V, const Shared& S, const
 }
 
 __device__ __forceinline__ double fric_eval(const View& V, const Shared& S, const double* x, const double* p, double alpha,
-                            double* gout, double* dout) {
+                            double* gout, double* dout, Tile& T) {
   const GelDev& G = *V.G;
   const int nv = G.n_v;
   const double eps = V.E->eps_v;
@@ -629,13 +781,14 @@ __device__ __forceinline__ double fric_eval(const View& V, const Shared& S, cons
     #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int v = F.gv[k];
-      if (v < 0 || G.fixed[v]) continue;
+      if (v < 0) continue;
+      const int q = pair_slot(V, F.slot, k, v);
+      if (q == (int)kNoSlot) continue;
       const double a = F.a[k];
       #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        atomicAdd(&gout[c * nv + v], F.mulam * a * fos * TD[c]);
         const double h = fos * (1.0 - F.n[c] * F.n[c]) + corr * uh[c] * uh[c];
-        atomicAdd(&dout[c * nv + v], F.mulam * a * a * h);
+        pair_add(T, q, gout, dout, c * nv + v, c, F.mulam * a * fos * TD[c], F.mulam * a * a * h);
       }
     }
   }
@@ -735,7 +888,7 @@ __device__ __forceinline__ double cull(View& V, Shared& S, const double* x, doub
   const int ntot = G.n_sv + G.n_se + G.n_sf;
   for (int i = threadIdx.x; i < ntot; i += blockDim.x) {
     int kind, gp, gvid[3], ngv;
-    if (i < G.n_sv) { kind = kVF; gp = i; gvid[0] = G.surf_v[i]; ngv = 1; }
+    if (i < G.n_sv) { kind = kVF; gvid[0] = G.surf_v[i]; gp = gvid[0]; ngv = 1; }  // VF pairs store the vertex id
     else if (i < G.n_sv + G.n_se) {
       kind = kEE; gp = i - G.n_sv; gvid[0] = G.surf_e[gp]; gvid[1] = G.surf_e[G.n_se + gp]; ngv = 2;
     } else {
@@ -868,8 +1021,13 @@ __device__ __forceinline__ void filter_pairs(View& V, Shared& S, const double* x
     const double d = pair_distance(P, f, r);
     if (d < thr) {
       const int slot = atomicAdd(&S.count, 1);
-      if (slot < cap) { V.pairs[slot] = pr; V.pd[slot] = d; }
-      else S.overflow = 1;
+      if (slot < cap) {
+        V.pairs[slot] = pr;
+        V.pd[slot] = d;
+        V.pslot[slot] = V.oslot[i];
+      } else {
+        S.overflow = 1;
+      }
     }
   }
   __syncthreads();
@@ -920,6 +1078,81 @@ __device__ __forceinline__ void snapshot(Solver& s, const double* x, double* dst
   __syncthreads();
 }
 
+// Packed contact slots of up to three gel vertices (vmap holds slot + 1).
+__device__ __forceinline__ uint64_t pack_slots(const View& V, const int gv[3]) {
+  uint64_t r = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    uint64_t q = kNoSlot;
+    if (gv[k] >= 0) {
+      const int m = V.vmap[gv[k]];
+      if (m > 0) q = (uint64_t)(m - 1);
+    }
+    r |= q << (16 * k);
+  }
+  return r;
+}
+
+// Contact slots of the outer list: every free gel vertex of an outer pair or a
+// friction pair gets a dense id (slot_v maps back), and each pair records the
+// slots of its vertices. More than kContactSlots vertices: slots_ok = 0 and
+// the pair passes use global atomics. vmap is all zero again on return.
+__device__ __forceinline__ void build_slots(Solver& s) {
+  View& V = s.V;
+  const GelDev& G = *V.G;
+  Shared& S = *s.S;
+  for (int i = threadIdx.x; i < V.nouter; i += blockDim.x) {
+    int gv[3];
+    pair_gel_ids(G, V.outer[i], gv);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (gv[k] >= 0 && !G.fixed[gv[k]]) V.vmap[gv[k]] = -1;
+  }
+  for (int i = threadIdx.x; i < V.nfric; i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int v = V.fric[i].gv[k];
+      if (v >= 0 && !G.fixed[v]) V.vmap[v] = -1;
+    }
+  }
+  if (threadIdx.x == 0) S.count = 0;
+  __syncthreads();
+  // every marked vertex is a free surface vertex
+  for (int i = threadIdx.x; i < G.n_sv; i += blockDim.x) {
+    const int v = G.surf_v[i];
+    if (V.vmap[v] == -1) {
+      const int q = atomicAdd(&S.count, 1);
+      if (q < kContactSlots) {
+        V.vmap[v] = q + 1;
+        V.slot_v[q] = v;
+      }
+    }
+  }
+  __syncthreads();
+  const int n = S.count;
+  const int ok = n <= kContactSlots;
+  if (ok) {
+    for (int i = threadIdx.x; i < V.nouter; i += blockDim.x) {
+      int gv[3];
+      pair_gel_ids(G, V.outer[i], gv);
+      V.oslot[i] = pack_slots(V, gv);
+    }
+    for (int i = threadIdx.x; i < V.nfric; i += blockDim.x) {
+      int gv[3] = {V.fric[i].gv[0], V.fric[i].gv[1], V.fric[i].gv[2]};
+      V.fric[i].slot = pack_slots(V, gv);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < G.n_sv; i += blockDim.x) V.vmap[G.surf_v[i]] = 0;
+  V.slots_ok = ok;
+  V.nslots = ok ? n : 0;
+  if (threadIdx.x == 0) {
+    s.L->slots_ok = ok;
+    s.L->n_slots = V.nslots;
+  }
+  __syncthreads();
+}
+
 // Two-level neighbour list. The outer list (radius dhat + buffer_out) comes from
 // the grid traversal; the inner list (radius dhat + buffer) filters it. Each
 // list remembers the surface positions and the indenter pose it was built at.
@@ -937,6 +1170,7 @@ __device__ __forceinline__ bool rebuild_outer(Solver& s, const double* x) {
   __syncthreads();
   V.nouter = min(cnt, s.outer_cap);
   snapshot(s, x, s.xs_o);
+  build_slots(s);
   if (threadIdx.x == 0) {
     for (int i = 0; i < 7; ++i) s.L->pose_o[i] = s.S->pose[i];
     s.L->n_outer = V.nouter;
@@ -997,6 +1231,8 @@ __device__ __forceinline__ bool ensure_lists(Solver& s, const double* x, double 
 __device__ __forceinline__ void load_lists(Solver& s) {
   s.V.nouter = s.L->valid_o ? s.L->n_outer : 0;
   s.V.npairs = s.L->valid_i ? s.L->n_inner : 0;
+  s.V.slots_ok = s.L->valid_o ? s.L->slots_ok : 0;
+  s.V.nslots = s.V.slots_ok ? s.L->n_slots : 0;
 }
 
 // Friction lag and smallest distance at (x, current pose) from the outer list:
@@ -1019,8 +1255,12 @@ __device__ __forceinline__ double lag_from_outer(Solver& s, const double* x, int
     dmin = fmin(dmin, d);
     if (mode == 1 && d < V.E->dhat && d > 0.0) {
       const int slot = atomicAdd(&S.count, 1);
-      if (slot < s.fric_cap) make_fric(V, P, f, r, d, pr, V.fric[slot]);
-      else S.overflow = 1;
+      if (slot < s.fric_cap) {
+        make_fric(V, P, f, r, d, pr, V.fric[slot]);
+        V.fric[slot].slot = V.oslot[i];  // friction pairs are outer pairs: same gel vertices
+      } else {
+        S.overflow = 1;
+      }
     }
   }
   __syncthreads();
@@ -1038,8 +1278,31 @@ __device__ __forceinline__ double eval_all(Solver& s, const double* x, const dou
   tock(*s.S, 5, t0);
   double eel = v[0];
   t0 = tick();
-  v[0] += pairs_eval(V, *s.S, x, p, alpha, g, dg, feas, nact);
-  if (V.nfric > 0) v[0] += fric_eval(V, *s.S, x, p, alpha, g, dg);
+  Tile& T = *s.T;
+  const int nv = V.G->n_v;
+  // contact terms accumulate per contact slot in LDS (the tile storage is free
+  // between element passes) and are added to g, dg once per vertex
+  if (V.slots_ok) {
+    for (int i = threadIdx.x; i < V.nslots; i += blockDim.x) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) { T.cg[c][i] = 0.0; T.cd[c][i] = 0.0; }
+    }
+    __syncthreads();
+  }
+  v[0] += pairs_eval(V, *s.S, x, p, alpha, g, dg, T, feas, nact);
+  if (V.nfric > 0) v[0] += fric_eval(V, *s.S, x, p, alpha, g, dg, T);
+  if (V.slots_ok) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < V.nslots; i += blockDim.x) {
+      const int vtx = V.slot_v[i];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        g[c * nv + vtx] += T.cg[c][i];
+        dg[c * nv + vtx] += T.cd[c][i];
+      }
+    }
+    __syncthreads();
+  }
   v[1] = (double)nact;
   v[2] = feas ? 0.0 : 1.0;  // max -> any infeasible
   double w[4] = {v[0], v[1], eel, v[2]};
@@ -1205,8 +1468,14 @@ __device__ __forceinline__ void make_view(const StepParams& P, int e, View& V) {
   V.outer = P.outer + E.ooff;
   V.nouter = 0;
   V.fric = P.fric + E.foff;
+  V.vmap = P.vmap + E.vtxoff;
+  V.oslot = P.oslot + E.ooff;
+  V.pslot = P.pslot + E.poff;
+  V.slot_v = P.slot_v + (long long)e * kContactSlots;
   V.npairs = 0;
   V.nfric = 0;
+  V.nslots = 0;
+  V.slots_ok = 0;
   V.mixed = P.precision;
 }
 
@@ -1416,17 +1685,27 @@ __global__ void __launch_bounds__(256) t2r_eval_kernel(EvalParams Q) {
   const EnvDev& E = *V.E;
   const int nv = G.n_v;
   load_lists(s);
+  bool ok = true;
   if (Q.has_lag && E.mu_f > 0.0) {
     if (threadIdx.x == 0) set_pose(S, I, Q.pose_lag);
     __syncthreads();
-    ensure_lists(s, V.xprev, 0.0);
-    lag_from_outer(s, V.xprev, 1);
-    V.nfric = min(S.count, s.fric_cap);
+    ok = ensure_lists(s, V.xprev, 0.0);
+    if (ok) {
+      lag_from_outer(s, V.xprev, 1);
+      V.nfric = min(S.count, s.fric_cap);
+      ok = S.overflow == 0;
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) set_pose(S, I, Q.pose);
   __syncthreads();
-  ensure_lists(s, V.x, 0.0);
+  if (ok) ok = ensure_lists(s, V.x, 0.0);
+  if (!ok) {
+    // a list overflowed: report it instead of evaluating a truncated list
+    if (threadIdx.x == 0) P.stats[0].status = kOverflow;
+    return;
+  }
+  if (threadIdx.x == 0) P.stats[0].status = 0;
   int feas, nact;
   double eel = 0.0;
   const double Etot = eval_all(s, V.x, V.p, 0.0, V.g0, V.diag, feas, nact, &eel);

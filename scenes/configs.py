@@ -115,6 +115,21 @@ def sphere_press_484v(n_envs: int = 1, n_steps: int = 10) -> Workload:
                     "1 env, 8x8x2 mm gel 10x10x3 hexes, icosphere r=3 pressed 0.6 mm in 10 steps")
 
 
+def peg_press_484v(tilt_deg: float = 1.0, depth: float = 0.3, n_steps: int = 3, mu_f: float = 0.0,
+                   shear=(0.0, 0.0), n_shear: int = 0) -> Workload:
+    """Small parity scene with every pair kind active: the 8x8x2 mm gel (484 v)
+    pressed by the end-on peg r=4 mm, tilted a little so that its flat face, its
+    rim edges and its rim vertices all come within dhat of the gel."""
+    g = mesh_class("c1")
+    ind = INDENTERS["peg4"]()
+    q = _yaw_tilt(0.3, np.deg2rad(tilt_deg))
+    poses = press_schedule(ind, q, (0.5, -0.3), depth, g.thickness, n_steps, shear=shear,
+                           n_shear=n_shear)
+    env = EnvSpec("c1", "peg4", 0.3, NU, mu_f, poses)
+    return Workload("peg_press_484v", 6, {"c1": g}, {"peg4": ind}, [env], "f64", 1e-6,
+                    "1 env, 484-vertex gel, slightly tilted end-on peg")
+
+
 def peg_press_shear_12k(n_envs: int = 1) -> Workload:
     """Single env, 20x16x4 mm gel with 40x32x8 hexes (12,177 v, 61,440 t), end-on peg
     r=4 mm with tilt U[-5,5] deg and yaw U[0,360) deg; 20 press steps to 0.8 mm then
@@ -218,6 +233,7 @@ WORKLOADS = {
     "mixed_batch": mixed_batch,
     "adjoint_peg_5k": adjoint_peg_5k,
     "micro_press": micro_press,
+    "peg_press_484v": peg_press_484v,
 }
 
 

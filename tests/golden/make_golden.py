@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle.sim import simulate  # noqa: E402
-from scenes.configs import micro_press, sphere_press_484v  # noqa: E402
+from scenes.configs import micro_press, peg_press_484v, sphere_press_484v  # noqa: E402
 
 
 def sphere_press():
@@ -44,6 +44,19 @@ def micro_friction():
     print(f"micro3_friction: {time.time() - t:.1f}s, active {r.n_active}")
 
 
+def peg_press_friction():
+    """Every pair kind active (tilted flat-ended peg), lagged friction and shear."""
+    w = peg_press_484v(mu_f=0.5, shear=(0.1, 0.05), n_shear=2)
+    env = w.envs[0]
+    t = time.time()
+    r = simulate(w.meshes["c1"], w.indenters["peg4"], env, mode="newton")
+    np.savez_compressed(os.path.join(HERE, "peg_press_484v_friction_newton.npz"),
+                        x=np.array(r.x), markers=np.array(r.markers), poses=env.poses,
+                        n_active=np.array(r.n_active), d_min=np.array(r.d_min))
+    print(f"peg_press_484v_friction: {time.time() - t:.1f}s, active {r.n_active}")
+
+
 if __name__ == "__main__":
-    micro_friction()
-    sphere_press()
+    which = sys.argv[1:] or ["micro_friction", "sphere_press", "peg_press_friction"]
+    for name in which:
+        globals()[name]()

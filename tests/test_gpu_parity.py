@@ -113,6 +113,48 @@ def test_eval_friction_matches_oracle():
     assert sc[1] == pytest.approx(prob.curvature(x, p), rel=1e-11)
 
 
+def test_eval_every_pair_kind_matches_oracle():
+    """A slightly tilted flat-ended peg hovering within dhat of the gel: gel
+    vertices against its face (VF), its rim vertices against gel faces (FV) and
+    rim edges against gel edges (EE) are all active. Frictionless, then with a
+    friction lag taken at the hover state."""
+    t2r = _gpu()
+    from scenes.configs import DHAT, peg_press_484v, pose_at_depth
+    w = peg_press_484v(mu_f=0.5)
+    g = w.meshes["c1"]
+    ind = w.indenters["peg4"]
+    p0 = w.envs[0].poses[0]
+    hover = pose_at_depth(ind, p0[3:], p0[:2], -0.3 * DHAT, g.thickness)
+    rng = np.random.default_rng(11)
+    free = g.fixed == 0
+    x0 = g.X.copy()
+    x0[free] += 2e-4 * rng.standard_normal((free.sum(), 3))
+    p = np.zeros_like(x0)
+    p[free] = rng.standard_normal((free.sum(), 3))
+    # frictionless evaluation at the hover state (the lag is ignored with mu = 0)
+    w0 = peg_press_484v(mu_f=0.0)
+    g_, d, sc, prob = _eval_both(t2r, w0, 0, x0, hover, p=p)
+    pairs, geo = prob.active(x0)
+    assert set(np.unique(pairs["kind"]).tolist()) == {0, 1, 2}
+    assert sc[4] == 1.0 and int(sc[3]) == len(pairs["idx"])
+    assert sc[0] == pytest.approx(prob.energy(x0), rel=1e-12)
+    assert sc[2] == pytest.approx(geo["d"].min(), rel=1e-13)
+    assert _rel(g_, prob.gradient(x0)) < 1e-11
+    assert _rel(d[free], prob.diag(x0)[free]) < 1e-11
+    assert sc[1] == pytest.approx(prob.curvature(x0, p), rel=1e-11)
+    # friction lagged at the hover state, evaluated after a small slide
+    pose = hover.copy()
+    pose[:2] += (0.02, 0.01)
+    x = x0.copy()
+    x[free] += 3e-4 * rng.standard_normal((free.sum(), 3))
+    g_, d, sc, prob = _eval_both(t2r, w, 0, x, pose, p=p, x_lag=x0, pose_lag=hover)
+    assert int(sc[6]) == len(prob.lag["lam"]) > 0
+    assert sc[0] == pytest.approx(prob.energy(x), rel=1e-12)
+    assert _rel(g_, prob.gradient(x)) < 1e-11
+    assert _rel(d[free], prob.diag(x)[free]) < 1e-11
+    assert sc[1] == pytest.approx(prob.curvature(x, p), rel=1e-11)
+
+
 def _run_steps(sim, poses, want_x=False):
     out_m, out_x, st = [], [], []
     for s in range(1, poses.shape[1]):
