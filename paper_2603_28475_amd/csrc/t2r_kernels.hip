@@ -240,45 +240,41 @@ __device__ __forceinline__ void tet_ids(uint64_t loc, int l[4]) {
   for (int k = 0; k < 4; ++k) l[k] = (int)((loc >> (16 * k)) & 0xffff);
 }
 
-// Registers of one thread's vertex slots of one tile.
-struct SlotRegs {
-  int v[kSlots];     // global vertex id (-1: slot unused)
-  int fl[kSlots];    // tile flags
-  double a[kSlots][3];
-  double b[kSlots][3];
+// Vertex ids and flags of one thread's slots of a tile. Loads are clamped to
+// valid addresses so that they issue unconditionally (exact wait counts); a
+// slot past the tile's vertices, or of a tile past the last, has fl = -1.
+struct SlotIdx {
+  int v[kSlots];
+  int fl[kSlots];
 };
 
-// Loads slot vertices of `tile`: a = x + alpha p (and b = p when WANT_P).
-template <bool WANT_P>
-__device__ __forceinline__ void fetch_slots(const GelDev& G, int tile, const double* x, const double* p,
-                                            double alpha, SlotRegs& R) {
-  const int nv = G.n_v;
-  const int v0 = G.tile_vstart[tile], ntv = G.tile_vstart[tile + 1] - v0;
+__device__ __forceinline__ void fetch_idx(const GelDev& G, int tile, SlotIdx& I) {
+  const bool live = tile < G.n_tiles;
+  const int t = live ? tile : G.n_tiles - 1;
+  const int v0 = G.tile_vstart[t], ntv = G.tile_vstart[t + 1] - v0;
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) {
     const int i = threadIdx.x + s * blockDim.x;
-    R.v[s] = -1;
-    if (i < ntv) {
-      const int v = G.tile_verts[v0 + i];
-      R.v[s] = v;
-      R.fl[s] = G.tile_flags[v0 + i];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double xv = x[c * nv + v];
-        if (WANT_P) {
-          R.a[s][c] = xv;
-          R.b[s][c] = p[c * nv + v];
-        } else {
-          R.a[s][c] = p ? fma(alpha, p[c * nv + v], xv) : xv;
-        }
-      }
-    }
+    const int j = v0 + min(i, ntv - 1);
+    I.v[s] = G.tile_verts[j];
+    const int f = G.tile_flags[j];
+    I.fl[s] = (live && i < ntv) ? f : -1;
   }
+}
+
+// First tet of this thread at or after tile `tile` (clamped to a valid id).
+__device__ __forceinline__ int first_tet(const GelDev& G, int tile) {
+  const int t = min(tile, G.n_tiles - 1);
+  return min(G.tile_tet[t] + (int)threadIdx.x, G.n_t - 1);
 }
 
 // Evaluates sum V psi, the gradient and diag(H) of the elastic term at
 // x + alpha p into gout/dout ([3][n_v]). Returns energy (thread partial) and
 // clears `feasible` on an inverted tet. Fixed vertices get g = 0, diag = 1.
+//
+// Pipeline per tile k: the positions of tile k+1, the slot ids of tile k+2,
+// the earlier partial sums of tile k's shared vertices and each thread's next
+// tet are loaded into registers while tile k's tets are computed from LDS.
 template <bool MIXED>
 __device__ __forceinline__ double elem_eval_impl(const View& V, const double* x, const double* p, double alpha,
                                                  double* gout, double* dout, Tile& T, int& feasible) {
@@ -286,59 +282,63 @@ __device__ __forceinline__ double elem_eval_impl(const View& V, const double* x,
   const EnvDev& E = *V.E;
   const int nv = G.n_v;
   const int B = blockDim.x;
+  const int NT = G.n_tiles;
   double energy = 0.0;
-  if (G.n_tiles == 0) return energy;
-  SlotRegs R;
+  if (NT == 0) return energy;
   // every g/d slot is zero between tiles: each flush clears what it read
   for (int i = threadIdx.x; i < kTileVerts; i += B) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) { T.g[c][i] = 0.0; T.d[c][i] = 0.0; }
   }
-  fetch_slots<false>(G, 0, x, p, alpha, R);
+  SlotIdx cur, nxt;
+  fetch_idx(G, 0, cur);
+  fetch_idx(G, 1, nxt);
+  double a[kSlots][3];
 #pragma unroll
   for (int s = 0; s < kSlots; ++s)
-    if (R.v[s] >= 0)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) T.x[c][threadIdx.x + s * B] = R.a[s][c];
+    for (int c = 0; c < 3; ++c) {
+      const double xv = x[c * nv + cur.v[s]];
+      a[s][c] = p ? fma(alpha, p[c * nv + cur.v[s]], xv) : xv;
+    }
+  TetIn<MIXED> tc;
+  load_tet<MIXED>(G, first_tet(G, 0), tc);
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s)
+    if (cur.fl[s] >= 0)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) T.x[c][threadIdx.x + s * B] = a[s][c];
   __syncthreads();
-  for (int tile = 0; tile < G.n_tiles; ++tile) {
+  for (int tile = 0; tile < NT; ++tile) {
     const int t0 = G.tile_tet[tile], t1 = G.tile_tet[tile + 1];
-    // this tile's slots: earlier partial sums of vertices shared with earlier tiles
-    int cur_v[kSlots], cur_fl[kSlots];
     double og[kSlots][3], od[kSlots][3];
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-      cur_v[s] = R.v[s];
-      cur_fl[s] = R.fl[s];
-      if (cur_v[s] >= 0 && !(cur_fl[s] & kFirstTouch)) {
+    for (int s = 0; s < kSlots; ++s)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          og[s][c] = gout[c * nv + cur_v[s]];
-          od[s][c] = dout[c * nv + cur_v[s]];
-        }
-      } else {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) { og[s][c] = 0.0; od[s][c] = 0.0; }
+      for (int c = 0; c < 3; ++c) {
+        og[s][c] = gout[c * nv + cur.v[s]];
+        od[s][c] = dout[c * nv + cur.v[s]];
       }
-    }
-    if (tile + 1 < G.n_tiles) fetch_slots<false>(G, tile + 1, x, p, alpha, R);
-    else {
 #pragma unroll
-      for (int s = 0; s < kSlots; ++s) R.v[s] = -1;
-    }
-    int e = t0 + threadIdx.x;
-    TetIn<MIXED> tc;
-    if (e < t1) load_tet<MIXED>(G, e, tc);
-    for (; e < t1; e += B) {
+    for (int s = 0; s < kSlots; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double xv = x[c * nv + nxt.v[s]];
+        a[s][c] = p ? fma(alpha, p[c * nv + nxt.v[s]], xv) : xv;
+      }
+    SlotIdx nn;
+    fetch_idx(G, tile + 2, nn);
+    for (int e = t0 + threadIdx.x; e < t1; e += B) {
       TetIn<MIXED> tn;
-      if (e + B < t1) load_tet<MIXED>(G, e + B, tn);
+      const int en = (e + B < t1) ? e + B : first_tet(G, tile + 1);
+      load_tet<MIXED>(G, en, tn);
       int l[4];
       tet_ids(tc.loc, l);
       double Ds[9];
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+      for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) Ds[a * 3 + k] = T.x[a][l[k + 1]] - T.x[a][l[0]];
+        for (int k = 0; k < 3; ++k) Ds[r * 3 + k] = T.x[r][l[k + 1]] - T.x[r][l[0]];
       double ed = 0.0;
       bool ok;
       if constexpr (MIXED) {
@@ -358,17 +358,21 @@ __device__ __forceinline__ double elem_eval_impl(const View& V, const double* x,
       else feasible = 0;
       tc = tn;
     }
+    // a thread without a tet here fetches its first tet of the next tile
+    if (t0 + (int)threadIdx.x >= t1) load_tet<MIXED>(G, first_tet(G, tile + 1), tc);
     __syncthreads();
     // flush this tile's slots, clear them, stage the next tile's positions
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) {
       const int i = threadIdx.x + s * B;
-      if (cur_v[s] >= 0) {
-        const int v = cur_v[s];
-        const bool fixed = cur_fl[s] & kFixedLast;
+      if (cur.fl[s] >= 0) {
+        const int v = cur.v[s];
+        const bool first = cur.fl[s] & kFirstTouch;
+        const bool fixed = cur.fl[s] & kFixedLast;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          double gv = T.g[c][i] + og[s][c], dv = T.d[c][i] + od[s][c];
+          double gv = T.g[c][i], dv = T.d[c][i];
+          if (!first) { gv += og[s][c]; dv += od[s][c]; }
           T.g[c][i] = 0.0;
           T.d[c][i] = 0.0;
           if (fixed) { gv = 0.0; dv = 1.0; }
@@ -376,11 +380,13 @@ __device__ __forceinline__ double elem_eval_impl(const View& V, const double* x,
           dout[c * nv + v] = dv;
         }
       }
-      if (R.v[s] >= 0) {
+      if (nxt.fl[s] >= 0) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) T.x[c][i] = R.a[s][c];
+        for (int c = 0; c < 3; ++c) T.x[c][i] = a[s][c];
       }
     }
+    cur = nxt;
+    nxt = nn;
     __syncthreads();
   }
   return energy;
@@ -392,60 +398,82 @@ __device__ __forceinline__ double elem_eval(const View& V, const double* x, cons
                  : elem_eval_impl<false>(V, x, p, alpha, gout, dout, T, feasible);
 }
 
-// p^T H_elastic p at x (thread partial).
+// p^T H_elastic p at x (thread partial); same pipeline as the eval pass.
 template <bool MIXED>
 __device__ __forceinline__ double elem_curv_impl(const View& V, const double* x, const double* p, Tile& T) {
   const GelDev& G = *V.G;
   const EnvDev& E = *V.E;
+  const int nv = G.n_v;
   const int B = blockDim.x;
+  const int NT = G.n_tiles;
   using Rl = typename TetIn<MIXED>::R;
   double curv = 0.0;
-  if (G.n_tiles == 0) return curv;
-  SlotRegs R;
-  fetch_slots<true>(G, 0, x, p, 0.0, R);
+  if (NT == 0) return curv;
+  SlotIdx cur, nxt;
+  fetch_idx(G, 0, cur);
+  fetch_idx(G, 1, nxt);
+  double a[kSlots][3], b[kSlots][3];
 #pragma unroll
   for (int s = 0; s < kSlots; ++s)
-    if (R.v[s] >= 0)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a[s][c] = x[c * nv + cur.v[s]];
+      b[s][c] = p[c * nv + cur.v[s]];
+    }
+  TetIn<MIXED> tc;
+  load_tet<MIXED>(G, first_tet(G, 0), tc);
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s)
+    if (cur.fl[s] >= 0)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        T.x[c][threadIdx.x + s * B] = R.a[s][c];
-        T.p[c][threadIdx.x + s * B] = R.b[s][c];
+        T.x[c][threadIdx.x + s * B] = a[s][c];
+        T.p[c][threadIdx.x + s * B] = b[s][c];
       }
   __syncthreads();
-  for (int tile = 0; tile < G.n_tiles; ++tile) {
+  for (int tile = 0; tile < NT; ++tile) {
     const int t0 = G.tile_tet[tile], t1 = G.tile_tet[tile + 1];
-    if (tile + 1 < G.n_tiles) fetch_slots<true>(G, tile + 1, x, p, 0.0, R);
-    int e = t0 + threadIdx.x;
-    TetIn<MIXED> tc;
-    if (e < t1) load_tet<MIXED>(G, e, tc);
-    for (; e < t1; e += B) {
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        a[s][c] = x[c * nv + nxt.v[s]];
+        b[s][c] = p[c * nv + nxt.v[s]];
+      }
+    SlotIdx nn;
+    fetch_idx(G, tile + 2, nn);
+    for (int e = t0 + threadIdx.x; e < t1; e += B) {
       TetIn<MIXED> tn;
-      if (e + B < t1) load_tet<MIXED>(G, e + B, tn);
+      const int en = (e + B < t1) ? e + B : first_tet(G, tile + 1);
+      load_tet<MIXED>(G, en, tn);
       int l[4];
       tet_ids(tc.loc, l);
       Rl Ds[9], dDs[9];
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+      for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          Ds[a * 3 + k] = (Rl)(T.x[a][l[k + 1]] - T.x[a][l[0]]);
-          dDs[a * 3 + k] = (Rl)(T.p[a][l[k + 1]] - T.p[a][l[0]]);
+          Ds[r * 3 + k] = (Rl)(T.x[r][l[k + 1]] - T.x[r][l[0]]);
+          dDs[r * 3 + k] = (Rl)(T.p[r][l[k + 1]] - T.p[r][l[0]]);
         }
       curv += (double)tet_curvature<Rl>(Ds, dDs, tc.Dm, tc.vol, (Rl)E.mu, (Rl)E.lam);
       tc = tn;
     }
+    if (t0 + (int)threadIdx.x >= t1) load_tet<MIXED>(G, first_tet(G, tile + 1), tc);
     __syncthreads();
-    if (tile + 1 < G.n_tiles) {
+    if (tile + 1 < NT) {
 #pragma unroll
       for (int s = 0; s < kSlots; ++s)
-        if (R.v[s] >= 0)
+        if (nxt.fl[s] >= 0)
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            T.x[c][threadIdx.x + s * B] = R.a[s][c];
-            T.p[c][threadIdx.x + s * B] = R.b[s][c];
+            T.x[c][threadIdx.x + s * B] = a[s][c];
+            T.p[c][threadIdx.x + s * B] = b[s][c];
           }
       __syncthreads();
     }
+    cur = nxt;
+    nxt = nn;
   }
   return curv;
 }
