@@ -95,6 +95,8 @@ struct t2r_ctx {
   double* d_xsnap = nullptr;
   FricPair* d_fric = nullptr;
   int* d_vmap = nullptr;
+  int* d_imap = nullptr;
+  int* d_islot_v = nullptr;
   uint64_t* d_oslot = nullptr;
   uint64_t* d_pslot = nullptr;
   int* d_slot_v = nullptr;
@@ -772,6 +774,8 @@ static StepParams step_params(t2r_ctx* c) {
   P.xsnap = c->d_xsnap;
   P.fric = c->d_fric;
   P.vmap = c->d_vmap;
+  P.imap = c->d_imap;
+  P.islot_v = c->d_islot_v;
   P.oslot = c->d_oslot;
   P.pslot = c->d_pslot;
   P.slot_v = c->d_slot_v;
@@ -827,6 +831,8 @@ t2r_status t2r_eval(t2r_ctx* c, int32_t env, const double* d_x, const double* d_
   ed.ooff = 0;
   ed.snoff = 0;
   ed.vtxoff = 0;
+  ed.imoff = 0;
+  const int niv = c->inds[E.ind].n_v;
   // scratch (freed before returning)
   std::vector<void*> tmp;
   auto talloc = [&](size_t b) -> void* {
@@ -862,8 +868,10 @@ t2r_status t2r_eval(t2r_ctx* c, int32_t env, const double* d_x, const double* d_
   int* svmap = (int*)talloc((size_t)nv * sizeof(int));
   uint64_t* soslot = (uint64_t*)talloc((size_t)ed.outer_cap * sizeof(uint64_t));
   uint64_t* spslot = (uint64_t*)talloc((size_t)ed.pair_cap * sizeof(uint64_t));
-  int* sslot_v = (int*)talloc((size_t)kContactSlots * sizeof(int));
-  if (tmp.size() != 19) { tfree(); return fail(c, T2R_E_NOMEM, "scratch allocation failed"); }
+  int* sslot_v = (int*)talloc((size_t)kGelSlots * sizeof(int));
+  int* simap = (int*)talloc((size_t)niv * sizeof(int));
+  int* sislot_v = (int*)talloc((size_t)kIndSlots * sizeof(int));
+  if (tmp.size() != 21) { tfree(); return fail(c, T2R_E_NOMEM, "scratch allocation failed"); }
   double hp[14];
   for (int k = 0; k < 7; ++k) { hp[k] = pose[k]; hp[7 + k] = (pose_lag ? pose_lag[k] : pose[k]); }
   hipError_t he = hipSuccess;
@@ -871,6 +879,7 @@ t2r_status t2r_eval(t2r_ctx* c, int32_t env, const double* d_x, const double* d_
   if (he == hipSuccess) he = hipMemcpyAsync(sposes, hp, sizeof hp, hipMemcpyHostToDevice, c->stream);
   if (he == hipSuccess) he = hipMemsetAsync(slists, 0, sizeof(ListState), c->stream);
   if (he == hipSuccess) he = hipMemsetAsync(svmap, 0, (size_t)nv * sizeof(int), c->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(simap, 0, (size_t)niv * sizeof(int), c->stream);
   if (he == hipSuccess) he = t2r_launch_aos_to_soa(d_x, sx, nv, c->stream);
   if (he == hipSuccess && d_p) he = t2r_launch_aos_to_soa(d_p, sp, nv, c->stream);
   if (he == hipSuccess && !d_p) he = hipMemsetAsync(sp, 0, vb, c->stream);
@@ -896,6 +905,8 @@ t2r_status t2r_eval(t2r_ctx* c, int32_t env, const double* d_x, const double* d_
   Q.sp.oslot = soslot;
   Q.sp.pslot = spslot;
   Q.sp.slot_v = sslot_v;
+  Q.sp.imap = simap;
+  Q.sp.islot_v = sislot_v;
   Q.sp.stats = sstats;
   Q.env = 0;
   Q.pose = sposes;
@@ -1072,7 +1083,7 @@ t2r_status commit(t2r_ctx* c) {
   c->d_inds = (IndDev*)di;
   // per-env layout
   c->h_envs.clear();
-  long long voff = 0, poff = 0, foff = 0, moff = 0, vtot = 0, soff = 0, ooff = 0, snoff = 0;
+  long long voff = 0, poff = 0, foff = 0, moff = 0, vtot = 0, soff = 0, ooff = 0, snoff = 0, imtot = 0;
   std::vector<long long> xoff, sofs;
   for (auto& e : c->envs) {
     const GelHost& g = c->gels[e.gel];
@@ -1093,6 +1104,7 @@ t2r_status commit(t2r_ctx* c) {
     d.ooff = ooff;
     d.snoff = snoff;
     d.vtxoff = vtot;
+    d.imoff = imtot;
     d.voff = voff;
     d.poff = poff;
     d.foff = foff;
@@ -1106,6 +1118,7 @@ t2r_status commit(t2r_ctx* c) {
     snoff += 6 * (long long)g.n_sv;
     moff += g.n_m;
     vtot += g.n_v;
+    imtot += c->inds[e.ind].n_v;
     soff += 3 * (long long)g.n_v + 7;
     c->h_envs.push_back(d);
   }
@@ -1140,11 +1153,14 @@ t2r_status commit(t2r_ctx* c) {
   c->d_vmap = alloc_n<int>(c, (size_t)vtot);
   c->d_oslot = alloc_n<uint64_t>(c, (size_t)ooff);
   c->d_pslot = alloc_n<uint64_t>(c, (size_t)poff);
-  c->d_slot_v = alloc_n<int>(c, c->envs.size() * (size_t)kContactSlots);
+  c->d_slot_v = alloc_n<int>(c, c->envs.size() * (size_t)kGelSlots);
+  c->d_imap = alloc_n<int>(c, (size_t)std::max(imtot, 1LL));
+  c->d_islot_v = alloc_n<int>(c, c->envs.size() * (size_t)kIndSlots);
   c->d_stats = alloc_n<EnvStats>(c, c->envs.size());
   if (!c->d_x || !c->d_xprev || !c->d_g0 || !c->d_g1 || !c->d_diag || !c->d_p || !c->d_pose_prev ||
       !c->d_pairs || !c->d_pair_d || !c->d_outer || !c->d_lists || !c->d_xsnap || !c->d_fric ||
-      !c->d_vmap || !c->d_oslot || !c->d_pslot || !c->d_slot_v || !c->d_stats) {
+      !c->d_vmap || !c->d_oslot || !c->d_pslot || !c->d_slot_v || !c->d_imap || !c->d_islot_v ||
+      !c->d_stats) {
     dev_free_all(c);
     return fail(c, T2R_E_NOMEM, "state allocation failed (%lld DOFs)", voff);
   }
@@ -1160,6 +1176,7 @@ t2r_status commit(t2r_ctx* c) {
   HIP_TRY(c, hipMemsetAsync(c->d_stats, 0, c->envs.size() * sizeof(EnvStats), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_lists, 0, c->envs.size() * sizeof(ListState), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_vmap, 0, (size_t)vtot * sizeof(int), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_imap, 0, (size_t)std::max(imtot, 1LL) * sizeof(int), c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->d_pose_prev, pose.data(), pose.size() * sizeof(double), hipMemcpyHostToDevice,
                             c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));  // host staging vectors go out of scope

@@ -15,12 +15,16 @@ constexpr int kTileTets = 1024;
 constexpr int kTileVerts = 512;   // local vertex ids are 16-bit
 constexpr int kMaxBlock = 1024;
 
-// Contact slots: the gel vertices touched by an env's coarse pair list get
-// dense ids below kContactSlots, so pair passes accumulate in LDS (in the
-// tile's storage) and write each vertex once per pass. Three 16-bit slot ids
-// are packed per pair; kNoSlot marks an absent or fixed vertex.
-constexpr int kContactSlots = 1024;
-constexpr uint32_t kNoSlot = 0xffff;
+// Contact slots: the gel and indenter vertices touched by an env's coarse pair
+// list get dense ids (below kGelSlots and kIndSlots), so pair passes stage
+// their positions in LDS (in the tile's storage), accumulate gradients there
+// and write each gel vertex once per pass. A pair record packs the slot of each
+// of its four points (kRecBits each) and its kind; a friction record packs
+// 10-bit gel and indenter slots, kNoSlot10 marking an unused point.
+constexpr int kGelSlots = 512;
+constexpr int kIndSlots = 1024;
+constexpr int kRecBits = 11;
+constexpr uint32_t kNoSlot10 = 1023;
 
 // Pair kinds of the contact list (top three bits of the first word).
 constexpr int kVF = 0;   // gel surface vertex  vs indenter triangle
@@ -87,6 +91,7 @@ struct EnvDev {
   long long ooff;          // offset of its outer (coarse) candidate list
   long long snoff;         // offset of its two surface-vertex snapshots (6 n_sv doubles)
   long long vtxoff;        // vertex offset (voff / 3) of its vertex map
+  long long imoff;         // offset of its indenter vertex map
   int pair_cap, fric_cap, outer_cap;
 };
 
@@ -98,14 +103,15 @@ struct FricPair {          // lagged friction data of one pair (Supp. A, eq. fri
   double n[3];             // unit normal, indenter closest point -> gel closest point
   double base[3];          // sum a x_prev - sum c y(q_prev)
   double mulam;            // mu_f * lambda = -mu_f kappa b'(d) at the lag
-  uint64_t slot;           // contact slots of gv[0..2] (kNoSlot where none)
+  uint64_t slot;           // gel slots of gv[0..2] (bits 0-29), indenter slots of iv[0..2] (bits 32-61)
 };
 
 struct ListState {         // neighbour lists kept across load steps
   double pose_o[7];        // indenter pose when the outer list was built
   double pose_i[7];        // ... and when the inner list was built
   int n_outer, n_inner, valid_o, valid_i;
-  int n_slots, slots_ok;   // contact slots of the outer list (slots_ok = 0: global atomics)
+  int n_slots, n_islots;   // gel and indenter contact slots of the outer list
+  int slots_ok;            // 0: too many vertices; pair passes gather from global memory
 };
 
 struct EnvStats {
@@ -134,10 +140,12 @@ struct StepParams {
   ListState* lists;        // [n_env]
   double* xsnap;           // [sum 6 n_sv] surface positions when the lists were built
   FricPair* fric;          // [sum fric_cap]
-  int* vmap;               // [sum n_v] vertex -> contact slot + 1 while slots are built, else 0
-  uint64_t* oslot;         // [sum outer_cap] packed contact slots of each outer pair
+  int* vmap;               // [sum n_v] gel vertex -> slot + 1 while slots are built, else 0
+  int* imap;               // [sum indenter n_v] ... for indenter vertices
+  uint64_t* oslot;         // [sum outer_cap] pair record of each outer pair
   uint64_t* pslot;         // [sum pair_cap] ... of each inner pair
-  int* slot_v;             // [n_env][kContactSlots] gel vertex of each contact slot
+  int* slot_v;             // [n_env][kGelSlots] gel vertex of each slot
+  int* islot_v;            // [n_env][kIndSlots] indenter vertex of each slot
   EnvStats* stats;         // [n_env]
   // inputs / outputs
   const double* pose_in;   // [n_env][7]

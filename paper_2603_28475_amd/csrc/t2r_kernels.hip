@@ -60,7 +60,7 @@ __device__ __forceinline__ void tock(Shared& S, int k, unsigned long long t0) {
 }
 
 // LDS of the element passes (staged tile) and, between them, of the pair
-// passes (per contact slot accumulators).
+// passes (slot positions and sums).
 union Tile {
   struct {
     double x[3][kTileVerts];
@@ -69,8 +69,11 @@ union Tile {
     double d[3][kTileVerts];
   };
   struct {
-    double cg[3][kContactSlots];
-    double cd[3][kContactSlots];
+    double gx[3][kGelSlots];   // gel slot positions
+    double gq[3][kGelSlots];   // gradient sums (eval) or p (curvature, CCD)
+    double gd[3][kGelSlots];   // diagonal sums (eval)
+    double pn[kGelSlots];      // |p|^2 (trial evaluations)
+    double iy[3][kIndSlots];   // indenter slot positions, world frame
   };
 };
 
@@ -193,11 +196,13 @@ struct View {
   int2* outer;     // coarse candidates within the outer radius
   FricPair* fric;
   int* vmap;
+  int* imap;
   uint64_t* oslot;
   uint64_t* pslot;
   int* slot_v;
+  int* islot_v;
   int npairs, nfric, nouter;
-  int nslots, slots_ok;
+  int nslots, nislots, slots_ok;
   int mixed;
 };
 
@@ -484,46 +489,96 @@ __device__ __forceinline__ double elem_curv(const View& V, const double* x, cons
 
 // ---------------------------------------------------------------------------
 // Contact pairs
+//
+// With contact slots (V.slots_ok) a pair pass first stages the positions of the
+// listed pairs' gel vertices and the world positions of their indenter
+// vertices in LDS; each pair is then one 8-byte record read, LDS reads and LDS
+// atomics, and the gradient sums reach global memory once per gel vertex.
+// Without slots (too many vertices near the indenter) the same passes gather
+// from global memory and add with global atomics.
 // ---------------------------------------------------------------------------
 struct PairPts {
   double z[4][3];
-  int gid[4];      // gel vertex id or -1 for indenter points
+  int gid[4];      // gel point: slot (LDS path) or vertex id (global path); -1: indenter point
   int kind;
 };
 
-// Gathers the four points of pair `pr`; gel points at x + alpha p.
+__device__ __forceinline__ int rec_kind(uint64_t r) { return (int)(r >> (4 * kRecBits)) & 3; }
+__device__ __forceinline__ int rec_slot(uint64_t r, int k) {
+  return (int)(r >> (kRecBits * k)) & ((1 << kRecBits) - 1);
+}
+// Point k of a pair is a gel point: VF (gel vertex, indenter triangle),
+// FV (indenter vertex, gel triangle), EE (gel edge, indenter edge).
+__device__ __forceinline__ bool point_is_gel(int kind, int k) {
+  return kind == kVF ? k == 0 : (kind == kFV ? k > 0 : k < 2);
+}
+
+// Vertex ids of the four points of pair `pr` (gel ids where point_is_gel).
+__device__ __forceinline__ void pair_point_ids(const GelDev& G, const IndDev& I, int2 pr, int id[4]) {
+  const int kind = (int)((unsigned)pr.x >> kKindShift);
+  const int gp = pr.x & kPrimMask, ip = pr.y;
+  if (kind == kVF) {
+    id[0] = gp;
+    id[1] = I.tri[ip]; id[2] = I.tri[I.n_f + ip]; id[3] = I.tri[2 * I.n_f + ip];
+  } else if (kind == kFV) {
+    id[0] = ip;
+    id[1] = G.surf_f[gp]; id[2] = G.surf_f[G.n_sf + gp]; id[3] = G.surf_f[2 * G.n_sf + gp];
+  } else {
+    id[0] = G.surf_e[gp]; id[1] = G.surf_e[G.n_se + gp];
+    id[2] = I.edge[ip]; id[3] = I.edge[I.n_e + ip];
+  }
+}
+
+// Global path: gathers the four points of pair `pr`; gel points at x + alpha p.
 __device__ __forceinline__ void load_pair(const View& V, const Shared& S, int2 pr, const double* x,
-                                 const double* p, double alpha, PairPts& P) {
+                                          const double* p, double alpha, PairPts& P) {
   const GelDev& G = *V.G;
   const IndDev& I = *V.I;
   const int nv = G.n_v;
   const int kind = (int)((unsigned)pr.x >> kKindShift);
-  const int gp = pr.x & kPrimMask, ip = pr.y;
+  int id[4];
+  pair_point_ids(G, I, pr, id);
   P.kind = kind;
-  int gv[4] = {-1, -1, -1, -1}, iv[4] = {-1, -1, -1, -1};
-  if (kind == kVF) {
-    gv[0] = gp;
-    iv[1] = I.tri[ip]; iv[2] = I.tri[I.n_f + ip]; iv[3] = I.tri[2 * I.n_f + ip];
-  } else if (kind == kFV) {
-    iv[0] = ip;
-    gv[1] = G.surf_f[gp]; gv[2] = G.surf_f[G.n_sf + gp]; gv[3] = G.surf_f[2 * G.n_sf + gp];
-  } else {
-    gv[0] = G.surf_e[gp]; gv[1] = G.surf_e[G.n_se + gp];
-    iv[2] = I.edge[ip]; iv[3] = I.edge[I.n_e + ip];
-  }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    P.gid[k] = gv[k];
-    if (gv[k] >= 0) {
-      #pragma unroll
+    if (point_is_gel(kind, k)) {
+      P.gid[k] = id[k];
+#pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double xv = x[c * nv + gv[k]];
-        P.z[k][c] = p ? fma(alpha, p[c * nv + gv[k]], xv) : xv;
+        const double xv = x[c * nv + id[k]];
+        P.z[k][c] = p ? fma(alpha, p[c * nv + id[k]], xv) : xv;
       }
     } else {
-      ind_world(S, I, iv[k], P.z[k]);
+      P.gid[k] = -1;
+      ind_world(S, I, id[k], P.z[k]);
     }
   }
+}
+
+// LDS path: the four points of a pair record from the staged slots.
+__device__ __forceinline__ void load_pair_lds(const Tile& T, uint64_t rec, PairPts& P) {
+  const int kind = rec_kind(rec);
+  P.kind = kind;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int q = rec_slot(rec, k);
+    if (point_is_gel(kind, k)) {
+      P.gid[k] = q;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) P.z[k][c] = T.gx[c][q];
+    } else {
+      P.gid[k] = -1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) P.z[k][c] = T.iy[c][q];
+    }
+  }
+}
+
+template <bool LDS>
+__device__ __forceinline__ void get_pair(const View& V, const Shared& S, const Tile& T, int2 pr, uint64_t rec,
+                                         const double* x, const double* p, double alpha, PairPts& P) {
+  if constexpr (LDS) load_pair_lds(T, rec, P);
+  else load_pair(V, S, pr, x, p, alpha, P);
 }
 
 __device__ __forceinline__ void classify(const PairPts& P, Feature& f) {
@@ -537,71 +592,104 @@ __device__ __forceinline__ double pair_distance(const PairPts& P, const Feature&
   return sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
 }
 
-// Gel vertex ids of a pair (-1 where unused), without touching positions.
-__device__ __forceinline__ void pair_gel_ids(const GelDev& G, int2 pr, int gv[3]) {
-  const int kind = (int)((unsigned)pr.x >> kKindShift);
-  const int gp = pr.x & kPrimMask;
-  gv[1] = gv[2] = -1;
-  if (kind == kVF) {
-    gv[0] = gp;
-  } else if (kind == kFV) {
-    gv[0] = G.surf_f[gp]; gv[1] = G.surf_f[G.n_sf + gp]; gv[2] = G.surf_f[2 * G.n_sf + gp];
-  } else {
-    gv[0] = G.surf_e[gp]; gv[1] = G.surf_e[G.n_se + gp];
+// Stages the slot points of the env for a pair pass. what: 0 positions x;
+// 1 positions x and p (in gq); 2 positions x + alpha p, |p|^2 (in pn) when
+// alpha > 0, cleared gradient/diagonal sums. The indenter points are placed at
+// the current pose. Starts and ends with a barrier.
+__device__ __forceinline__ void stage_points(const View& V, const Shared& S, Tile& T, const double* x,
+                                             const double* p, double alpha, int what) {
+  const GelDev& G = *V.G;
+  const IndDev& I = *V.I;
+  const int nv = G.n_v;
+  __syncthreads();  // the tile storage may still be read by the previous pass
+  for (int i = threadIdx.x; i < V.nslots; i += blockDim.x) {
+    const int v = V.slot_v[i];
+    double pv2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double xv = x[c * nv + v];
+      if (what == 2) {
+        const double pv = p ? p[c * nv + v] : 0.0;
+        T.gx[c][i] = fma(alpha, pv, xv);
+        T.gq[c][i] = 0.0;
+        T.gd[c][i] = 0.0;
+        pv2 += pv * pv;
+      } else {
+        T.gx[c][i] = xv;
+        if (what == 1) T.gq[c][i] = p[c * nv + v];
+      }
+    }
+    if (what == 2) T.pn[i] = pv2;
   }
+  for (int i = threadIdx.x; i < V.nislots; i += blockDim.x) {
+    double y[3];
+    ind_world(S, I, V.islot_v[i], y);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) T.iy[c][i] = y[c];
+  }
+  __syncthreads();
 }
 
-// Adds (gval, dval) to component c of a pair vertex: into its LDS contact slot
-// q, or with a global atomic when the env has no slots (q < 0).
-__device__ __forceinline__ void pair_add(Tile& T, int q, double* gout, double* dout, int idx, int c,
-                                         double gval, double dval) {
-  if (q >= 0) {
-    atomicAdd(&T.cg[c][q], gval);
-    atomicAdd(&T.cd[c][q], dval);
-  } else {
-    atomicAdd(&gout[idx], gval);
-    atomicAdd(&dout[idx], dval);
+// Adds the staged gradient/diagonal sums of the slots to gout/dout (free gel
+// vertices only). Starts with a barrier.
+__device__ __forceinline__ void flush_slots(const View& V, const Tile& T, double* gout, double* dout) {
+  const GelDev& G = *V.G;
+  const int nv = G.n_v;
+  __syncthreads();
+  for (int i = threadIdx.x; i < V.nslots; i += blockDim.x) {
+    const int v = V.slot_v[i];
+    if (G.fixed[v]) continue;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      gout[c * nv + v] += T.gq[c][i];
+      dout[c * nv + v] += T.gd[c][i];
+    }
   }
-}
-
-// Slot of the j-th gel vertex of a pair (pair_gel_ids order); -1: use global
-// atomics; kNoSlot: fixed vertex (no contribution).
-__device__ __forceinline__ int pair_slot(const View& V, uint64_t sl, int j, int v) {
-  if (V.slots_ok) return (int)((sl >> (16 * j)) & 0xffff);
-  return V.G->fixed[v] ? (int)kNoSlot : -1;
 }
 
 // Barrier energy, gradient and diag of every candidate pair at x + alpha p.
 // For a trial step, a pair whose cached distance minus the largest motion of
 // its gel vertices stays >= dhat is inactive (and positive) at the trial point:
 // its cache keeps that lower bound and no exact distance is computed.
-__device__ __forceinline__ double pairs_eval(const View& V, const Shared& S, const double* x, const double* p,
-                             double alpha, double* gout, double* dout, Tile& T, int& feasible, int& nactive) {
+template <bool LDS>
+__device__ __forceinline__ double pairs_eval(const View& V, const Shared& S, Tile& T, const double* x,
+                                             const double* p, double alpha, double* gout, double* dout,
+                                             int& feasible, int& nactive) {
   const GelDev& G = *V.G;
   const EnvDev& E = *V.E;
   const int nv = G.n_v;
   const double dh = E.dhat, kap = E.kappa;
   double energy = 0.0;
   for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
-    const int2 pr = V.pairs[i];
-    const uint64_t sl = V.slots_ok ? V.pslot[i] : 0ull;
+    int2 pr = make_int2(0, 0);
+    uint64_t rec = 0;
+    if constexpr (LDS) rec = V.pslot[i];
+    else pr = V.pairs[i];
     if (alpha > 0.0) {
-      int gv[3];
-      pair_gel_ids(G, pr, gv);
       double l2 = 0.0;
+      if constexpr (LDS) {
+        const int kind = rec_kind(rec);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        if (gv[k] < 0) continue;
-        double sq = 0.0;
+        for (int k = 0; k < 4; ++k)
+          if (point_is_gel(kind, k)) l2 = fmax(l2, T.pn[rec_slot(rec, k)]);
+      } else {
+        int id[4];
+        pair_point_ids(G, *V.I, pr, id);
+        const int kind = (int)((unsigned)pr.x >> kKindShift);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) { const double pc = p[c * nv + gv[k]]; sq += pc * pc; }
-        l2 = fmax(l2, sq);
+        for (int k = 0; k < 4; ++k) {
+          if (!point_is_gel(kind, k)) continue;
+          double sq = 0.0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) { const double pc = p[c * nv + id[k]]; sq += pc * pc; }
+          l2 = fmax(l2, sq);
+        }
       }
       const double lb = V.pd[i] - alpha * sqrt(l2);
       if (lb >= dh) { V.pd[i] = lb; continue; }
     }
     PairPts P;
-    load_pair(V, S, pr, x, p, alpha, P);
+    get_pair<LDS>(V, S, T, pr, rec, x, p, alpha, P);
     Feature f;
     classify(P, f);
     double r[3];
@@ -620,33 +708,41 @@ __device__ __forceinline__ double pairs_eval(const View& V, const Shared& S, con
     for (int w = 0; w < 2; ++w)
       #pragma unroll
       for (int c = 0; c < 3; ++c)
-        D[w][c] = f.cw[0][w] * P.z[0][c] + f.cw[1][w] * P.z[1][c] + f.cw[2][w] * P.z[2][c] + f.cw[3][w] * P.z[3][c];
+        D[w][c] = cw_of(f, 0, w) * P.z[0][c] + cw_of(f, 1, w) * P.z[1][c] + cw_of(f, 2, w) * P.z[2][c] + cw_of(f, 3, w) * P.z[3][c];
     double Mi[2][2];
     gram_inverse(D, f.k, Mi);
     #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = P.gid[k];
       if (v < 0) continue;
-      const int q = pair_slot(V, sl, (P.kind == kFV) ? k - 1 : k, v);
-      if (q == (int)kNoSlot) continue;
+      if (!LDS && G.fixed[v]) continue;
       const double ci = f.c[k];
       #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const double gi = ci * n[c];
         double u0 = 0.0, u1 = 0.0;
-        if (f.k > 0) u0 = f.cw[k][0] * r[c] + ci * D[0][c];
-        if (f.k > 1) u1 = f.cw[k][1] * r[c] + ci * D[1][c];
+        if (f.k > 0) u0 = cw_of(f, k, 0) * r[c] + ci * D[0][c];
+        if (f.k > 1) u1 = cw_of(f, k, 1) * r[c] + ci * D[1][c];
         const double uMu = u0 * (Mi[0][0] * u0 + Mi[0][1] * u1) + u1 * (Mi[1][0] * u0 + Mi[1][1] * u1);
         const double hdd = (ci * ci - uMu) * invd - gi * gi * invd;
-        pair_add(T, q, gout, dout, c * nv + v, c, kap * b1 * gi, kap * (b2 * gi * gi + b1 * hdd));
+        const double gval = kap * b1 * gi, dval = kap * (b2 * gi * gi + b1 * hdd);
+        if constexpr (LDS) {
+          atomicAdd(&T.gq[c][v], gval);
+          atomicAdd(&T.gd[c][v], dval);
+        } else {
+          atomicAdd(&gout[c * nv + v], gval);
+          atomicAdd(&dout[c * nv + v], dval);
+        }
       }
     }
   }
   return energy;
 }
 
-// p^T H_barrier p at x (thread partial).
-__device__ __forceinline__ double pairs_curv(const View& V, const Shared& S, const double* x, const double* p) {
+// p^T H_barrier p at x (thread partial). LDS path: gx = x, gq = p.
+template <bool LDS>
+__device__ __forceinline__ double pairs_curv(const View& V, const Shared& S, const Tile& T, const double* x,
+                                             const double* p) {
   const GelDev& G = *V.G;
   const EnvDev& E = *V.E;
   const int nv = G.n_v;
@@ -654,8 +750,12 @@ __device__ __forceinline__ double pairs_curv(const View& V, const Shared& S, con
   double curv = 0.0;
   for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
     if (!(V.pd[i] < dh)) continue;  // inactive at x: no barrier curvature
+    int2 pr = make_int2(0, 0);
+    uint64_t rec = 0;
+    if constexpr (LDS) rec = V.pslot[i];
+    else pr = V.pairs[i];
     PairPts P;
-    load_pair(V, S, V.pairs[i], x, nullptr, 0.0, P);
+    get_pair<LDS>(V, S, T, pr, rec, x, nullptr, 0.0, P);
     Feature f;
     classify(P, f);
     double r[3];
@@ -670,22 +770,22 @@ __device__ __forceinline__ double pairs_curv(const View& V, const Shared& S, con
     for (int w = 0; w < 2; ++w)
       #pragma unroll
       for (int c = 0; c < 3; ++c)
-        D[w][c] = f.cw[0][w] * P.z[0][c] + f.cw[1][w] * P.z[1][c] + f.cw[2][w] * P.z[2][c] + f.cw[3][w] * P.z[3][c];
+        D[w][c] = cw_of(f, 0, w) * P.z[0][c] + cw_of(f, 1, w) * P.z[1][c] + cw_of(f, 2, w) * P.z[2][c] + cw_of(f, 3, w) * P.z[3][c];
     double Mi[2][2];
     gram_inverse(D, f.k, Mi);
     double q[3] = {0, 0, 0}, vv[2] = {0, 0};
     #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = P.gid[k];
-      if (v < 0 || G.fixed[v]) continue;
+      if (v < 0) continue;
       double pk[3];
       #pragma unroll
-      for (int c = 0; c < 3; ++c) pk[c] = p[c * nv + v];
+      for (int c = 0; c < 3; ++c) pk[c] = LDS ? T.gq[c][v] : p[c * nv + v];  // p = 0 on fixed vertices
       #pragma unroll
       for (int c = 0; c < 3; ++c) q[c] += f.c[k] * pk[c];
       const double rp = dot3(r, pk);
       #pragma unroll
-      for (int w = 0; w < 2; ++w) if (w < f.k) vv[w] += f.cw[k][w] * rp + f.c[k] * dot3(D[w], pk);
+      for (int w = 0; w < 2; ++w) if (w < f.k) vv[w] += cw_of(f, k, w) * rp + f.c[k] * dot3(D[w], pk);
     }
     const double nq = dot3(n, q);
     const double vMv = vv[0] * (Mi[0][0] * vv[0] + Mi[0][1] * vv[1]) + vv[1] * (Mi[1][0] * vv[0] + Mi[1][1] * vv[1]);
@@ -696,11 +796,17 @@ __device__ __forceinline__ double pairs_curv(const View& V, const Shared& S, con
 }
 
 // Smallest distance over candidate pairs at x (thread partial; kInf if none).
-__device__ __forceinline__ double pairs_dmin(const View& V, const Shared& S, const double* x, int& nactive) {
+template <bool LDS>
+__device__ __forceinline__ double pairs_dmin(const View& V, const Shared& S, const Tile& T, const double* x,
+                                             int& nactive) {
   double dmin = kInf;
   for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
+    int2 pr = make_int2(0, 0);
+    uint64_t rec = 0;
+    if constexpr (LDS) rec = V.pslot[i];
+    else pr = V.pairs[i];
     PairPts P;
-    load_pair(V, S, V.pairs[i], x, nullptr, 0.0, P);
+    get_pair<LDS>(V, S, T, pr, rec, x, nullptr, 0.0, P);
     Feature f;
     classify(P, f);
     double r[3];
@@ -711,30 +817,48 @@ __device__ __forceinline__ double pairs_dmin(const View& V, const Shared& S, con
   return dmin;
 }
 
-
 // Conservative advancement: largest t <= amax keeping each pair at >= kCcdGap of its
 // distance at x, gel points moving along p, indenter static (thread partial min).
 // The distance at x comes from the per-pair cache, so pairs that cannot close
-// their gap within amax cost only the gather of p at their gel vertices.
-__device__ __forceinline__ double pairs_ccd(const View& V, const Shared& S, const double* x, const double* p, double amax) {
+// their gap within amax cost only the look-up of p at their gel vertices.
+// LDS path: gx = x, gq = p.
+template <bool LDS>
+__device__ __forceinline__ double pairs_ccd(const View& V, const Shared& S, const Tile& T, const double* x,
+                                            const double* p, double amax) {
   const GelDev& G = *V.G;
   const int nv = G.n_v;
   double tmin = amax;
   for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
-    const int2 pr = V.pairs[i];
+    int2 pr = make_int2(0, 0);
+    uint64_t rec = 0;
+    if constexpr (LDS) rec = V.pslot[i];
+    else pr = V.pairs[i];
     const double d0 = V.pd[i];
     if (!(d0 > 0.0)) { tmin = 0.0; continue; }
-    int gv[3];
-    pair_gel_ids(G, pr, gv);
     double l2 = 0.0;
+    if constexpr (LDS) {
+      const int kind = rec_kind(rec);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int v = gv[k];
-      if (v < 0) continue;
-      double s = 0.0;
+      for (int k = 0; k < 4; ++k) {
+        if (!point_is_gel(kind, k)) continue;
+        const int q = rec_slot(rec, k);
+        double s = 0.0;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) { const double pc = p[c * nv + v]; s += pc * pc; }
-      l2 = fmax(l2, s);
+        for (int c = 0; c < 3; ++c) s += T.gq[c][q] * T.gq[c][q];
+        l2 = fmax(l2, s);
+      }
+    } else {
+      int id[4];
+      pair_point_ids(G, *V.I, pr, id);
+      const int kind = (int)((unsigned)pr.x >> kKindShift);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (!point_is_gel(kind, k)) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { const double pc = p[c * nv + id[k]]; s += pc * pc; }
+        l2 = fmax(l2, s);
+      }
     }
     const double l = sqrt(l2);
     const double gap = kCcdGap * d0;
@@ -744,7 +868,16 @@ __device__ __forceinline__ double pairs_ccd(const View& V, const Shared& S, cons
       if (l * (amax - t) <= d - gap) { t = amax; break; }
       t += (d - gap) / l;
       PairPts Q;
-      load_pair(V, S, pr, x, p, t, Q);
+      get_pair<LDS>(V, S, T, pr, rec, x, p, t, Q);
+      if constexpr (LDS) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int q = Q.gid[k];
+          if (q < 0) continue;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) Q.z[k][c] = fma(t, T.gq[c][q], Q.z[k][c]);
+        }
+      }
       Feature g;
       classify(Q, g);
       double r[3];
@@ -759,35 +892,52 @@ __device__ __forceinline__ double pairs_ccd(const View& V, const Shared& S, cons
 // ---------------------------------------------------------------------------
 // Lagged friction (Supp. A, eqs. friction_energy, friction_mollifier)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void fric_delta(const View& V, const Shared& S, const FricPair& F, const double* x,
-                                  const double* p, double alpha, double Dl[3]) {
+__device__ __forceinline__ int fric_gslot(const FricPair& F, int k) { return (int)(F.slot >> (10 * k)) & 1023; }
+__device__ __forceinline__ int fric_islot(const FricPair& F, int k) { return (int)(F.slot >> (32 + 10 * k)) & 1023; }
+
+// Tangential relative displacement input: Dl = sum a x - sum c y - base.
+template <bool LDS>
+__device__ __forceinline__ void fric_delta(const View& V, const Shared& S, const Tile& T, const FricPair& F,
+                                           const double* x, const double* p, double alpha, double Dl[3]) {
   const int nv = V.G->n_v;
   const IndDev& I = *V.I;
   #pragma unroll
   for (int c = 0; c < 3; ++c) Dl[c] = -F.base[c];
   #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const int v = F.gv[k];
-    if (v < 0) continue;
-    #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double xv = x[c * nv + v];
-      Dl[c] += F.a[k] * (p ? fma(alpha, p[c * nv + v], xv) : xv);
+    if (F.gv[k] < 0) continue;
+    if constexpr (LDS) {
+      const int q = fric_gslot(F, k);
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) Dl[c] += F.a[k] * T.gx[c][q];
+    } else {
+      const int v = F.gv[k];
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double xv = x[c * nv + v];
+        Dl[c] += F.a[k] * (p ? fma(alpha, p[c * nv + v], xv) : xv);
+      }
     }
   }
   #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const int j = F.iv[k];
-    if (j < 0) continue;
+    if (F.iv[k] < 0) continue;
     double y[3];
-    ind_world(S, I, j, y);
+    if constexpr (LDS) {
+      const int q = fric_islot(F, k);
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) y[c] = T.iy[c][q];
+    } else {
+      ind_world(S, I, F.iv[k], y);
+    }
     #pragma unroll
     for (int c = 0; c < 3; ++c) Dl[c] -= F.c[k] * y[c];
   }
 }
 
-__device__ __forceinline__ double fric_eval(const View& V, const Shared& S, const double* x, const double* p, double alpha,
-                            double* gout, double* dout, Tile& T) {
+template <bool LDS>
+__device__ __forceinline__ double fric_eval(const View& V, const Shared& S, Tile& T, const double* x,
+                                            const double* p, double alpha, double* gout, double* dout) {
   const GelDev& G = *V.G;
   const int nv = G.n_v;
   const double eps = V.E->eps_v;
@@ -795,7 +945,7 @@ __device__ __forceinline__ double fric_eval(const View& V, const Shared& S, cons
   for (int i = threadIdx.x; i < V.nfric; i += blockDim.x) {
     const FricPair F = V.fric[i];
     double Dl[3];
-    fric_delta(V, S, F, x, p, alpha, Dl);
+    fric_delta<LDS>(V, S, T, F, x, p, alpha, Dl);
     const double nD = dot3(F.n, Dl);
     double TD[3];
     #pragma unroll
@@ -810,20 +960,29 @@ __device__ __forceinline__ double fric_eval(const View& V, const Shared& S, cons
     for (int k = 0; k < 3; ++k) {
       const int v = F.gv[k];
       if (v < 0) continue;
-      const int q = pair_slot(V, F.slot, k, v);
-      if (q == (int)kNoSlot) continue;
+      if (!LDS && G.fixed[v]) continue;
       const double a = F.a[k];
       #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const double h = fos * (1.0 - F.n[c] * F.n[c]) + corr * uh[c] * uh[c];
-        pair_add(T, q, gout, dout, c * nv + v, c, F.mulam * a * fos * TD[c], F.mulam * a * a * h);
+        const double gval = F.mulam * a * fos * TD[c], dval = F.mulam * a * a * h;
+        if constexpr (LDS) {
+          const int q = fric_gslot(F, k);
+          atomicAdd(&T.gq[c][q], gval);
+          atomicAdd(&T.gd[c][q], dval);
+        } else {
+          atomicAdd(&gout[c * nv + v], gval);
+          atomicAdd(&dout[c * nv + v], dval);
+        }
       }
     }
   }
   return energy;
 }
 
-__device__ __forceinline__ double fric_curv(const View& V, const Shared& S, const double* x, const double* p) {
+template <bool LDS>
+__device__ __forceinline__ double fric_curv(const View& V, const Shared& S, const Tile& T, const double* x,
+                                            const double* p) {
   const GelDev& G = *V.G;
   const int nv = G.n_v;
   const double eps = V.E->eps_v;
@@ -831,7 +990,7 @@ __device__ __forceinline__ double fric_curv(const View& V, const Shared& S, cons
   for (int i = threadIdx.x; i < V.nfric; i += blockDim.x) {
     const FricPair F = V.fric[i];
     double Dl[3];
-    fric_delta(V, S, F, x, nullptr, 0.0, Dl);
+    fric_delta<LDS>(V, S, T, F, x, nullptr, 0.0, Dl);
     const double nD = dot3(F.n, Dl);
     double TD[3];
     #pragma unroll
@@ -843,9 +1002,15 @@ __device__ __forceinline__ double fric_curv(const View& V, const Shared& S, cons
     #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int v = F.gv[k];
-      if (v < 0 || G.fixed[v]) continue;
-      #pragma unroll
-      for (int c = 0; c < 3; ++c) q[c] += F.a[k] * p[c * nv + v];
+      if (v < 0) continue;
+      if constexpr (LDS) {
+        const int sl = fric_gslot(F, k);
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) q[c] += F.a[k] * T.gq[c][sl];
+      } else {
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) q[c] += F.a[k] * p[c * nv + v];
+      }
     }
     const double nq = dot3(F.n, q);
     double uq = 0.0;
@@ -866,30 +1031,35 @@ __device__ __forceinline__ int cell_of(double v, double o, double inv, int dim) 
 }
 
 // Writes the friction record of a pair closer than dhat at the lag state.
+// id: vertex ids of the four points; rec: the pair's slot record (used only
+// when the env has slots).
 __device__ __forceinline__ void make_fric(const View& V, const PairPts& P, const Feature& f, const double r[3],
-                                 double d, int2 pr, FricPair& F) {
-  const IndDev& I = *V.I;
+                                          double d, const int id[4], uint64_t rec, FricPair& F) {
   const EnvDev& E = *V.E;
   const int kind = P.kind;
   const double sgn = (kind == kFV) ? -1.0 : 1.0;  // r = gel - indenter for VF and EE
   #pragma unroll
   for (int c = 0; c < 3; ++c) F.n[c] = sgn * r[c] / d;
-  const int gp = pr.x & kPrimMask, ip = pr.y;
   #pragma unroll
   for (int k = 0; k < 3; ++k) { F.gv[k] = -1; F.iv[k] = -1; F.a[k] = 0.0; F.c[k] = 0.0; }
+  uint64_t gs = 0x3fffffffull, is = 0x3fffffffull;  // three 10-bit kNoSlot10 fields each
   int ng = 0, ni = 0;
   #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if (P.gid[k] >= 0) { F.gv[ng] = P.gid[k]; F.a[ng] = sgn * f.c[k]; ++ng; }
+    const uint64_t q = (uint64_t)rec_slot(rec, k) & 1023u;
+    if (point_is_gel(kind, k)) {
+      F.gv[ng] = id[k];
+      F.a[ng] = sgn * f.c[k];
+      gs = (gs & ~(1023ull << (10 * ng))) | (q << (10 * ng));
+      ++ng;
+    } else {
+      F.iv[ni] = id[k];
+      F.c[ni] = -sgn * f.c[k];
+      is = (is & ~(1023ull << (10 * ni))) | (q << (10 * ni));
+      ++ni;
+    }
   }
-  int ids[3] = {-1, -1, -1};
-  if (kind == kVF) { ids[0] = I.tri[ip]; ids[1] = I.tri[I.n_f + ip]; ids[2] = I.tri[2 * I.n_f + ip]; }
-  else if (kind == kFV) { ids[0] = ip; }
-  else { ids[0] = I.edge[ip]; ids[1] = I.edge[I.n_e + ip]; }
-  #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (P.gid[k] < 0) { F.iv[ni] = ids[ni]; F.c[ni] = -sgn * f.c[k]; ++ni; }
-  }
+  F.slot = gs | (is << 32);
   #pragma unroll
   for (int c = 0; c < 3; ++c) {
     double s = 0.0;
@@ -900,13 +1070,11 @@ __device__ __forceinline__ void make_fric(const View& V, const PairPts& P, const
   double b, b1, b2;
   barrier3(d, E.dhat, b, b1, b2);
   F.mulam = -E.mu_f * E.kappa * b1;
-  (void)gp;
 }
 
-// mode 0: candidate pairs (d < thr) into V.pairs; mode 1: friction records for
-// pairs with d < dhat; mode 2: distances only; mode 3: coarse candidates
-// (d < thr) into V.outer. Returns the thread's smallest d.
-__device__ __forceinline__ double cull(View& V, Shared& S, const double* x, double thr, int mode, int cap) {
+// Coarse candidates (exact distance < thr) into V.outer, at most cap of them
+// (S.overflow set beyond). Returns the thread's smallest distance.
+__device__ __forceinline__ double cull(View& V, Shared& S, const double* x, double thr, int cap) {
   const GelDev& G = *V.G;
   const IndDev& I = *V.I;
   const int nv = G.n_v;
@@ -994,17 +1162,9 @@ __device__ __forceinline__ double cull(View& V, Shared& S, const double* x, doub
             double r[3];
             const double d = pair_distance(P, f, r);
             dmin = fmin(dmin, d);
-            if (mode == 0 && d < thr) {
-              const int slot = atomicAdd(&S.count, 1);
-              if (slot < cap) { V.pairs[slot] = pr; V.pd[slot] = d; }
-              else S.overflow = 1;
-            } else if (mode == 3 && d < thr) {
+            if (d < thr) {
               const int slot = atomicAdd(&S.count, 1);
               if (slot < cap) V.outer[slot] = pr;
-              else S.overflow = 1;
-            } else if (mode == 1 && d < V.E->dhat && d > 0.0) {
-              const int slot = atomicAdd(&S.count, 1);
-              if (slot < cap) make_fric(V, P, f, r, d, pr, V.fric[slot]);
               else S.overflow = 1;
             }
           }
@@ -1036,13 +1196,16 @@ struct Solver {
 
 // Inner candidate list from the outer one: exact distance of every coarse pair,
 // keep those below thr. Work is one pair per thread, so it stays balanced.
-__device__ __forceinline__ void filter_pairs(View& V, Shared& S, const double* x, double thr, int cap) {
+template <bool LDS>
+__device__ __forceinline__ void filter_pairs(View& V, Shared& S, const Tile& T, const double* x, double thr,
+                                             int cap) {
   if (threadIdx.x == 0) { S.count = 0; S.overflow = 0; }
   __syncthreads();
   for (int i = threadIdx.x; i < V.nouter; i += blockDim.x) {
     const int2 pr = V.outer[i];
+    const uint64_t rec = LDS ? V.oslot[i] : 0ull;
     PairPts P;
-    load_pair(V, S, pr, x, nullptr, 0.0, P);
+    get_pair<LDS>(V, S, T, pr, rec, x, nullptr, 0.0, P);
     Feature f;
     classify(P, f);
     double r[3];
@@ -1052,7 +1215,7 @@ __device__ __forceinline__ void filter_pairs(View& V, Shared& S, const double* x
       if (slot < cap) {
         V.pairs[slot] = pr;
         V.pd[slot] = d;
-        V.pslot[slot] = V.oslot[i];
+        V.pslot[slot] = rec;
       } else {
         S.overflow = 1;
       }
@@ -1061,13 +1224,22 @@ __device__ __forceinline__ void filter_pairs(View& V, Shared& S, const double* x
   __syncthreads();
 }
 
-// Largest displacement of any indenter point between two poses: |dt| + theta r_max.
+// Largest displacement of any indenter point between two poses:
+// |dt| + 2 sin(theta/2) r_max, theta the relative rotation angle; sin(theta/2)
+// is the norm of the vector part of q_b conj(q_a) (unit quaternions), which
+// stays accurate for small angles.
 __device__ __forceinline__ double ind_motion(const double a[7], const double b[7], double r_max) {
-  double dt = 0.0, qa = 0.0, na = 0.0, nb = 0.0;
+  double dt = 0.0, na = 0.0, nb = 0.0;
   for (int i = 0; i < 3; ++i) dt += (a[i] - b[i]) * (a[i] - b[i]);
-  for (int i = 3; i < 7; ++i) { qa += a[i] * b[i]; na += a[i] * a[i]; nb += b[i] * b[i]; }
-  const double c = fmin(1.0, fabs(qa) / sqrt(na * nb));
-  return sqrt(dt) + 2.0 * acos(c) * r_max;
+  for (int i = 3; i < 7; ++i) { na += a[i] * a[i]; nb += b[i] * b[i]; }
+  const double wa = a[3], wb = b[3];
+  const double va[3] = {a[4], a[5], a[6]}, vb[3] = {b[4], b[5], b[6]};
+  double v[3];
+  v[0] = wa * vb[0] - wb * va[0] - (vb[1] * va[2] - vb[2] * va[1]);
+  v[1] = wa * vb[1] - wb * va[1] - (vb[2] * va[0] - vb[0] * va[2]);
+  v[2] = wa * vb[2] - wb * va[2] - (vb[0] * va[1] - vb[1] * va[0]);
+  const double sh = fmin(1.0, sqrt((v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / (na * nb)));
+  return sqrt(dt) + 2.0 * sh * r_max * (1.0 + 1e-12);
 }
 
 // Largest surface-vertex displacement since each snapshot and largest |p| on the
@@ -1106,77 +1278,87 @@ __device__ __forceinline__ void snapshot(Solver& s, const double* x, double* dst
   __syncthreads();
 }
 
-// Packed contact slots of up to three gel vertices (vmap holds slot + 1).
-__device__ __forceinline__ uint64_t pack_slots(const View& V, const int gv[3]) {
-  uint64_t r = 0;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    uint64_t q = kNoSlot;
-    if (gv[k] >= 0) {
-      const int m = V.vmap[gv[k]];
-      if (m > 0) q = (uint64_t)(m - 1);
-    }
-    r |= q << (16 * k);
-  }
-  return r;
-}
-
-// Contact slots of the outer list: every free gel vertex of an outer pair or a
-// friction pair gets a dense id (slot_v maps back), and each pair records the
-// slots of its vertices. More than kContactSlots vertices: slots_ok = 0 and
-// the pair passes use global atomics. vmap is all zero again on return.
+// Contact slots of the outer list: every gel and indenter vertex of an outer
+// pair or a friction pair gets a dense slot (slot_v / islot_v map back), each
+// outer pair gets its record (slots of its four points and its kind) and each
+// friction pair its slots. More than kGelSlots gel or kIndSlots indenter
+// vertices: slots_ok = 0 and the pair passes use the global path. The maps
+// vmap / imap are all zero again on return.
 __device__ __forceinline__ void build_slots(Solver& s) {
   View& V = s.V;
   const GelDev& G = *V.G;
+  const IndDev& I = *V.I;
   Shared& S = *s.S;
   for (int i = threadIdx.x; i < V.nouter; i += blockDim.x) {
-    int gv[3];
-    pair_gel_ids(G, V.outer[i], gv);
+    const int2 pr = V.outer[i];
+    const int kind = (int)((unsigned)pr.x >> kKindShift);
+    int id[4];
+    pair_point_ids(G, I, pr, id);
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      if (gv[k] >= 0 && !G.fixed[gv[k]]) V.vmap[gv[k]] = -1;
+    for (int k = 0; k < 4; ++k) {
+      if (point_is_gel(kind, k)) V.vmap[id[k]] = -1;
+      else V.imap[id[k]] = -1;
+    }
   }
   for (int i = threadIdx.x; i < V.nfric; i += blockDim.x) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const int v = V.fric[i].gv[k];
-      if (v >= 0 && !G.fixed[v]) V.vmap[v] = -1;
+      if (V.fric[i].gv[k] >= 0) V.vmap[V.fric[i].gv[k]] = -1;
+      if (V.fric[i].iv[k] >= 0) V.imap[V.fric[i].iv[k]] = -1;
     }
   }
-  if (threadIdx.x == 0) S.count = 0;
+  if (threadIdx.x == 0) { S.count = 0; S.overflow = 0; }
   __syncthreads();
-  // every marked vertex is a free surface vertex
-  for (int i = threadIdx.x; i < G.n_sv; i += blockDim.x) {
-    const int v = G.surf_v[i];
+  for (int v = threadIdx.x; v < G.n_v; v += blockDim.x) {
     if (V.vmap[v] == -1) {
       const int q = atomicAdd(&S.count, 1);
-      if (q < kContactSlots) {
-        V.vmap[v] = q + 1;
-        V.slot_v[q] = v;
-      }
+      if (q < kGelSlots) { V.vmap[v] = q + 1; V.slot_v[q] = v; }
+    }
+  }
+  for (int j = threadIdx.x; j < I.n_v; j += blockDim.x) {
+    if (V.imap[j] == -1) {
+      const int q = atomicAdd(&S.overflow, 1);
+      if (q < kIndSlots) { V.imap[j] = q + 1; V.islot_v[q] = j; }
     }
   }
   __syncthreads();
-  const int n = S.count;
-  const int ok = n <= kContactSlots;
+  const int ng = S.count, ni = S.overflow;
+  const int ok = ng <= kGelSlots && ni <= kIndSlots;
   if (ok) {
     for (int i = threadIdx.x; i < V.nouter; i += blockDim.x) {
-      int gv[3];
-      pair_gel_ids(G, V.outer[i], gv);
-      V.oslot[i] = pack_slots(V, gv);
+      const int2 pr = V.outer[i];
+      const int kind = (int)((unsigned)pr.x >> kKindShift);
+      int id[4];
+      pair_point_ids(G, I, pr, id);
+      uint64_t rec = (uint64_t)kind << (4 * kRecBits);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int m = point_is_gel(kind, k) ? V.vmap[id[k]] : V.imap[id[k]];
+        rec |= (uint64_t)(m - 1) << (kRecBits * k);
+      }
+      V.oslot[i] = rec;
     }
     for (int i = threadIdx.x; i < V.nfric; i += blockDim.x) {
-      int gv[3] = {V.fric[i].gv[0], V.fric[i].gv[1], V.fric[i].gv[2]};
-      V.fric[i].slot = pack_slots(V, gv);
+      uint64_t gs = 0, is = 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int gv = V.fric[i].gv[k], iv = V.fric[i].iv[k];
+        gs |= (uint64_t)(gv >= 0 ? V.vmap[gv] - 1 : (int)kNoSlot10) << (10 * k);
+        is |= (uint64_t)(iv >= 0 ? V.imap[iv] - 1 : (int)kNoSlot10) << (10 * k);
+      }
+      V.fric[i].slot = gs | (is << 32);
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < G.n_sv; i += blockDim.x) V.vmap[G.surf_v[i]] = 0;
+  for (int v = threadIdx.x; v < G.n_v; v += blockDim.x) V.vmap[v] = 0;
+  for (int j = threadIdx.x; j < I.n_v; j += blockDim.x) V.imap[j] = 0;
   V.slots_ok = ok;
-  V.nslots = ok ? n : 0;
+  V.nslots = ok ? ng : 0;
+  V.nislots = ok ? ni : 0;
   if (threadIdx.x == 0) {
     s.L->slots_ok = ok;
     s.L->n_slots = V.nslots;
+    s.L->n_islots = V.nislots;
   }
   __syncthreads();
 }
@@ -1192,7 +1374,7 @@ __device__ __forceinline__ void build_slots(Solver& s) {
 __device__ __forceinline__ bool rebuild_outer(Solver& s, const double* x) {
   View& V = s.V;
   const unsigned long long t0 = tick();
-  cull(V, *s.S, x, V.E->dhat + s.buffer_out, 3, s.outer_cap);
+  cull(V, *s.S, x, V.E->dhat + s.buffer_out, s.outer_cap);
   const int ov = s.S->overflow;
   const int cnt = s.S->count;
   __syncthreads();
@@ -1214,7 +1396,12 @@ __device__ __forceinline__ bool rebuild_outer(Solver& s, const double* x) {
 __device__ __forceinline__ bool refilter(Solver& s, const double* x) {
   View& V = s.V;
   const unsigned long long t0 = tick();
-  filter_pairs(V, *s.S, x, V.E->dhat + s.buffer, s.pair_cap);
+  if (V.slots_ok) {
+    stage_points(V, *s.S, *s.T, x, nullptr, 0.0, 0);
+    filter_pairs<true>(V, *s.S, *s.T, x, V.E->dhat + s.buffer, s.pair_cap);
+  } else {
+    filter_pairs<false>(V, *s.S, *s.T, x, V.E->dhat + s.buffer, s.pair_cap);
+  }
   const int ov = s.S->overflow;
   const int cnt = s.S->count;
   __syncthreads();
@@ -1261,21 +1448,25 @@ __device__ __forceinline__ void load_lists(Solver& s) {
   s.V.npairs = s.L->valid_i ? s.L->n_inner : 0;
   s.V.slots_ok = s.L->valid_o ? s.L->slots_ok : 0;
   s.V.nslots = s.V.slots_ok ? s.L->n_slots : 0;
+  s.V.nislots = s.V.slots_ok ? s.L->n_islots : 0;
 }
 
 // Friction lag and smallest distance at (x, current pose) from the outer list:
 // exact distance of every coarse pair; pairs closer than dhat get a friction
 // record when mode == 1. Requires a valid outer list. Returns the thread's min d.
-__device__ __forceinline__ double lag_from_outer(Solver& s, const double* x, int mode) {
+template <bool LDS>
+__device__ __forceinline__ double lag_pass(Solver& s, const double* x, int mode) {
   View& V = s.V;
   Shared& S = *s.S;
+  const Tile& T = *s.T;
   if (threadIdx.x == 0) { S.count = 0; S.overflow = 0; }
   __syncthreads();
   double dmin = kInf;
   for (int i = threadIdx.x; i < V.nouter; i += blockDim.x) {
     const int2 pr = V.outer[i];
+    const uint64_t rec = LDS ? V.oslot[i] : 0ull;
     PairPts P;
-    load_pair(V, S, pr, x, nullptr, 0.0, P);
+    get_pair<LDS>(V, S, T, pr, rec, x, nullptr, 0.0, P);
     Feature f;
     classify(P, f);
     double r[3];
@@ -1284,8 +1475,9 @@ __device__ __forceinline__ double lag_from_outer(Solver& s, const double* x, int
     if (mode == 1 && d < V.E->dhat && d > 0.0) {
       const int slot = atomicAdd(&S.count, 1);
       if (slot < s.fric_cap) {
-        make_fric(V, P, f, r, d, pr, V.fric[slot]);
-        V.fric[slot].slot = V.oslot[i];  // friction pairs are outer pairs: same gel vertices
+        int id[4];
+        pair_point_ids(*V.G, *V.I, pr, id);
+        make_fric(V, P, f, r, d, id, rec, V.fric[slot]);
       } else {
         S.overflow = 1;
       }
@@ -1293,6 +1485,31 @@ __device__ __forceinline__ double lag_from_outer(Solver& s, const double* x, int
   }
   __syncthreads();
   return dmin;
+}
+
+__device__ __forceinline__ double lag_from_outer(Solver& s, const double* x, int mode) {
+  if (s.V.slots_ok) {
+    stage_points(s.V, *s.S, *s.T, x, nullptr, 0.0, 0);
+    return lag_pass<true>(s, x, mode);
+  }
+  return lag_pass<false>(s, x, mode);
+}
+
+// Smallest pair distance and active count at x over the inner list (block-wide).
+__device__ __forceinline__ double dmin_all(Solver& s, const double* x, int& nactive) {
+  View& V = s.V;
+  int na = 0;
+  double dm;
+  if (V.slots_ok) {
+    stage_points(V, *s.S, *s.T, x, nullptr, 0.0, 0);
+    dm = pairs_dmin<true>(V, *s.S, *s.T, x, na);
+  } else {
+    dm = pairs_dmin<false>(V, *s.S, *s.T, x, na);
+  }
+  double w[2] = {(double)na, -dm};
+  block_reduce<1, 1>(w, *s.S);
+  nactive = (int)w[0];
+  return -w[1];
 }
 
 // Evaluates Pi, grad (-> g) and diag at x + alpha p. Returns energy; feasible in flag.
@@ -1307,29 +1524,15 @@ __device__ __forceinline__ double eval_all(Solver& s, const double* x, const dou
   double eel = v[0];
   t0 = tick();
   Tile& T = *s.T;
-  const int nv = V.G->n_v;
-  // contact terms accumulate per contact slot in LDS (the tile storage is free
-  // between element passes) and are added to g, dg once per vertex
+  const Shared& S = *s.S;
   if (V.slots_ok) {
-    for (int i = threadIdx.x; i < V.nslots; i += blockDim.x) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) { T.cg[c][i] = 0.0; T.cd[c][i] = 0.0; }
-    }
-    __syncthreads();
-  }
-  v[0] += pairs_eval(V, *s.S, x, p, alpha, g, dg, T, feas, nact);
-  if (V.nfric > 0) v[0] += fric_eval(V, *s.S, x, p, alpha, g, dg, T);
-  if (V.slots_ok) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < V.nslots; i += blockDim.x) {
-      const int vtx = V.slot_v[i];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        g[c * nv + vtx] += T.cg[c][i];
-        dg[c * nv + vtx] += T.cd[c][i];
-      }
-    }
-    __syncthreads();
+    stage_points(V, S, T, x, p, alpha, 2);
+    v[0] += pairs_eval<true>(V, S, T, x, p, alpha, g, dg, feas, nact);
+    if (V.nfric > 0) v[0] += fric_eval<true>(V, S, T, x, p, alpha, g, dg);
+    flush_slots(V, T, g, dg);
+  } else {
+    v[0] += pairs_eval<false>(V, S, T, x, p, alpha, g, dg, feas, nact);
+    if (V.nfric > 0) v[0] += fric_eval<false>(V, S, T, x, p, alpha, g, dg);
   }
   v[1] = (double)nact;
   v[2] = feas ? 0.0 : 1.0;  // max -> any infeasible
@@ -1348,8 +1551,16 @@ __device__ __forceinline__ double curvature_all(Solver& s, const double* x, cons
   double c = elem_curv(V, x, p, *s.T);
   tock(*s.S, 2, t0);
   t0 = tick();
-  c += pairs_curv(V, *s.S, x, p);
-  if (V.nfric > 0) c += fric_curv(V, *s.S, x, p);
+  Tile& T = *s.T;
+  const Shared& S = *s.S;
+  if (V.slots_ok) {
+    stage_points(V, S, T, x, p, 0.0, 1);
+    c += pairs_curv<true>(V, S, T, x, p);
+    if (V.nfric > 0) c += fric_curv<true>(V, S, T, x, p);
+  } else {
+    c += pairs_curv<false>(V, S, T, x, p);
+    if (V.nfric > 0) c += fric_curv<false>(V, S, T, x, p);
+  }
   double w[1] = {c};
   block_reduce<1, 0>(w, *s.S);
   tock(*s.S, 3, t0);
@@ -1411,7 +1622,13 @@ __device__ __forceinline__ int pncg(Solver& s, double tol, int max_iters, int& i
     }
     t0 = tick();
     {
-      double w = pairs_ccd(V, *s.S, x, V.p, alpha);
+      double w;
+      if (V.slots_ok) {
+        stage_points(V, *s.S, *s.T, x, V.p, 0.0, 1);
+        w = pairs_ccd<true>(V, *s.S, *s.T, x, V.p, alpha);
+      } else {
+        w = pairs_ccd<false>(V, *s.S, *s.T, x, V.p, alpha);
+      }
       alpha = block_min(w, *s.S);
     }
     tock(*s.S, 4, t0);
@@ -1499,10 +1716,13 @@ __device__ __forceinline__ void make_view(const StepParams& P, int e, View& V) {
   V.vmap = P.vmap + E.vtxoff;
   V.oslot = P.oslot + E.ooff;
   V.pslot = P.pslot + E.poff;
-  V.slot_v = P.slot_v + (long long)e * kContactSlots;
+  V.slot_v = P.slot_v + (long long)e * kGelSlots;
+  V.imap = P.imap + E.imoff;
+  V.islot_v = P.islot_v + (long long)e * kIndSlots;
   V.npairs = 0;
   V.nfric = 0;
   V.nslots = 0;
+  V.nislots = 0;
   V.slots_ok = 0;
   V.mixed = P.precision;
 }
@@ -1660,8 +1880,7 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
       if (stt & (kOverflow | kInfeasible)) { status_acc = stt; break; }
       if (!(stt & kConverged)) status_acc = (status_acc & ~kConverged) | stt;
       int na2 = 0;
-      double dm = pairs_dmin(V, S, V.x, na2);
-      dmin = block_min(dm, S);
+      dmin = dmin_all(s, V.x, na2);
     }
     if (tau < 1.0 && !(status_acc & (kOverflow | kInfeasible))) status_acc = (status_acc & ~kConverged) | kSubsteps;
   }
@@ -1676,11 +1895,8 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
   }
   {
     int na2 = 0;
-    double dm = pairs_dmin(V, S, V.x, na2);
-    double w[2] = {(double)na2, -dm};
-    block_reduce<1, 1>(w, S);
-    st.d_min = -w[1];
-    st.n_active = (int)w[0];
+    st.d_min = dmin_all(s, V.x, na2);
+    st.n_active = na2;
   }
   st.substeps = sub;
   st.restarts = s.restarts;
@@ -1740,8 +1956,7 @@ __global__ void __launch_bounds__(256) t2r_eval_kernel(EvalParams Q) {
   double curv = 0.0;
   if (Q.has_p) curv = curvature_all(s, V.x, V.p);
   int na2 = 0;
-  double dm = pairs_dmin(V, S, V.x, na2);
-  dm = block_min(dm, S);
+  const double dm = dmin_all(s, V.x, na2);
   for (int j = threadIdx.x; j < 3 * nv; j += blockDim.x) {
     const int v = j / 3, c = j - 3 * v;
     if (Q.grad_out) Q.grad_out[j] = V.g0[c * nv + v];

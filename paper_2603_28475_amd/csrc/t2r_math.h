@@ -200,11 +200,20 @@ __device__ __forceinline__ void mollifier3(double s, double eps, double& f, doub
 //   p^T Hess(d) p = (|q|^2 - v^T M^-1 v)/d - (n.q)^2/d,
 //        q = sum c_i p_i,  v_w = sum_i Cw_iw (r.p_i) + c_i (D_w.p_i)
 // ---------------------------------------------------------------------------
+// Cw has entries in {-1, 0, 1}: two bits per (point i, free parameter w) at
+// bit 4 i + 2 w (0: 0, 1: +1, 3: -1), which keeps a feature in few registers.
 struct Feature {
   double c[4];
-  double cw[4][2];
+  int cw;
   int k;
 };
+
+__host__ __device__ constexpr int cw_bits(int i, int w, int sign) { return (sign > 0 ? 1 : 3) << (4 * i + 2 * w); }
+
+__device__ __forceinline__ double cw_of(const Feature& f, int i, int w) {
+  const int b = (f.cw >> (4 * i + 2 * w)) & 3;
+  return b == 0 ? 0.0 : (b == 1 ? 1.0 : -1.0);
+}
 
 __device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
@@ -224,8 +233,7 @@ __device__ __forceinline__ void classify_pt(const double p[3], const double a[3]
     bp[i] = p[i] - b[i];
     cp[i] = p[i] - c[i];
   }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) f.cw[i][0] = f.cw[i][1] = 0.0;
+  f.cw = 0;
   f.c[0] = 1.0;
   const double d1 = dot3(ab, ap), d2 = dot3(ac, ap);
   if (d1 <= 0.0 && d2 <= 0.0) {  // vertex a
@@ -241,7 +249,7 @@ __device__ __forceinline__ void classify_pt(const double p[3], const double a[3]
   if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {  // edge ab
     const double v = d1 / (d1 - d3);
     f.c[1] = -(1.0 - v); f.c[2] = -v; f.c[3] = 0.0; f.k = 1;
-    f.cw[1][0] = 1.0; f.cw[2][0] = -1.0;
+    f.cw = cw_bits(1, 0, 1) | cw_bits(2, 0, -1);
     return;
   }
   const double d5 = dot3(ab, cp), d6 = dot3(ac, cp);
@@ -253,21 +261,20 @@ __device__ __forceinline__ void classify_pt(const double p[3], const double a[3]
   if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {  // edge ac
     const double w = d2 / (d2 - d6);
     f.c[1] = -(1.0 - w); f.c[2] = 0.0; f.c[3] = -w; f.k = 1;
-    f.cw[1][0] = 1.0; f.cw[3][0] = -1.0;
+    f.cw = cw_bits(1, 0, 1) | cw_bits(3, 0, -1);
     return;
   }
   const double va = d3 * d6 - d5 * d4;
   if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {  // edge bc
     const double w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
     f.c[1] = 0.0; f.c[2] = -(1.0 - w); f.c[3] = -w; f.k = 1;
-    f.cw[2][0] = 1.0; f.cw[3][0] = -1.0;
+    f.cw = cw_bits(2, 0, 1) | cw_bits(3, 0, -1);
     return;
   }
   const double den = 1.0 / (va + vb + vc);  // face interior
   const double v = vb * den, w = vc * den;
   f.c[1] = -(1.0 - v - w); f.c[2] = -v; f.c[3] = -w; f.k = 2;
-  f.cw[1][0] = 1.0; f.cw[2][0] = -1.0;
-  f.cw[1][1] = 1.0; f.cw[3][1] = -1.0;
+  f.cw = cw_bits(1, 0, 1) | cw_bits(2, 0, -1) | cw_bits(1, 1, 1) | cw_bits(3, 1, -1);
 }
 
 // Edge-edge below this relative sin^2 of the angle is treated as parallel.
@@ -301,15 +308,14 @@ __device__ __forceinline__ void classify_ee(const double a0[3], const double a1[
     s = fmin(fmax((B - C) / A, 0.0), 1.0);
   }
   f.c[0] = 1.0 - s; f.c[1] = s; f.c[2] = -(1.0 - t); f.c[3] = -t;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) f.cw[i][0] = f.cw[i][1] = 0.0;
+  f.cw = 0;
   const bool si = (s > 0.0) && (s < 1.0);
   const bool ti = (t > 0.0) && (t < 1.0);
   // free parameters in order (s first): constant indices only, no dynamic indexing
-  if (si) { f.cw[0][0] = -1.0; f.cw[1][0] = 1.0; }
+  if (si) f.cw |= cw_bits(0, 0, -1) | cw_bits(1, 0, 1);
   if (ti) {
-    if (si) { f.cw[2][1] = 1.0; f.cw[3][1] = -1.0; }
-    else { f.cw[2][0] = 1.0; f.cw[3][0] = -1.0; }
+    if (si) f.cw |= cw_bits(2, 1, 1) | cw_bits(3, 1, -1);
+    else f.cw |= cw_bits(2, 0, 1) | cw_bits(3, 0, -1);
   }
   f.k = (si ? 1 : 0) + (ti ? 1 : 0);
 }

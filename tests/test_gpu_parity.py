@@ -196,6 +196,21 @@ def test_friction_sequence_matches_newton_oracle():
     assert np.abs(m - gold["markers"]).max() <= 1e-6
 
 
+def test_peg_friction_sequence_matches_newton_oracle():
+    """Tilted flat-ended peg with every pair kind active, lagged friction: three
+    press steps then two shear steps, against the oracle's Newton minimiser."""
+    t2r = _gpu()
+    from scenes.configs import peg_press_484v
+    w = peg_press_484v(mu_f=0.5, shear=(0.1, 0.05), n_shear=2)
+    gold = np.load(os.path.join(HERE, "golden", "peg_press_484v_friction_newton.npz"))
+    sim = _build(t2r, w, tol=1e-10, substep_tol=1e-8, max_iters=400000)
+    poses = np.stack([e.poses for e in w.envs])
+    m, x, st = _run_steps(sim, poses, want_x=True)
+    assert np.all(st & 1), st
+    assert np.abs(x - gold["x"]).max() <= 1e-6
+    assert np.abs(m - gold["markers"]).max() <= 1e-6
+
+
 def _certify_equilibrium(w, env, pose, x, bound=1e-6):
     """The oracle's Newton started from x must not move: x is a minimiser of Pi."""
     from oracle.newton import newton_solve
