@@ -7,6 +7,16 @@
 
 #include <hip/hip_runtime.h>
 
+// In the kernels' device code the device pointers held by these descriptors
+// are global-address-space pointers, so that their loads and stores are
+// global (not flat) memory instructions: a wait for LDS results then does not
+// also wait for outstanding global loads.
+#if defined(__HIP_DEVICE_COMPILE__) && defined(T2R_KERNEL_TU)
+#define T2R_G __attribute__((address_space(1)))
+#else
+#define T2R_G
+#endif
+
 namespace t2r {
 
 // Tet tiles: a workgroup stages one tile's vertices in LDS, evaluates its tets
@@ -42,9 +52,9 @@ struct Grid {              // uniform grid over an indenter's local bounding box
   double origin[3];
   double inv_cell;         // 1 / cell edge (cells are cubes)
   int dims[3];
-  const int* start;        // [ncell+1] CSR offsets
-  const int* items;        // primitive ids per cell
-  const double* box;       // [6][n_prim]: lo xyz, hi xyz of each primitive (local frame)
+  const T2R_G int* start;        // [ncell+1] CSR offsets
+  const T2R_G int* items;        // primitive ids per cell
+  const T2R_G double* box;       // [6][n_prim]: lo xyz, hi xyz of each primitive (local frame)
   int n_prim;
 };
 
@@ -52,32 +62,32 @@ struct GelDev {
   int n_v, n_t, n_tiles, n_sv, n_se, n_sf, n_m;
   double vol_total;        // sum of rest volumes
   double diag_rest_max;    // largest rest elastic diagonal entry for mu = 1, lam = 0
-  const double* X;         // [3][n_v]
-  const uint8_t* fixed;    // [n_v]
-  const int* tet;          // [4][n_t] global vertex ids, tiled order
-  const uint64_t* tet_local;  // [n_t] four 16-bit local ids
-  const double* Dinv;      // [9][n_t] Dm^-1 row-major entries
-  const double* vol;       // [n_t]
-  const float* Dinv32;     // [9][n_t] FP32 copy (mixed precision)
-  const float* vol32;      // [n_t]
-  const int* tile_tet;     // [n_tiles+1]
-  const int* tile_vstart;  // [n_tiles+1]
-  const int* tile_verts;   // global vertex ids of each tile
-  const uint8_t* tile_flags;  // kFirstTouch | kLastTouch | kFixedLast per tile vertex
-  const int* surf_v;       // [n_sv]
-  const int* surf_e;       // [2][n_se]
-  const int* surf_f;       // [3][n_sf]
-  const int* marker_tri;   // [3][n_m]
-  const double* marker_w;  // [3][n_m]
+  const T2R_G double* X;         // [3][n_v]
+  const T2R_G uint8_t* fixed;    // [n_v]
+  const T2R_G int* tet;          // [4][n_t] global vertex ids, tiled order
+  const T2R_G uint64_t* tet_local;  // [n_t] four 16-bit local ids
+  const T2R_G double* Dinv;      // [9][n_t] Dm^-1 row-major entries
+  const T2R_G double* vol;       // [n_t]
+  const T2R_G float* Dinv32;     // [9][n_t] FP32 copy (mixed precision)
+  const T2R_G float* vol32;      // [n_t]
+  const T2R_G int* tile_tet;     // [n_tiles+1]
+  const T2R_G int* tile_vstart;  // [n_tiles+1]
+  const T2R_G int* tile_verts;   // global vertex ids of each tile
+  const T2R_G uint8_t* tile_flags;  // kFirstTouch | kLastTouch | kFixedLast per tile vertex
+  const T2R_G int* surf_v;       // [n_sv]
+  const T2R_G int* surf_e;       // [2][n_se]
+  const T2R_G int* surf_f;       // [3][n_sf]
+  const T2R_G int* marker_tri;   // [3][n_m]
+  const T2R_G double* marker_w;  // [3][n_m]
 };
 
 struct IndDev {
   int n_v, n_f, n_e;
   double r_max;            // largest |y| over local vertices
   double box_lo[3], box_hi[3];  // local bounding box
-  const double* Y;         // [3][n_v]
-  const int* tri;          // [3][n_f]
-  const int* edge;         // [2][n_e]
+  const T2R_G double* Y;         // [3][n_v]
+  const T2R_G int* tri;          // [3][n_f]
+  const T2R_G int* edge;         // [2][n_e]
   Grid gv, ge, gf;         // grids of vertices, edges and triangles
 };
 
@@ -122,38 +132,38 @@ struct EnvStats {
 };
 
 struct StepParams {
-  const GelDev* gels;
-  const IndDev* inds;
-  const EnvDev* envs;
+  const T2R_G GelDev* gels;
+  const T2R_G IndDev* inds;
+  const T2R_G EnvDev* envs;
   int n_env;
   // state
-  double* x;               // [sum 3 n_v]
-  double* xprev;
-  double* g0;
-  double* g1;
-  double* diag;
-  double* p;
-  double* pose_prev;       // [n_env][7]
-  int2* pairs;             // [sum pair_cap]
-  double* pair_d;          // [sum pair_cap] distance of each candidate at the current x
-  int2* outer;             // [sum outer_cap] coarse candidates (wider radius, rebuilt rarely)
-  ListState* lists;        // [n_env]
-  double* xsnap;           // [sum 6 n_sv] surface positions when the lists were built
-  FricPair* fric;          // [sum fric_cap]
-  int* vmap;               // [sum n_v] gel vertex -> slot + 1 while slots are built, else 0
-  int* imap;               // [sum indenter n_v] ... for indenter vertices
-  uint64_t* oslot;         // [sum outer_cap] pair record of each outer pair
-  uint64_t* pslot;         // [sum pair_cap] ... of each inner pair
-  int* slot_v;             // [n_env][kGelSlots] gel vertex of each slot
-  int* islot_v;            // [n_env][kIndSlots] indenter vertex of each slot
-  EnvStats* stats;         // [n_env]
+  T2R_G double* x;               // [sum 3 n_v]
+  T2R_G double* xprev;
+  T2R_G double* g0;
+  T2R_G double* g1;
+  T2R_G double* diag;
+  T2R_G double* p;
+  T2R_G double* pose_prev;       // [n_env][7]
+  T2R_G int2* pairs;             // [sum pair_cap]
+  T2R_G double* pair_d;          // [sum pair_cap] distance of each candidate at the current x
+  T2R_G int2* outer;             // [sum outer_cap] coarse candidates (wider radius, rebuilt rarely)
+  T2R_G ListState* lists;        // [n_env]
+  T2R_G double* xsnap;           // [sum 6 n_sv] surface positions when the lists were built
+  T2R_G FricPair* fric;          // [sum fric_cap]
+  T2R_G int* vmap;               // [sum n_v] gel vertex -> slot + 1 while slots are built, else 0
+  T2R_G int* imap;               // [sum indenter n_v] ... for indenter vertices
+  T2R_G uint64_t* oslot;         // [sum outer_cap] pair record of each outer pair
+  T2R_G uint64_t* pslot;         // [sum pair_cap] ... of each inner pair
+  T2R_G int* slot_v;             // [n_env][kGelSlots] gel vertex of each slot
+  T2R_G int* islot_v;            // [n_env][kIndSlots] indenter vertex of each slot
+  T2R_G EnvStats* stats;         // [n_env]
   // inputs / outputs
-  const double* pose_in;   // [n_env][7]
-  const int* env_mask;     // [n_env] or null
-  double* markers_out;     // [sum n_m][3] or null
-  double* x_out;           // [sum n_v][3] or null
-  int* status_out;         // [n_env] or null
-  long long* x_out_off;    // [n_env] vertex offsets into x_out
+  const T2R_G double* pose_in;   // [n_env][7]
+  const T2R_G int* env_mask;     // [n_env] or null
+  T2R_G double* markers_out;     // [sum n_m][3] or null
+  T2R_G double* x_out;           // [sum n_v][3] or null
+  T2R_G int* status_out;         // [n_env] or null
+  T2R_G long long* x_out_off;    // [n_env] vertex offsets into x_out
   // options
   double clock_khz;        // wall-clock counter rate (phase timers)
   double tol, substep_tol;
@@ -163,12 +173,12 @@ struct StepParams {
 struct EvalParams {
   StepParams sp;           // state pointers point at scratch copies
   int env;
-  const double* pose;      // device [7]
-  const double* pose_lag;  // device [7]
+  const T2R_G double* pose;      // device [7]
+  const T2R_G double* pose_lag;  // device [7]
   int has_lag, has_p;
-  double* grad_out;        // [n_v][3] or null
-  double* diag_out;
-  double* scalars_out;     // [8]
+  T2R_G double* grad_out;        // [n_v][3] or null
+  T2R_G double* diag_out;
+  T2R_G double* scalars_out;     // [8]
 };
 
 }  // namespace t2r

@@ -20,6 +20,7 @@
 
 #include <hip/hip_runtime.h>
 
+#define T2R_KERNEL_TU 1
 #include "t2r_internal.h"
 #include "t2r_math.h"
 
@@ -182,25 +183,25 @@ __device__ __forceinline__ void ind_world(const Shared& S, const IndDev& I, int 
 // Env view: pointers of one env's state
 // ---------------------------------------------------------------------------
 struct View {
-  const GelDev* G;
-  const IndDev* I;
-  const EnvDev* E;
-  double* x;
-  double* xprev;
-  double* g0;
-  double* g1;
-  double* diag;
-  double* p;
-  int2* pairs;
-  double* pd;      // distance of each candidate pair at the current x
-  int2* outer;     // coarse candidates within the outer radius
-  FricPair* fric;
-  int* vmap;
-  int* imap;
-  uint64_t* oslot;
-  uint64_t* pslot;
-  int* slot_v;
-  int* islot_v;
+  const T2R_G GelDev* G;
+  const T2R_G IndDev* I;
+  const T2R_G EnvDev* E;
+  T2R_G double* x;
+  T2R_G double* xprev;
+  T2R_G double* g0;
+  T2R_G double* g1;
+  T2R_G double* diag;
+  T2R_G double* p;
+  T2R_G int2* pairs;
+  T2R_G double* pd;      // distance of each candidate pair at the current x
+  T2R_G int2* outer;     // coarse candidates within the outer radius
+  T2R_G FricPair* fric;
+  T2R_G int* vmap;
+  T2R_G int* imap;
+  T2R_G uint64_t* oslot;
+  T2R_G uint64_t* pslot;
+  T2R_G int* slot_v;
+  T2R_G int* islot_v;
   int npairs, nfric, nouter;
   int nslots, nislots, slots_ok;
   int mixed;
@@ -274,8 +275,9 @@ __device__ __forceinline__ int first_tet(const GelDev& G, int tile) {
 }
 
 // Evaluates sum V psi, the gradient and diag(H) of the elastic term at
-// x + alpha p into gout/dout ([3][n_v]). Returns energy (thread partial) and
-// clears `feasible` on an inverted tet. Fixed vertices get g = 0, diag = 1.
+// x + alpha p (p not null) into gout/dout ([3][n_v]). Returns energy (thread
+// partial) and clears `feasible` on an inverted tet. Fixed vertices get g = 0,
+// diag = 1.
 //
 // Pipeline per tile k: the positions of tile k+1, the slot ids of tile k+2,
 // the earlier partial sums of tile k's shared vertices and each thread's next
@@ -302,10 +304,7 @@ __device__ __forceinline__ double elem_eval_impl(const View& V, const double* x,
 #pragma unroll
   for (int s = 0; s < kSlots; ++s)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double xv = x[c * nv + cur.v[s]];
-      a[s][c] = p ? fma(alpha, p[c * nv + cur.v[s]], xv) : xv;
-    }
+    for (int c = 0; c < 3; ++c) a[s][c] = fma(alpha, p[c * nv + cur.v[s]], x[c * nv + cur.v[s]]);
   TetIn<MIXED> tc;
   load_tet<MIXED>(G, first_tet(G, 0), tc);
 #pragma unroll
@@ -327,10 +326,7 @@ __device__ __forceinline__ double elem_eval_impl(const View& V, const double* x,
 #pragma unroll
     for (int s = 0; s < kSlots; ++s)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double xv = x[c * nv + nxt.v[s]];
-        a[s][c] = p ? fma(alpha, p[c * nv + nxt.v[s]], xv) : xv;
-      }
+      for (int c = 0; c < 3; ++c) a[s][c] = fma(alpha, p[c * nv + nxt.v[s]], x[c * nv + nxt.v[s]]);
     SlotIdx nn;
     fetch_idx(G, tile + 2, nn);
     for (int e = t0 + threadIdx.x; e < t1; e += B) {
@@ -593,9 +589,9 @@ __device__ __forceinline__ double pair_distance(const PairPts& P, const Feature&
 }
 
 // Stages the slot points of the env for a pair pass. what: 0 positions x;
-// 1 positions x and p (in gq); 2 positions x + alpha p, |p|^2 (in pn) when
-// alpha > 0, cleared gradient/diagonal sums. The indenter points are placed at
-// the current pose. Starts and ends with a barrier.
+// 1 positions x and p (in gq); 2 positions x + alpha p, |p|^2 (in pn), cleared
+// gradient/diagonal sums (p not null for 1 and 2). The indenter points are
+// placed at the current pose. Starts and ends with a barrier.
 __device__ __forceinline__ void stage_points(const View& V, const Shared& S, Tile& T, const double* x,
                                              const double* p, double alpha, int what) {
   const GelDev& G = *V.G;
@@ -609,7 +605,7 @@ __device__ __forceinline__ void stage_points(const View& V, const Shared& S, Til
     for (int c = 0; c < 3; ++c) {
       const double xv = x[c * nv + v];
       if (what == 2) {
-        const double pv = p ? p[c * nv + v] : 0.0;
+        const double pv = p[c * nv + v];
         T.gx[c][i] = fma(alpha, pv, xv);
         T.gq[c][i] = 0.0;
         T.gd[c][i] = 0.0;
@@ -1698,10 +1694,10 @@ __device__ __forceinline__ int pncg(Solver& s, double tol, int max_iters, int& i
 }
 
 __device__ __forceinline__ void make_view(const StepParams& P, int e, View& V) {
-  const EnvDev& E = P.envs[e];
-  V.E = &E;
-  V.G = &P.gels[E.gel];
-  V.I = &P.inds[E.ind];
+  V.E = P.envs + e;
+  const EnvDev& E = *V.E;
+  V.G = P.gels + E.gel;
+  V.I = P.inds + E.ind;
   V.x = P.x + E.voff;
   V.xprev = P.xprev + E.voff;
   V.g0 = P.g0 + E.voff;
