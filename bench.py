@@ -37,7 +37,9 @@ def parse():
     ap.add_argument("--envs", type=int, default=2048)
     ap.add_argument("--precision", choices=["f64", "mixed"], default="mixed")
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--plain-envs", type=int, default=8, help="envs timed one launch each (0: skip)")
+    ap.add_argument("--plain-envs", type=int, default=4, help="envs timed one launch each (0: skip)")
+    ap.add_argument("--launch", choices=["sequence", "per-step"], default="sequence",
+                    help="sequence: the K timed load steps of every env in one launch; per-step: one launch per load step")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle budget (0: skip)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--quiet", action="store_true")
@@ -135,32 +137,54 @@ def main():
     stream = torch.cuda.current_stream()
     nv = sim.n_v[0]
 
-    for s in range(1, W + 1):
-        sim.step(pose_steps[s])
+    def seq(a, b):  # poses of load steps a..b-1 as (steps, n_env, 7)
+        return poses[:, a:b].transpose(0, 1).contiguous()
+
+    if W > 0:
+        if args.launch == "sequence":
+            sim.step_sequence(seq(1, W + 1))
+        else:
+            for s in range(1, W + 1):
+                sim.step(pose_steps[s])
         torch.cuda.synchronize()
         st = sim.stats()
-        log(args, f"warmup step {s}: iters/env {np.mean([x['iters'] for x in st]):.0f}")
+        log(args, f"warmup ({W} load steps): iters/env {np.mean([x['iters'] for x in st]):.0f}")
 
     torch.cuda.synchronize()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    iters = []
+    iters = []          # per launch: PNCG iterations of every env
+    launch_ms = []
     status_ok = True
     t0 = time.perf_counter()
-    for k in range(K):
-        s = W + 1 + k
-        starts[k].record(stream)
-        sim.step(pose_steps[s])
-        ends[k].record(stream)
-        st = sim.stats()  # synchronises; needed for the per-launch iteration counts
+    if args.launch == "sequence":
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        _, status = sim.step_sequence(seq(W + 1, W + K + 1))
+        end.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        launch_ms.append(start.elapsed_time(end))
+        st = sim.stats()
         iters.append(np.array([x["iters"] for x in st], dtype=np.int64))
-        status_ok &= all(x["status"] & t2r.ENV_CONVERGED for x in st)
-        log(args, f"step {s}: {starts[k].elapsed_time(ends[k]):.1f} ms, iters/env mean "
-                  f"{iters[-1].mean():.0f} max {iters[-1].max()}, substeps "
-                  f"{np.mean([x['substeps'] for x in st]):.1f}, cand {np.mean([x['n_candidates'] for x in st]):.0f}")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    launch_ms = [starts[k].elapsed_time(ends[k]) for k in range(K)]
+        status_ok = bool(((status.cpu().numpy() & t2r.ENV_CONVERGED) != 0).all())
+        log(args, f"load steps {W + 1}..{W + K} in one launch: {launch_ms[0]:.1f} ms, iters/env-step mean "
+                  f"{iters[0].mean() / K:.0f}, env total max {iters[0].max()}")
+    else:
+        starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+        ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+        for k in range(K):
+            s = W + 1 + k
+            starts[k].record(stream)
+            sim.step(pose_steps[s])
+            ends[k].record(stream)
+            st = sim.stats()  # synchronises; needed for the per-launch iteration counts
+            iters.append(np.array([x["iters"] for x in st], dtype=np.int64))
+            status_ok &= all(x["status"] & t2r.ENV_CONVERGED for x in st)
+            log(args, f"step {s}: {starts[k].elapsed_time(ends[k]):.1f} ms, iters/env mean "
+                      f"{iters[-1].mean():.0f} max {iters[-1].max()}")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        launch_ms = [starts[k].elapsed_time(ends[k]) for k in range(K)]
     value = args.envs * K / wall
     # roofline of the step kernel: algorithmic vector bytes per launch / launch time
     bytes_per_launch = [float(it.sum()) * BYTES_PER_VERT_ITER * nv for it in iters]
@@ -175,23 +199,27 @@ def main():
 
     plain = None
     if args.plain_envs > 0:
-        # unbatched: the same solver, one env per launch, on a sample of envs
+        # unbatched: the same solver and launch mode, one env per context, on a sample of envs
         n = min(args.plain_envs, args.envs)
         sims = [Sim.from_workload(workload, opts, envs=[i]) for i in range(n)]
-        # advance each plain env through the warmup steps, then time one step each
         for i_, sm in enumerate(sims):
-            for s in range(1, W + 1):
-                sm.step(poses[i_:i_ + 1, s].contiguous())
+            if W > 0:
+                sm.step_sequence(poses[i_:i_ + 1, 1:W + 1].transpose(0, 1).contiguous())
         torch.cuda.synchronize()
         tp = time.perf_counter()
         for i_, sm in enumerate(sims):
-            sm.step(poses[i_:i_ + 1, W + 1].contiguous())
+            if args.launch == "sequence":
+                sm.step_sequence(poses[i_:i_ + 1, W + 1:W + K + 1].transpose(0, 1).contiguous())
+            else:
+                for s in range(W + 1, W + K + 1):
+                    sm.step(poses[i_:i_ + 1, s].contiguous())
         torch.cuda.synchronize()
         dtp = time.perf_counter() - tp
-        plain = {"value": n / dtp, "unit": "env-steps/s", "sample": f"envs 0..{n - 1}, step {W + 1}, "
-                 "one launch per env", "batched_over_plain": value / (n / dtp)}
+        plain = {"value": n * K / dtp, "unit": "env-steps/s",
+                 "sample": f"envs 0..{n - 1}, load steps {W + 1}..{W + K}, one env per launch",
+                 "batched_over_plain": value / (n * K / dtp)}
 
-    iters_mean = float(np.mean([it.mean() for it in iters]))
+    iters_mean = float(sum(it.sum() for it in iters)) / (args.envs * K)
     cpu = cpu_baseline(args, workload, iters_mean) if args.cpu_seconds > 0 else None
     line = {
         "metric": "env-steps/s at fixed PNCG tol (batched)",
@@ -210,7 +238,7 @@ def main():
                    "gel_tets": workload.meshes["5k"].n_tets, "indenter": "peg r=4 mm, 2048 tris",
                    "load_steps_timed": f"{W + 1}..{W + K} of 20", "tol_mm": args.tol,
                    "precision": args.precision, "all_converged": bool(status_ok),
-                   "pncg_iters_per_env_step": float(np.mean([it.mean() for it in iters]))},
+                   "pncg_iters_per_env_step": iters_mean, "launch": args.launch},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic,
                      "kernel": "t2r_step_kernel", "launch_ms": launch_ms},

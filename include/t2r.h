@@ -101,17 +101,20 @@ typedef struct {
   int32_t block_size;
 } t2r_solver_opts;
 
-/* Per-environment counters of the last t2r_step (t2r_get_stats). */
+/* Per-environment counters of the last launch (t2r_step or t2r_step_sequence;
+ * t2r_get_stats). Counts are summed over the launch's load steps; status,
+ * n_candidates, n_active, n_friction, d_min, residual and energy are those of
+ * its last load step. */
 typedef struct {
-  int32_t status;        /* T2R_ENV_* bits */
-  int32_t iters;         /* PNCG iterations, all solves of the step */
+  int32_t status;        /* T2R_ENV_* bits of the last load step */
+  int32_t iters;         /* PNCG iterations, all solves of all load steps */
   int32_t substeps;      /* continuation solves */
   int32_t restarts;      /* direction resets to -P g */
   int32_t halvings;      /* line-search halvings */
   int32_t reculls;       /* candidate-list refreshes (filter of the outer list) */
   int32_t n_candidates;  /* candidate pairs at the last cull */
   int32_t n_active;      /* pairs closer than dhat at the end */
-  int32_t n_friction;    /* lagged friction pairs */
+  int32_t n_friction;    /* lagged friction pairs of the last load step */
   int32_t max_solve_iters;
   int32_t outer_builds;  /* grid traversals building the outer candidate list */
   int32_t reserved;
@@ -121,7 +124,7 @@ typedef struct {
   double phase_ms[10];   /* ms spent by this env's workgroup in: [0] coarse (grid) culls,
                             [1] candidate filtering, [2] curvature elements, [3] curvature
                             pairs, [4] CCD, [5] evaluation elements, [6] evaluation pairs
-                            and friction, [7] vector passes, [8] the whole step, [9] friction lag */
+                            and friction, [7] vector passes, [8] the whole launch, [9] friction lag */
 } t2r_env_stats;
 
 /* Fills *o with the defaults: tol 1e-6, substep_tol 1e-4, max_iters 20000,
@@ -198,6 +201,27 @@ t2r_status t2r_env_count(const t2r_ctx* ctx, int32_t* n_env, int64_t* total_vert
  * All work is enqueued on the context's stream; the call does not wait. */
 t2r_status t2r_step(t2r_ctx* ctx, const double* d_pose, const int32_t* d_env_mask,
                     double* d_markers, double* d_x, int32_t* d_status);
+
+/* Advances every environment through n_steps consecutive load steps in one
+ * launch (a scripted indenter trajectory, Sec. 3.1: the simulator replays the
+ * recorded press and shear poses): load step k moves the indenter to
+ * d_poses[k][env][7], exactly as n_steps calls of t2r_step would. Each env's
+ * workgroup keeps its env for all steps, so the uneven cost of individual
+ * solves averages out over the trajectory; envs whose previous launch took
+ * longest start first.
+ *   n_steps    >= 1
+ *   d_poses    device [n_steps][n_env][7]
+ *   d_env_mask device [n_env] int32 or NULL; envs with 0 skip every step
+ *   d_markers  device [n_steps][sum n_m][3] or NULL: marker displacements after
+ *              each load step
+ *   d_x        device [sum n_v][3] or NULL: positions after the last step
+ *   d_status   device [n_steps][n_env] int32 or NULL: T2R_ENV_* bits per step
+ * A step that overflows or becomes infeasible is rolled back (the env keeps its
+ * previous pose) and the next step starts from there. Asynchronous like
+ * t2r_step; t2r_step is this call with n_steps = 1. */
+t2r_status t2r_step_sequence(t2r_ctx* ctx, int32_t n_steps, const double* d_poses,
+                             const int32_t* d_env_mask, double* d_markers, double* d_x,
+                             int32_t* d_status);
 
 /* Diagnostic evaluation of one env's step energy at given positions, without
  * touching its state: the friction lag is taken at (d_x_lag, pose_lag) when

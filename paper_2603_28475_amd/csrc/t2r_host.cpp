@@ -97,6 +97,7 @@ struct t2r_ctx {
   int* d_vmap = nullptr;
   int* d_imap = nullptr;
   int* d_islot_v = nullptr;
+  int* d_order = nullptr;
   uint64_t* d_oslot = nullptr;
   uint64_t* d_pslot = nullptr;
   int* d_slot_v = nullptr;
@@ -780,6 +781,9 @@ static StepParams step_params(t2r_ctx* c) {
   P.pslot = c->d_pslot;
   P.slot_v = c->d_slot_v;
   P.stats = c->d_stats;
+  P.order = nullptr;
+  P.n_steps = 1;
+  P.markers_stride = 0;
   P.x_out_off = c->d_xout_off;
   P.clock_khz = c->clock_khz;
   P.tol = c->opts.tol;
@@ -791,22 +795,35 @@ static StepParams step_params(t2r_ctx* c) {
   return P;
 }
 
-t2r_status t2r_step(t2r_ctx* c, const double* d_pose, const int32_t* d_mask, double* d_markers, double* d_x,
-                    int32_t* d_status) {
+t2r_status t2r_step_sequence(t2r_ctx* c, int32_t n_steps, const double* d_poses, const int32_t* d_mask,
+                             double* d_markers, double* d_x, int32_t* d_status) {
   if (!c) return T2R_E_ARG;
-  if (!d_pose) return fail(c, T2R_E_ARG, "d_pose is NULL");
+  if (!d_poses) return fail(c, T2R_E_ARG, "d_poses is NULL");
+  if (n_steps < 1) return fail(c, T2R_E_ARG, "n_steps must be >= 1 (got %d)", n_steps);
   if (c->envs.empty()) return fail(c, T2R_E_STATE, "no environments");
   t2r_status s = commit(c);
   if (s != T2R_OK) return s;
   StepParams P = step_params(c);
-  P.pose_in = d_pose;
+  P.n_steps = n_steps;
+  P.pose_in = d_poses;
   P.env_mask = d_mask;
   P.markers_out = d_markers;
+  P.markers_stride = 3 * c->total_markers;
   P.x_out = d_x;
   P.status_out = d_status;
+  if (P.n_env > 1) {
+    // longest previous launch first (see t2r_order_kernel)
+    HIP_TRY(c, t2r_launch_order(&P, c->d_order, c->stream));
+    P.order = c->d_order;
+  }
   HIP_TRY(c, t2r_launch_step(&P, block_of(c), c->stream));
   c->err.clear();
   return T2R_OK;
+}
+
+t2r_status t2r_step(t2r_ctx* c, const double* d_pose, const int32_t* d_mask, double* d_markers, double* d_x,
+                    int32_t* d_status) {
+  return t2r_step_sequence(c, 1, d_pose, d_mask, d_markers, d_x, d_status);
 }
 
 t2r_status t2r_eval(t2r_ctx* c, int32_t env, const double* d_x, const double* d_p, const double* d_x_lag,
@@ -1157,10 +1174,11 @@ t2r_status commit(t2r_ctx* c) {
   c->d_imap = alloc_n<int>(c, (size_t)std::max(imtot, 1LL));
   c->d_islot_v = alloc_n<int>(c, c->envs.size() * (size_t)kIndSlots);
   c->d_stats = alloc_n<EnvStats>(c, c->envs.size());
+  c->d_order = alloc_n<int>(c, c->envs.size());
   if (!c->d_x || !c->d_xprev || !c->d_g0 || !c->d_g1 || !c->d_diag || !c->d_p || !c->d_pose_prev ||
       !c->d_pairs || !c->d_pair_d || !c->d_outer || !c->d_lists || !c->d_xsnap || !c->d_fric ||
       !c->d_vmap || !c->d_oslot || !c->d_pslot || !c->d_slot_v || !c->d_imap || !c->d_islot_v ||
-      !c->d_stats) {
+      !c->d_stats || !c->d_order) {
     dev_free_all(c);
     return fail(c, T2R_E_NOMEM, "state allocation failed (%lld DOFs)", voff);
   }

@@ -25,6 +25,11 @@ constexpr int kTileTets = 1024;
 constexpr int kTileVerts = 512;   // local vertex ids are 16-bit
 constexpr int kMaxBlock = 1024;
 
+// Workgroups take envs in order of decreasing duration of their previous load
+// step, so the longest solves start first and the launch ends with short ones.
+// Up to kOrderMax envs are sorted (one workgroup); beyond that envs go in id order.
+constexpr int kOrderMax = 8192;
+
 // Contact slots: the gel and indenter vertices touched by an env's coarse pair
 // list get dense ids (below kGelSlots and kIndSlots), so pair passes stage
 // their positions in LDS (in the tile's storage), accumulate gradients there
@@ -157,12 +162,15 @@ struct StepParams {
   T2R_G int* slot_v;             // [n_env][kGelSlots] gel vertex of each slot
   T2R_G int* islot_v;            // [n_env][kIndSlots] indenter vertex of each slot
   T2R_G EnvStats* stats;         // [n_env]
+  const T2R_G int* order;        // [n_env] env of each workgroup (longest expected first) or null
   // inputs / outputs
-  const T2R_G double* pose_in;   // [n_env][7]
+  const T2R_G double* pose_in;   // [n_steps][n_env][7]
   const T2R_G int* env_mask;     // [n_env] or null
-  T2R_G double* markers_out;     // [sum n_m][3] or null
+  T2R_G double* markers_out;     // [n_steps][sum n_m][3] or null
+  long long markers_stride;      // doubles per load step in markers_out (3 sum n_m)
+  int n_steps;                   // load steps in this launch
   T2R_G double* x_out;           // [sum n_v][3] or null
-  T2R_G int* status_out;         // [n_env] or null
+  T2R_G int* status_out;         // [n_steps][n_env] or null
   T2R_G long long* x_out_off;    // [n_env] vertex offsets into x_out
   // options
   double clock_khz;        // wall-clock counter rate (phase timers)
@@ -185,6 +193,7 @@ struct EvalParams {
 
 extern "C" {
 hipError_t t2r_launch_step(const t2r::StepParams* p, int block, hipStream_t stream);
+hipError_t t2r_launch_order(const t2r::StepParams* p, int* order, hipStream_t stream);
 hipError_t t2r_launch_eval(const t2r::EvalParams* p, int block, hipStream_t stream);
 hipError_t t2r_launch_pack_state(const t2r::StepParams* p, const double* in, double* out,
                                  const long long* state_off, int direction, hipStream_t stream);

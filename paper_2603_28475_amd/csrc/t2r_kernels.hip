@@ -1742,32 +1742,6 @@ __device__ __forceinline__ void init_solver(Solver& s, const StepParams& P, Shar
   s.reculls = s.restarts = s.halvings = s.ncand = s.outer_builds = 0;
 }
 
-__device__ __forceinline__ void write_outputs(const StepParams& P, int e, const View& V) {
-  const GelDev& G = *V.G;
-  const int nv = G.n_v;
-  if (P.markers_out) {
-    double* mo = P.markers_out + 3 * V.E->moff;
-    for (int m = threadIdx.x; m < G.n_m; m += blockDim.x) {
-      #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        double u = 0.0;
-        #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const int v = G.marker_tri[k * G.n_m + m];
-          u += G.marker_w[k * G.n_m + m] * (V.x[c * nv + v] - G.X[c * nv + v]);
-        }
-        mo[3 * m + c] = u;
-      }
-    }
-  }
-  if (P.x_out) {
-    double* xo = P.x_out + 3 * P.x_out_off[e];
-    for (int j = threadIdx.x; j < 3 * nv; j += blockDim.x) {
-      const int v = j / 3, c = j - 3 * v;
-      xo[j] = V.x[c * nv + v];
-    }
-  }
-}
 
 }  // namespace t2r
 
@@ -1775,44 +1749,21 @@ using namespace t2r;
 
 // Two workgroups of 256 threads (or one of 512) per CU: 2 waves per SIMD, which
 // the register budget of the fully inlined step allows without spilling.
-template <int BLOCK>
-__global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel(StepParams P) {
-  __shared__ Shared S;
-  __shared__ Tile T;
-  const int e = blockIdx.x;
-  if (e >= P.n_env) return;
-  Solver s;
-  make_view(P, e, s.V);
+// One load step of env e: the indenter moves from the env's previous pose to
+// q1 in continuation substeps (each a PNCG solve), with friction lagged at the
+// previous equilibrium. On overflow or infeasibility the state is rolled back
+// and the previous pose kept. Counters accumulate into st; returns the status.
+__device__ __forceinline__ int load_step(const StepParams& P, int e, Solver& s, Shared& S, const double q1[7],
+                                         EnvStats& st) {
   View& V = s.V;
-  init_solver(s, P, S, T);
   const GelDev& G = *V.G;
   const IndDev& I = *V.I;
   const EnvDev& E = *V.E;
   const int n = 3 * G.n_v;
-  const unsigned long long t_start = tick();
-  if (threadIdx.x < 10) S.tacc[threadIdx.x] = 0ull;
-  __syncthreads();
-  EnvStats st;
-  st.status = 0; st.iters = 0; st.substeps = 0; st.restarts = 0; st.halvings = 0; st.reculls = 0;
-  st.n_candidates = 0; st.n_active = 0; st.n_friction = 0; st.max_solve_iters = 0;
-  st.outer_builds = 0; st.pad = 0;
-  st.d_min = kInf; st.residual = 0.0; st.energy = 0.0;
-  for (int k = 0; k < 10; ++k) st.phase_ms[k] = 0.0;
-
-  double* pose_prev = P.pose_prev + 7 * e;
-  double q0[7], q1[7];
+  T2R_G double* pose_prev = P.pose_prev + 7 * e;
+  double q0[7];
   #pragma unroll
-  for (int i = 0; i < 7; ++i) { q0[i] = pose_prev[i]; q1[i] = P.pose_in[7 * e + i]; }
-  bool skip = P.env_mask && P.env_mask[e] == 0;
-  bool bad = false;
-  #pragma unroll
-  for (int i = 0; i < 7; ++i) bad |= !isfinite(q1[i]);
-  if (skip || bad) {
-    st.status = skip ? kSkipped : kNonFinite;
-    write_outputs(P, e, V);
-    if (threadIdx.x == 0) { P.stats[e] = st; if (P.status_out) P.status_out[e] = st.status; }
-    return;
-  }
+  for (int i = 0; i < 7; ++i) q0[i] = pose_prev[i];
   // keep x_{s-1} for the friction lag and for rollback
   for (int j = threadIdx.x; j < n; j += blockDim.x) V.xprev[j] = V.x[j];
   // friction lag and starting distance at (x_{s-1}, q_{s-1}), from the outer
@@ -1820,10 +1771,10 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
   // built exceeds its margin)
   if (threadIdx.x == 0) set_pose(S, I, q0);
   __syncthreads();
-  load_lists(s);
+  int status = 0;
   double dmin_start;
   if (!ensure_lists(s, V.x, 0.0)) {
-    st.status |= kOverflow;
+    status |= kOverflow;
     dmin_start = 0.0;
   } else {
     const int mode = (E.mu_f > 0.0) ? 1 : 2;
@@ -1833,7 +1784,7 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
     dmin_start = block_min(dm, S);
     tock(S, 9, t0);
     V.nfric = (mode == 1) ? min(cnt, s.fric_cap) : 0;
-    if (ov) st.status |= kOverflow;
+    if (ov) status |= kOverflow;
   }
   st.n_friction = V.nfric;
   int status_acc = kConverged;
@@ -1841,8 +1792,6 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
   int sub = 0;
   double res = 0.0, energy = 0.0;
   int nact = 0;
-  const bool rollback_needed = false;
-  (void)rollback_needed;
   if (!(dmin_start > 0.0)) {
     status_acc = kInfeasible;
   } else {
@@ -1880,8 +1829,8 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
     }
     if (tau < 1.0 && !(status_acc & (kOverflow | kInfeasible))) status_acc = (status_acc & ~kConverged) | kSubsteps;
   }
-  st.status |= status_acc;
-  if (st.status & (kOverflow | kInfeasible)) {
+  status |= status_acc;
+  if (status & (kOverflow | kInfeasible)) {
     // roll back to x_{s-1}; the previous pose is kept
     for (int j = threadIdx.x; j < n; j += blockDim.x) V.x[j] = V.xprev[j];
     __syncthreads();
@@ -1889,25 +1838,100 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
     #pragma unroll
     for (int i = 0; i < 7; ++i) pose_prev[i] = q1[i];
   }
+  __syncthreads();
   {
     int na2 = 0;
     st.d_min = dmin_all(s, V.x, na2);
     st.n_active = na2;
   }
-  st.substeps = sub;
+  st.substeps += sub;
+  st.residual = res;
+  st.energy = energy;
+  return status;
+}
+
+// Marker displacements of env e at its current state into the output block of
+// load step k.
+__device__ __forceinline__ void write_markers(const StepParams& P, int k, const View& V) {
+  if (!P.markers_out) return;
+  const GelDev& G = *V.G;
+  const int nv = G.n_v;
+  T2R_G double* mo = P.markers_out + (long long)k * P.markers_stride + 3 * V.E->moff;
+  for (int m = threadIdx.x; m < G.n_m; m += blockDim.x) {
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double u = 0.0;
+      #pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int v = G.marker_tri[j * G.n_m + m];
+        u += G.marker_w[j * G.n_m + m] * (V.x[c * nv + v] - G.X[c * nv + v]);
+      }
+      mo[3 * m + c] = u;
+    }
+  }
+}
+
+// Every env advances through P.n_steps load steps (poses pose_in[k][env]).
+// One workgroup owns one env for the whole launch; workgroups take envs in
+// P.order (longest expected first).
+// Two workgroups of 256 threads (or one of 512) per CU: 2 waves per SIMD.
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel(StepParams P) {
+  __shared__ Shared S;
+  __shared__ Tile T;
+  const int e = P.order ? P.order[blockIdx.x] : (int)blockIdx.x;
+  if (e >= P.n_env) return;
+  Solver s;
+  make_view(P, e, s.V);
+  View& V = s.V;
+  init_solver(s, P, S, T);
+  const GelDev& G = *V.G;
+  const int nv = G.n_v;
+  const unsigned long long t_start = tick();
+  if (threadIdx.x < 10) S.tacc[threadIdx.x] = 0ull;
+  __syncthreads();
+  EnvStats st;
+  st.status = 0; st.iters = 0; st.substeps = 0; st.restarts = 0; st.halvings = 0; st.reculls = 0;
+  st.n_candidates = 0; st.n_active = 0; st.n_friction = 0; st.max_solve_iters = 0;
+  st.outer_builds = 0; st.pad = 0;
+  st.d_min = kInf; st.residual = 0.0; st.energy = 0.0;
+  for (int k = 0; k < 10; ++k) st.phase_ms[k] = 0.0;
+  const bool skip = P.env_mask && P.env_mask[e] == 0;
+  load_lists(s);
+  for (int k = 0; k < P.n_steps; ++k) {
+    double q1[7];
+    bool bad = false;
+    #pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      q1[i] = P.pose_in[((long long)k * P.n_env + e) * 7 + i];
+      bad |= !isfinite(q1[i]);
+    }
+    int status;
+    if (skip || bad) {
+      status = skip ? kSkipped : kNonFinite;
+    } else {
+      status = load_step(P, e, s, S, q1, st);
+    }
+    st.status = status;
+    write_markers(P, k, V);
+    if (threadIdx.x == 0 && P.status_out) P.status_out[(long long)k * P.n_env + e] = status;
+  }
   st.restarts = s.restarts;
   st.halvings = s.halvings;
   st.reculls = s.reculls;
   st.outer_builds = s.outer_builds;
   st.n_candidates = s.ncand;
-  st.residual = res;
-  st.energy = energy;
-  write_outputs(P, e, V);
+  if (P.x_out) {
+    T2R_G double* xo = P.x_out + 3 * P.x_out_off[e];
+    for (int j = threadIdx.x; j < 3 * nv; j += blockDim.x) {
+      const int v = j / 3, c = j - 3 * v;
+      xo[j] = V.x[c * nv + v];
+    }
+  }
   if (threadIdx.x == 0) {
     S.tacc[8] = wall_clock64() - t_start;
     for (int k = 0; k < 10; ++k) st.phase_ms[k] = (double)S.tacc[k] / P.clock_khz;
     P.stats[e] = st;
-    if (P.status_out) P.status_out[e] = st.status;
   }
 }
 
@@ -2010,6 +2034,50 @@ extern "C" hipError_t t2r_launch_step(const StepParams* p, int block, hipStream_
     hipLaunchKernelGGL(t2r_step_kernel<256>, dim3(p->n_env), dim3(256), 0, stream, *p);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// Longest-first env order from the durations of the previous load step (stats
+// zeroed before the first step: id order). Bitonic sort of (duration, id) keys
+// in LDS, one workgroup.
+__global__ void __launch_bounds__(1024) t2r_order_kernel(StepParams P, int* order) {
+  __shared__ unsigned long long key[kOrderMax];
+  const int n = P.n_env;
+  if (n > kOrderMax) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) order[i] = i;
+    return;
+  }
+  int np = 1;
+  while (np < n) np <<= 1;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    unsigned long long k = ~0ull;
+    if (i < n) {
+      const double ms = P.stats[i].phase_ms[8];
+      const float c = (ms > 0.0 && isfinite(ms)) ? (float)ms : 0.0f;
+      // descending duration = ascending inverted bits (c >= 0), then ascending id
+      k = ((unsigned long long)(~__float_as_uint(c)) << 32) | (unsigned)i;
+    }
+    key[i] = k;
+  }
+  __syncthreads();
+  for (int size = 2; size <= np; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool up = (i & size) == 0;
+          const unsigned long long a = key[i], b = key[j];
+          if ((a > b) == up) { key[i] = b; key[j] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) order[i] = (int)(key[i] & 0xffffffffu);
+}
+
+extern "C" hipError_t t2r_launch_order(const StepParams* p, int* order, hipStream_t stream) {
+  hipLaunchKernelGGL(t2r_order_kernel, dim3(1), dim3(1024), 0, stream, *p, order);
   return hipGetLastError();
 }
 

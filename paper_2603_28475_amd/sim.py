@@ -59,6 +59,18 @@ class Sim:
         self.ctx.step(p, m, self.markers, self.x if want_x else None, self.status)
         return self.markers, self.status
 
+    def step_sequence(self, poses, mask=None, want_x=False):
+        """Load steps k = 0..S-1 of every env to poses[k] ((S, n_env, 7)) in one launch.
+        Returns (markers tensor (S, sum n_m, 3), status tensor (S, n_env)), not synchronised."""
+        p = torch.as_tensor(np.asarray(poses, dtype=np.float64) if not torch.is_tensor(poses) else poses,
+                            dtype=torch.float64, device=self.device).contiguous()
+        n_steps = p.shape[0]
+        m = None if mask is None else torch.as_tensor(mask, dtype=torch.int32, device=self.device)
+        markers = torch.zeros((n_steps, sum(self.n_m), 3), dtype=torch.float64, device=self.device)
+        status = torch.zeros((n_steps, self.n_env), dtype=torch.int32, device=self.device)
+        self.ctx.step_sequence(n_steps, p, m, markers, self.x if want_x else None, status)
+        return markers, status
+
     def split_markers(self, markers=None):
         markers = self.markers if markers is None else markers
         return torch.split(markers, self.n_m)

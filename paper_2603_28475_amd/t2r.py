@@ -65,6 +65,7 @@ SIGNATURES = [
     ("t2r_add_envs", C.c_int32, [_P, C.c_int32, _PI, _PI, C.POINTER(Material), _PD, _PI]),
     ("t2r_env_count", C.c_int32, [_P, _PI, C.POINTER(C.c_int64)]),
     ("t2r_step", C.c_int32, [_P, _P, _P, _P, _P, _P]),
+    ("t2r_step_sequence", C.c_int32, [_P, C.c_int32, _P, _P, _P, _P, _P]),
     ("t2r_eval", C.c_int32, [_P, C.c_int32, _P, _P, _P, _PD, _PD, _P, _P, _P]),
     ("t2r_get_stats", C.c_int32, [_P, _P, C.c_size_t]),
     ("t2r_state_size", C.c_int32, [_P, C.POINTER(C.c_int64)]),
@@ -201,6 +202,10 @@ class Context:
     def step(self, d_pose, d_mask=None, d_markers=None, d_x=None, d_status=None):
         self.check(lib.t2r_step(self.handle, _tptr(d_pose), _tptr(d_mask), _tptr(d_markers),
                                 _tptr(d_x), _tptr(d_status)))
+
+    def step_sequence(self, n_steps, d_poses, d_mask=None, d_markers=None, d_x=None, d_status=None):
+        self.check(lib.t2r_step_sequence(self.handle, int(n_steps), _tptr(d_poses), _tptr(d_mask),
+                                         _tptr(d_markers), _tptr(d_x), _tptr(d_status)))
 
     def eval(self, env, d_x, pose, d_p=None, d_x_lag=None, pose_lag=None, d_grad=None, d_diag=None,
              d_scalars=None):

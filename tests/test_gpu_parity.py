@@ -182,6 +182,26 @@ def test_sphere_press_sequence_matches_newton_oracle():
     assert err_x <= 1e-6, err_x
 
 
+def test_multi_step_launch_matches_newton_oracle():
+    """All ten load steps of the sphere press in one t2r_step_sequence launch:
+    per-step markers and the final positions against the oracle's Newton path."""
+    t2r = _gpu()
+    from scenes.configs import sphere_press_484v
+    w = sphere_press_484v()
+    gold = np.load(os.path.join(HERE, "golden", "sphere_press_484v_newton.npz"))
+    sim = _build(t2r, w, tol=1e-10, substep_tol=1e-6, max_iters=200000)
+    poses = np.stack([e.poses for e in w.envs])            # (1, S+1, 7)
+    seq = np.ascontiguousarray(poses[:, 1:].transpose(1, 0, 2))  # (S, 1, 7)
+    m, st = sim.step_sequence(seq, want_x=True)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    assert np.all(st & 1), st
+    assert np.abs(m.cpu().numpy() - gold["markers"]).max() <= 1e-6
+    assert np.abs(sim.x.cpu().numpy() - gold["x"][-1]).max() <= 1e-6
+    stats = sim.stats()[0]
+    assert stats["iters"] > 0 and stats["substeps"] >= seq.shape[0]
+
+
 def test_friction_sequence_matches_newton_oracle():
     t2r = _gpu()
     from scenes.configs import micro_press
