@@ -26,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
+FP64_PEAK = 78.6e12        # FLOP/s, MI355X FP64 vector (256 CU x 4 SIMD x 16 lanes x FMA x 2.4 GHz)
+FLOPS_PER_TET_ITER = 600   # element flops per tet per PNCG iteration (reference schedule)
 BYTES_PER_VERT_ITER = 384  # 16 vector passes x 3 coords x 8 B per PNCG iteration
 
 
@@ -189,13 +191,26 @@ def main():
     # roofline of the step kernel: algorithmic vector bytes per launch / launch time
     bytes_per_launch = [float(it.sum()) * BYTES_PER_VERT_ITER * nv for it in iters]
     achieved = float(np.mean([b / (t * 1e-3) for b, t in zip(bytes_per_launch, launch_ms)]))
+    # HBM bytes of the same launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled
+    # by a 1 GiB copy), valid only for the kernel source they were taken with
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
-    if os.path.exists(tfile):
+    tfile = os.path.join(ROOT, "profiles", f"t2r_step_kernel_{workload.name}_traffic.json")
+    if os.path.exists(tfile) and args.launch == "sequence" and W == 1 and K == 19:
         with open(tfile) as fh:
             tr = json.load(fh)
-        if tr.get("source_hash") == source_hash() and tr.get("envs") == args.envs:
+        if (tr.get("source_hash") == source_hash() and tr.get("envs") == args.envs
+                and tr.get("precision") == args.precision):
             traffic = tr.get("bytes_per_launch")
+    # FP64-vector view of the same launch: element flops per iteration under the
+    # reference schedule (about 350 per tet for energy, gradient and diagonal,
+    # 250 per tet for the curvature), against 78.6 TFLOP/s
+    n_t = workload.meshes["5k"].n_tets
+    flops = float(sum(it.sum() for it in iters)) * FLOPS_PER_TET_ITER * n_t
+    alu_achieved = flops / (sum(launch_ms) * 1e-3)
+    # time-based roofline (per env-iteration, each pass at its binding roof)
+    t_roof_iter = (max(72 * nv / HBM_PEAK, 350 * n_t / FP64_PEAK) + max(48 * nv / HBM_PEAK, 250 * n_t / FP64_PEAK)
+                   + 264 * nv / HBM_PEAK)
+    t_roof = float(sum(it.sum() for it in iters)) * t_roof_iter
 
     plain = None
     if args.plain_envs > 0:
@@ -241,7 +256,10 @@ def main():
                    "pncg_iters_per_env_step": iters_mean, "launch": args.launch},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic,
-                     "kernel": "t2r_step_kernel", "launch_ms": launch_ms},
+                     "kernel": "t2r_step_kernel", "launch_ms": launch_ms,
+                     "alu": {"achieved": alu_achieved / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+                             "frac": alu_achieved / FP64_PEAK},
+                     "t_roof_frac": t_roof / (sum(launch_ms) * 1e-3)},
         "plain": plain,
         "cpu_baseline": cpu,
     }
