@@ -36,7 +36,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=19)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--envs", type=int, default=2048)
+    ap.add_argument("--workload", choices=["peg_batch_5k", "mixed_batch"], default="peg_batch_5k",
+                    help="peg_batch_5k: uniform 2048 x 5k gels (headline); mixed_batch: 512 envs over "
+                         "three gel sizes and three indenters")
+    ap.add_argument("--envs", type=int, default=0, help="0: the workload's own count")
     ap.add_argument("--precision", choices=["f64", "mixed"], default="mixed")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--plain-envs", type=int, default=4, help="envs timed one launch each (0: skip)")
@@ -108,7 +111,7 @@ def main():
 
     from paper_2603_28475_amd import t2r
     from paper_2603_28475_amd.sim import Sim
-    from scenes.configs import peg_batch_5k
+    from scenes.configs import mixed_batch, peg_batch_5k
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -124,7 +127,10 @@ def main():
         return
     W, K = args.warmup, args.steps
     n_steps = W + K
-    workload = peg_batch_5k(n_envs=args.envs, n_steps=20, precision=args.precision)
+    if args.envs <= 0:
+        args.envs = 2048 if args.workload == "peg_batch_5k" else 512
+    make = peg_batch_5k if args.workload == "peg_batch_5k" else mixed_batch
+    workload = make(n_envs=args.envs, n_steps=20, precision=args.precision)
     if n_steps > workload.n_steps:
         print(f"warmup + steps must be <= {workload.n_steps}", file=sys.stderr)
         sys.exit(1)
@@ -137,7 +143,8 @@ def main():
     pose_steps = [poses[:, s].contiguous() for s in range(n_steps + 1)]
     log(args, f"built {args.envs} envs in {time.perf_counter() - t_build:.1f}s")
     stream = torch.cuda.current_stream()
-    nv = sim.n_v[0]
+    nv_env = np.array([workload.meshes[e.mesh].n_verts for e in workload.envs], dtype=np.float64)
+    nt_env = np.array([workload.meshes[e.mesh].n_tets for e in workload.envs], dtype=np.float64)
 
     def seq(a, b):  # poses of load steps a..b-1 as (steps, n_env, 7)
         return poses[:, a:b].transpose(0, 1).contiguous()
@@ -189,7 +196,7 @@ def main():
         launch_ms = [starts[k].elapsed_time(ends[k]) for k in range(K)]
     value = args.envs * K / wall
     # roofline of the step kernel: algorithmic vector bytes per launch / launch time
-    bytes_per_launch = [float(it.sum()) * BYTES_PER_VERT_ITER * nv for it in iters]
+    bytes_per_launch = [float((it * nv_env).sum()) * BYTES_PER_VERT_ITER for it in iters]
     achieved = float(np.mean([b / (t * 1e-3) for b, t in zip(bytes_per_launch, launch_ms)]))
     # HBM bytes of the same launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled
     # by a 1 GiB copy), valid only for the kernel source they were taken with
@@ -204,13 +211,12 @@ def main():
     # FP64-vector view of the same launch: element flops per iteration under the
     # reference schedule (about 350 per tet for energy, gradient and diagonal,
     # 250 per tet for the curvature), against 78.6 TFLOP/s
-    n_t = workload.meshes["5k"].n_tets
-    flops = float(sum(it.sum() for it in iters)) * FLOPS_PER_TET_ITER * n_t
+    flops = float(sum((it * nt_env).sum() for it in iters)) * FLOPS_PER_TET_ITER
     alu_achieved = flops / (sum(launch_ms) * 1e-3)
     # time-based roofline (per env-iteration, each pass at its binding roof)
-    t_roof_iter = (max(72 * nv / HBM_PEAK, 350 * n_t / FP64_PEAK) + max(48 * nv / HBM_PEAK, 250 * n_t / FP64_PEAK)
-                   + 264 * nv / HBM_PEAK)
-    t_roof = float(sum(it.sum() for it in iters)) * t_roof_iter
+    t_roof_iter = (np.maximum(72 * nv_env / HBM_PEAK, 350 * nt_env / FP64_PEAK)
+                   + np.maximum(48 * nv_env / HBM_PEAK, 250 * nt_env / FP64_PEAK) + 264 * nv_env / HBM_PEAK)
+    t_roof = float(sum((it * t_roof_iter).sum() for it in iters))
 
     plain = None
     if args.plain_envs > 0:
@@ -249,8 +255,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == 0 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": workload.name, "envs": args.envs, "gel_verts": nv,
-                   "gel_tets": workload.meshes["5k"].n_tets, "indenter": "peg r=4 mm, 2048 tris",
+        "config": {"workload": workload.name, "envs": args.envs,
+                   "gel_verts": sorted({int(m.n_verts) for m in workload.meshes.values()}),
+                   "gel_tets": sorted({int(m.n_tets) for m in workload.meshes.values()}),
+                   "indenters": sorted(workload.indenters),
                    "load_steps_timed": f"{W + 1}..{W + K} of 20", "tol_mm": args.tol,
                    "precision": args.precision, "all_converged": bool(status_ok),
                    "pncg_iters_per_env_step": iters_mean, "launch": args.launch},

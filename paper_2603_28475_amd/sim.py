@@ -17,10 +17,13 @@ from . import t2r
 
 
 class Sim:
-    def __init__(self, opts: t2r.SolverOpts | None = None, device: str | int = "cuda:0"):
+    def __init__(self, opts: t2r.SolverOpts | None = None, device: str | int = "cuda:0", stream=None):
+        """stream: the torch stream the library enqueues on (default: the current
+        stream; graph_step needs a non-default one, e.g. torch.cuda.Stream())."""
         self.device = torch.device(device)
-        self.stream = torch.cuda.current_stream(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = t2r.Context(opts, self.stream.cuda_stream)
+        self._graph = None
         self.gel_ids = {}
         self.ind_ids = {}
         self.env_gel = []
@@ -29,10 +32,10 @@ class Sim:
 
     @classmethod
     def from_workload(cls, workload, opts: t2r.SolverOpts | None = None, device="cuda:0",
-                      envs=None):
+                      envs=None, stream=None):
         """Builds every gel and indenter class of a scenes.Workload and its envs
         (all of them, or the listed indices)."""
-        sim = cls(opts, device)
+        sim = cls(opts, device, stream)
         for name, g in workload.meshes.items():
             sim.gel_ids[name] = sim.ctx.add_gel(g.X, g.tets, g.fixed, g.markers)
         for name, ind in workload.indenters.items():
@@ -70,6 +73,30 @@ class Sim:
         status = torch.zeros((n_steps, self.n_env), dtype=torch.int32, device=self.device)
         self.ctx.step_sequence(n_steps, p, m, markers, self.x if want_x else None, status)
         return markers, status
+
+    def graph_step(self, poses):
+        """One load step of every env, replayed from a captured HIP graph.
+
+        The first call runs the step eagerly (so that every device buffer exists)
+        and then captures the library's launches for one step (env ordering and
+        the step kernel) on this Sim's stream; later calls copy `poses` into the
+        captured pose buffer and replay. Needs a non-default stream. Returns
+        (markers, status) like step(), not synchronised."""
+        p = torch.as_tensor(np.asarray(poses, dtype=np.float64) if not torch.is_tensor(poses) else poses,
+                            dtype=torch.float64, device=self.device)
+        with torch.cuda.stream(self.stream):
+            if self._graph is None:
+                self._pose_buf = p.clone().contiguous()
+                self.ctx.step(self._pose_buf, None, self.markers, None, self.status)
+                self.stream.synchronize()
+                graph = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(graph, stream=self.stream):
+                    self.ctx.step(self._pose_buf, None, self.markers, None, self.status)
+                self._graph = graph
+            else:
+                self._pose_buf.copy_(p)
+                self._graph.replay()
+        return self.markers, self.status
 
     def split_markers(self, markers=None):
         markers = self.markers if markers is None else markers

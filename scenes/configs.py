@@ -190,6 +190,25 @@ def mixed_batch(n_envs: int = 512, n_steps: int = 20, precision: str = "mixed") 
                     f"{n_envs} envs over 3 gel sizes and 3 indenters")
 
 
+def uneven_small(n_steps: int = 4, precision: str = "f64") -> Workload:
+    """Small uneven batch for parity: two gel sizes (484 and 2,142 vertices) and
+    all three indenter shapes in one batch, seeded poses, 0.3 mm press."""
+    meshes = {k: mesh_class(k) for k in ("c1", "2k")}
+    inds = {k: INDENTERS[k]() for k in ("sphere3", "peg4", "nut8")}
+    combos = [("c1", "sphere3"), ("2k", "peg4"), ("c1", "nut8"), ("2k", "sphere3")]
+    envs = []
+    for e, (mk, ik) in enumerate(combos):
+        r = _rng(7, e)
+        xy = r.uniform(-0.5, 0.5, 2)
+        yaw = np.deg2rad(r.uniform(0.0, 360.0))
+        E = r.uniform(0.2, 0.5)
+        poses = press_schedule(inds[ik], _yaw_tilt(yaw, np.deg2rad(1.0)), xy, 0.3, meshes[mk].thickness,
+                               n_steps)
+        envs.append(EnvSpec(mk, ik, E, NU, 0.0, poses))
+    return Workload("uneven_small", 7, meshes, inds, envs, precision, 1e-6,
+                    "4 envs over 2 gel sizes and 3 indenters")
+
+
 def adjoint_peg_5k(n_envs: int = 64) -> Workload:
     """64 x 5k-vertex gels, peg: 10 press steps to 0.6 mm then 10 shear steps of 0.5 mm
     total. Hidden per-env parameters theta* (E, nu, mu, pose offset) are drawn here and
@@ -234,6 +253,7 @@ WORKLOADS = {
     "adjoint_peg_5k": adjoint_peg_5k,
     "micro_press": micro_press,
     "peg_press_484v": peg_press_484v,
+    "uneven_small": uneven_small,
 }
 
 

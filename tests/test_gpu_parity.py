@@ -231,6 +231,53 @@ def test_peg_friction_sequence_matches_newton_oracle():
     assert np.abs(m - gold["markers"]).max() <= 1e-6
 
 
+def test_uneven_batch_matches_single_env_launches():
+    """Two gel sizes and three indenter shapes in one launch (the uneven-batch
+    layout): every env's trajectory equals its own single-env launch, or is an
+    equilibrium the oracle's Newton does not move."""
+    t2r = _gpu()
+    from scenes.configs import uneven_small
+    w = uneven_small(n_steps=4)
+    opts = dict(tol=1e-8, substep_tol=1e-8, max_iters=400000)
+    seq = lambda idx: np.ascontiguousarray(np.stack([w.envs[i].poses[1:] for i in idx]).transpose(1, 0, 2))
+    sim = _build(t2r, w, **opts)
+    m, st = sim.step_sequence(seq(range(len(w.envs))), want_x=True)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() & 1), st
+    xb = [a.cpu().numpy().copy() for a in sim.split_x()]
+    for i, env in enumerate(w.envs):
+        one = _build(t2r, w, envs=[i], **opts)
+        _, st1 = one.step_sequence(seq([i]), want_x=True)
+        torch.cuda.synchronize()
+        assert np.all(st1.cpu().numpy() & 1)
+        x1 = one.x.cpu().numpy()
+        if np.abs(xb[i] - x1).max() > 1e-6:
+            _certify_equilibrium(w, env, env.poses[-1], xb[i], bound=1e-5)
+
+
+def test_graph_captured_step_matches_eager_steps():
+    """The step replayed from a captured HIP graph, with eager library work and
+    synchronisations between replays, gives the eager steps' results."""
+    t2r = _gpu()
+    from paper_2603_28475_amd.sim import Sim
+    from scenes.configs import sphere_press_484v
+    w = sphere_press_484v(n_envs=3, n_steps=6)
+    o = t2r.default_opts(tol=1e-10, substep_tol=1e-6, max_iters=200000)
+    eager = Sim.from_workload(w, o)
+    side = torch.cuda.Stream()
+    graphed = Sim.from_workload(w, o, stream=side)
+    poses = np.stack([e.poses for e in w.envs])
+    for s in range(1, poses.shape[1]):
+        me, ste = eager.step(poses[:, s])
+        mg, stg = graphed.graph_step(poses[:, s])
+        side.synchronize()
+        torch.cuda.synchronize()
+        stats = graphed.stats()          # eager library call between replays
+        assert len(stats) == 3
+        assert np.all(stg.cpu().numpy() & 1) and np.all(ste.cpu().numpy() & 1)
+        assert np.abs(mg.cpu().numpy() - me.cpu().numpy()).max() <= 1e-6, s
+
+
 def _certify_equilibrium(w, env, pose, x, bound=1e-6):
     """The oracle's Newton started from x must not move: x is a minimiser of Pi."""
     from oracle.newton import newton_solve
