@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle budget (0: skip)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the block-shape / pair-capacity autotuner (setup, not timed)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -148,6 +150,12 @@ def main():
 
     def seq(a, b):  # poses of load steps a..b-1 as (steps, n_env, 7)
         return poses[:, a:b].transpose(0, 1).contiguous()
+
+    tuned = None
+    if not args.no_autotune and args.block == 0:
+        # setup (not timed): trial the first load step with each block shape, state restored
+        tuned = sim.autotune(seq(1, 2), target_steps=K if args.launch == "sequence" else 1)
+        log(args, f"autotune: {tuned}")
 
     if W > 0:
         if args.launch == "sequence":
@@ -261,7 +269,9 @@ def main():
                    "indenters": sorted(workload.indenters),
                    "load_steps_timed": f"{W + 1}..{W + K} of 20", "tol_mm": args.tol,
                    "precision": args.precision, "all_converged": bool(status_ok),
-                   "pncg_iters_per_env_step": iters_mean, "launch": args.launch},
+                   "pncg_iters_per_env_step": iters_mean, "launch": args.launch,
+                   "block_size": sim.ctx.get_opts().block_size or 256,
+                   "autotune_trial_ms": tuned["trial_ms"] if tuned else None},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic,
                      "kernel": "t2r_step_kernel", "launch_ms": launch_ms,

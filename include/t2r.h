@@ -117,7 +117,7 @@ typedef struct {
   int32_t n_friction;    /* lagged friction pairs of the last load step */
   int32_t max_solve_iters;
   int32_t outer_builds;  /* grid traversals building the outer candidate list */
-  int32_t reserved;
+  int32_t n_outer;       /* coarse (outer) candidate pairs at the end */
   double d_min;          /* smallest gel/indenter distance at the end (mm), inf if none < dhat */
   double residual;       /* final |P g|_inf (mm) */
   double energy;         /* final Pi (N mm) */
@@ -125,6 +125,8 @@ typedef struct {
                             [1] candidate filtering, [2] curvature elements, [3] curvature
                             pairs, [4] CCD, [5] evaluation elements, [6] evaluation pairs
                             and friction, [7] vector passes, [8] the whole launch, [9] friction lag */
+  double list_fill;      /* largest (list length / capacity) of the inner, outer and friction
+                            lists during the launch; > 1 means a list overflowed */
 } t2r_env_stats;
 
 /* Fills *o with the defaults: tol 1e-6, substep_tol 1e-4, max_iters 20000,
@@ -164,9 +166,10 @@ t2r_status t2r_add_gel(t2r_ctx* ctx, int32_t n_v, const double* X, int32_t n_t,
                        const int32_t* tets, const uint8_t* fixed, int32_t n_m,
                        const double* markers, int32_t* gel_id);
 
-/* Counts of a gel class: out[0..8] = n_v, n_t, surface vertices, surface edges,
- * surface triangles, markers, tiles, top-face triangles, fixed vertices. Host only. */
-t2r_status t2r_gel_info(const t2r_ctx* ctx, int32_t gel_id, int32_t* out9);
+/* Counts of a gel class: out[0..9] = n_v, n_t, surface vertices, surface edges,
+ * surface triangles, markers, tiles, top-face triangles, fixed vertices, and the
+ * inner pair-list capacity its envs get under the current options. Host only. */
+t2r_status t2r_gel_info(const t2r_ctx* ctx, int32_t gel_id, int32_t* out10);
 
 /* Host copy of a gel class's embedding: marker_tri[n_m][3] vertex ids and
  * marker_w[n_m][3] barycentric weights (either pointer may be NULL). */
@@ -251,8 +254,17 @@ t2r_status t2r_set_state(t2r_ctx* ctx, const double* d_state);
 /* Puts the listed envs (host ids) back at rest with their initial pose. */
 t2r_status t2r_reset_envs(t2r_ctx* ctx, const int32_t* env_ids, int32_t n);
 
-/* Sets the contact pair capacity per env (reallocates; state is kept). */
+/* Sets the contact pair capacity per env (0: automatic). After the first GPU
+ * call this reallocates the pair lists (positions and poses are kept; the lists
+ * are rebuilt on the next step). T2R_E_NOMEM leaves the old capacity. */
 t2r_status t2r_set_pair_capacity(t2r_ctx* ctx, int32_t capacity);
+
+/* Reads / replaces the solver options. Every field may change between steps
+ * (block_size picks the workgroup shape of the next launch; a new
+ * pair_capacity reallocates as t2r_set_pair_capacity). Invalid options:
+ * T2R_E_ARG and no change. */
+t2r_status t2r_get_opts(const t2r_ctx* ctx, t2r_solver_opts* out);
+t2r_status t2r_set_opts(t2r_ctx* ctx, const t2r_solver_opts* opts);
 
 /* Adjoint of the marker loss over the steps since the last reset; not in this
  * build (T2R_E_UNSUPPORTED). */

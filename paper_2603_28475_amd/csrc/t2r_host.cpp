@@ -139,6 +139,18 @@ void* dev_alloc(t2r_ctx* c, size_t bytes) {
   return p;
 }
 
+void dev_free(t2r_ctx* c, void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < c->allocs.size(); ++i) {
+    if (c->allocs[i] == p) {
+      if (c->free_fn) c->free_fn(p, c->alloc_user);
+      else (void)hipFree(p);
+      c->allocs.erase(c->allocs.begin() + (long)i);
+      return;
+    }
+  }
+}
+
 void dev_free_all(t2r_ctx* c) {
   for (void* p : c->allocs) {
     if (c->free_fn) c->free_fn(p, c->alloc_user);
@@ -236,6 +248,8 @@ void build_grid(IndHost::GridHost& G, const std::vector<std::array<double, 6>>& 
 }
 
 t2r_status commit(t2r_ctx* c);
+t2r_status relayout_lists(t2r_ctx* c);
+int pair_cap_of(const t2r_ctx* c, const GelHost& g);
 
 }  // namespace
 
@@ -614,6 +628,7 @@ t2r_status t2r_gel_info(const t2r_ctx* c, int32_t id, int32_t* out) {
   const GelHost& g = c->gels[id];
   out[0] = g.n_v; out[1] = g.n_t; out[2] = g.n_sv; out[3] = g.n_se; out[4] = g.n_sf;
   out[5] = g.n_m; out[6] = (int)g.tile_tet.size() - 1; out[7] = g.n_top; out[8] = g.n_fixed;
+  out[9] = pair_cap_of(c, g);
   return T2R_OK;
 }
 
@@ -1012,8 +1027,31 @@ t2r_status t2r_reset_envs(t2r_ctx* c, const int32_t* ids, int32_t n) {
 t2r_status t2r_set_pair_capacity(t2r_ctx* c, int32_t cap) {
   if (!c || cap < 0) return T2R_E_ARG;
   if (cap > (1 << 24)) return fail(c, T2R_E_ARG, "pair capacity too large");
-  if (c->committed) return fail(c, T2R_E_STATE, "pair capacity must be set before the first GPU call");
+  const int32_t old = c->opts.pair_capacity;
   c->opts.pair_capacity = cap;
+  if (c->committed && cap != old) {
+    const t2r_status s = relayout_lists(c);
+    if (s != T2R_OK) { c->opts.pair_capacity = old; return s; }
+  }
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_get_opts(const t2r_ctx* c, t2r_solver_opts* out) {
+  if (!c || !out) return T2R_E_ARG;
+  *out = c->opts;
+  return T2R_OK;
+}
+
+t2r_status t2r_set_opts(t2r_ctx* c, const t2r_solver_opts* o) {
+  if (!c || !o) return T2R_E_ARG;
+  t2r_status s = check_opts(c, o);
+  if (s != T2R_OK) return s;
+  if (o->pair_capacity != c->opts.pair_capacity) {
+    s = t2r_set_pair_capacity(c, o->pair_capacity);
+    if (s != T2R_OK) return s;
+  }
+  c->opts = *o;
   c->err.clear();
   return T2R_OK;
 }
@@ -1072,6 +1110,61 @@ T* alloc_n(t2r_ctx* c, size_t n) {
   return (T*)dev_alloc(c, n * sizeof(T));
 }
 
+int pair_cap_of(const t2r_ctx* c, const GelHost& g) {
+  const int cap = c->opts.pair_capacity;
+  return cap > 0 ? cap : std::max(8192, 3 * (g.n_sv + g.n_se + g.n_sf));
+}
+
+// After the first GPU call: new pair-list capacities. The lists are rebuilt on
+// the next step anyway, so the old buffers are dropped (state vectors kept)
+// and every env's lists are marked invalid.
+t2r_status relayout_lists(t2r_ctx* c) {
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::vector<EnvDev> he = c->h_envs;
+  long long poff = 0, foff = 0, ooff = 0;
+  for (size_t i = 0; i < he.size(); ++i) {
+    EnvDev& d = he[i];
+    const int cap = pair_cap_of(c, c->gels[d.gel]);
+    d.pair_cap = cap;
+    d.fric_cap = std::max(1024, cap / 2);
+    d.outer_cap = 4 * cap;
+    d.poff = poff;
+    d.foff = foff;
+    d.ooff = ooff;
+    poff += cap;
+    foff += d.fric_cap;
+    ooff += d.outer_cap;
+  }
+  int2* pairs = alloc_n<int2>(c, (size_t)poff);
+  double* pair_d = alloc_n<double>(c, (size_t)poff);
+  int2* outer = alloc_n<int2>(c, (size_t)ooff);
+  uint64_t* oslot = alloc_n<uint64_t>(c, (size_t)ooff);
+  uint64_t* pslot = alloc_n<uint64_t>(c, (size_t)poff);
+  FricPair* fric = alloc_n<FricPair>(c, (size_t)foff);
+  const EnvDev* de = nullptr;
+  t2r_status s = T2R_OK;
+  if (pairs && pair_d && outer && oslot && pslot && fric) s = upload(c, he, &de);
+  if (!(pairs && pair_d && outer && oslot && pslot && fric) || s != T2R_OK || !de) {
+    for (void* p : {(void*)pairs, (void*)pair_d, (void*)outer, (void*)oslot, (void*)pslot, (void*)fric})
+      dev_free(c, p);
+    return fail(c, T2R_E_NOMEM, "pair list allocation failed (%lld inner pairs)", poff);
+  }
+  for (void* p : {(void*)c->d_pairs, (void*)c->d_pair_d, (void*)c->d_outer, (void*)c->d_oslot,
+                  (void*)c->d_pslot, (void*)c->d_fric, (void*)c->d_envs})
+    dev_free(c, p);
+  c->d_pairs = pairs;
+  c->d_pair_d = pair_d;
+  c->d_outer = outer;
+  c->d_oslot = oslot;
+  c->d_pslot = pslot;
+  c->d_fric = fric;
+  c->d_envs = (EnvDev*)de;
+  c->h_envs = he;
+  HIP_TRY(c, hipMemsetAsync(c->d_lists, 0, c->envs.size() * sizeof(ListState), c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return T2R_OK;
+}
+
 t2r_status commit(t2r_ctx* c) {
   if (c->committed) return T2R_OK;
   int dev_count = 0;
@@ -1113,8 +1206,7 @@ t2r_status commit(t2r_ctx* c) {
     d.eps_v = e.mat.eps_v;
     d.dhat = e.mat.dhat;
     d.kappa = e.mat.kappa;
-    int cap = c->opts.pair_capacity;
-    if (cap == 0) cap = std::max(8192, 3 * (g.n_sv + g.n_se + g.n_sf));
+    const int cap = pair_cap_of(c, g);
     d.pair_cap = cap;
     d.fric_cap = std::max(1024, cap / 2);
     d.outer_cap = 4 * cap;

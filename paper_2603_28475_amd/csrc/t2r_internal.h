@@ -131,9 +131,10 @@ struct ListState {         // neighbour lists kept across load steps
 
 struct EnvStats {
   int status, iters, substeps, restarts, halvings, reculls, n_candidates, n_active,
-      n_friction, max_solve_iters, outer_builds, pad;
+      n_friction, max_solve_iters, outer_builds, n_outer;
   double d_min, residual, energy;
   double phase_ms[10];     // see t2r_env_stats
+  double list_fill;        // largest list length / capacity seen in the launch
 };
 
 struct StepParams {

@@ -1188,6 +1188,7 @@ struct Solver {
   double* xs_i;       // [3][n_sv] ... at the inner build
   // stats
   int reculls, restarts, halvings, ncand, outer_builds;
+  double fill;        // largest list length / capacity seen
 };
 
 // Inner candidate list from the outer one: exact distance of every coarse pair,
@@ -1375,6 +1376,7 @@ __device__ __forceinline__ bool rebuild_outer(Solver& s, const double* x) {
   const int cnt = s.S->count;
   __syncthreads();
   V.nouter = min(cnt, s.outer_cap);
+  s.fill = fmax(s.fill, (double)cnt / s.outer_cap);
   snapshot(s, x, s.xs_o);
   build_slots(s);
   if (threadIdx.x == 0) {
@@ -1402,6 +1404,7 @@ __device__ __forceinline__ bool refilter(Solver& s, const double* x) {
   const int cnt = s.S->count;
   __syncthreads();
   V.npairs = min(cnt, s.pair_cap);
+  s.fill = fmax(s.fill, (double)cnt / s.pair_cap);
   s.ncand = V.npairs;
   ++s.reculls;
   snapshot(s, x, s.xs_i);
@@ -1740,6 +1743,7 @@ __device__ __forceinline__ void init_solver(Solver& s, const StepParams& P, Shar
   s.xs_o = P.xsnap + E.snoff;
   s.xs_i = P.xsnap + E.snoff + 3 * (long long)G.n_sv;
   s.reculls = s.restarts = s.halvings = s.ncand = s.outer_builds = 0;
+  s.fill = 0.0;
 }
 
 
@@ -1784,6 +1788,7 @@ __device__ __forceinline__ int load_step(const StepParams& P, int e, Solver& s, 
     dmin_start = block_min(dm, S);
     tock(S, 9, t0);
     V.nfric = (mode == 1) ? min(cnt, s.fric_cap) : 0;
+    if (mode == 1) s.fill = fmax(s.fill, (double)cnt / s.fric_cap);
     if (ov) status |= kOverflow;
   }
   st.n_friction = V.nfric;
@@ -1893,9 +1898,10 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
   EnvStats st;
   st.status = 0; st.iters = 0; st.substeps = 0; st.restarts = 0; st.halvings = 0; st.reculls = 0;
   st.n_candidates = 0; st.n_active = 0; st.n_friction = 0; st.max_solve_iters = 0;
-  st.outer_builds = 0; st.pad = 0;
+  st.outer_builds = 0; st.n_outer = 0;
   st.d_min = kInf; st.residual = 0.0; st.energy = 0.0;
   for (int k = 0; k < 10; ++k) st.phase_ms[k] = 0.0;
+  st.list_fill = 0.0;
   const bool skip = P.env_mask && P.env_mask[e] == 0;
   load_lists(s);
   for (int k = 0; k < P.n_steps; ++k) {
@@ -1921,6 +1927,8 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
   st.reculls = s.reculls;
   st.outer_builds = s.outer_builds;
   st.n_candidates = s.ncand;
+  st.n_outer = V.nouter;
+  st.list_fill = s.fill;
   if (P.x_out) {
     T2R_G double* xo = P.x_out + 3 * P.x_out_off[e];
     for (int j = threadIdx.x; j < 3 * nv; j += blockDim.x) {

@@ -43,6 +43,7 @@ class Sim:
         sel = workload.envs if envs is None else [workload.envs[i] for i in envs]
         sim.ctx.add_envs([sim.gel_ids[e.mesh] for e in sel], [sim.ind_ids[e.indenter] for e in sel],
                          [e.material() for e in sel], np.stack([e.poses[0] for e in sel]))
+        sim.env_gel = [sim.gel_ids[e.mesh] for e in sel]
         for e in sel:
             info = sim.ctx.gel_info(sim.gel_ids[e.mesh])
             sim.n_m.append(info["n_m"])
@@ -97,6 +98,53 @@ class Sim:
                 self._pose_buf.copy_(p)
                 self._graph.replay()
         return self.markers, self.status
+
+    def autotune(self, poses, blocks=(256, 512), target_steps=1):
+        """Picks the workgroup shape and pair-list capacity for this batch.
+
+        Runs the trial load steps `poses` ((S, n_env, 7)) from the current state
+        once per candidate block shape and keeps the faster one for launches of
+        `target_steps` load steps: short launches are judged by their measured
+        duration; long ones (>= 4 steps) by the larger of the slowest env and
+        the summed env time over the resident workgroup slots (2 per CU at 256
+        threads, 1 at 512), since their imbalance averages out. Doubles the
+        pair capacity while any list of the trial used more than half of it,
+        and restores the state (positions and poses). Tuning time is setup, not
+        part of a timed step. Returns {"block_size", "pair_capacity",
+        "trial_ms", "predicted_ms", "list_fill"}."""
+        import time
+        saved = torch.empty(self.ctx.state_size(), dtype=torch.float64, device=self.device)
+        self.ctx.get_state(saved)
+        opts = self.ctx.get_opts()
+        n_cu = torch.cuda.get_device_properties(self.device).multi_processor_count
+        trial_ms, predicted, used = {}, {}, 0.0
+        for b in blocks:
+            opts.block_size = b
+            self.ctx.set_opts(opts)
+            self.ctx.set_state(saved)
+            self.stream.synchronize()
+            t0 = time.perf_counter()
+            self.step_sequence(poses)
+            self.stream.synchronize()
+            trial_ms[b] = 1e3 * (time.perf_counter() - t0)
+            st = self.stats()
+            env_ms = [x["phase_ms"][8] for x in st]
+            slots = n_cu * (2 if b == 256 else 1)
+            predicted[b] = (max(max(env_ms), sum(env_ms) / slots) if target_steps >= 4 else trial_ms[b])
+            used = max([used] + [x["list_fill"] for x in st])
+        opts.block_size = min(predicted, key=predicted.get)
+        grow = 1
+        while used > 0.5:
+            grow, used = 2 * grow, used / 2
+        if grow > 1:
+            # automatic capacities differ per gel class; a fixed one takes the largest, grown
+            base = max(self.ctx.gel_info(g)["pair_capacity"] for g in set(self.env_gel))
+            opts.pair_capacity = grow * base
+        self.ctx.set_opts(opts)
+        self.ctx.set_state(saved)
+        self.stream.synchronize()
+        return {"block_size": opts.block_size, "pair_capacity": opts.pair_capacity, "trial_ms": trial_ms,
+                "predicted_ms": predicted, "list_fill": used * grow}
 
     def split_markers(self, markers=None):
         markers = self.markers if markers is None else markers

@@ -36,8 +36,8 @@ class EnvStats(C.Structure):
                 ("restarts", C.c_int32), ("halvings", C.c_int32), ("reculls", C.c_int32),
                 ("n_candidates", C.c_int32), ("n_active", C.c_int32), ("n_friction", C.c_int32),
                 ("max_solve_iters", C.c_int32), ("outer_builds", C.c_int32),
-                ("reserved", C.c_int32), ("d_min", C.c_double), ("residual", C.c_double),
-                ("energy", C.c_double), ("phase_ms", C.c_double * 10)]
+                ("n_outer", C.c_int32), ("d_min", C.c_double), ("residual", C.c_double),
+                ("energy", C.c_double), ("phase_ms", C.c_double * 10), ("list_fill", C.c_double)]
 
 
 class T2RError(RuntimeError):
@@ -73,6 +73,8 @@ SIGNATURES = [
     ("t2r_set_state", C.c_int32, [_P, _P]),
     ("t2r_reset_envs", C.c_int32, [_P, _PI, C.c_int32]),
     ("t2r_set_pair_capacity", C.c_int32, [_P, C.c_int32]),
+    ("t2r_get_opts", C.c_int32, [_P, C.POINTER(SolverOpts)]),
+    ("t2r_set_opts", C.c_int32, [_P, C.POINTER(SolverOpts)]),
     ("t2r_backward", C.c_int32, [_P, _P, _P]),
 ]
 
@@ -153,9 +155,9 @@ class Context:
         return gid.value
 
     def gel_info(self, gid) -> dict:
-        out = np.zeros(9, np.int32)
+        out = np.zeros(10, np.int32)
         self.check(lib.t2r_gel_info(self.handle, gid, _dptr(out, C.c_int32)))
-        keys = ["n_v", "n_t", "n_sv", "n_se", "n_sf", "n_m", "n_tiles", "n_top", "n_fixed"]
+        keys = ["n_v", "n_t", "n_sv", "n_se", "n_sf", "n_m", "n_tiles", "n_top", "n_fixed", "pair_capacity"]
         return dict(zip(keys, out.tolist()))
 
     def gel_markers(self, gid):
@@ -197,6 +199,14 @@ class Context:
 
     def set_pair_capacity(self, cap):
         self.check(lib.t2r_set_pair_capacity(self.handle, cap))
+
+    def get_opts(self) -> SolverOpts:
+        o = SolverOpts()
+        self.check(lib.t2r_get_opts(self.handle, C.byref(o)))
+        return o
+
+    def set_opts(self, opts: SolverOpts):
+        self.check(lib.t2r_set_opts(self.handle, C.byref(opts)))
 
     # -- GPU entry points (torch tensors on the context's device) -----------
     def step(self, d_pose, d_mask=None, d_markers=None, d_x=None, d_status=None):

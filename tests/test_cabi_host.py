@@ -112,3 +112,26 @@ def test_workload_classes_build_on_the_host():
     first = ctx.add_envs([gid] * 3, [iid] * 3, [e.material() for e in w.envs],
                          np.stack([e.poses[0] for e in w.envs]))
     assert first == 0 and ctx.env_count()[0] == 3
+
+
+def test_options_roundtrip_and_capacity_rule():
+    t2r = _t2r()
+    ctx = t2r.Context()
+    o = ctx.get_opts()
+    assert o.block_size == 0 and o.pair_capacity == 0
+    o.block_size = 512
+    o.tol = 1e-8
+    ctx.set_opts(o)
+    assert ctx.get_opts().block_size == 512 and ctx.get_opts().tol == 1e-8
+    bad = ctx.get_opts()
+    bad.block_size = 100
+    with pytest.raises(t2r.T2RError):
+        ctx.set_opts(bad)
+    assert ctx.get_opts().block_size == 512
+    for name in ("c1", "5k"):
+        g = mesh_class(name)
+        gid = ctx.add_gel(g.X, g.tets, g.fixed, g.markers)
+        info = ctx.gel_info(gid)
+        assert info["pair_capacity"] == max(8192, 3 * (info["n_sv"] + info["n_se"] + info["n_sf"]))
+    ctx.set_pair_capacity(5000)
+    assert ctx.gel_info(gid)["pair_capacity"] == 5000

@@ -278,6 +278,35 @@ def test_graph_captured_step_matches_eager_steps():
         assert np.abs(mg.cpu().numpy() - me.cpu().numpy()).max() <= 1e-6, s
 
 
+def test_autotune_restores_state_and_capacity_regrow_keeps_solving():
+    """The autotuner's trial steps leave positions and poses as they were; a
+    pair capacity changed after the first step reallocates the lists and the
+    next steps still match the oracle path."""
+    t2r = _gpu()
+    from scenes.configs import sphere_press_484v
+    w = sphere_press_484v(n_envs=2, n_steps=10)
+    gold = np.load(os.path.join(HERE, "golden", "sphere_press_484v_newton.npz"))
+    sim = _build(t2r, w, tol=1e-10, substep_tol=1e-6, max_iters=200000)
+    poses = np.stack([e.poses for e in w.envs])
+    sim.step(poses[:, 1])
+    torch.cuda.synchronize()
+    before = torch.empty(sim.ctx.state_size(), dtype=torch.float64, device="cuda:0")
+    sim.ctx.get_state(before)
+    res = sim.autotune(np.ascontiguousarray(poses[:, 2:4].transpose(1, 0, 2)))
+    assert res["block_size"] in (256, 512) and set(res["trial_ms"]) == {256, 512}
+    after = torch.empty_like(before)
+    sim.ctx.get_state(after)
+    torch.cuda.synchronize()
+    assert torch.equal(before, after)
+    sim.ctx.set_pair_capacity(2 * sim.ctx.gel_info(0)["pair_capacity"])
+    for s in range(2, poses.shape[1]):
+        m, st = sim.step(poses[:, s], want_x=True)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() & 1)
+    # env 0 is the golden env
+    assert np.abs(sim.split_x()[0].cpu().numpy() - gold["x"][-1]).max() <= 1e-6
+
+
 def _certify_equilibrium(w, env, pose, x, bound=1e-6):
     """The oracle's Newton started from x must not move: x is a minimiser of Pi."""
     from oracle.newton import newton_solve
