@@ -266,8 +266,27 @@ t2r_status t2r_set_pair_capacity(t2r_ctx* ctx, int32_t capacity);
 t2r_status t2r_get_opts(const t2r_ctx* ctx, t2r_solver_opts* out);
 t2r_status t2r_set_opts(t2r_ctx* ctx, const t2r_solver_opts* opts);
 
-/* Adjoint of the marker loss over the steps since the last reset; not in this
- * build (T2R_E_UNSUPPORTED). */
+/* Gradient of a loss L on the marker displacements of the current equilibrium
+ * (the result of the last load step) with respect to each env's parameters
+ * theta = (E, nu, mu_f, dt_x, dt_y, dt_z, dw_x, dw_y, dw_z): material, friction
+ * coefficient and a rigid offset of the indenter that moves every indenter
+ * point y to exp([dw]x)(y - t) + t + dt (t the indenter origin at the current
+ * pose), taken at dt = dw = 0. Implicit differentiation at the equilibrium
+ * (the spec adjoint; the paper itself calibrates without gradients):
+ *   H lambda = dL/dx  (exact Hessian of the step energy, free DOFs; Jacobi-
+ *                      preconditioned CG to a relative residual of 1e-10, at
+ *                      most max_iters iterations, matrix-free on the GPU),
+ *   dL/dtheta = -lambda^T dg/dtheta.
+ * Covers frictionless equilibria (every env mu_f = 0): the last step then does
+ * not depend on earlier steps, and dL/dmu_f is the derivative at mu_f = 0
+ * (friction lagged at the previous equilibrium, with unit coefficient).
+ *   d_dL_du  device [sum n_m][3]: dL/du, envs in order
+ *   d_grad   device [n_env][9]: dL/dtheta
+ * Per-env CG iterations, relative residual and status (T2R_ENV_CONVERGED,
+ * T2R_ENV_MAXITER, T2R_ENV_NONFINITE for a Hessian that is not positive on
+ * the CG directions) are reported by t2r_get_stats. Errors: T2R_E_UNSUPPORTED
+ * if an env has mu_f != 0, T2R_E_STATE before the first load step.
+ * Asynchronous; positions and poses are not changed. */
 t2r_status t2r_backward(t2r_ctx* ctx, const double* d_dL_du, double* d_grad);
 
 #ifdef __cplusplus

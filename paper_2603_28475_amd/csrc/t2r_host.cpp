@@ -98,6 +98,9 @@ struct t2r_ctx {
   int* d_imap = nullptr;
   int* d_islot_v = nullptr;
   int* d_order = nullptr;
+  double* d_pose_lag = nullptr;
+  double* d_adj = nullptr;
+  bool stepped = false;
   uint64_t* d_oslot = nullptr;
   uint64_t* d_pslot = nullptr;
   int* d_slot_v = nullptr;
@@ -797,6 +800,11 @@ static StepParams step_params(t2r_ctx* c) {
   P.slot_v = c->d_slot_v;
   P.stats = c->d_stats;
   P.order = nullptr;
+  P.pose_lag = c->d_pose_lag;
+  P.adj = c->d_adj;
+  P.dL_du = nullptr;
+  P.grad_out = nullptr;
+  P.cg_tol = 1e-10;
   P.n_steps = 1;
   P.markers_stride = 0;
   P.x_out_off = c->d_xout_off;
@@ -832,6 +840,7 @@ t2r_status t2r_step_sequence(t2r_ctx* c, int32_t n_steps, const double* d_poses,
     P.order = c->d_order;
   }
   HIP_TRY(c, t2r_launch_step(&P, block_of(c), c->stream));
+  c->stepped = true;
   c->err.clear();
   return T2R_OK;
 }
@@ -1056,8 +1065,21 @@ t2r_status t2r_set_opts(t2r_ctx* c, const t2r_solver_opts* o) {
   return T2R_OK;
 }
 
-t2r_status t2r_backward(t2r_ctx* c, const double*, double*) {
-  return fail(c, T2R_E_UNSUPPORTED, "the adjoint is not part of this build");
+t2r_status t2r_backward(t2r_ctx* c, const double* d_dL_du, double* d_grad) {
+  if (!c) return T2R_E_ARG;
+  for (size_t i = 0; i < c->envs.size(); ++i)
+    if (c->envs[i].mat.mu_f != 0.0)
+      return fail(c, T2R_E_UNSUPPORTED,
+                  "env %zu has mu_f = %g: the adjoint covers frictionless equilibria (mu_f = 0)", i,
+                  c->envs[i].mat.mu_f);
+  if (!d_dL_du || !d_grad) return fail(c, T2R_E_ARG, "d_dL_du and d_grad are required");
+  if (!c->committed || !c->stepped) return fail(c, T2R_E_STATE, "no load step has run");
+  StepParams P = step_params(c);
+  P.dL_du = d_dL_du;
+  P.grad_out = d_grad;
+  HIP_TRY(c, t2r_launch_backward(&P, block_of(c), c->stream));
+  c->err.clear();
+  return T2R_OK;
 }
 
 }  // extern "C"
@@ -1267,10 +1289,12 @@ t2r_status commit(t2r_ctx* c) {
   c->d_islot_v = alloc_n<int>(c, c->envs.size() * (size_t)kIndSlots);
   c->d_stats = alloc_n<EnvStats>(c, c->envs.size());
   c->d_order = alloc_n<int>(c, c->envs.size());
+  c->d_pose_lag = alloc_n<double>(c, 7 * c->envs.size());
+  c->d_adj = alloc_n<double>(c, nd);
   if (!c->d_x || !c->d_xprev || !c->d_g0 || !c->d_g1 || !c->d_diag || !c->d_p || !c->d_pose_prev ||
       !c->d_pairs || !c->d_pair_d || !c->d_outer || !c->d_lists || !c->d_xsnap || !c->d_fric ||
       !c->d_vmap || !c->d_oslot || !c->d_pslot || !c->d_slot_v || !c->d_imap || !c->d_islot_v ||
-      !c->d_stats || !c->d_order) {
+      !c->d_stats || !c->d_order || !c->d_pose_lag || !c->d_adj) {
     dev_free_all(c);
     return fail(c, T2R_E_NOMEM, "state allocation failed (%lld DOFs)", voff);
   }
@@ -1288,6 +1312,8 @@ t2r_status commit(t2r_ctx* c) {
   HIP_TRY(c, hipMemsetAsync(c->d_vmap, 0, (size_t)vtot * sizeof(int), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_imap, 0, (size_t)std::max(imtot, 1LL) * sizeof(int), c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->d_pose_prev, pose.data(), pose.size() * sizeof(double), hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_pose_lag, pose.data(), pose.size() * sizeof(double), hipMemcpyHostToDevice,
                             c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));  // host staging vectors go out of scope
   c->committed = true;

@@ -150,6 +150,8 @@ struct StepParams {
   T2R_G double* diag;
   T2R_G double* p;
   T2R_G double* pose_prev;       // [n_env][7]
+  T2R_G double* pose_lag;        // [n_env][7] q_{s-1} of the last load step (friction lag pose)
+  T2R_G double* adj;             // [sum 3 n_v] adjoint scratch vector
   T2R_G int2* pairs;             // [sum pair_cap]
   T2R_G double* pair_d;          // [sum pair_cap] distance of each candidate at the current x
   T2R_G int2* outer;             // [sum outer_cap] coarse candidates (wider radius, rebuilt rarely)
@@ -177,6 +179,10 @@ struct StepParams {
   double clock_khz;        // wall-clock counter rate (phase timers)
   double tol, substep_tol;
   int max_iters, max_substeps, precision, armijo;
+  // adjoint
+  const T2R_G double* dL_du;     // [sum n_m][3]
+  T2R_G double* grad_out;        // [n_env][9]
+  double cg_tol;                 // relative residual of the adjoint solve
 };
 
 struct EvalParams {
@@ -195,6 +201,7 @@ struct EvalParams {
 extern "C" {
 hipError_t t2r_launch_step(const t2r::StepParams* p, int block, hipStream_t stream);
 hipError_t t2r_launch_order(const t2r::StepParams* p, int* order, hipStream_t stream);
+hipError_t t2r_launch_backward(const t2r::StepParams* p, int block, hipStream_t stream);
 hipError_t t2r_launch_eval(const t2r::EvalParams* p, int block, hipStream_t stream);
 hipError_t t2r_launch_pack_state(const t2r::StepParams* p, const double* in, double* out,
                                  const long long* state_off, int direction, hipStream_t stream);

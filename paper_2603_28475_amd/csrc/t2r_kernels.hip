@@ -83,6 +83,7 @@ union Tile {
 template <int NS, int NM>
 __device__ __forceinline__ void block_reduce(double* v, Shared& S) {
   constexpr int N = NS + NM;
+  static_assert(N <= 8, "block_reduce: at most 8 values (8 slots per wave in Shared::red)");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
 #pragma unroll
@@ -1030,7 +1031,7 @@ __device__ __forceinline__ int cell_of(double v, double o, double inv, int dim) 
 // id: vertex ids of the four points; rec: the pair's slot record (used only
 // when the env has slots).
 __device__ __forceinline__ void make_fric(const View& V, const PairPts& P, const Feature& f, const double r[3],
-                                          double d, const int id[4], uint64_t rec, FricPair& F) {
+                                          double d, const int id[4], uint64_t rec, double muf, FricPair& F) {
   const EnvDev& E = *V.E;
   const int kind = P.kind;
   const double sgn = (kind == kFV) ? -1.0 : 1.0;  // r = gel - indenter for VF and EE
@@ -1065,7 +1066,7 @@ __device__ __forceinline__ void make_fric(const View& V, const PairPts& P, const
   }
   double b, b1, b2;
   barrier3(d, E.dhat, b, b1, b2);
-  F.mulam = -E.mu_f * E.kappa * b1;
+  F.mulam = -muf * E.kappa * b1;
 }
 
 // Coarse candidates (exact distance < thr) into V.outer, at most cap of them
@@ -1454,7 +1455,7 @@ __device__ __forceinline__ void load_lists(Solver& s) {
 // exact distance of every coarse pair; pairs closer than dhat get a friction
 // record when mode == 1. Requires a valid outer list. Returns the thread's min d.
 template <bool LDS>
-__device__ __forceinline__ double lag_pass(Solver& s, const double* x, int mode) {
+__device__ __forceinline__ double lag_pass(Solver& s, const double* x, int mode, double muf) {
   View& V = s.V;
   Shared& S = *s.S;
   const Tile& T = *s.T;
@@ -1476,7 +1477,7 @@ __device__ __forceinline__ double lag_pass(Solver& s, const double* x, int mode)
       if (slot < s.fric_cap) {
         int id[4];
         pair_point_ids(*V.G, *V.I, pr, id);
-        make_fric(V, P, f, r, d, id, rec, V.fric[slot]);
+        make_fric(V, P, f, r, d, id, rec, muf, V.fric[slot]);
       } else {
         S.overflow = 1;
       }
@@ -1486,12 +1487,14 @@ __device__ __forceinline__ double lag_pass(Solver& s, const double* x, int mode)
   return dmin;
 }
 
-__device__ __forceinline__ double lag_from_outer(Solver& s, const double* x, int mode) {
+// muf: the friction coefficient the records carry (the env's own, or 1 for the
+// derivative with respect to it).
+__device__ __forceinline__ double lag_from_outer(Solver& s, const double* x, int mode, double muf) {
   if (s.V.slots_ok) {
     stage_points(s.V, *s.S, *s.T, x, nullptr, 0.0, 0);
-    return lag_pass<true>(s, x, mode);
+    return lag_pass<true>(s, x, mode, muf);
   }
-  return lag_pass<false>(s, x, mode);
+  return lag_pass<false>(s, x, mode, muf);
 }
 
 // Smallest pair distance and active count at x over the inner list (block-wide).
@@ -1768,6 +1771,8 @@ __device__ __forceinline__ int load_step(const StepParams& P, int e, Solver& s, 
   double q0[7];
   #pragma unroll
   for (int i = 0; i < 7; ++i) q0[i] = pose_prev[i];
+  // q_{s-1} of this load step (its friction lag pose), kept for the adjoint
+  if (threadIdx.x < 7) P.pose_lag[7 * e + threadIdx.x] = q0[threadIdx.x];
   // keep x_{s-1} for the friction lag and for rollback
   for (int j = threadIdx.x; j < n; j += blockDim.x) V.xprev[j] = V.x[j];
   // friction lag and starting distance at (x_{s-1}, q_{s-1}), from the outer
@@ -1783,7 +1788,7 @@ __device__ __forceinline__ int load_step(const StepParams& P, int e, Solver& s, 
   } else {
     const int mode = (E.mu_f > 0.0) ? 1 : 2;
     const unsigned long long t0 = tick();
-    double dm = lag_from_outer(s, V.x, mode);
+    double dm = lag_from_outer(s, V.x, mode, E.mu_f);
     const int cnt = S.count, ov = S.overflow;
     dmin_start = block_min(dm, S);
     tock(S, 9, t0);
@@ -1943,6 +1948,563 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
   }
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint: gradient of a marker loss at a frictionless equilibrium x*
+// (implicit differentiation: H lambda = dL/dx, dL/dtheta = -lambda^T dg/dtheta;
+// theta = E, nu, mu_f and a rigid pose offset). The solve is Jacobi-PCG with the
+// exact Hessian applied matrix-free; all arithmetic is FP64.
+// ---------------------------------------------------------------------------
+
+// out = H_elastic v at x ([3][n_v]; every vertex written, fixed vertices 0).
+__device__ __forceinline__ void elem_hvp(const View& V, const double* x, const double* v, double* out, Tile& T) {
+  const GelDev& G = *V.G;
+  const EnvDev& E = *V.E;
+  const int nv = G.n_v;
+  const int B = blockDim.x;
+  const double mu = E.mu, lam = E.lam;
+  for (int i = threadIdx.x; i < kTileVerts; i += B) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) T.g[c][i] = 0.0;
+  }
+  for (int tile = 0; tile < G.n_tiles; ++tile) {
+    const int t0 = G.tile_tet[tile], t1 = G.tile_tet[tile + 1];
+    SlotIdx cur;
+    fetch_idx(G, tile, cur);
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s)
+      if (cur.fl[s] >= 0)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          T.x[c][threadIdx.x + s * B] = x[c * nv + cur.v[s]];
+          T.p[c][threadIdx.x + s * B] = v[c * nv + cur.v[s]];
+        }
+    __syncthreads();
+    for (int e = t0 + threadIdx.x; e < t1; e += B) {
+      TetIn<false> t;
+      load_tet<false>(G, e, t);
+      int l[4];
+      tet_ids(t.loc, l);
+      double F[9], dF[9];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          double f = 0.0, df = 0.0;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            f += (T.x[a][l[k + 1]] - T.x[a][l[0]]) * t.Dm[k * 3 + b];
+            df += (T.p[a][l[k + 1]] - T.p[a][l[0]]) * t.Dm[k * 3 + b];
+          }
+          F[a * 3 + b] = f;
+          dF[a * 3 + b] = df;
+        }
+      double C[9];  // cofactor = J F^-T
+      C[0] = F[4] * F[8] - F[5] * F[7];
+      C[1] = F[5] * F[6] - F[3] * F[8];
+      C[2] = F[3] * F[7] - F[4] * F[6];
+      C[3] = F[2] * F[7] - F[1] * F[8];
+      C[4] = F[0] * F[8] - F[2] * F[6];
+      C[5] = F[1] * F[6] - F[0] * F[7];
+      C[6] = F[1] * F[5] - F[2] * F[4];
+      C[7] = F[2] * F[3] - F[0] * F[5];
+      C[8] = F[0] * F[4] - F[1] * F[3];
+      const double J = F[0] * C[0] + F[1] * C[1] + F[2] * C[2];
+      const double iJ = 1.0 / J;
+      const double lnJ = log(J);
+      // A = F^-1 dF (F^-1 = C^T / J)
+      double A[9];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          A[a * 3 + b] = (C[0 * 3 + a] * dF[0 * 3 + b] + C[1 * 3 + a] * dF[1 * 3 + b] +
+                          C[2 * 3 + a] * dF[2 * 3 + b]) * iJ;
+      const double trA = A[0] + A[4] + A[8];
+      // dP = mu dF + (mu - lam lnJ) F^-T dF^T F^-T + lam tr(A) F^-T, with
+      // (F^-T dF^T F^-T)_ab = (A F^-1)_ba = sum_k A_bk C_ak / J
+      const double c1 = mu - lam * lnJ, c2 = lam * trA;
+      double dP[9];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          const double q = (A[b * 3 + 0] * C[a * 3 + 0] + A[b * 3 + 1] * C[a * 3 + 1] + A[b * 3 + 2] * C[a * 3 + 2]) * iJ;
+          dP[a * 3 + b] = t.vol * (mu * dF[a * 3 + b] + c1 * q + c2 * C[a * 3 + b] * iJ);
+        }
+      double s0[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 1; i < 4; ++i)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const double o = dP[a * 3 + 0] * t.Dm[(i - 1) * 3 + 0] + dP[a * 3 + 1] * t.Dm[(i - 1) * 3 + 1] +
+                           dP[a * 3 + 2] * t.Dm[(i - 1) * 3 + 2];
+          atomicAdd(&T.g[a][l[i]], o);
+          s0[a] += o;
+        }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) atomicAdd(&T.g[a][l[0]], -s0[a]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+      const int i = threadIdx.x + s * B;
+      if (cur.fl[s] < 0) continue;
+      const int vtx = cur.v[s];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double o = T.g[c][i];
+        T.g[c][i] = 0.0;
+        if (!(cur.fl[s] & kFirstTouch)) o += out[c * nv + vtx];
+        if (cur.fl[s] & kFixedLast) o = 0.0;
+        out[c * nv + vtx] = o;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Thread partials of lambda^T g_mu and lambda^T g_lam, where the elastic
+// gradient is mu g_mu + lam g_lam: sum_e V (F - F^-T) : dF and
+// sum_e V ln J F^-T : dF with dF the deformation gradient of lambda.
+__device__ __forceinline__ void elem_theta(const View& V, const double* x, const double* lv, Tile& T,
+                                           double& c_mu, double& c_lam) {
+  const GelDev& G = *V.G;
+  const int nv = G.n_v;
+  const int B = blockDim.x;
+  for (int tile = 0; tile < G.n_tiles; ++tile) {
+    const int t0 = G.tile_tet[tile], t1 = G.tile_tet[tile + 1];
+    SlotIdx cur;
+    fetch_idx(G, tile, cur);
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s)
+      if (cur.fl[s] >= 0)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          T.x[c][threadIdx.x + s * B] = x[c * nv + cur.v[s]];
+          T.p[c][threadIdx.x + s * B] = lv[c * nv + cur.v[s]];
+        }
+    __syncthreads();
+    for (int e = t0 + threadIdx.x; e < t1; e += B) {
+      TetIn<false> t;
+      load_tet<false>(G, e, t);
+      int l[4];
+      tet_ids(t.loc, l);
+      double F[9], dF[9];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          double f = 0.0, df = 0.0;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            f += (T.x[a][l[k + 1]] - T.x[a][l[0]]) * t.Dm[k * 3 + b];
+            df += (T.p[a][l[k + 1]] - T.p[a][l[0]]) * t.Dm[k * 3 + b];
+          }
+          F[a * 3 + b] = f;
+          dF[a * 3 + b] = df;
+        }
+      double C[9];
+      C[0] = F[4] * F[8] - F[5] * F[7];
+      C[1] = F[5] * F[6] - F[3] * F[8];
+      C[2] = F[3] * F[7] - F[4] * F[6];
+      C[3] = F[2] * F[7] - F[1] * F[8];
+      C[4] = F[0] * F[8] - F[2] * F[6];
+      C[5] = F[1] * F[6] - F[0] * F[7];
+      C[6] = F[1] * F[5] - F[2] * F[4];
+      C[7] = F[2] * F[3] - F[0] * F[5];
+      C[8] = F[0] * F[4] - F[1] * F[3];
+      const double J = F[0] * C[0] + F[1] * C[1] + F[2] * C[2];
+      const double iJ = 1.0 / J;
+      double fdf = 0.0, cdf = 0.0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        fdf += F[k] * dF[k];
+        cdf += C[k] * dF[k];
+      }
+      c_mu += t.vol * (fdf - cdf * iJ);
+      c_lam += t.vol * log(J) * cdf * iJ;
+    }
+    __syncthreads();
+  }
+}
+
+// Barrier Hessian times v at x, added into gout (LDS sums: gq = v, gd = out).
+template <bool LDS>
+__device__ __forceinline__ void pairs_hvp(const View& V, const Shared& S, Tile& T, const double* x,
+                                          const double* v, double* out) {
+  const GelDev& G = *V.G;
+  const EnvDev& E = *V.E;
+  const int nv = G.n_v;
+  const double dh = E.dhat, kap = E.kappa;
+  for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
+    if (!(V.pd[i] < dh)) continue;
+    int2 pr = make_int2(0, 0);
+    uint64_t rec = 0;
+    if constexpr (LDS) rec = V.pslot[i];
+    else pr = V.pairs[i];
+    PairPts P;
+    get_pair<LDS>(V, S, T, pr, rec, x, nullptr, 0.0, P);
+    Feature f;
+    classify(P, f);
+    double r[3];
+    const double d = pair_distance(P, f, r);
+    if (!(d > 0.0) || d >= dh) continue;
+    double b, b1, b2;
+    barrier3(d, dh, b, b1, b2);
+    const double invd = 1.0 / d;
+    const double n[3] = {r[0] * invd, r[1] * invd, r[2] * invd};
+    double D[2][3];
+    #pragma unroll
+    for (int w = 0; w < 2; ++w)
+      #pragma unroll
+      for (int c = 0; c < 3; ++c)
+        D[w][c] = cw_of(f, 0, w) * P.z[0][c] + cw_of(f, 1, w) * P.z[1][c] + cw_of(f, 2, w) * P.z[2][c] + cw_of(f, 3, w) * P.z[3][c];
+    double Mi[2][2];
+    gram_inverse(D, f.k, Mi);
+    double q[3] = {0, 0, 0}, vv[2] = {0, 0};
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int g = P.gid[k];
+      if (g < 0) continue;
+      double pk[3];
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) pk[c] = LDS ? T.gq[c][g] : v[c * nv + g];
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) q[c] += f.c[k] * pk[c];
+      const double rp = dot3(r, pk);
+      #pragma unroll
+      for (int w = 0; w < 2; ++w) if (w < f.k) vv[w] += cw_of(f, k, w) * rp + f.c[k] * dot3(D[w], pk);
+    }
+    const double wv[2] = {Mi[0][0] * vv[0] + Mi[0][1] * vv[1], Mi[1][0] * vv[0] + Mi[1][1] * vv[1]};
+    const double nq = dot3(n, q);
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int g = P.gid[k];
+      if (g < 0) continue;
+      if (!LDS && G.fixed[g]) continue;
+      const double ci = f.c[k];
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double hv = ci * q[c] - ci * n[c] * nq;
+        #pragma unroll
+        for (int w = 0; w < 2; ++w)
+          if (w < f.k) hv -= (cw_of(f, k, w) * r[c] + ci * D[w][c]) * wv[w];
+        const double o = kap * (b2 * nq * ci * n[c] + b1 * hv * invd);
+        if constexpr (LDS) atomicAdd(&T.gd[c][g], o);
+        else atomicAdd(&out[c * nv + g], o);
+      }
+    }
+  }
+}
+
+// Thread partials of lambda^T (d g / d theta_pose) over the barrier pairs for
+// the six pose directions: translations e_a, and rotations e_a x (y - t) of
+// the indenter points about the indenter origin t. LDS path: gq = lambda.
+template <bool LDS>
+__device__ __forceinline__ void pairs_pose(const View& V, const Shared& S, const Tile& T, const double* x,
+                                           const double* lv, double acc[6]) {
+  const EnvDev& E = *V.E;
+  const int nv = V.G->n_v;
+  const double dh = E.dhat, kap = E.kappa;
+  for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
+    if (!(V.pd[i] < dh)) continue;
+    int2 pr = make_int2(0, 0);
+    uint64_t rec = 0;
+    if constexpr (LDS) rec = V.pslot[i];
+    else pr = V.pairs[i];
+    PairPts P;
+    get_pair<LDS>(V, S, T, pr, rec, x, nullptr, 0.0, P);
+    Feature f;
+    classify(P, f);
+    double r[3];
+    const double d = pair_distance(P, f, r);
+    if (!(d > 0.0) || d >= dh) continue;
+    double b, b1, b2;
+    barrier3(d, dh, b, b1, b2);
+    const double invd = 1.0 / d;
+    const double n[3] = {r[0] * invd, r[1] * invd, r[2] * invd};
+    double D[2][3];
+    #pragma unroll
+    for (int w = 0; w < 2; ++w)
+      #pragma unroll
+      for (int c = 0; c < 3; ++c)
+        D[w][c] = cw_of(f, 0, w) * P.z[0][c] + cw_of(f, 1, w) * P.z[1][c] + cw_of(f, 2, w) * P.z[2][c] + cw_of(f, 3, w) * P.z[3][c];
+    double Mi[2][2];
+    gram_inverse(D, f.k, Mi);
+    // gel side (lambda)
+    double q1[3] = {0, 0, 0}, v1[2] = {0, 0};
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int g = P.gid[k];
+      if (g < 0) continue;
+      double pk[3];
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) pk[c] = LDS ? T.gq[c][g] : lv[c * nv + g];
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) q1[c] += f.c[k] * pk[c];
+      const double rp = dot3(r, pk);
+      #pragma unroll
+      for (int w = 0; w < 2; ++w) if (w < f.k) v1[w] += cw_of(f, k, w) * rp + f.c[k] * dot3(D[w], pk);
+    }
+    const double n1 = dot3(n, q1);
+    const double m1[2] = {Mi[0][0] * v1[0] + Mi[0][1] * v1[1], Mi[1][0] * v1[0] + Mi[1][1] * v1[1]};
+    #pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      double q2[3] = {0, 0, 0}, v2[2] = {0, 0};
+      #pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (P.gid[k] >= 0) continue;
+        double dy[3] = {0.0, 0.0, 0.0};
+        if (a < 3) {
+          dy[a] = 1.0;
+        } else {
+          double y[3];
+          #pragma unroll
+          for (int c = 0; c < 3; ++c) y[c] = P.z[k][c] - S.t[c];
+          const int ax = a - 3;  // e_ax x y
+          dy[0] = (ax == 1 ? y[2] : 0.0) - (ax == 2 ? y[1] : 0.0);
+          dy[1] = (ax == 2 ? y[0] : 0.0) - (ax == 0 ? y[2] : 0.0);
+          dy[2] = (ax == 0 ? y[1] : 0.0) - (ax == 1 ? y[0] : 0.0);
+        }
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) q2[c] += f.c[k] * dy[c];
+        const double rp = dot3(r, dy);
+        #pragma unroll
+        for (int w = 0; w < 2; ++w) if (w < f.k) v2[w] += cw_of(f, k, w) * rp + f.c[k] * dot3(D[w], dy);
+      }
+      const double n2 = dot3(n, q2);
+      const double hd = (dot3(q1, q2) - (m1[0] * v2[0] + m1[1] * v2[1])) * invd - n1 * n2 * invd;
+      acc[a] += kap * (b2 * n1 * n2 + b1 * hd);
+    }
+  }
+}
+
+// Thread partial of lambda^T (d g / d mu_f) at mu_f = 0: the lagged friction
+// gradient with unit coefficient (records built with mu_f = 1). LDS path:
+// gx = x, gq = lambda.
+template <bool LDS>
+__device__ __forceinline__ double fric_mu(const View& V, const Shared& S, const Tile& T, const double* x,
+                                          const double* lv) {
+  const int nv = V.G->n_v;
+  const double eps = V.E->eps_v;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < V.nfric; i += blockDim.x) {
+    const FricPair F = V.fric[i];
+    double Dl[3];
+    fric_delta<LDS>(V, S, T, F, x, nullptr, 0.0, Dl);
+    const double nD = dot3(F.n, Dl);
+    double TD[3];
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) TD[c] = Dl[c] - nD * F.n[c];
+    const double s = sqrt(dot3(TD, TD));
+    double f, fos, corr;
+    mollifier3(s, eps, f, fos, corr);
+    #pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int v = F.gv[k];
+      if (v < 0 || V.G->fixed[v]) continue;
+      double lk[3];
+      if constexpr (LDS) {
+        const int q = fric_gslot(F, k);
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) lk[c] = T.gq[c][q];
+      } else {
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) lk[c] = lv[c * nv + v];
+      }
+      acc += F.mulam * F.a[k] * fos * dot3(TD, lk);
+    }
+  }
+  return acc;
+}
+
+// out = H v (elastic + barrier; the equilibrium is frictionless), fixed DOFs 0.
+__device__ __forceinline__ void hess_vec(Solver& s, const double* x, const double* v, double* out) {
+  View& V = s.V;
+  elem_hvp(V, x, v, out, *s.T);
+  if (V.slots_ok) {
+    stage_points(V, *s.S, *s.T, x, v, 0.0, 1);
+    Tile& T = *s.T;
+    for (int i = threadIdx.x; i < V.nslots; i += blockDim.x) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) T.gd[c][i] = 0.0;
+    }
+    __syncthreads();
+    pairs_hvp<true>(V, *s.S, T, x, v, out);
+    const GelDev& G = *V.G;
+    const int nv = G.n_v;
+    __syncthreads();
+    for (int i = threadIdx.x; i < V.nslots; i += blockDim.x) {
+      const int vtx = V.slot_v[i];
+      if (G.fixed[vtx]) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) out[c * nv + vtx] += T.gd[c][i];
+    }
+  } else {
+    __syncthreads();
+    pairs_hvp<false>(V, *s.S, *s.T, x, v, out);
+  }
+  __syncthreads();
+}
+
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_backward_kernel(StepParams P) {
+  __shared__ Shared S;
+  __shared__ Tile T;
+  const int e = blockIdx.x;
+  if (e >= P.n_env) return;
+  Solver s;
+  make_view(P, e, s.V);
+  View& V = s.V;
+  init_solver(s, P, S, T);
+  const GelDev& G = *V.G;
+  const IndDev& I = *V.I;
+  const EnvDev& E = *V.E;
+  const int nv = G.n_v;
+  const int n = 3 * nv;
+  EnvStats st;
+  st.status = 0; st.iters = 0; st.substeps = 0; st.restarts = 0; st.halvings = 0; st.reculls = 0;
+  st.n_candidates = 0; st.n_active = 0; st.n_friction = 0; st.max_solve_iters = 0;
+  st.outer_builds = 0; st.n_outer = 0; st.d_min = 0.0; st.residual = 0.0; st.energy = 0.0;
+  for (int k = 0; k < 10; ++k) st.phase_ms[k] = 0.0;
+  st.list_fill = 0.0;
+  const unsigned long long t_start = tick();
+  load_lists(s);
+  double ql[7], qc[7];
+  #pragma unroll
+  for (int i = 0; i < 7; ++i) { ql[i] = P.pose_lag[7 * e + i]; qc[i] = P.pose_prev[7 * e + i]; }
+  // friction records with unit coefficient at the lag (x_{s-1}, q_{s-1})
+  if (threadIdx.x == 0) set_pose(S, I, ql);
+  __syncthreads();
+  bool ok = ensure_lists(s, V.xprev, 0.0);
+  int nfric_lag = 0;
+  if (ok) {
+    lag_from_outer(s, V.xprev, 1, 1.0);
+    nfric_lag = min(S.count, s.fric_cap);
+    ok = S.overflow == 0;
+  }
+  __syncthreads();
+  V.nfric = nfric_lag;  // kept while the lists may be rebuilt, so the records keep their slots
+  if (threadIdx.x == 0) set_pose(S, I, qc);
+  __syncthreads();
+  if (ok) ok = ensure_lists(s, V.x, 0.0);
+  double grad[9];
+  for (int k = 0; k < 9; ++k) grad[k] = 0.0;
+  if (!ok) {
+    st.status = kOverflow;
+  } else {
+    // Jacobi preconditioner at x* (the equilibrium is frictionless)
+    V.nfric = 0;
+    int feas, nact;
+    eval_all(s, V.x, V.p, 0.0, V.g1, V.diag, feas, nact);
+    // rhs = W^T dL/du (free DOFs) in g1, lambda = 0 in g0
+    for (int j = threadIdx.x; j < n; j += blockDim.x) { V.g0[j] = 0.0; V.g1[j] = 0.0; }
+    __syncthreads();
+    const T2R_G double* du = P.dL_du + 3 * E.moff;
+    for (int m = threadIdx.x; m < G.n_m; m += blockDim.x) {
+      #pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int v = G.marker_tri[k * G.n_m + m];
+        const double w = G.marker_w[k * G.n_m + m];
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) atomicAdd(&V.g1[c * nv + v], w * du[3 * m + c]);
+      }
+    }
+    __syncthreads();
+    double a2[3] = {0.0, 0.0, 0.0};  // r.z, r.r, -
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const int v = j >= 2 * nv ? j - 2 * nv : (j >= nv ? j - nv : j);
+      double r = V.g1[j];
+      if (G.fixed[v]) { r = 0.0; V.g1[j] = 0.0; }
+      const double Pj = 1.0 / fmax(V.diag[j], s.floor_d);
+      V.diag[j] = Pj;
+      V.p[j] = Pj * r;
+      a2[0] += r * Pj * r;
+      a2[1] += r * r;
+    }
+    double w2[2] = {a2[0], a2[1]};
+    block_reduce<2, 0>(w2, S);
+    double rz = w2[0];
+    const double r0 = sqrt(w2[1]);
+    double rn = r0;
+    int it = 0;
+    for (; it < P.max_iters && rn > P.cg_tol * r0 && r0 > 0.0; ++it) {
+      hess_vec(s, V.x, V.p, P.adj + E.voff);
+      const double* Ad = P.adj + E.voff;
+      double c1[1] = {0.0};
+      for (int j = threadIdx.x; j < n; j += blockDim.x) c1[0] += V.p[j] * Ad[j];
+      block_reduce<1, 0>(c1, S);
+      if (!(c1[0] > 0.0)) { st.status |= kNonFinite; break; }
+      const double alpha = rz / c1[0];
+      double c2[2] = {0.0, 0.0};
+      for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        V.g0[j] = fma(alpha, V.p[j], V.g0[j]);
+        const double r = V.g1[j] - alpha * Ad[j];
+        V.g1[j] = r;
+        c2[0] += r * V.diag[j] * r;
+        c2[1] += r * r;
+      }
+      block_reduce<2, 0>(c2, S);
+      const double beta = c2[0] / rz;
+      rz = c2[0];
+      rn = sqrt(c2[1]);
+      for (int j = threadIdx.x; j < n; j += blockDim.x) V.p[j] = fma(beta, V.p[j], V.diag[j] * V.g1[j]);
+      __syncthreads();
+    }
+    st.iters = it;
+    st.residual = r0 > 0.0 ? rn / r0 : 0.0;
+    if (!(rn <= P.cg_tol * r0) && r0 > 0.0) st.status |= kMaxIter;
+    else if (!(st.status & kNonFinite)) st.status |= kConverged;
+    // lambda^T dg/dtheta
+    double cm = 0.0, cl = 0.0;
+    elem_theta(V, V.x, V.g0, T, cm, cl);
+    double pose_acc[6] = {0, 0, 0, 0, 0, 0};
+    double cf = 0.0;
+    V.nfric = nfric_lag;
+    if (V.slots_ok) {
+      stage_points(V, S, T, V.x, V.g0, 0.0, 1);
+      pairs_pose<true>(V, S, T, V.x, V.g0, pose_acc);
+      cf = fric_mu<true>(V, S, T, V.x, V.g0);
+    } else {
+      pairs_pose<false>(V, S, T, V.x, V.g0, pose_acc);
+      cf = fric_mu<false>(V, S, T, V.x, V.g0);
+    }
+    double red[9] = {cm, cl, cf, pose_acc[0], pose_acc[1], pose_acc[2], pose_acc[3], pose_acc[4], pose_acc[5]};
+    block_reduce<3, 0>(red, S);
+    block_reduce<6, 0>(red + 3, S);
+    // Lame partials: mu = E / (2 (1 + nu)), lam = E nu / ((1 + nu)(1 - 2 nu))
+    const double mu = E.mu, lam = E.lam;
+    const double Ey = mu * (3.0 * lam + 2.0 * mu) / (lam + mu);
+    const double nu = lam / (2.0 * (lam + mu));
+    const double dmu_dE = 1.0 / (2.0 * (1.0 + nu));
+    const double dlam_dE = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    const double dmu_dnu = -Ey / (2.0 * (1.0 + nu) * (1.0 + nu));
+    const double dlam_dnu = Ey * (1.0 + 2.0 * nu * nu) / ((1.0 + nu) * (1.0 + nu) * (1.0 - 2.0 * nu) * (1.0 - 2.0 * nu));
+    grad[0] = -(red[0] * dmu_dE + red[1] * dlam_dE);
+    grad[1] = -(red[0] * dmu_dnu + red[1] * dlam_dnu);
+    grad[2] = -red[2];
+    for (int k = 0; k < 6; ++k) grad[3 + k] = -red[3 + k];
+  }
+  if (threadIdx.x < 9) P.grad_out[9 * e + threadIdx.x] = grad[threadIdx.x];
+  if (threadIdx.x == 0) {
+    st.n_friction = nfric_lag;
+    st.n_candidates = V.npairs;
+    st.n_outer = V.nouter;
+    st.phase_ms[8] = (double)(wall_clock64() - t_start) / P.clock_khz;
+    P.stats[e] = st;
+  }
+}
+
+extern "C" hipError_t t2r_launch_backward(const StepParams* p, int block, hipStream_t stream) {
+  if (block == 512)
+    hipLaunchKernelGGL(t2r_backward_kernel<512>, dim3(p->n_env), dim3(512), 0, stream, *p);
+  else if (block == 256)
+    hipLaunchKernelGGL(t2r_backward_kernel<256>, dim3(p->n_env), dim3(256), 0, stream, *p);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 // Diagnostic evaluation of one env (state arrays are scratch copies).
 __global__ void __launch_bounds__(256) t2r_eval_kernel(EvalParams Q) {
   __shared__ Shared S;
@@ -1963,7 +2525,7 @@ __global__ void __launch_bounds__(256) t2r_eval_kernel(EvalParams Q) {
     __syncthreads();
     ok = ensure_lists(s, V.xprev, 0.0);
     if (ok) {
-      lag_from_outer(s, V.xprev, 1);
+      lag_from_outer(s, V.xprev, 1, E.mu_f);
       V.nfric = min(S.count, s.fric_cap);
       ok = S.overflow == 0;
     }

@@ -75,6 +75,14 @@ class Sim:
         self.ctx.step_sequence(n_steps, p, m, markers, self.x if want_x else None, status)
         return markers, status
 
+    def backward(self, dL_du):
+        """dL/dtheta (n_env, 9) of a loss on the current markers: theta = (E, nu, mu_f,
+        dt (3), dw (3)) per env (see t2r_backward). dL_du: (sum n_m, 3). Not synchronised."""
+        g = torch.as_tensor(dL_du, dtype=torch.float64, device=self.device).contiguous()
+        out = torch.zeros((self.n_env, 9), dtype=torch.float64, device=self.device)
+        self.ctx.backward(g, out)
+        return out
+
     def graph_step(self, poses):
         """One load step of every env, replayed from a captured HIP graph.
 

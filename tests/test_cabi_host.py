@@ -90,7 +90,12 @@ def test_invalid_inputs_are_rejected_on_the_host():
     assert ctx.state_size() == 3 * g.n_verts + 7
     with pytest.raises(t2r.T2RError) as e:
         ctx.backward(None, None)
-    assert e.value.code == t2r.T2R_E_UNSUPPORTED
+    assert e.value.code == t2r.T2R_E_ARG            # no outputs
+    fr = ctx.add_envs([gid], [iid], [(0.3, 0.45, 0.5, 1e-3, 0.05, 1e3)], pose)
+    assert fr == 1
+    with pytest.raises(t2r.T2RError) as e:
+        ctx.backward(None, None)
+    assert e.value.code == t2r.T2R_E_UNSUPPORTED     # friction: the adjoint is frictionless only
 
 
 def test_invalid_options_are_rejected():

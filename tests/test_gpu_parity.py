@@ -307,6 +307,83 @@ def test_autotune_restores_state_and_capacity_regrow_keeps_solving():
     assert np.abs(sim.split_x()[0].cpu().numpy() - gold["x"][-1]).max() <= 1e-6
 
 
+def _adjoint_scene():
+    from scenes.configs import micro_press
+    return micro_press(mesh="micro3", indenter="sphere_small", depth=0.15, n_steps=3, xy=(0.12, -0.07),
+                       q=(0.9990482, 0.0, 0.0436194, 0.0))
+
+
+def _gpu_forward(t2r, w, env, tol=1e-11):
+    """Per-step launches; returns the Sim and the positions after every step."""
+    sim = _build(t2r, w, tol=tol, substep_tol=tol, max_iters=400000)
+    xs = []
+    for s in range(1, env.poses.shape[0]):
+        _, st = sim.step(env.poses[s][None], want_x=True)
+        torch.cuda.synchronize()
+        assert int(st.cpu()[0]) & 1
+        xs.append(sim.x.cpu().numpy().copy())
+    return sim, xs
+
+
+@pytest.mark.parametrize("scene", ["micro", "c1"])
+def test_adjoint_matches_oracle_adjoint_at_the_same_state(scene):
+    """t2r_backward against the oracle's direct-solve adjoint at the GPU's own
+    equilibrium (E, nu, mu_f at 0, translation and rotation offsets)."""
+    t2r = _gpu()
+    from oracle.adjoint import adjoint_gradient
+    from scenes.configs import sphere_press_484v
+    w = _adjoint_scene() if scene == "micro" else sphere_press_484v(n_steps=4)
+    env = w.envs[0]
+    sim, xs = _gpu_forward(t2r, w, env)
+    rng = np.random.default_rng(5)
+    m = sim.markers.cpu().numpy()
+    dL_du = m - 0.02 * rng.standard_normal(m.shape)
+    g = sim.backward(dL_du)
+    torch.cuda.synchronize()
+    st = sim.stats()[0]
+    assert st["status"] & 1 and st["residual"] <= 1e-10, st
+    gel, ind, prob = _oracle_problem(w, env)
+    prob.set_pose(env.poses[-1])
+    ref, _ = adjoint_gradient(prob, xs[-1], dL_du, x_prev=xs[-2], pose_prev=env.poses[-2])
+    got = g.cpu().numpy()[0]
+    scale = np.abs(ref).max()
+    assert np.all(np.abs(got - ref) <= 1e-6 * np.maximum(np.abs(ref), 1e-3 * scale)), (got, ref)
+
+
+def test_adjoint_matches_central_differences_of_the_gpu_forward():
+    """GPU gradients of L = 1/2 |u - u_t|^2 against central differences of the
+    GPU forward itself (E, nu, pose offsets; h = 1e-6 relative / absolute)."""
+    t2r = _gpu()
+    import dataclasses
+    from oracle.adjoint import offset_pose
+    w = _adjoint_scene()
+    env = w.envs[0]
+    rng = np.random.default_rng(11)
+    u_t = 0.02 * rng.standard_normal((len(w.meshes[env.mesh].markers), 3))
+    sim, _ = _gpu_forward(t2r, w, env, tol=1e-12)
+    u = sim.markers.cpu().numpy()
+    g = sim.backward(u - u_t).cpu().numpy()[0]
+
+    def loss(dE=0.0, dnu=0.0, dt=np.zeros(3), dw=np.zeros(3)):
+        e = dataclasses.replace(env, E=env.E + dE, nu=env.nu + dnu,
+                                poses=np.stack([offset_pose(p, dt, dw) for p in env.poses]))
+        wp = dataclasses.replace(w, envs=[e])
+        s, _ = _gpu_forward(t2r, wp, e, tol=1e-12)
+        return 0.5 * float(np.sum((s.markers.cpu().numpy() - u_t) ** 2))
+
+    fd = {}
+    hE, hnu = 1e-6 * env.E, 1e-6 * env.nu
+    fd[0] = (loss(dE=hE) - loss(dE=-hE)) / (2 * hE)
+    fd[1] = (loss(dnu=hnu) - loss(dnu=-hnu)) / (2 * hnu)
+    for a in range(6):
+        v = np.zeros(6)
+        v[a] = 1e-6
+        fd[3 + a] = (loss(dt=v[:3], dw=v[3:]) - loss(dt=-v[:3], dw=-v[3:])) / 2e-6
+    scale = max(abs(x) for x in fd.values())
+    for i, f in fd.items():
+        assert abs(g[i] - f) <= 1e-4 * max(abs(f), 1e-3 * scale), (i, g[i], f)
+
+
 def _certify_equilibrium(w, env, pose, x, bound=1e-6):
     """The oracle's Newton started from x must not move: x is a minimiser of Pi."""
     from oracle.newton import newton_solve
