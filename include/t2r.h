@@ -189,6 +189,11 @@ t2r_status t2r_add_envs(t2r_ctx* ctx, int32_t n, const int32_t* gel_ids,
                         const int32_t* ind_ids, const t2r_material* mats,
                         const double* pose0, int32_t* first_env);
 
+/* Replaces the material of the listed envs (host env ids, host materials,
+ * validated as in t2r_add_envs). Takes effect from the next launch; changed
+ * envs rebuild their contact lists. Synchronises the context's stream. */
+t2r_status t2r_set_materials(t2r_ctx* ctx, int32_t n, const int32_t* env_ids, const t2r_material* mats);
+
 /* Number of environments and total vertices over all envs. */
 t2r_status t2r_env_count(const t2r_ctx* ctx, int32_t* n_env, int64_t* total_verts);
 

@@ -727,6 +727,43 @@ t2r_status t2r_add_indenter(t2r_ctx* c, int32_t n_v, const double* Y, int32_t n_
   return T2R_OK;
 }
 
+static bool valid_material(const t2r_material& m) {
+  return m.E > 0 && m.nu > 0 && m.nu < 0.5 && m.mu_f >= 0 && m.eps_v > 0 && m.dhat > 0 && m.kappa > 0 &&
+         isfinite(m.E) && isfinite(m.mu_f) && isfinite(m.eps_v) && isfinite(m.dhat) && isfinite(m.kappa);
+}
+
+static void material_to_dev(const t2r_material& m, EnvDev& d) {
+  d.mu = m.E / (2.0 * (1.0 + m.nu));
+  d.lam = m.E * m.nu / ((1.0 + m.nu) * (1.0 - 2.0 * m.nu));
+  d.mu_f = m.mu_f;
+  d.eps_v = m.eps_v;
+  d.dhat = m.dhat;
+  d.kappa = m.kappa;
+}
+
+t2r_status t2r_set_materials(t2r_ctx* c, int32_t n, const int32_t* env_ids, const t2r_material* mats) {
+  if (!c) return T2R_E_ARG;
+  if (n < 0 || (n > 0 && (!env_ids || !mats))) return fail(c, T2R_E_ARG, "bad arguments");
+  for (int i = 0; i < n; ++i) {
+    if (env_ids[i] < 0 || env_ids[i] >= (int)c->envs.size()) return fail(c, T2R_E_ARG, "bad env id %d", env_ids[i]);
+    if (!valid_material(mats[i])) return fail(c, T2R_E_ARG, "env %d: invalid material", env_ids[i]);
+  }
+  if (c->committed) HIP_TRY(c, hipStreamSynchronize(c->stream));  // earlier work may read the descriptors
+  for (int i = 0; i < n; ++i) {
+    const int e = env_ids[i];
+    c->envs[e].mat = mats[i];
+    if (c->committed) {
+      material_to_dev(mats[i], c->h_envs[e]);
+      HIP_TRY(c, hipMemcpyAsync(c->d_envs + e, &c->h_envs[e], sizeof(EnvDev), hipMemcpyHostToDevice, c->stream));
+      // list radii follow dhat: rebuild this env's lists on its next step
+      HIP_TRY(c, hipMemsetAsync(c->d_lists + e, 0, sizeof(ListState), c->stream));
+    }
+  }
+  if (c->committed) HIP_TRY(c, hipStreamSynchronize(c->stream));  // host copies are pageable
+  c->err.clear();
+  return T2R_OK;
+}
+
 t2r_status t2r_add_envs(t2r_ctx* c, int32_t n, const int32_t* gel_ids, const int32_t* ind_ids,
                         const t2r_material* mats, const double* pose0, int32_t* first_env) {
   if (!c) return T2R_E_ARG;
@@ -740,10 +777,7 @@ t2r_status t2r_add_envs(t2r_ctx* c, int32_t n, const int32_t* gel_ids, const int
     if (e.gel < 0 || e.gel >= (int)c->gels.size()) return fail(c, T2R_E_ARG, "env %d: bad gel id %d", i, e.gel);
     if (e.ind < 0 || e.ind >= (int)c->inds.size()) return fail(c, T2R_E_ARG, "env %d: bad indenter id %d", i, e.ind);
     const t2r_material& m = mats[i];
-    if (!(m.E > 0) || !(m.nu > 0 && m.nu < 0.5) || !(m.mu_f >= 0) || !(m.eps_v > 0) || !(m.dhat > 0) ||
-        !(m.kappa > 0) || !isfinite(m.E) || !isfinite(m.mu_f) || !isfinite(m.eps_v) || !isfinite(m.dhat) ||
-        !isfinite(m.kappa))
-      return fail(c, T2R_E_ARG, "env %d: invalid material", i);
+    if (!valid_material(m)) return fail(c, T2R_E_ARG, "env %d: invalid material", i);
     e.mat = m;
     double qn = 0.0;
     for (int k = 0; k < 7; ++k) {
@@ -1222,12 +1256,7 @@ t2r_status commit(t2r_ctx* c) {
     EnvDev d{};
     d.gel = e.gel;
     d.ind = e.ind;
-    d.mu = e.mat.E / (2.0 * (1.0 + e.mat.nu));
-    d.lam = e.mat.E * e.mat.nu / ((1.0 + e.mat.nu) * (1.0 - 2.0 * e.mat.nu));
-    d.mu_f = e.mat.mu_f;
-    d.eps_v = e.mat.eps_v;
-    d.dhat = e.mat.dhat;
-    d.kappa = e.mat.kappa;
+    material_to_dev(e.mat, d);
     const int cap = pair_cap_of(c, g);
     d.pair_cap = cap;
     d.fric_cap = std::max(1024, cap / 2);

@@ -24,6 +24,7 @@ class Sim:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = t2r.Context(opts, self.stream.cuda_stream)
         self._graph = None
+        self.mats = []
         self.gel_ids = {}
         self.ind_ids = {}
         self.env_gel = []
@@ -44,6 +45,7 @@ class Sim:
         sim.ctx.add_envs([sim.gel_ids[e.mesh] for e in sel], [sim.ind_ids[e.indenter] for e in sel],
                          [e.material() for e in sel], np.stack([e.poses[0] for e in sel]))
         sim.env_gel = [sim.gel_ids[e.mesh] for e in sel]
+        sim.mats = [e.material() for e in sel]
         for e in sel:
             info = sim.ctx.gel_info(sim.gel_ids[e.mesh])
             sim.n_m.append(info["n_m"])

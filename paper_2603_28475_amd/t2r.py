@@ -64,6 +64,7 @@ SIGNATURES = [
     ("t2r_add_indenter", C.c_int32, [_P, C.c_int32, _PD, C.c_int32, _PI, _PI]),
     ("t2r_add_envs", C.c_int32, [_P, C.c_int32, _PI, _PI, C.POINTER(Material), _PD, _PI]),
     ("t2r_env_count", C.c_int32, [_P, _PI, C.POINTER(C.c_int64)]),
+    ("t2r_set_materials", C.c_int32, [_P, C.c_int32, _PI, C.POINTER(Material)]),
     ("t2r_step", C.c_int32, [_P, _P, _P, _P, _P, _P]),
     ("t2r_step_sequence", C.c_int32, [_P, C.c_int32, _P, _P, _P, _P, _P]),
     ("t2r_eval", C.c_int32, [_P, C.c_int32, _P, _P, _P, _PD, _PD, _P, _P, _P]),
@@ -185,6 +186,12 @@ class Context:
         self.check(lib.t2r_add_envs(self.handle, n, _dptr(g, C.c_int32), _dptr(i, C.c_int32), m,
                                     _dptr(p, C.c_double), C.byref(first)))
         return first.value
+
+    def set_materials(self, env_ids, mats):
+        n = len(env_ids)
+        ids = np.ascontiguousarray(env_ids, dtype=np.int32)
+        m = (Material * n)(*[Material(*mt) for mt in mats])
+        self.check(lib.t2r_set_materials(self.handle, n, _dptr(ids, C.c_int32), m))
 
     def env_count(self):
         n = C.c_int32()

@@ -384,6 +384,37 @@ def test_adjoint_matches_central_differences_of_the_gpu_forward():
         assert abs(g[i] - f) <= 1e-4 * max(abs(f), 1e-3 * scale), (i, g[i], f)
 
 
+def test_marker_field_autograd_matches_differences_at_an_offset_pose():
+    """MarkerField (torch.autograd) at a nonzero pose offset: its gradient equals
+    central differences of its own forward (E, a translation and a rotation
+    component; the rotation goes through the SO(3) left Jacobian)."""
+    t2r = _gpu()
+    from paper_2603_28475_amd.autograd import MarkerField
+    w = _adjoint_scene()
+    env = w.envs[0]
+    sim = _build(t2r, w, tol=1e-12, substep_tol=1e-12, max_iters=400000)
+    poses = env.poses[1:][:, None, :]
+    rng = np.random.default_rng(2)
+    u_t = torch.as_tensor(0.02 * rng.standard_normal((len(w.meshes[env.mesh].markers), 3)), device="cuda:0")
+    theta0 = np.array([[env.E, env.nu, 0.0, 0.01, -0.02, 0.005, 0.02, -0.03, 0.1]])
+
+    def loss(th):
+        u = MarkerField.apply(torch.tensor(th, dtype=torch.float64), sim, poses)
+        return 0.5 * ((u - u_t) ** 2).sum()
+
+    th = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+    L = 0.5 * ((MarkerField.apply(th, sim, poses) - u_t) ** 2).sum()
+    L.backward()
+    g = th.grad.numpy()[0]
+    for i, h in ((0, 1e-6 * env.E), (4, 1e-6), (6, 1e-6), (8, 1e-6)):
+        tp, tm = theta0.copy(), theta0.copy()
+        tp[0, i] += h
+        tm[0, i] -= h
+        with torch.no_grad():
+            fd = (float(loss(tp)) - float(loss(tm))) / (2 * h)
+        assert abs(g[i] - fd) <= 1e-4 * max(abs(fd), 1e-3 * np.abs(g).max()), (i, g[i], fd)
+
+
 def _certify_equilibrium(w, env, pose, x, bound=1e-6):
     """The oracle's Newton started from x must not move: x is a minimiser of Pi."""
     from oracle.newton import newton_solve
