@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle budget (0: skip)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time the adjoint instead: 64 envs of the 5k gel, frictionless, 20 load steps "
+                         "forward, then one t2r_backward launch (prints its own JSON line)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the block-shape / pair-capacity autotuner (setup, not timed)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -99,6 +102,53 @@ def cpu_baseline(args, workload, iters_per_env_step):
                       f"{iters_per_env_step:.0f} iterations per env-step (GPU run mean)"}
 
 
+def adjoint_bench(args):
+    """Adjoint grads/s: gradients of a marker loss with respect to (E, nu, mu_f,
+    6-DoF pose offset) for 64 envs of the 5k gel after a 20-step press + shear
+    trajectory. The adjoint covers frictionless equilibria, so mu_f = 0 here
+    (the gradient with respect to mu_f is the derivative at 0)."""
+    import dataclasses
+    import numpy as np
+    import torch
+    from paper_2603_28475_amd import t2r
+    from paper_2603_28475_amd.sim import Sim
+    from scenes.configs import adjoint_peg_5k
+    n = args.envs if args.envs > 0 else 64
+    w = adjoint_peg_5k(n_envs=n)
+    w = dataclasses.replace(w, envs=[dataclasses.replace(e, mu_f=0.0) for e in w.envs])
+    sim = Sim.from_workload(w, t2r.default_opts(tol=args.tol, precision=0, max_iters=50000))
+    poses = np.stack([e.poses for e in w.envs])          # (n, S+1, 7)
+    seq = np.ascontiguousarray(poses[:, 1:].transpose(1, 0, 2))
+    stream = torch.cuda.current_stream()
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record(stream)
+    markers, status = sim.step_sequence(seq)
+    f1.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = f0.elapsed_time(f1)
+    rng = np.random.default_rng(5)
+    u = markers[-1]
+    dL_du = (u - torch.as_tensor(0.01 * rng.standard_normal(tuple(u.shape)), device=u.device)).contiguous()
+    b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b0.record(stream)
+    g = sim.backward(dL_du)
+    b1.record(stream)
+    torch.cuda.synchronize()
+    bwd_ms = b0.elapsed_time(b1)
+    st = sim.stats()
+    cg = np.array([x["iters"] for x in st])
+    ok = all(x["status"] & t2r.ENV_CONVERGED for x in st) and bool(torch.isfinite(g).all())
+    line = {"metric": "adjoint grads/s", "value": n / (bwd_ms * 1e-3), "unit": "grads/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": w.name + "_frictionless", "envs": n, "load_steps": int(seq.shape[0]),
+                       "grad": "dL/d(E, nu, mu_f, dt, dw) of the final markers", "cg_rel_tol": 1e-10,
+                       "cg_iters_mean": float(cg.mean()), "cg_iters_max": int(cg.max()),
+                       "all_converged": ok},
+            "backward_ms": bwd_ms, "forward_ms": fwd_ms,
+            "grads_per_s_with_forward": n / ((bwd_ms + fwd_ms) * 1e-3)}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -118,6 +168,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.adjoint:
+        return adjoint_bench(args)
     if args.copy_calibration:
         # a plain copy kernel of known size: 1 GiB read + 1 GiB written per launch
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
