@@ -98,6 +98,7 @@ struct t2r_ctx {
   int* d_imap = nullptr;
   int* d_islot_v = nullptr;
   int* d_order = nullptr;
+  double* d_motion = nullptr;
   double* d_pose_lag = nullptr;
   double* d_adj = nullptr;
   bool stepped = false;
@@ -870,7 +871,7 @@ t2r_status t2r_step_sequence(t2r_ctx* c, int32_t n_steps, const double* d_poses,
   P.status_out = d_status;
   if (P.n_env > 1) {
     // longest previous launch first (see t2r_order_kernel)
-    HIP_TRY(c, t2r_launch_order(&P, c->d_order, c->stream));
+    HIP_TRY(c, t2r_launch_order(&P, c->d_order, c->d_motion, c->stream));
     P.order = c->d_order;
   }
   HIP_TRY(c, t2r_launch_step(&P, block_of(c), c->stream));
@@ -1318,12 +1319,13 @@ t2r_status commit(t2r_ctx* c) {
   c->d_islot_v = alloc_n<int>(c, c->envs.size() * (size_t)kIndSlots);
   c->d_stats = alloc_n<EnvStats>(c, c->envs.size());
   c->d_order = alloc_n<int>(c, c->envs.size());
+  c->d_motion = alloc_n<double>(c, c->envs.size());
   c->d_pose_lag = alloc_n<double>(c, 7 * c->envs.size());
   c->d_adj = alloc_n<double>(c, nd);
   if (!c->d_x || !c->d_xprev || !c->d_g0 || !c->d_g1 || !c->d_diag || !c->d_p || !c->d_pose_prev ||
       !c->d_pairs || !c->d_pair_d || !c->d_outer || !c->d_lists || !c->d_xsnap || !c->d_fric ||
       !c->d_vmap || !c->d_oslot || !c->d_pslot || !c->d_slot_v || !c->d_imap || !c->d_islot_v ||
-      !c->d_stats || !c->d_order || !c->d_pose_lag || !c->d_adj) {
+      !c->d_stats || !c->d_order || !c->d_motion || !c->d_pose_lag || !c->d_adj) {
     dev_free_all(c);
     return fail(c, T2R_E_NOMEM, "state allocation failed (%lld DOFs)", voff);
   }
@@ -1337,6 +1339,7 @@ t2r_status commit(t2r_ctx* c) {
   }
   HIP_TRY(c, hipMemsetAsync(c->d_p, 0, nd * sizeof(double), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_stats, 0, c->envs.size() * sizeof(EnvStats), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_motion, 0, c->envs.size() * sizeof(double), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_lists, 0, c->envs.size() * sizeof(ListState), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_vmap, 0, (size_t)vtot * sizeof(int), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_imap, 0, (size_t)std::max(imtot, 1LL) * sizeof(int), c->stream));

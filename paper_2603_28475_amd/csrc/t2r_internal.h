@@ -25,8 +25,9 @@ constexpr int kTileTets = 1024;
 constexpr int kTileVerts = 512;   // local vertex ids are 16-bit
 constexpr int kMaxBlock = 1024;
 
-// Workgroups take envs in order of decreasing duration of their previous load
-// step, so the longest solves start first and the launch ends with short ones.
+// Workgroups take envs in order of decreasing expected cost (indenter motion of
+// the launch, scaled by the env's previous cost per unit motion), so the
+// longest solves start first and the launch ends with short ones.
 // Up to kOrderMax envs are sorted (one workgroup); beyond that envs go in id order.
 constexpr int kOrderMax = 8192;
 
@@ -200,7 +201,7 @@ struct EvalParams {
 
 extern "C" {
 hipError_t t2r_launch_step(const t2r::StepParams* p, int block, hipStream_t stream);
-hipError_t t2r_launch_order(const t2r::StepParams* p, int* order, hipStream_t stream);
+hipError_t t2r_launch_order(const t2r::StepParams* p, int* order, double* motion, hipStream_t stream);
 hipError_t t2r_launch_backward(const t2r::StepParams* p, int block, hipStream_t stream);
 hipError_t t2r_launch_eval(const t2r::EvalParams* p, int block, hipStream_t stream);
 hipError_t t2r_launch_pack_state(const t2r::StepParams* p, const double* in, double* out,

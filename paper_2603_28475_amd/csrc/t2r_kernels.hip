@@ -2607,10 +2607,12 @@ extern "C" hipError_t t2r_launch_step(const StepParams* p, int block, hipStream_
   return hipGetLastError();
 }
 
-// Longest-first env order from the durations of the previous load step (stats
-// zeroed before the first step: id order). Bitonic sort of (duration, id) keys
-// in LDS, one workgroup.
-__global__ void __launch_bounds__(1024) t2r_order_kernel(StepParams P, int* order) {
+// Longest-first env order. The expected cost of an env is the indenter motion
+// of this launch (the summed bound |dt| + 2 sin(theta/2) r_max over its load
+// steps) scaled by the square root of the env's previous cost per unit of
+// motion (previous launch duration / its motion; 1 before the first launch).
+// Bitonic sort of (cost, id) keys in LDS, one workgroup.
+__global__ void __launch_bounds__(1024) t2r_order_kernel(StepParams P, int* order, double* motion) {
   __shared__ unsigned long long key[kOrderMax];
   const int n = P.n_env;
   if (n > kOrderMax) {
@@ -2622,8 +2624,24 @@ __global__ void __launch_bounds__(1024) t2r_order_kernel(StepParams P, int* orde
   for (int i = threadIdx.x; i < np; i += blockDim.x) {
     unsigned long long k = ~0ull;
     if (i < n) {
-      const double ms = P.stats[i].phase_ms[8];
-      const float c = (ms > 0.0 && isfinite(ms)) ? (float)ms : 0.0f;
+      const double r_max = P.inds[P.envs[i].ind].r_max;
+      double m = 0.0, q0[7], q1[7];
+      for (int c = 0; c < 7; ++c) q0[c] = P.pose_prev[7 * i + c];
+      for (int s = 0; s < P.n_steps; ++s) {
+        bool fin = true;
+        for (int c = 0; c < 7; ++c) {
+          q1[c] = P.pose_in[((long long)s * n + i) * 7 + c];
+          fin &= isfinite(q1[c]);
+        }
+        if (!fin) continue;
+        m += ind_motion(q0, q1, r_max);
+        for (int c = 0; c < 7; ++c) q0[c] = q1[c];
+      }
+      const double ms = P.stats[i].phase_ms[8], pm = motion[i];
+      const double rate = (ms > 0.0 && pm > 0.0 && isfinite(ms)) ? ms / pm : 1.0;
+      motion[i] = m;
+      const double cost = m * sqrt(rate);
+      const float c = (cost > 0.0 && isfinite(cost)) ? (float)cost : 0.0f;
       // descending duration = ascending inverted bits (c >= 0), then ascending id
       k = ((unsigned long long)(~__float_as_uint(c)) << 32) | (unsigned)i;
     }
@@ -2646,8 +2664,8 @@ __global__ void __launch_bounds__(1024) t2r_order_kernel(StepParams P, int* orde
   for (int i = threadIdx.x; i < n; i += blockDim.x) order[i] = (int)(key[i] & 0xffffffffu);
 }
 
-extern "C" hipError_t t2r_launch_order(const StepParams* p, int* order, hipStream_t stream) {
-  hipLaunchKernelGGL(t2r_order_kernel, dim3(1), dim3(1024), 0, stream, *p, order);
+extern "C" hipError_t t2r_launch_order(const StepParams* p, int* order, double* motion, hipStream_t stream) {
+  hipLaunchKernelGGL(t2r_order_kernel, dim3(1), dim3(1024), 0, stream, *p, order, motion);
   return hipGetLastError();
 }
 
