@@ -89,7 +89,10 @@ typedef struct { double E, nu, mu_f, eps_v, dhat, kappa; } t2r_material;
  *                 list holds 4x and the friction list 1/2 of it
  *   armijo        1: require sufficient decrease of Pi in the line search
  *   block_size    threads per env workgroup: 256 (two envs per CU) or 512 (one env
- *                 per CU, for few large envs); 0 = 256 */
+ *                 per CU, for few large envs); 0 = 256
+ *   warm_start    1: when a load step continues the previous step's indenter
+ *                 motion, start from x_{s-1} + f (x_{s-1} - x_{s-2}) (f = ratio of
+ *                 the motions) if that point is feasible; 0: start from x_{s-1} */
 typedef struct {
   double tol;
   double substep_tol;
@@ -99,6 +102,7 @@ typedef struct {
   int32_t pair_capacity;
   int32_t armijo;
   int32_t block_size;
+  int32_t warm_start;
 } t2r_solver_opts;
 
 /* Per-environment counters of the last launch (t2r_step or t2r_step_sequence;
@@ -130,7 +134,7 @@ typedef struct {
 } t2r_env_stats;
 
 /* Fills *o with the defaults: tol 1e-6, substep_tol 1e-4, max_iters 20000,
- * max_substeps 1000, precision 0, pair_capacity 0, armijo 1, block_size 0. */
+ * max_substeps 1000, precision 0, pair_capacity 0, armijo 1, block_size 0, warm_start 1. */
 void t2r_default_opts(t2r_solver_opts* o);
 
 /* Creates a context bound to `hip_stream` (a hipStream_t, or NULL for the null

@@ -270,6 +270,7 @@ void t2r_default_opts(t2r_solver_opts* o) {
   o->pair_capacity = 0;
   o->armijo = 1;
   o->block_size = 0;
+  o->warm_start = 1;
 }
 
 static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
@@ -280,6 +281,7 @@ static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
   if (o->pair_capacity < 0) return fail(c, T2R_E_ARG, "pair_capacity must be >= 0");
   if (o->block_size != 0 && o->block_size != 256 && o->block_size != 512)
     return fail(c, T2R_E_ARG, "block_size must be 0 (256), 256 or 512");
+  if (o->warm_start != 0 && o->warm_start != 1) return fail(c, T2R_E_ARG, "warm_start must be 0 or 1");
   return T2R_OK;
 }
 
@@ -850,6 +852,7 @@ static StepParams step_params(t2r_ctx* c) {
   P.max_substeps = c->opts.max_substeps;
   P.precision = c->opts.precision;
   P.armijo = c->opts.armijo;
+  P.warm_start = c->opts.warm_start;
   return P;
 }
 
@@ -1061,6 +1064,8 @@ t2r_status t2r_reset_envs(t2r_ctx* c, const int32_t* ids, int32_t n) {
                               hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->d_pose_prev + 7 * (size_t)ids[i], e.pose0, 7 * sizeof(double),
                               hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_pose_lag + 7 * (size_t)ids[i], e.pose0, 7 * sizeof(double),
+                              hipMemcpyHostToDevice, c->stream));  // no motion history
     HIP_TRY(c, hipMemsetAsync(c->d_lists + ids[i], 0, sizeof(ListState), c->stream));
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));  // host pose0 copies are pageable

@@ -180,6 +180,7 @@ struct StepParams {
   double clock_khz;        // wall-clock counter rate (phase timers)
   double tol, substep_tol;
   int max_iters, max_substeps, precision, armijo;
+  int warm_start;                // extrapolate the previous load step's displacement
   // adjoint
   const T2R_G double* dL_du;     // [sum n_m][3]
   T2R_G double* grad_out;        // [n_env][9]

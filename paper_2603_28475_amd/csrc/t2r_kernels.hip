@@ -1768,13 +1768,33 @@ __device__ __forceinline__ int load_step(const StepParams& P, int e, Solver& s, 
   const EnvDev& E = *V.E;
   const int n = 3 * G.n_v;
   T2R_G double* pose_prev = P.pose_prev + 7 * e;
-  double q0[7];
+  double q0[7], qpp[7];
   #pragma unroll
-  for (int i = 0; i < 7; ++i) q0[i] = pose_prev[i];
+  for (int i = 0; i < 7; ++i) { q0[i] = pose_prev[i]; qpp[i] = P.pose_lag[7 * e + i]; }
+  __syncthreads();  // every thread has read q_{s-2} before it is replaced
   // q_{s-1} of this load step (its friction lag pose), kept for the adjoint
   if (threadIdx.x < 7) P.pose_lag[7 * e + threadIdx.x] = q0[threadIdx.x];
-  // keep x_{s-1} for the friction lag and for rollback
-  for (int j = threadIdx.x; j < n; j += blockDim.x) V.xprev[j] = V.x[j];
+  // Warm start: when this step continues the previous one's indenter motion,
+  // solve from x_{s-1} + f (x_{s-1} - x_{s-2}), f the ratio of the motions
+  // (the quasi-static counterpart of the inertial predictor x + h v).
+  double fac = 0.0;
+  if (P.warm_start) {
+    const double m_prev = ind_motion(qpp, q0, I.r_max), m_cur = ind_motion(q0, q1, I.r_max);
+    double d1d2 = 0.0, d1 = 0.0, d2 = 0.0, qs = 0.0;
+    for (int i = 3; i < 7; ++i) qs += q0[i] * q1[i];
+    for (int i = 0; i < 7; ++i) {
+      const double b = (i >= 3 && qs < 0.0) ? -q1[i] : q1[i];  // same quaternion hemisphere
+      const double u = q0[i] - qpp[i], w = b - q0[i];
+      d1d2 += u * w; d1 += u * u; d2 += w * w;
+    }
+    if (m_prev > 0.0 && m_cur > 0.0 && d1d2 > 0.9 * sqrt(d1 * d2)) fac = m_cur / m_prev;
+  }
+  // keep x_{s-1} for the friction lag and for rollback (g1 holds the warm start)
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const double xc = V.x[j], xo = V.xprev[j];
+    V.xprev[j] = xc;
+    if (fac > 0.0) V.g1[j] = fma(fac, xc - xo, xc);
+  }
   // friction lag and starting distance at (x_{s-1}, q_{s-1}), from the outer
   // list kept since the last step (rebuilt here if the motion since it was
   // built exceeds its margin)
@@ -1797,6 +1817,29 @@ __device__ __forceinline__ int load_step(const StepParams& P, int e, Solver& s, 
     if (ov) status |= kOverflow;
   }
   st.n_friction = V.nfric;
+  if (fac > 0.0 && !(status & kOverflow) && dmin_start > 0.0) {
+    // take the warm start only if it is feasible at q_{s-1}: J > 0 and d > 0
+    for (int j = threadIdx.x; j < n; j += blockDim.x) V.x[j] = V.g1[j];
+    __syncthreads();
+    int feas = 1;
+    elem_eval(V, V.x, V.p, 0.0, V.g1, V.diag, *s.T, feas);
+    double f1[1] = {feas ? 0.0 : 1.0};
+    block_reduce<0, 1>(f1, S);
+    bool ok = f1[0] == 0.0 && ensure_lists(s, V.x, 0.0);
+    double dm = 0.0;
+    if (ok) {
+      int na = 0;
+      dm = dmin_all(s, V.x, na);
+      ok = dm > 0.0;
+    }
+    if (ok) {
+      dmin_start = dm;
+    } else {
+      for (int j = threadIdx.x; j < n; j += blockDim.x) V.x[j] = V.xprev[j];
+      __syncthreads();
+      if (!ensure_lists(s, V.x, 0.0)) status |= kOverflow;
+    }
+  }
   int status_acc = kConverged;
   double tau = 0.0, dmin = dmin_start;
   int sub = 0;
@@ -2579,7 +2622,10 @@ __global__ void t2r_pack_kernel(StepParams P, const double* in, double* out, con
       const int v = j / 3, c = j - 3 * v;
       P.x[E.voff + c * nv + v] = in[base + j];
     }
-    if (threadIdx.x < 7) P.pose_prev[7 * e + threadIdx.x] = in[base + 3 * nv + threadIdx.x];
+    if (threadIdx.x < 7) {
+      P.pose_prev[7 * e + threadIdx.x] = in[base + 3 * nv + threadIdx.x];
+      P.pose_lag[7 * e + threadIdx.x] = in[base + 3 * nv + threadIdx.x];  // no motion history
+    }
   } else {
     for (int j = threadIdx.x; j < 3 * nv; j += blockDim.x) {
       const int v = j / 3, c = j - 3 * v;

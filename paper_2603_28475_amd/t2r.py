@@ -28,7 +28,8 @@ class Material(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("substep_tol", C.c_double), ("max_iters", C.c_int32),
                 ("max_substeps", C.c_int32), ("precision", C.c_int32),
-                ("pair_capacity", C.c_int32), ("armijo", C.c_int32), ("block_size", C.c_int32)]
+                ("pair_capacity", C.c_int32), ("armijo", C.c_int32), ("block_size", C.c_int32),
+                ("warm_start", C.c_int32)]
 
 
 class EnvStats(C.Structure):
