@@ -1817,6 +1817,7 @@ __device__ __forceinline__ int load_step(const StepParams& P, int e, Solver& s, 
     if (ov) status |= kOverflow;
   }
   st.n_friction = V.nfric;
+  bool direct = false;  // the warm start is feasible at q_s: one solve, no intermediate poses
   if (fac > 0.0 && !(status & kOverflow) && dmin_start > 0.0) {
     // take the warm start only if it is feasible at q_{s-1}: J > 0 and d > 0
     for (int j = threadIdx.x; j < n; j += blockDim.x) V.x[j] = V.g1[j];
@@ -1834,6 +1835,14 @@ __device__ __forceinline__ int load_step(const StepParams& P, int e, Solver& s, 
     }
     if (ok) {
       dmin_start = dm;
+      if (threadIdx.x == 0) set_pose(S, I, q1);
+      __syncthreads();
+      if (ensure_lists(s, V.x, 0.0)) {
+        int na = 0;
+        direct = dmin_all(s, V.x, na) > 0.05 * E.dhat;
+      }
+      if (threadIdx.x == 0) set_pose(S, I, q0);
+      __syncthreads();
     } else {
       for (int j = threadIdx.x; j < n; j += blockDim.x) V.x[j] = V.xprev[j];
       __syncthreads();
@@ -1859,7 +1868,7 @@ __device__ __forceinline__ int load_step(const StepParams& P, int e, Solver& s, 
     const double theta = 2.0 * acos(cth);
     const double rate = dt + theta * I.r_max;
     while (tau < 1.0 && sub < P.max_substeps) {
-      const double dtau = (rate > 0.0) ? 0.5 * fmin(E.dhat, dmin) / rate : 1.0 - tau;
+      const double dtau = (rate > 0.0 && !direct) ? 0.5 * fmin(E.dhat, dmin) / rate : 1.0 - tau;
       const double tau_new = fmin(1.0, tau + dtau);
       if (threadIdx.x == 0) {
         double q[7];
