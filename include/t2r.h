@@ -294,9 +294,44 @@ t2r_status t2r_set_opts(t2r_ctx* ctx, const t2r_solver_opts* opts);
  * Per-env CG iterations, relative residual and status (T2R_ENV_CONVERGED,
  * T2R_ENV_MAXITER, T2R_ENV_NONFINITE for a Hessian that is not positive on
  * the CG directions) are reported by t2r_get_stats. Errors: T2R_E_UNSUPPORTED
- * if an env has mu_f != 0, T2R_E_STATE before the first load step.
- * Asynchronous; positions and poses are not changed. */
+ * if an env has mu_f != 0 (use t2r_backward_sequence), T2R_E_STATE before the
+ * first load step. Asynchronous; positions and poses are not changed. */
 t2r_status t2r_backward(t2r_ctx* ctx, const double* d_dL_du, double* d_grad);
+
+/* Starts recording a trajectory tape of at most max_steps load steps (device
+ * memory: (max_steps + 1) x (sum 3 n_v + 7 n_env) doubles, owned by the
+ * context). Entry 0 is the current state of every env; each later t2r_step /
+ * t2r_step_sequence appends every env's positions and pose after each of its
+ * load steps. t2r_reset_envs and t2r_set_state restart the recording from the
+ * new state. max_steps = 0 stops recording and frees the tape. A launch that
+ * would exceed the tape returns T2R_E_STATE without stepping.
+ * Errors: T2R_E_ARG (max_steps < 0), T2R_E_NOMEM (tape not allocated,
+ * recording off). */
+t2r_status t2r_record(t2r_ctx* ctx, int32_t max_steps);
+
+/* Load steps on the tape (-1: not recording). */
+t2r_status t2r_tape_length(const t2r_ctx* ctx, int32_t* n_steps);
+
+/* Gradient of a loss L on the marker displacements of the last n_steps
+ * recorded load steps with respect to each env's theta (as t2r_backward; the
+ * pose offset applies to every pose of the window, including the lag pose of
+ * its first step). With lagged friction (Supp. A, eq. friction_energy) step s
+ * depends on (x_{s-1}, q_{s-1}) through lambda_k, the closest points and the
+ * normal of its friction pairs, so the solve runs backwards through the
+ * window, last step first:
+ *   H_s lambda_s = W^T dL/du_s - (d g_{s+1}/d x_s)^T lambda_{s+1},
+ *   dL/dtheta = -sum_s lambda_s^T d g_s/d theta,
+ * H_s the exact Hessian of step s with its friction term (Jacobi-PCG to the
+ * relative residual 1e-10, at most max_iters iterations per step). The state
+ * before the window's first step is taken as given (record from rest to
+ * differentiate a whole trajectory). Every state is read from the tape.
+ *   d_dL_du  device [n_steps][sum n_m][3]: dL/du of each step, oldest first
+ *   d_grad   device [n_env][9]: dL/dtheta
+ * Stats as t2r_backward (iterations summed over the steps, the largest
+ * relative residual, substeps = n_steps). Errors: T2R_E_STATE without a tape,
+ * T2R_E_ARG for n_steps outside [1, t2r_tape_length]. Asynchronous; positions,
+ * poses and the tape are not changed. */
+t2r_status t2r_backward_sequence(t2r_ctx* ctx, int32_t n_steps, const double* d_dL_du, double* d_grad);
 
 #ifdef __cplusplus
 }

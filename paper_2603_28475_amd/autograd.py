@@ -1,14 +1,16 @@
-"""torch.autograd access to the adjoint (t2r_backward).
+"""torch.autograd access to the adjoint (t2r_backward_sequence).
 
-MarkerField.apply(theta, sim, poses) returns the marker displacements after a
-scripted trajectory as a differentiable function of per-env parameters
-theta = (E, nu, mu_f, dt_x, dt_y, dt_z, dw_x, dw_y, dw_z): material, friction
-coefficient and a rigid offset applied to every pose of the trajectory (the
-indenter point y becomes exp([dw]x) R Y + t + dt). The forward resets the envs,
-applies the materials and offsets and runs the trajectory in one launch; the
-backward calls t2r_backward (frictionless equilibria) and maps its rotation
-gradient, taken for an incremental rotation at the offset pose, to dw through
-the left Jacobian of SO(3).
+MarkerTrajectory.apply(theta, sim, poses) returns the marker displacements of
+every load step of a scripted trajectory, (S, sum n_m, 3), as a differentiable
+function of per-env parameters theta = (E, nu, mu_f, dt_x, dt_y, dt_z, dw_x,
+dw_y, dw_z): material, friction coefficient and a rigid offset applied to every
+pose of the trajectory (the indenter point y becomes exp([dw]x) R Y + t + dt).
+The forward resets the envs, applies the materials and offsets, records a tape
+and runs the trajectory in one launch; the backward differentiates through
+every step (and the friction lag between them) with t2r_backward_sequence and
+maps its rotation gradient, taken for an incremental rotation at the offset
+pose, to dw through the left Jacobian of SO(3). MarkerField.apply returns the
+last step only.
 """
 
 from __future__ import annotations
@@ -53,7 +55,7 @@ def offset_poses(poses, theta):
     return out
 
 
-class MarkerField(torch.autograd.Function):
+class MarkerTrajectory(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta, sim, poses):
         th = theta.detach().cpu().numpy().astype(np.float64)
@@ -61,16 +63,38 @@ class MarkerField(torch.autograd.Function):
         mats = [(th[i, 0], th[i, 1], th[i, 2], *sim.mats[i][3:]) for i in range(n)]
         sim.ctx.set_materials(list(range(n)), mats)
         sim.ctx.reset_envs(list(range(n)))
+        # the start pose (the friction lag pose of the first step) takes the offset too
+        state = torch.empty(sim.ctx.state_size(), dtype=torch.float64, device=sim.device)
+        sim.ctx.get_state(state)
+        sim.stream.synchronize()
+        st = state.cpu().numpy()
+        off = 0
+        for e in range(n):
+            off += 3 * sim.n_v[e]
+            st[off:off + 7] = offset_poses(st[off:off + 7][None, None, :], th[e:e + 1])[0, 0]
+            off += 7
+        with torch.cuda.stream(sim.stream):
+            state.copy_(torch.from_numpy(st))
+        sim.ctx.set_state(state)
         seq = offset_poses(np.asarray(poses, dtype=np.float64), th)
+        sim.record(seq.shape[0])
         markers, status = sim.step_sequence(seq)
         ctx.sim = sim
         ctx.theta = th
         ctx.status = status
-        return markers[-1].clone()
+        return markers.clone()
 
     @staticmethod
     def backward(ctx, grad_u):
-        g = ctx.sim.backward(grad_u.contiguous()).cpu().numpy()
+        g = ctx.sim.backward_sequence(grad_u.contiguous()).cpu().numpy()
         for e in range(g.shape[0]):
             g[e, 6:9] = _left_jacobian(ctx.theta[e, 6:9]).T @ g[e, 6:9]
         return torch.as_tensor(g, dtype=torch.float64), None, None
+
+
+class MarkerField:
+    """Marker displacements of the last load step of the trajectory."""
+
+    @staticmethod
+    def apply(theta, sim, poses):
+        return MarkerTrajectory.apply(theta, sim, poses)[-1]

@@ -102,6 +102,11 @@ struct t2r_ctx {
   double* d_pose_lag = nullptr;
   double* d_adj = nullptr;
   bool stepped = false;
+  // trajectory tape (t2r_record): tape_cap recorded steps at most, tape_len so far
+  double *d_tape_x = nullptr, *d_tape_q = nullptr;
+  int tape_cap = 0, tape_len = 0;
+  // two-entry tape of the single-step adjoint (x_{s-1}, x_s)
+  double *d_bw_x = nullptr, *d_bw_q = nullptr;
   uint64_t* d_oslot = nullptr;
   uint64_t* d_pslot = nullptr;
   int* d_slot_v = nullptr;
@@ -254,6 +259,20 @@ void build_grid(IndHost::GridHost& G, const std::vector<std::array<double, 6>>& 
 t2r_status commit(t2r_ctx* c);
 t2r_status relayout_lists(t2r_ctx* c);
 int pair_cap_of(const t2r_ctx* c, const GelHost& g);
+template <typename T>
+T* alloc_n(t2r_ctx* c, size_t n);
+
+// Restarts the recording from the current state of every env (tape entry 0).
+t2r_status tape_seed(t2r_ctx* c) {
+  c->tape_len = 0;
+  if (!c->d_tape_x) return T2R_OK;
+  if (hipMemcpyAsync(c->d_tape_x, c->d_x, (size_t)c->total_dofs * sizeof(double), hipMemcpyDeviceToDevice,
+                     c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->d_tape_q, c->d_pose_prev, 7 * c->envs.size() * sizeof(double), hipMemcpyDeviceToDevice,
+                     c->stream) != hipSuccess)
+    return fail(c, T2R_E_HIP, "tape copy failed");
+  return T2R_OK;
+}
 
 }  // namespace
 
@@ -839,9 +858,15 @@ static StepParams step_params(t2r_ctx* c) {
   P.order = nullptr;
   P.pose_lag = c->d_pose_lag;
   P.adj = c->d_adj;
+  P.tape_x = nullptr;
+  P.tape_q = nullptr;
+  P.tape_stride = c->total_dofs;
+  P.tape_k0 = 0;
   P.dL_du = nullptr;
   P.grad_out = nullptr;
   P.cg_tol = 1e-10;
+  P.bw_steps = 0;
+  P.bw_last = 0;
   P.n_steps = 1;
   P.markers_stride = 0;
   P.x_out_off = c->d_xout_off;
@@ -864,8 +889,16 @@ t2r_status t2r_step_sequence(t2r_ctx* c, int32_t n_steps, const double* d_poses,
   if (c->envs.empty()) return fail(c, T2R_E_STATE, "no environments");
   t2r_status s = commit(c);
   if (s != T2R_OK) return s;
+  if (c->d_tape_x && c->tape_len + n_steps > c->tape_cap)
+    return fail(c, T2R_E_STATE, "the tape holds %d more load steps (%d requested); t2r_record restarts it",
+                c->tape_cap - c->tape_len, n_steps);
   StepParams P = step_params(c);
   P.n_steps = n_steps;
+  if (c->d_tape_x) {
+    P.tape_x = c->d_tape_x;
+    P.tape_q = c->d_tape_q;
+    P.tape_k0 = c->tape_len;
+  }
   P.pose_in = d_poses;
   P.env_mask = d_mask;
   P.markers_out = d_markers;
@@ -879,6 +912,7 @@ t2r_status t2r_step_sequence(t2r_ctx* c, int32_t n_steps, const double* d_poses,
   }
   HIP_TRY(c, t2r_launch_step(&P, block_of(c), c->stream));
   c->stepped = true;
+  if (c->d_tape_x) c->tape_len += n_steps;
   c->err.clear();
   return T2R_OK;
 }
@@ -1046,6 +1080,8 @@ t2r_status t2r_set_state(t2r_ctx* c, const double* d_state) {
   HIP_TRY(c, t2r_launch_pack_state(&P, d_state, nullptr, c->d_state_off, 0, c->stream));
   // positions changed arbitrarily: every neighbour list must be rebuilt
   HIP_TRY(c, hipMemsetAsync(c->d_lists, 0, c->envs.size() * sizeof(ListState), c->stream));
+  s = tape_seed(c);
+  if (s != T2R_OK) return s;
   c->err.clear();
   return T2R_OK;
 }
@@ -1068,6 +1104,8 @@ t2r_status t2r_reset_envs(t2r_ctx* c, const int32_t* ids, int32_t n) {
                               hipMemcpyHostToDevice, c->stream));  // no motion history
     HIP_TRY(c, hipMemsetAsync(c->d_lists + ids[i], 0, sizeof(ListState), c->stream));
   }
+  s = tape_seed(c);
+  if (s != T2R_OK) return s;
   HIP_TRY(c, hipStreamSynchronize(c->stream));  // host pose0 copies are pageable
   c->err.clear();
   return T2R_OK;
@@ -1105,21 +1143,98 @@ t2r_status t2r_set_opts(t2r_ctx* c, const t2r_solver_opts* o) {
   return T2R_OK;
 }
 
+t2r_status t2r_record(t2r_ctx* c, int32_t max_steps) {
+  if (!c || max_steps < 0) return T2R_E_ARG;
+  if (c->envs.empty()) return fail(c, T2R_E_STATE, "no environments");
+  t2r_status s = commit(c);
+  if (s != T2R_OK) return s;
+  if (c->d_tape_x) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  dev_free(c, c->d_tape_x);
+  dev_free(c, c->d_tape_q);
+  c->d_tape_x = c->d_tape_q = nullptr;
+  c->tape_cap = c->tape_len = 0;
+  if (max_steps == 0) {
+    c->err.clear();
+    return T2R_OK;
+  }
+  const size_t entries = (size_t)max_steps + 1;
+  c->d_tape_x = alloc_n<double>(c, entries * (size_t)c->total_dofs);
+  c->d_tape_q = alloc_n<double>(c, entries * 7 * c->envs.size());
+  if (!c->d_tape_x || !c->d_tape_q) {
+    dev_free(c, c->d_tape_x);
+    dev_free(c, c->d_tape_q);
+    c->d_tape_x = c->d_tape_q = nullptr;
+    return fail(c, T2R_E_NOMEM, "tape of %d load steps does not fit", max_steps);
+  }
+  c->tape_cap = max_steps;
+  s = tape_seed(c);
+  if (s != T2R_OK) return s;
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_tape_length(const t2r_ctx* c, int32_t* n_steps) {
+  if (!c || !n_steps) return T2R_E_ARG;
+  *n_steps = c->d_tape_x ? c->tape_len : -1;
+  return T2R_OK;
+}
+
+static t2r_status launch_adjoint(t2r_ctx* c, StepParams& P, const double* d_dL_du, double* d_grad) {
+  P.dL_du = d_dL_du;
+  P.grad_out = d_grad;
+  P.markers_stride = 3 * c->total_markers;
+  HIP_TRY(c, t2r_launch_backward(&P, block_of(c), c->stream));
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_backward_sequence(t2r_ctx* c, int32_t n_steps, const double* d_dL_du, double* d_grad) {
+  if (!c) return T2R_E_ARG;
+  if (!d_dL_du || !d_grad) return fail(c, T2R_E_ARG, "d_dL_du and d_grad are required");
+  if (!c->d_tape_x) return fail(c, T2R_E_STATE, "no tape: call t2r_record before the load steps");
+  if (n_steps < 1 || n_steps > c->tape_len)
+    return fail(c, T2R_E_ARG, "n_steps must be in [1, %d] (the recorded load steps), got %d", c->tape_len,
+                n_steps);
+  StepParams P = step_params(c);
+  P.tape_x = c->d_tape_x;
+  P.tape_q = c->d_tape_q;
+  P.bw_steps = n_steps;
+  P.bw_last = c->tape_len;
+  return launch_adjoint(c, P, d_dL_du, d_grad);
+}
+
 t2r_status t2r_backward(t2r_ctx* c, const double* d_dL_du, double* d_grad) {
   if (!c) return T2R_E_ARG;
   for (size_t i = 0; i < c->envs.size(); ++i)
     if (c->envs[i].mat.mu_f != 0.0)
       return fail(c, T2R_E_UNSUPPORTED,
-                  "env %zu has mu_f = %g: the adjoint covers frictionless equilibria (mu_f = 0)", i,
-                  c->envs[i].mat.mu_f);
+                  "env %zu has mu_f = %g: with friction the equilibrium depends on the earlier steps "
+                  "(t2r_record + t2r_backward_sequence)", i, c->envs[i].mat.mu_f);
   if (!d_dL_du || !d_grad) return fail(c, T2R_E_ARG, "d_dL_du and d_grad are required");
   if (!c->committed || !c->stepped) return fail(c, T2R_E_STATE, "no load step has run");
+  // a two-entry tape: (x_{s-1}, q_{s-1}) and (x_s, q_s) of the last load step
+  const size_t nd = (size_t)c->total_dofs, nq = 7 * c->envs.size();
+  if (!c->d_bw_x) {
+    c->d_bw_x = alloc_n<double>(c, 2 * nd);
+    c->d_bw_q = alloc_n<double>(c, 2 * nq);
+    if (!c->d_bw_x || !c->d_bw_q) {
+      dev_free(c, c->d_bw_x);
+      dev_free(c, c->d_bw_q);
+      c->d_bw_x = c->d_bw_q = nullptr;
+      return fail(c, T2R_E_NOMEM, "adjoint scratch");
+    }
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->d_bw_x, c->d_xprev, nd * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_bw_x + nd, c->d_x, nd * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_bw_q, c->d_pose_lag, nq * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_bw_q + nq, c->d_pose_prev, nq * sizeof(double), hipMemcpyDeviceToDevice,
+                            c->stream));
   StepParams P = step_params(c);
-  P.dL_du = d_dL_du;
-  P.grad_out = d_grad;
-  HIP_TRY(c, t2r_launch_backward(&P, block_of(c), c->stream));
-  c->err.clear();
-  return T2R_OK;
+  P.tape_x = c->d_bw_x;
+  P.tape_q = c->d_bw_q;
+  P.bw_steps = 1;
+  P.bw_last = 1;
+  return launch_adjoint(c, P, d_dL_du, d_grad);
 }
 
 }  // extern "C"

@@ -181,10 +181,19 @@ struct StepParams {
   double tol, substep_tol;
   int max_iters, max_substeps, precision, armijo;
   int warm_start;                // extrapolate the previous load step's displacement
+  // trajectory tape: entry k holds every env's positions ([sum 3 n_v], the
+  // layout of x) and pose ([n_env][7]) after the k-th recorded load step
+  // (entry 0: the state when recording started)
+  T2R_G double* tape_x;          // [entries][sum 3 n_v] or null (step kernel: no recording)
+  T2R_G double* tape_q;          // [entries][n_env][7]
+  long long tape_stride;         // doubles per positions entry (sum 3 n_v)
+  int tape_k0;                   // step kernel: load step k of the launch writes entry tape_k0 + k + 1
   // adjoint
-  const T2R_G double* dL_du;     // [sum n_m][3]
+  const T2R_G double* dL_du;     // [bw_steps][sum n_m][3] (markers_stride doubles per step)
   T2R_G double* grad_out;        // [n_env][9]
   double cg_tol;                 // relative residual of the adjoint solve
+  int bw_steps;                  // load steps differentiated (the last bw_steps recorded)
+  int bw_last;                   // tape entry of the last step's equilibrium
 };
 
 struct EvalParams {

@@ -1977,6 +1977,12 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
     }
     st.status = status;
     write_markers(P, k, V);
+    if (P.tape_x) {
+      const long long ent = (long long)P.tape_k0 + k + 1;
+      T2R_G double* tx = P.tape_x + ent * P.tape_stride + V.E->voff;
+      for (int j = threadIdx.x; j < 3 * nv; j += blockDim.x) tx[j] = V.x[j];
+      if (threadIdx.x < 7) P.tape_q[(ent * P.n_env + e) * 7 + threadIdx.x] = P.pose_prev[7 * e + threadIdx.x];
+    }
     if (threadIdx.x == 0 && P.status_out) P.status_out[(long long)k * P.n_env + e] = status;
   }
   st.restarts = s.restarts;
@@ -2331,15 +2337,14 @@ __device__ __forceinline__ void pairs_pose(const View& V, const Shared& S, const
   }
 }
 
-// Thread partial of lambda^T (d g / d mu_f) at mu_f = 0: the lagged friction
-// gradient with unit coefficient (records built with mu_f = 1). LDS path:
-// gx = x, gq = lambda.
+// out += H_f v: Hessian-vector product of the lagged friction term (records
+// carry mu_f lambda_k). LDS path: gx = x and gq = v at the gel slots, sums in gd.
 template <bool LDS>
-__device__ __forceinline__ double fric_mu(const View& V, const Shared& S, const Tile& T, const double* x,
-                                          const double* lv) {
-  const int nv = V.G->n_v;
+__device__ __forceinline__ void fric_hvp(const View& V, const Shared& S, Tile& T, const double* x,
+                                         const double* v, double* out) {
+  const GelDev& G = *V.G;
+  const int nv = G.n_v;
   const double eps = V.E->eps_v;
-  double acc = 0.0;
   for (int i = threadIdx.x; i < V.nfric; i += blockDim.x) {
     const FricPair F = V.fric[i];
     double Dl[3];
@@ -2351,26 +2356,262 @@ __device__ __forceinline__ double fric_mu(const View& V, const Shared& S, const 
     const double s = sqrt(dot3(TD, TD));
     double f, fos, corr;
     mollifier3(s, eps, f, fos, corr);
+    double q[3] = {0, 0, 0};
+    #pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int vv = F.gv[k];
+      if (vv < 0) continue;
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) q[c] += F.a[k] * (LDS ? T.gq[c][fric_gslot(F, k)] : v[c * nv + vv]);
+    }
+    const double nq = dot3(F.n, q);
+    double uh[3] = {0, 0, 0}, uq = 0.0;
+    if (s > 0) {
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) uh[c] = TD[c] / s;
+      uq = dot3(uh, q);
+    }
+    double hq[3];
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) hq[c] = F.mulam * (fos * (q[c] - nq * F.n[c]) + corr * uq * uh[c]);
+    #pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int vv = F.gv[k];
+      if (vv < 0) continue;
+      if (!LDS && G.fixed[vv]) continue;
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double o = F.a[k] * hq[c];
+        if constexpr (LDS) atomicAdd(&T.gd[c][fric_gslot(F, k)], o);
+        else atomicAdd(&out[c * nv + vv], o);
+      }
+    }
+  }
+}
+
+// Friction terms of one load step of the adjoint, over the lag records (built
+// at (x_{s-1}, q_{s-1}) with coefficient mrec lambda_k); S holds q_s. Adds
+//   acc[0]   += lambda^T g_f / mu_f                     (d/d mu_f: unit coefficient)
+//   acc[1+a] += lambda^T (d g_f / d y(q_s)) dy_a        (pose offset at q_s)
+//   acc[1+a] += (d Q / d y(q_{s-1})) . dy_a             (pose offset at q_{s-1})
+//   carry    -= d Q / d x_{s-1}                         (free gel vertices)
+// with Q = lambda^T g_f and dy_a the pose directions (translations e_a,
+// rotations e_a x (y - t) about the indenter origin t of that pose). Q depends
+// on the lag points through lambda_k = -kappa b'(d), the normal n, the
+// relative displacement and the closest-point weights c(w); the free
+// parameters w move with the points by the implicit-function theorem on the
+// closest-point optimality D^T r = 0: (D^T D) dw = -sum_i (Cw_i r + c_i D) dz_i.
+// Global-memory path (one pass per load step).
+__device__ void fric_adjoint(const View& V, const Shared& S, Tile& T, const double* xs, const double* xp,
+                             const double* lam, const double qp[7], double mrec, double acc[7],
+                             double* carry) {
+  const GelDev& G = *V.G;
+  const IndDev& I = *V.I;
+  const EnvDev& E = *V.E;
+  const int nv = G.n_v;
+  const double eps = E.eps_v, dh = E.dhat, kap = E.kappa, muf = E.mu_f;
+  double Rp[9];
+  quat_to_R(qp + 3, Rp);
+  for (int i = threadIdx.x; i < V.nfric; i += blockDim.x) {
+    const FricPair F = V.fric[i];
+    const double lamk = F.mulam / mrec;
+    double Dl[3];
+    fric_delta<false>(V, S, T, F, xs, nullptr, 0.0, Dl);
+    const double nD0 = dot3(F.n, Dl);
+    double TD[3];
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) TD[c] = Dl[c] - nD0 * F.n[c];
+    const double sl = sqrt(dot3(TD, TD));
+    double f, fos, corr;
+    mollifier3(sl, eps, f, fos, corr);
+    double uh[3] = {0, 0, 0};
+    if (sl > 0) {
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) uh[c] = TD[c] / sl;
+    }
+    // d/d mu_f and q1 = sum a_k lambda_k
+    double q1[3] = {0, 0, 0};
     #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int v = F.gv[k];
-      if (v < 0 || V.G->fixed[v]) continue;
+      if (v < 0) continue;
       double lk[3];
-      if constexpr (LDS) {
-        const int q = fric_gslot(F, k);
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) { lk[c] = lam[c * nv + v]; q1[c] += F.a[k] * lk[c]; }
+      acc[0] += lamk * F.a[k] * fos * dot3(TD, lk);
+    }
+    if (!(muf > 0.0)) continue;
+    const double w = muf * lamk;
+    // pose at q_s: the indenter points enter the relative displacement with -c_j
+    {
+      const double n1 = dot3(F.n, q1), u1 = dot3(uh, q1);
+      #pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        double q2[3] = {0, 0, 0};
         #pragma unroll
-        for (int c = 0; c < 3; ++c) lk[c] = T.gq[c][q];
-      } else {
-        #pragma unroll
-        for (int c = 0; c < 3; ++c) lk[c] = lv[c * nv + v];
+        for (int k = 0; k < 3; ++k) {
+          if (F.iv[k] < 0) continue;
+          double y[3], dy[3] = {0, 0, 0};
+          ind_world(S, I, F.iv[k], y);
+          if (a < 3) {
+            dy[a] = 1.0;
+          } else {
+            const int ax = a - 3;
+            const double yr[3] = {y[0] - S.t[0], y[1] - S.t[1], y[2] - S.t[2]};
+            dy[0] = (ax == 1 ? yr[2] : 0.0) - (ax == 2 ? yr[1] : 0.0);
+            dy[1] = (ax == 2 ? yr[0] : 0.0) - (ax == 0 ? yr[2] : 0.0);
+            dy[2] = (ax == 0 ? yr[1] : 0.0) - (ax == 1 ? yr[0] : 0.0);
+          }
+          #pragma unroll
+          for (int c = 0; c < 3; ++c) q2[c] -= F.c[k] * dy[c];
+        }
+        acc[1 + a] += w * (fos * (dot3(q1, q2) - n1 * dot3(F.n, q2)) + corr * u1 * dot3(uh, q2));
       }
-      acc += F.mulam * F.a[k] * fos * dot3(TD, lk);
+    }
+    // the lag: points in the distance routine's order (make_fric keeps it)
+    int ng = 0;
+    #pragma unroll
+    for (int k = 0; k < 3; ++k) ng += F.gv[k] >= 0 ? 1 : 0;
+    PairPts P;
+    P.kind = ng == 1 ? kVF : (ng == 3 ? kFV : kEE);
+    double Z[4][3], L[4][3];
+    int vid[4];
+    {
+      int jg = 0, ji = 0;
+      #pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (point_is_gel(P.kind, k)) {
+          const int v = F.gv[jg++];
+          vid[k] = v;
+          P.gid[k] = v;
+          #pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            P.z[k][c] = xp[c * nv + v];
+            Z[k][c] = xs[c * nv + v];
+            L[k][c] = lam[c * nv + v];
+          }
+        } else {
+          const int j = F.iv[ji++];
+          vid[k] = j;
+          P.gid[k] = -1;
+          const double a0 = I.Y[j], a1 = I.Y[I.n_v + j], a2 = I.Y[2 * I.n_v + j];
+          double y[3];
+          ind_world(S, I, j, y);
+          #pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            P.z[k][c] = Rp[c * 3 + 0] * a0 + Rp[c * 3 + 1] * a1 + Rp[c * 3 + 2] * a2 + qp[c];
+            Z[k][c] = y[c];
+            L[k][c] = 0.0;
+          }
+        }
+      }
+    }
+    Feature fe;
+    classify(P, fe);
+    double r[3];
+    const double d = pair_distance(P, fe, r);
+    if (!(d > 0.0) || d >= dh) continue;
+    const double sig = (P.kind == kFV) ? -1.0 : 1.0;
+    double b, b1, b2;
+    barrier3(d, dh, b, b1, b2);
+    const double lamd = -kap * b1;
+    double rh[3], nn[3], Dt[3] = {0, 0, 0}, Lb[3] = {0, 0, 0};
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) { rh[c] = r[c] / d; nn[c] = sig * rh[c]; }
+    #pragma unroll
+    for (int k = 0; k < 4; ++k)
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Dt[c] += sig * fe.c[k] * (Z[k][c] - P.z[k][c]);
+        Lb[c] += fe.c[k] * L[k][c];
+      }
+    const double nD = dot3(nn, Dt);
+    double u[3];
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) u[c] = Dt[c] - nD * nn[c];
+    const double su = sqrt(dot3(u, u));
+    double phi, dphi;
+    if (su < eps) { phi = -su / (eps * eps) + 2.0 / eps; dphi = -1.0 / (eps * eps); }
+    else { phi = 1.0 / su; dphi = -1.0 / (su * su); }
+    const double Cq = sig * dot3(Lb, u);
+    // reverse mode through Q = mu_f lambda(d) phi(|u|) C
+    const double lam_b = muf * phi * Cq, phi_b = muf * lamd * Cq, C_b = muf * lamd * phi;
+    const double d_b = lam_b * (-kap * b2);
+    const double s_b = phi_b * dphi;
+    double ub[3], Lbb[3];
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      ub[c] = C_b * sig * Lb[c] + (su > 0.0 ? s_b * u[c] / su : 0.0);
+      Lbb[c] = C_b * sig * u[c];
+    }
+    const double nub = dot3(nn, ub);
+    double Dtb[3], rb[3];
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) Dtb[c] = ub[c] - nub * nn[c];
+    {
+      double rhb[3];
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) rhb[c] = sig * (-nD * ub[c] - nub * Dt[c]);
+      const double rr = dot3(rh, rhb);
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) rb[c] = (rhb[c] - rr * rh[c]) / d + d_b * rh[c];
+    }
+    double cb[4], Zb[4][3];
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double dz[3];
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) dz[c] = Z[k][c] - P.z[k][c];
+      cb[k] = sig * dot3(Dtb, dz) + dot3(Lbb, L[k]) + dot3(rb, P.z[k]);
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) Zb[k][c] = (-sig * Dtb[c] + rb[c]) * fe.c[k];
+    }
+    // closest-point parameters
+    double D[2][3];
+    #pragma unroll
+    for (int a = 0; a < 2; ++a)
+      #pragma unroll
+      for (int c = 0; c < 3; ++c)
+        D[a][c] = cw_of(fe, 0, a) * P.z[0][c] + cw_of(fe, 1, a) * P.z[1][c] + cw_of(fe, 2, a) * P.z[2][c] +
+                  cw_of(fe, 3, a) * P.z[3][c];
+    double Mi[2][2];
+    gram_inverse(D, fe.k, Mi);
+    double wb[2] = {0, 0};
+    #pragma unroll
+    for (int a = 0; a < 2; ++a)
+      if (a < fe.k)
+        #pragma unroll
+        for (int k = 0; k < 4; ++k) wb[a] += cb[k] * cw_of(fe, k, a);
+    const double m[2] = {Mi[0][0] * wb[0] + Mi[0][1] * wb[1], Mi[1][0] * wb[0] + Mi[1][1] * wb[1]};
+    #pragma unroll
+    for (int k = 0; k < 4; ++k)
+      #pragma unroll
+      for (int a = 0; a < 2; ++a)
+        if (a < fe.k)
+          #pragma unroll
+          for (int c = 0; c < 3; ++c) Zb[k][c] -= (cw_of(fe, k, a) * r[c] + fe.c[k] * D[a][c]) * m[a];
+    // scatter: gel points to the carry, indenter points to the pose offset at q_{s-1}
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (P.gid[k] >= 0) {
+        const int v = vid[k];
+        if (G.fixed[v]) continue;
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) atomicAdd(&carry[c * nv + v], -Zb[k][c]);
+      } else {
+        const double yr[3] = {P.z[k][0] - qp[0], P.z[k][1] - qp[1], P.z[k][2] - qp[2]};
+        #pragma unroll
+        for (int a = 0; a < 3; ++a) acc[1 + a] += Zb[k][a];
+        // e_ax x yr
+        acc[4] += Zb[k][1] * (-yr[2]) + Zb[k][2] * yr[1];
+        acc[5] += Zb[k][0] * yr[2] + Zb[k][2] * (-yr[0]);
+        acc[6] += Zb[k][0] * (-yr[1]) + Zb[k][1] * yr[0];
+      }
     }
   }
-  return acc;
 }
 
-// out = H v (elastic + barrier; the equilibrium is frictionless), fixed DOFs 0.
+// out = H v at x (elastic + barrier + the friction records in V.nfric), fixed DOFs 0.
 __device__ __forceinline__ void hess_vec(Solver& s, const double* x, const double* v, double* out) {
   View& V = s.V;
   elem_hvp(V, x, v, out, *s.T);
@@ -2383,6 +2624,7 @@ __device__ __forceinline__ void hess_vec(Solver& s, const double* x, const doubl
     }
     __syncthreads();
     pairs_hvp<true>(V, *s.S, T, x, v, out);
+    fric_hvp<true>(V, *s.S, T, x, v, out);
     const GelDev& G = *V.G;
     const int nv = G.n_v;
     __syncthreads();
@@ -2395,10 +2637,16 @@ __device__ __forceinline__ void hess_vec(Solver& s, const double* x, const doubl
   } else {
     __syncthreads();
     pairs_hvp<false>(V, *s.S, *s.T, x, v, out);
+    fric_hvp<false>(V, *s.S, *s.T, x, v, out);
   }
   __syncthreads();
 }
 
+// Adjoint of the last P.bw_steps recorded load steps, last step first:
+//   H_s lambda_s = W^T dL/du_s + carry_s,   carry_{s-1} = -(d g_s / d x_{s-1})^T lambda_s,
+//   dL/dtheta = -sum_s lambda_s^T d g_s / d theta,
+// with every state read from the tape. The env's own positions, poses and
+// friction records are not changed; its neighbour lists are rebuilt as needed.
 template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_backward_kernel(StepParams P) {
   __shared__ Shared S;
@@ -2422,71 +2670,83 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_backward_ke
   st.list_fill = 0.0;
   const unsigned long long t_start = tick();
   load_lists(s);
-  double ql[7], qc[7];
-  #pragma unroll
-  for (int i = 0; i < 7; ++i) { ql[i] = P.pose_lag[7 * e + i]; qc[i] = P.pose_prev[7 * e + i]; }
-  // friction records with unit coefficient at the lag (x_{s-1}, q_{s-1})
-  if (threadIdx.x == 0) set_pose(S, I, ql);
+  const double muf = E.mu_f;
+  const double mrec = muf > 0.0 ? muf : 1.0;  // coefficient the lag records are built with
+  T2R_G double* Ad = P.adj + E.voff;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) V.g1[j] = 0.0;  // carry into the last step: none
   __syncthreads();
-  bool ok = ensure_lists(s, V.xprev, 0.0);
-  int nfric_lag = 0;
-  if (ok) {
-    lag_from_outer(s, V.xprev, 1, 1.0);
-    nfric_lag = min(S.count, s.fric_cap);
-    ok = S.overflow == 0;
-  }
-  __syncthreads();
-  V.nfric = nfric_lag;  // kept while the lists may be rebuilt, so the records keep their slots
-  if (threadIdx.x == 0) set_pose(S, I, qc);
-  __syncthreads();
-  if (ok) ok = ensure_lists(s, V.x, 0.0);
-  double grad[9];
-  for (int k = 0; k < 9; ++k) grad[k] = 0.0;
-  if (!ok) {
-    st.status = kOverflow;
-  } else {
-    // Jacobi preconditioner at x* (the equilibrium is frictionless)
+  // thread partials of lambda^T dg/dtheta: mu-, lambda-elastic, mu_f, pose (6)
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  bool ok = true;
+  int status = kConverged;
+  for (int w = 0; w < P.bw_steps && ok; ++w) {
+    const long long k = (long long)P.bw_last - w;
+    T2R_G double* xs = P.tape_x + k * P.tape_stride + E.voff;
+    T2R_G double* xp = xs - P.tape_stride;
+    double qs[7], qp[7];
+    #pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      qs[i] = P.tape_q[(k * P.n_env + e) * 7 + i];
+      qp[i] = P.tape_q[((k - 1) * P.n_env + e) * 7 + i];
+    }
+    V.x = xs;
+    V.xprev = xp;
+    // friction records at the lag (x_{s-1}, q_{s-1})
     V.nfric = 0;
-    int feas, nact;
-    eval_all(s, V.x, V.p, 0.0, V.g1, V.diag, feas, nact);
-    // rhs = W^T dL/du (free DOFs) in g1, lambda = 0 in g0
-    for (int j = threadIdx.x; j < n; j += blockDim.x) { V.g0[j] = 0.0; V.g1[j] = 0.0; }
+    if (threadIdx.x == 0) set_pose(S, I, qp);
     __syncthreads();
-    const T2R_G double* du = P.dL_du + 3 * E.moff;
-    for (int m = threadIdx.x; m < G.n_m; m += blockDim.x) {
-      #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int v = G.marker_tri[k * G.n_m + m];
-        const double w = G.marker_w[k * G.n_m + m];
-        #pragma unroll
-        for (int c = 0; c < 3; ++c) atomicAdd(&V.g1[c * nv + v], w * du[3 * m + c]);
-      }
+    ok = ensure_lists(s, xp, 0.0);
+    int nfric = 0;
+    if (ok) {
+      lag_from_outer(s, xp, 1, mrec);
+      nfric = min(S.count, s.fric_cap);
+      ok = S.overflow == 0;
     }
     __syncthreads();
-    double a2[3] = {0.0, 0.0, 0.0};  // r.z, r.r, -
+    V.nfric = nfric;  // kept while the lists may be rebuilt, so the records keep their slots
+    if (threadIdx.x == 0) set_pose(S, I, qs);
+    __syncthreads();
+    if (ok) ok = ensure_lists(s, xs, 0.0);
+    if (!ok) break;
+    st.n_friction = max(st.n_friction, nfric);
+    // rhs = carry + W^T dL/du_s (free DOFs) in g1, lambda = 0 in g0
+    const T2R_G double* du = P.dL_du + (long long)(P.bw_steps - 1 - w) * P.markers_stride + 3 * E.moff;
+    for (int m = threadIdx.x; m < G.n_m; m += blockDim.x) {
+      #pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int v = G.marker_tri[t * G.n_m + m];
+        const double wt = G.marker_w[t * G.n_m + m];
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) atomicAdd(&V.g1[c * nv + v], wt * du[3 * m + c]);
+      }
+    }
+    // Jacobi preconditioner at x_s (the gradient output is scratch)
+    V.nfric = muf > 0.0 ? nfric : 0;
+    int feas, nact;
+    eval_all(s, xs, V.p, 0.0, Ad, V.diag, feas, nact);
+    double a2[2] = {0.0, 0.0};
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
       const int v = j >= 2 * nv ? j - 2 * nv : (j >= nv ? j - nv : j);
       double r = V.g1[j];
       if (G.fixed[v]) { r = 0.0; V.g1[j] = 0.0; }
       const double Pj = 1.0 / fmax(V.diag[j], s.floor_d);
       V.diag[j] = Pj;
+      V.g0[j] = 0.0;
       V.p[j] = Pj * r;
       a2[0] += r * Pj * r;
       a2[1] += r * r;
     }
-    double w2[2] = {a2[0], a2[1]};
-    block_reduce<2, 0>(w2, S);
-    double rz = w2[0];
-    const double r0 = sqrt(w2[1]);
+    block_reduce<2, 0>(a2, S);
+    double rz = a2[0];
+    const double r0 = sqrt(a2[1]);
     double rn = r0;
     int it = 0;
     for (; it < P.max_iters && rn > P.cg_tol * r0 && r0 > 0.0; ++it) {
-      hess_vec(s, V.x, V.p, P.adj + E.voff);
-      const double* Ad = P.adj + E.voff;
+      hess_vec(s, xs, V.p, Ad);
       double c1[1] = {0.0};
       for (int j = threadIdx.x; j < n; j += blockDim.x) c1[0] += V.p[j] * Ad[j];
       block_reduce<1, 0>(c1, S);
-      if (!(c1[0] > 0.0)) { st.status |= kNonFinite; break; }
+      if (!(c1[0] > 0.0)) { status |= kNonFinite; break; }
       const double alpha = rz / c1[0];
       double c2[2] = {0.0, 0.0};
       for (int j = threadIdx.x; j < n; j += blockDim.x) {
@@ -2503,27 +2763,40 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_backward_ke
       for (int j = threadIdx.x; j < n; j += blockDim.x) V.p[j] = fma(beta, V.p[j], V.diag[j] * V.g1[j]);
       __syncthreads();
     }
-    st.iters = it;
-    st.residual = r0 > 0.0 ? rn / r0 : 0.0;
-    if (!(rn <= P.cg_tol * r0) && r0 > 0.0) st.status |= kMaxIter;
-    else if (!(st.status & kNonFinite)) st.status |= kConverged;
-    // lambda^T dg/dtheta
-    double cm = 0.0, cl = 0.0;
-    elem_theta(V, V.x, V.g0, T, cm, cl);
+    st.iters += it;
+    st.max_solve_iters = max(st.max_solve_iters, it);
+    st.residual = fmax(st.residual, r0 > 0.0 ? rn / r0 : 0.0);
+    if (!(rn <= P.cg_tol * r0) && r0 > 0.0) status |= kMaxIter;
+    // lambda^T dg/dtheta: elastic and barrier terms
+    elem_theta(V, xs, V.g0, T, acc[0], acc[1]);
     double pose_acc[6] = {0, 0, 0, 0, 0, 0};
-    double cf = 0.0;
-    V.nfric = nfric_lag;
     if (V.slots_ok) {
-      stage_points(V, S, T, V.x, V.g0, 0.0, 1);
-      pairs_pose<true>(V, S, T, V.x, V.g0, pose_acc);
-      cf = fric_mu<true>(V, S, T, V.x, V.g0);
+      stage_points(V, S, T, xs, V.g0, 0.0, 1);
+      pairs_pose<true>(V, S, T, xs, V.g0, pose_acc);
     } else {
-      pairs_pose<false>(V, S, T, V.x, V.g0, pose_acc);
-      cf = fric_mu<false>(V, S, T, V.x, V.g0);
+      pairs_pose<false>(V, S, T, xs, V.g0, pose_acc);
     }
-    double red[9] = {cm, cl, cf, pose_acc[0], pose_acc[1], pose_acc[2], pose_acc[3], pose_acc[4], pose_acc[5]};
-    block_reduce<3, 0>(red, S);
-    block_reduce<6, 0>(red + 3, S);
+    #pragma unroll
+    for (int a = 0; a < 6; ++a) acc[3 + a] += pose_acc[a];
+    // friction terms and the carry into step s-1 (g1 is free once the solve is done)
+    V.nfric = nfric;
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x) V.g1[j] = 0.0;
+    __syncthreads();
+    double fa[7] = {0, 0, 0, 0, 0, 0, 0};
+    fric_adjoint(V, S, T, xs, xp, V.g0, qp, mrec, fa, V.g1);
+    acc[2] += fa[0];
+    #pragma unroll
+    for (int a = 0; a < 6; ++a) acc[3 + a] += fa[1 + a];
+    __syncthreads();
+  }
+  double grad[9];
+  for (int k = 0; k < 9; ++k) grad[k] = 0.0;
+  block_reduce<3, 0>(acc, S);
+  block_reduce<6, 0>(acc + 3, S);
+  if (!ok) {
+    status = kOverflow;
+  } else {
     // Lame partials: mu = E / (2 (1 + nu)), lam = E nu / ((1 + nu)(1 - 2 nu))
     const double mu = E.mu, lam = E.lam;
     const double Ey = mu * (3.0 * lam + 2.0 * mu) / (lam + mu);
@@ -2532,16 +2805,18 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_backward_ke
     const double dlam_dE = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
     const double dmu_dnu = -Ey / (2.0 * (1.0 + nu) * (1.0 + nu));
     const double dlam_dnu = Ey * (1.0 + 2.0 * nu * nu) / ((1.0 + nu) * (1.0 + nu) * (1.0 - 2.0 * nu) * (1.0 - 2.0 * nu));
-    grad[0] = -(red[0] * dmu_dE + red[1] * dlam_dE);
-    grad[1] = -(red[0] * dmu_dnu + red[1] * dlam_dnu);
-    grad[2] = -red[2];
-    for (int k = 0; k < 6; ++k) grad[3 + k] = -red[3 + k];
+    grad[0] = -(acc[0] * dmu_dE + acc[1] * dlam_dE);
+    grad[1] = -(acc[0] * dmu_dnu + acc[1] * dlam_dnu);
+    grad[2] = -acc[2];
+    for (int k = 0; k < 6; ++k) grad[3 + k] = -acc[3 + k];
+    if (status & (kMaxIter | kNonFinite)) status &= ~kConverged;
   }
   if (threadIdx.x < 9) P.grad_out[9 * e + threadIdx.x] = grad[threadIdx.x];
   if (threadIdx.x == 0) {
-    st.n_friction = nfric_lag;
+    st.status = status;
     st.n_candidates = V.npairs;
     st.n_outer = V.nouter;
+    st.substeps = P.bw_steps;
     st.phase_ms[8] = (double)(wall_clock64() - t_start) / P.clock_khz;
     P.stats[e] = st;
   }

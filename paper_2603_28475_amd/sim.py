@@ -85,6 +85,20 @@ class Sim:
         self.ctx.backward(g, out)
         return out
 
+    def record(self, max_steps):
+        """Starts a trajectory tape of at most max_steps load steps from the current
+        state (0 stops recording); see t2r_record."""
+        self.ctx.record(max_steps)
+
+    def backward_sequence(self, dL_du):
+        """dL/dtheta (n_env, 9) of a loss on the markers of the last S recorded load
+        steps; dL_du: (S, sum n_m, 3), oldest step first (see t2r_backward_sequence).
+        Not synchronised."""
+        g = torch.as_tensor(dL_du, dtype=torch.float64, device=self.device).contiguous()
+        out = torch.zeros((self.n_env, 9), dtype=torch.float64, device=self.device)
+        self.ctx.backward_sequence(g.shape[0], g, out)
+        return out
+
     def graph_step(self, poses):
         """One load step of every env, replayed from a captured HIP graph.
 

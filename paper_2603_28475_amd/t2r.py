@@ -78,6 +78,9 @@ SIGNATURES = [
     ("t2r_get_opts", C.c_int32, [_P, C.POINTER(SolverOpts)]),
     ("t2r_set_opts", C.c_int32, [_P, C.POINTER(SolverOpts)]),
     ("t2r_backward", C.c_int32, [_P, _P, _P]),
+    ("t2r_record", C.c_int32, [_P, C.c_int32]),
+    ("t2r_tape_length", C.c_int32, [_P, C.POINTER(C.c_int32)]),
+    ("t2r_backward_sequence", C.c_int32, [_P, C.c_int32, _P, _P]),
 ]
 
 
@@ -256,3 +259,14 @@ class Context:
 
     def backward(self, d_dL_du, d_grad):
         self.check(lib.t2r_backward(self.handle, _tptr(d_dL_du), _tptr(d_grad)))
+
+    def record(self, max_steps):
+        self.check(lib.t2r_record(self.handle, int(max_steps)))
+
+    def tape_length(self):
+        n = C.c_int32(0)
+        self.check(lib.t2r_tape_length(self.handle, C.byref(n)))
+        return n.value
+
+    def backward_sequence(self, n_steps, d_dL_du, d_grad):
+        self.check(lib.t2r_backward_sequence(self.handle, int(n_steps), _tptr(d_dL_du), _tptr(d_grad)))

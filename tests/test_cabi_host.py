@@ -8,6 +8,7 @@ import re
 
 import numpy as np
 import pytest
+import torch
 
 from oracle.geometry import GelGeometry
 from scenes.configs import INDENTERS, sphere_press_484v
@@ -95,7 +96,18 @@ def test_invalid_inputs_are_rejected_on_the_host():
     assert fr == 1
     with pytest.raises(t2r.T2RError) as e:
         ctx.backward(None, None)
-    assert e.value.code == t2r.T2R_E_UNSUPPORTED     # friction: the adjoint is frictionless only
+    assert e.value.code == t2r.T2R_E_UNSUPPORTED     # friction: needs the sequence adjoint
+    assert ctx.tape_length() == -1                   # not recording
+    with pytest.raises(t2r.T2RError) as e:
+        ctx.record(-1)
+    assert e.value.code == t2r.T2R_E_ARG
+    with pytest.raises(t2r.T2RError) as e:
+        ctx.backward_sequence(1, None, None)
+    assert e.value.code == t2r.T2R_E_ARG            # no outputs
+    host = torch.zeros(4, dtype=torch.float64)       # never dereferenced: rejected first
+    with pytest.raises(t2r.T2RError) as e:
+        ctx.backward_sequence(1, host, host)
+    assert e.value.code == t2r.T2R_E_STATE          # no tape
 
 
 def test_invalid_options_are_rejected():

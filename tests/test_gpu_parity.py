@@ -415,6 +415,155 @@ def test_marker_field_autograd_matches_differences_at_an_offset_pose():
         assert abs(g[i] - fd) <= 1e-4 * max(abs(fd), 1e-3 * np.abs(g).max()), (i, g[i], fd)
 
 
+def _plate_friction_scene():
+    """A tilted plate pressed (two steps) and slid (two steps) with friction 0.5
+    on the 32-vertex gel: the friction lag of the slide steps holds VF, FV and EE
+    pairs."""
+    from scenes.configs import micro_press
+    q = np.array([0.99996192, 0.00610865, 0.00436331, 0.0])
+    q /= np.linalg.norm(q)
+    return micro_press(mesh="micro3", indenter="plate", depth=0.08, n_steps=2, mu_f=0.5,
+                       shear=(0.05, 0.02), n_shear=2, xy=(0.1, -0.05), q=tuple(q))
+
+
+def _recorded_run(t2r, w, env, tol):
+    """Per-step launches from rest with a tape; returns the Sim, the positions
+    and the markers after every step."""
+    S = env.poses.shape[0] - 1
+    sim = _build(t2r, w, tol=tol, substep_tol=tol, max_iters=400000)
+    sim.record(S)
+    xs, ms = [], []
+    for s in range(1, S + 1):
+        m, st = sim.step(env.poses[s][None], want_x=True)
+        torch.cuda.synchronize()
+        assert int(st.cpu()[0]) & 1
+        xs.append(sim.x.cpu().numpy().copy())
+        ms.append(m.cpu().numpy().copy())
+    assert sim.ctx.tape_length() == S
+    return sim, xs, ms
+
+
+def test_backward_sequence_with_friction_matches_oracle_adjoint():
+    """t2r_backward_sequence through a friction trajectory against the oracle's
+    sequence adjoint at the GPU's own states (loss on two of the four steps)."""
+    t2r = _gpu()
+    from oracle.adjoint import adjoint_sequence
+    w = _plate_friction_scene()
+    env = w.envs[0]
+    print("plate friction scene, backward_sequence vs oracle", flush=True)
+    sim, xs, ms = _recorded_run(t2r, w, env, 1e-11)
+    rng = np.random.default_rng(9)
+    du = np.zeros((len(ms),) + ms[0].shape)
+    du[1] = 0.5 * (ms[1] - 0.02 * rng.standard_normal(ms[1].shape))
+    du[3] = ms[3] - 0.02 * rng.standard_normal(ms[3].shape)
+    g = sim.backward_sequence(du)
+    torch.cuda.synchronize()
+    st = sim.stats()[0]
+    assert st["status"] & 1 and st["residual"] <= 1e-10 and st["n_friction"] > 0, st
+    gel, ind, prob = _oracle_problem(w, env)
+    ref = adjoint_sequence(prob, [gel.X] + xs, env.poses, du)
+    got = g.cpu().numpy()[0]
+    scale = np.abs(ref).max()
+    assert np.all(np.abs(got - ref) <= 1e-6 * np.maximum(np.abs(ref), 1e-3 * scale)), (got, ref)
+    # one step only: the state before it is taken as given (the oracle from x_3)
+    g1 = sim.backward_sequence(du[3:]).cpu().numpy()[0]
+    ref1 = adjoint_sequence(prob, [xs[2], xs[3]], env.poses[3:], du[3:])
+    assert np.all(np.abs(g1 - ref1) <= 1e-6 * np.maximum(np.abs(ref1), 1e-3 * np.abs(ref1).max())), (g1, ref1)
+
+
+def test_backward_sequence_with_friction_matches_central_differences_of_the_gpu_forward():
+    """GPU sequence gradients (all nine parameters, friction coefficient included)
+    against central differences of the GPU forward itself."""
+    t2r = _gpu()
+    import dataclasses
+    from oracle.adjoint import offset_pose
+    w = _plate_friction_scene()
+    env = w.envs[0]
+    S = env.poses.shape[0] - 1
+    rng = np.random.default_rng(4)
+    n_m = len(w.meshes[env.mesh].markers)
+    u_t = 0.02 * rng.standard_normal((S, n_m, 3))
+    wts = np.array([0.0, 0.5, 0.0, 1.0])
+    print("plate friction scene, backward_sequence vs central differences", flush=True)
+    sim, _, ms = _recorded_run(t2r, w, env, 1e-12)
+    du = np.stack([wts[s] * (ms[s] - u_t[s]) for s in range(S)])
+    g = sim.backward_sequence(du).cpu().numpy()[0]
+
+    def loss(v):
+        e = dataclasses.replace(env, E=env.E + v[0], nu=env.nu + v[1], mu_f=env.mu_f + v[2],
+                                poses=np.stack([offset_pose(p, v[3:6], v[6:9]) for p in env.poses]))
+        _, _, m = _recorded_run(t2r, dataclasses.replace(w, envs=[e]), e, 1e-12)
+        return sum(0.5 * wts[s] * float(np.sum((m[s] - u_t[s]) ** 2)) for s in range(S))
+
+    # steps large enough that the forward's stopping tolerance (1e-12 mm) stays
+    # far below the difference, small enough for the O(h^2) term
+    hs = [1e-4 * env.E, 1e-4 * env.nu, 1e-5] + [1e-5] * 6
+    fd = np.zeros(9)
+    for i, h in enumerate(hs):
+        v = np.zeros(9)
+        v[i] = h
+        fd[i] = (loss(v) - loss(-v)) / (2 * h)
+    scale = np.abs(fd).max()
+    assert abs(fd[2]) > 1e-3 * scale                 # the friction path matters here
+    for i in range(9):
+        assert abs(g[i] - fd[i]) <= 1e-4 * max(abs(fd[i]), 1e-3 * scale), (i, g[i], fd[i])
+
+
+def test_marker_trajectory_autograd_with_friction():
+    """MarkerTrajectory (torch.autograd over every step) with friction at a nonzero
+    pose offset against central differences of its own forward."""
+    t2r = _gpu()
+    from paper_2603_28475_amd.autograd import MarkerTrajectory
+    w = _plate_friction_scene()
+    env = w.envs[0]
+    sim = _build(t2r, w, tol=1e-12, substep_tol=1e-12, max_iters=400000)
+    poses = env.poses[1:][:, None, :]
+    rng = np.random.default_rng(6)
+    S = poses.shape[0]
+    u_t = torch.as_tensor(0.02 * rng.standard_normal((S, len(w.meshes[env.mesh].markers), 3)), device="cuda:0")
+    theta0 = np.array([[env.E, env.nu, 0.4, 0.01, -0.02, 0.005, 0.01, -0.02, 0.05]])
+
+    def loss(th):
+        u = MarkerTrajectory.apply(torch.tensor(th, dtype=torch.float64), sim, poses)
+        return 0.5 * ((u - u_t) ** 2).sum()
+
+    th = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+    L = 0.5 * ((MarkerTrajectory.apply(th, sim, poses) - u_t) ** 2).sum()
+    L.backward()
+    g = th.grad.numpy()[0]
+    for i, h in ((0, 1e-4 * env.E), (2, 1e-5), (3, 1e-5), (7, 1e-5)):
+        tp, tm = theta0.copy(), theta0.copy()
+        tp[0, i] += h
+        tm[0, i] -= h
+        with torch.no_grad():
+            fd = (float(loss(tp)) - float(loss(tm))) / (2 * h)
+        assert abs(g[i] - fd) <= 1e-4 * max(abs(fd), 1e-3 * np.abs(g).max()), (i, g[i], fd)
+
+
+def test_tape_limits():
+    """A full tape refuses the launch (no step taken); record(0) stops recording."""
+    t2r = _gpu()
+    w = _plate_friction_scene()
+    env = w.envs[0]
+    sim = _build(t2r, w, tol=1e-10, substep_tol=1e-10, max_iters=400000)
+    sim.record(1)
+    sim.step(env.poses[1][None])
+    torch.cuda.synchronize()
+    before = sim.markers.cpu().numpy().copy()
+    with pytest.raises(t2r.T2RError) as e:
+        sim.step(env.poses[2][None])
+    assert e.value.code == t2r.T2R_E_STATE
+    torch.cuda.synchronize()
+    assert np.array_equal(sim.markers.cpu().numpy(), before)
+    assert sim.ctx.tape_length() == 1
+    with pytest.raises(t2r.T2RError):
+        sim.backward_sequence(np.zeros((2,) + before.shape))   # more steps than recorded
+    sim.record(0)
+    assert sim.ctx.tape_length() == -1
+    sim.step(env.poses[2][None])                              # recording off: no limit
+    torch.cuda.synchronize()
+
+
 def _certify_equilibrium(w, env, pose, x, bound=1e-6):
     """The oracle's Newton started from x must not move: x is a minimiser of Pi."""
     from oracle.newton import newton_solve
