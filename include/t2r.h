@@ -89,7 +89,8 @@ typedef struct { double E, nu, mu_f, eps_v, dhat, kappa; } t2r_material;
  *                 list holds 4x and the friction list 1/2 of it
  *   armijo        1: require sufficient decrease of Pi in the line search
  *   block_size    threads per env workgroup: 256 (two envs per CU) or 512 (one env
- *                 per CU, for few large envs); 0 = 256
+ *                 per CU, for few large envs); 0 = automatic: 512 while the envs
+ *                 do not outnumber the compute units, else 256
  *   warm_start    1: when a load step continues the previous step's indenter
  *                 motion, start from x_{s-1} + f (x_{s-1} - x_{s-2}) (f = ratio of
  *                 the motions) if that point is feasible; 0: start from x_{s-1} */

@@ -116,6 +116,7 @@ struct t2r_ctx {
   long long total_dofs = 0, total_verts = 0, total_markers = 0, state_size = 0;
   int pair_cap = 0;
   double clock_khz = 1.0;
+  int n_cu = 256;      // compute units of the device (set at the first GPU call)
 };
 
 namespace {
@@ -827,7 +828,12 @@ t2r_status t2r_env_count(const t2r_ctx* c, int32_t* n_env, int64_t* total_verts)
   return T2R_OK;
 }
 
-static int block_of(const t2r_ctx* c) { return c->opts.block_size ? c->opts.block_size : 256; }
+// Workgroup shape (one workgroup per env): automatic = 512 threads while the envs
+// do not fill every compute unit at one workgroup each, else 256 (two per CU).
+static int block_of(const t2r_ctx* c) {
+  if (c->opts.block_size) return c->opts.block_size;
+  return (int)c->envs.size() <= c->n_cu ? 512 : 256;
+}
 
 static StepParams step_params(t2r_ctx* c) {
   StepParams P{};
@@ -1352,6 +1358,9 @@ t2r_status commit(t2r_ctx* c) {
     HIP_TRY(c, hipGetDevice(&dev));
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
       c->clock_khz = (double)khz;
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+      c->n_cu = cu;
   }
   t2r_status s;
   for (auto& g : c->gels)
