@@ -564,6 +564,51 @@ def test_tape_limits():
     torch.cuda.synchronize()
 
 
+def test_c5_sampled_gradients_match_oracle_at_full_size():
+    """The calibration-gradient workload at full size and in the bench's launch
+    shape (64 envs of the 5k gel, peg, 10 press + 10 shear steps with friction,
+    automatic block shape, FP64): the gradient over the last five recorded steps
+    (all sliding, friction lag active) of two sampled envs against the oracle's
+    sparse-solve sequence adjoint at the GPU's own states."""
+    t2r = _gpu()
+    from oracle.adjoint import adjoint_sequence
+    from paper_2603_28475_amd.autograd import offset_poses
+    from scenes.configs import adjoint_peg_5k
+    w = adjoint_peg_5k(n_envs=64)
+    sim = _build(t2r, w, tol=1e-8, precision=0, max_iters=50000)
+    n = len(w.envs)
+    th0 = np.array([[e.E, e.nu, e.mu_f, *e.extra["theta0"]["dt"], *e.extra["theta0"]["dw"]] for e in w.envs])
+    seq = offset_poses(np.stack([e.poses for e in w.envs])[:, 1:].transpose(1, 0, 2), th0)
+    S = seq.shape[0]
+    print("C5 64x5k forward with tape", flush=True)
+    sim.record(S)
+    xs = []
+    for s in range(S):
+        _, st = sim.step(seq[s], want_x=True)
+        torch.cuda.synchronize()
+        assert np.all(st.cpu().numpy() & 1), s
+        xs.append(sim.x.cpu().numpy().copy())
+    W = 5
+    n_m = sim.n_m[0]
+    rng = np.random.default_rng(12)
+    du = np.zeros((W, n * n_m, 3))
+    du[-1] = 0.1 * rng.standard_normal(du[-1].shape)
+    du[-3] = 0.05 * rng.standard_normal(du[-3].shape)
+    print("C5 backward over the last 5 steps", flush=True)
+    g = sim.backward_sequence(du).cpu().numpy()
+    stats = sim.stats()
+    assert all(x["status"] & 1 for x in stats)
+    nv = sim.n_v[0]
+    for e in (0, 37):
+        print(f"C5 env {e}: oracle sequence adjoint", flush=True)
+        gel, ind, prob = _oracle_problem(w, w.envs[e])
+        states = [xs[k][e * nv:(e + 1) * nv] for k in range(S - W - 1, S)]
+        poses = seq[S - W - 1:S, e]
+        ref = adjoint_sequence(prob, states, poses, du[:, e * n_m:(e + 1) * n_m])
+        scale = np.abs(ref).max()
+        assert np.all(np.abs(g[e] - ref) <= 1e-6 * np.maximum(np.abs(ref), 1e-3 * scale)), (e, g[e], ref)
+
+
 def _certify_equilibrium(w, env, pose, x, bound=1e-6):
     """The oracle's Newton started from x must not move: x is a minimiser of Pi."""
     from oracle.newton import newton_solve
