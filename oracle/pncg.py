@@ -3,7 +3,9 @@ Test infrastructure only.
 
 From Supp. A (eqs. dk_direction and step_size) with these readings:
   * P_k = diag(H(x_k))^-1, re-evaluated at every iterate, from the exact
-    (unprojected) diagonal; entries are floored at 1e-12 mu max_v sum_e V_e |g_i|^2
+    (unprojected) diagonal with each contact pair's contribution clamped at
+    zero (StepProblem.precond_diag: close pairs make the exact entry negative
+    in the tangential directions); entries are floored at 1e-12 mu max_v sum_e V_e |g_i|^2
     (a fixed fraction of the largest rest-state stiffness of a free vertex) so
     the inverse exists; the floor is per env, not per iterate, so the kernels
     can apply P in the same pass that finishes diag.
@@ -18,8 +20,10 @@ From Supp. A (eqs. dk_direction and step_size) with these readings:
     conservative CCD step over pairs closer than 2 dhat.
   * The trial point is accepted when it is feasible (every J > 0, every
     d > 0) and, if armijo is on, Pi drops by at least 1e-4 alpha |g^T p| up to
-    a rounding guard 1e-13 mu sum_e V_e (a fixed multiple of the energy scale, so
-    that rounding noise in Pi cannot stall the search near convergence);
+    a rounding guard 1e-13 (mu sum_e V_e + |Pi|) (the elastic energy scale plus
+    the energy's magnitude, which barrier terms of close pairs dominate in
+    contact, so that rounding noise in Pi cannot stall the search near
+    convergence);
     otherwise alpha is halved, at most 30 times.
   * Convergence: |P g|_inf <= tol (mm), the Jacobi-Newton displacement estimate.
 """
@@ -38,7 +42,7 @@ MAX_HALVINGS = 30
 
 
 def _precond(prob, x, free):
-    dg = prob.diag(x)
+    dg = prob.precond_diag(x)
     floor = DIAG_FLOOR * prob.diag_scale
     P = 1.0 / np.maximum(dg, floor)
     P[~free] = 0.0
@@ -80,7 +84,7 @@ def pncg_solve(prob, x0, tol=1e-6, max_iters=100000, armijo=True, record=None):
             xt = x + alpha * p
             Et = prob.energy(xt)
             if np.isfinite(Et) and (not armijo or
-                                    Et <= E + ARMIJO_C * alpha * gp + ENERGY_GUARD * prob.energy_ref):
+                                    Et <= E + ARMIJO_C * alpha * gp + ENERGY_GUARD * (prob.energy_ref + abs(E))):
                 ok = True
                 break
             alpha *= 0.5

@@ -258,13 +258,14 @@ class StepProblem:
         return out
 
     def _blocks(self, x, project):
-        """Yield (dof_index (n,m), blocks (n,m,m)) for every Hessian contribution."""
+        """Yield (term, dof_index (n,m), blocks (n,m,m)) for every Hessian
+        contribution; term is 'elastic', 'barrier' or 'friction'."""
         g = self.gel
         He = element_hessian(x, g.tets, g.Dm_inv, g.vol, self.mu, self.lam)
         if project:
             He = psd_project(He)
         dof = (3 * g.tets[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 12)
-        yield dof, He
+        yield "elastic", dof, He
         pairs, res = self.active(x)
         if len(pairs["idx"]):
             d, grad, Hd = distance_derivatives(res["Z"], res["c"], res["Cw"], res["k"])
@@ -278,7 +279,7 @@ class StepProblem:
             if project:
                 Hb = psd_project(Hb)
             dof = (3 * np.where(gel_pt, pairs["idx"], 0)[:, :, None] + np.arange(3)).reshape(-1, 12)
-            yield dof, Hb
+            yield "barrier", dof, Hb
         if self.lag is not None and len(self.lag["lam"]):
             gel_pt, gid, TD, s = self._friction_terms(x)
             eps = self.eps_v
@@ -295,12 +296,12 @@ class StepProblem:
             if project:
                 Hf = psd_project(Hf)
             dof = (3 * gid[:, :, None] + np.arange(3)).reshape(-1, 12)
-            yield dof, Hf
+            yield "friction", dof, Hf
 
     def hessian(self, x, project=True):
         n = 3 * self.nv
         rows, cols, vals = [], [], []
-        for dof, H in self._blocks(x, project):
+        for _, dof, H in self._blocks(x, project):
             m = dof.shape[1]
             rows.append(np.repeat(dof, m, axis=1).ravel())
             cols.append(np.tile(dof, (1, m)).ravel())
@@ -311,15 +312,30 @@ class StepProblem:
     def diag(self, x):
         """Exact (unprojected) diagonal of the Hessian, (N_v, 3)."""
         out = np.zeros(3 * self.nv)
-        for dof, H in self._blocks(x, project=False):
+        for _, dof, H in self._blocks(x, project=False):
             np.add.at(out, dof, np.einsum("nii->ni", H))
+        return out.reshape(-1, 3)
+
+    def precond_diag(self, x):
+        """Diagonal of the Jacobi preconditioner P = diag(H)^-1 (Supp. A), (N_v, 3):
+        the exact diagonal with each contact pair's contribution to an entry
+        clamped at zero. For a close pair kappa b'(d) d^2d/dx^2 is negative in the
+        directions tangent to the contact, and outweighs kappa b''(d) (dd/dx)^2
+        there, so the exact entry can be negative, which a Jacobi preconditioner
+        cannot use. Elastic and friction contributions are kept as they are."""
+        out = np.zeros(3 * self.nv)
+        for term, dof, H in self._blocks(x, project=False):
+            dd = np.einsum("nii->ni", H)
+            if term == "barrier":
+                dd = np.maximum(dd, 0.0)
+            np.add.at(out, dof, dd)
         return out.reshape(-1, 3)
 
     def curvature(self, x, p):
         """p^T H(x) p with the exact Hessian."""
         pf = np.asarray(p, dtype=np.float64).ravel()
         tot = 0.0
-        for dof, H in self._blocks(x, project=False):
+        for _, dof, H in self._blocks(x, project=False):
             pv = pf[dof]
             tot += float(np.einsum("ni,nij,nj->", pv, H, pv))
         return tot

@@ -101,6 +101,7 @@ struct t2r_ctx {
   double* d_motion = nullptr;
   double* d_pose_lag = nullptr;
   double* d_adj = nullptr;
+  double* d_gap = nullptr;  // [n_env] d_min at the start of each env's previous load step
   bool stepped = false;
   // trajectory tape (t2r_record): tape_cap recorded steps at most, tape_len so far
   double *d_tape_x = nullptr, *d_tape_q = nullptr;
@@ -884,6 +885,7 @@ static StepParams step_params(t2r_ctx* c) {
   P.precision = c->opts.precision;
   P.armijo = c->opts.armijo;
   P.warm_start = c->opts.warm_start;
+  P.gap0 = c->d_gap;
   return P;
 }
 
@@ -1086,6 +1088,7 @@ t2r_status t2r_set_state(t2r_ctx* c, const double* d_state) {
   HIP_TRY(c, t2r_launch_pack_state(&P, d_state, nullptr, c->d_state_off, 0, c->stream));
   // positions changed arbitrarily: every neighbour list must be rebuilt
   HIP_TRY(c, hipMemsetAsync(c->d_lists, 0, c->envs.size() * sizeof(ListState), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_gap, 0, c->envs.size() * sizeof(double), c->stream));
   s = tape_seed(c);
   if (s != T2R_OK) return s;
   c->err.clear();
@@ -1109,6 +1112,7 @@ t2r_status t2r_reset_envs(t2r_ctx* c, const int32_t* ids, int32_t n) {
     HIP_TRY(c, hipMemcpyAsync(c->d_pose_lag + 7 * (size_t)ids[i], e.pose0, 7 * sizeof(double),
                               hipMemcpyHostToDevice, c->stream));  // no motion history
     HIP_TRY(c, hipMemsetAsync(c->d_lists + ids[i], 0, sizeof(ListState), c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d_gap + ids[i], 0, sizeof(double), c->stream));
   }
   s = tape_seed(c);
   if (s != T2R_OK) return s;
@@ -1451,7 +1455,8 @@ t2r_status commit(t2r_ctx* c) {
   c->d_motion = alloc_n<double>(c, c->envs.size());
   c->d_pose_lag = alloc_n<double>(c, 7 * c->envs.size());
   c->d_adj = alloc_n<double>(c, nd);
-  if (!c->d_x || !c->d_xprev || !c->d_g0 || !c->d_g1 || !c->d_diag || !c->d_p || !c->d_pose_prev ||
+  c->d_gap = alloc_n<double>(c, c->envs.size());
+  if (!c->d_gap || !c->d_x || !c->d_xprev || !c->d_g0 || !c->d_g1 || !c->d_diag || !c->d_p || !c->d_pose_prev ||
       !c->d_pairs || !c->d_pair_d || !c->d_outer || !c->d_lists || !c->d_xsnap || !c->d_fric ||
       !c->d_vmap || !c->d_oslot || !c->d_pslot || !c->d_slot_v || !c->d_imap || !c->d_islot_v ||
       !c->d_stats || !c->d_order || !c->d_motion || !c->d_pose_lag || !c->d_adj) {
@@ -1469,6 +1474,7 @@ t2r_status commit(t2r_ctx* c) {
   HIP_TRY(c, hipMemsetAsync(c->d_p, 0, nd * sizeof(double), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_stats, 0, c->envs.size() * sizeof(EnvStats), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_motion, 0, c->envs.size() * sizeof(double), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_gap, 0, c->envs.size() * sizeof(double), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_lists, 0, c->envs.size() * sizeof(ListState), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_vmap, 0, (size_t)vtot * sizeof(int), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_imap, 0, (size_t)std::max(imtot, 1LL) * sizeof(int), c->stream));

@@ -181,6 +181,7 @@ struct StepParams {
   double tol, substep_tol;
   int max_iters, max_substeps, precision, armijo;
   int warm_start;                // extrapolate the previous load step's displacement
+  T2R_G double* gap0;            // [n_env] d_min at the start of the env's previous load step (0: unknown)
   // trajectory tape: entry k holds every env's positions ([sum 3 n_v], the
   // layout of x) and pose ([n_env][7]) after the k-th recorded load step
   // (entry 0: the state when recording started)

@@ -722,7 +722,9 @@ __device__ __forceinline__ double pairs_eval(const View& V, const Shared& S, Til
         if (f.k > 1) u1 = cw_of(f, k, 1) * r[c] + ci * D[1][c];
         const double uMu = u0 * (Mi[0][0] * u0 + Mi[0][1] * u1) + u1 * (Mi[1][0] * u0 + Mi[1][1] * u1);
         const double hdd = (ci * ci - uMu) * invd - gi * gi * invd;
-        const double gval = kap * b1 * gi, dval = kap * (b2 * gi * gi + b1 * hdd);
+        // preconditioner diagonal: the pair's contribution clamped at zero (b' < 0
+        // makes it negative in directions tangent to a close contact)
+        const double gval = kap * b1 * gi, dval = kap * fmax(0.0, b2 * gi * gi + b1 * hdd);
         if constexpr (LDS) {
           atomicAdd(&T.gq[c][v], gval);
           atomicAdd(&T.gd[c][v], dval);
@@ -1636,9 +1638,12 @@ __device__ __forceinline__ int pncg(Solver& s, double tol, int max_iters, int& i
     tock(*s.S, 4, t0);
     bool ok = false;
     double E1 = E0;
+    // rounding guard: the energy sum's rounding noise grows with |Pi| (barrier
+    // terms of close pairs dominate it in contact), on top of the elastic scale
+    const double guard = s.guard + kEnergyGuard * fabs(E0);
     for (int h = 0; h <= kMaxHalvings; ++h) {
       E1 = eval_all(s, x, V.p, alpha, g1, V.diag, feas, nact);
-      if (feas && (!s.armijo || E1 <= E0 + kArmijoC * alpha * gp + s.guard)) { ok = true; break; }
+      if (feas && (!s.armijo || E1 <= E0 + kArmijoC * alpha * gp + guard)) { ok = true; break; }
       alpha *= 0.5;
       ++s.halvings;
     }
@@ -1775,11 +1780,16 @@ __device__ __forceinline__ int load_step(const StepParams& P, int e, Solver& s, 
   // q_{s-1} of this load step (its friction lag pose), kept for the adjoint
   if (threadIdx.x < 7) P.pose_lag[7 * e + threadIdx.x] = q0[threadIdx.x];
   // Warm start: when this step continues the previous one's indenter motion,
-  // solve from x_{s-1} + f (x_{s-1} - x_{s-2}), f the ratio of the motions
-  // (the quasi-static counterpart of the inertial predictor x + h v).
-  double fac = 0.0;
+  // solve from x_{s-1} + f (x_{s-1} - x_{s-2}) (the quasi-static counterpart
+  // of the inertial predictor x + h v), f the ratio of this step's indenter
+  // motion to the part of the previous one that moved the gel: all of it in
+  // contact; if the previous step started out of contact (d_min >= dhat), its
+  // motion less the gap it closed (d_min at its start minus d_min at its end).
+  double fac = 0.0, m_prev = 0.0, m_cur = 0.0;
+  bool cont = false;
   if (P.warm_start) {
-    const double m_prev = ind_motion(qpp, q0, I.r_max), m_cur = ind_motion(q0, q1, I.r_max);
+    m_prev = ind_motion(qpp, q0, I.r_max);
+    m_cur = ind_motion(q0, q1, I.r_max);
     double d1d2 = 0.0, d1 = 0.0, d2 = 0.0, qs = 0.0;
     for (int i = 3; i < 7; ++i) qs += q0[i] * q1[i];
     for (int i = 0; i < 7; ++i) {
@@ -1787,13 +1797,13 @@ __device__ __forceinline__ int load_step(const StepParams& P, int e, Solver& s, 
       const double u = q0[i] - qpp[i], w = b - q0[i];
       d1d2 += u * w; d1 += u * u; d2 += w * w;
     }
-    if (m_prev > 0.0 && m_cur > 0.0 && d1d2 > 0.9 * sqrt(d1 * d2)) fac = m_cur / m_prev;
+    cont = m_prev > 0.0 && m_cur > 0.0 && d1d2 > 0.9 * sqrt(d1 * d2);
   }
-  // keep x_{s-1} for the friction lag and for rollback (g1 holds the warm start)
+  // keep x_{s-1} for the friction lag and for rollback (g1 holds x_{s-1} - x_{s-2})
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
     const double xc = V.x[j], xo = V.xprev[j];
     V.xprev[j] = xc;
-    if (fac > 0.0) V.g1[j] = fma(fac, xc - xo, xc);
+    if (cont) V.g1[j] = xc - xo;
   }
   // friction lag and starting distance at (x_{s-1}, q_{s-1}), from the outer
   // list kept since the last step (rebuilt here if the motion since it was
@@ -1817,10 +1827,19 @@ __device__ __forceinline__ int load_step(const StepParams& P, int e, Solver& s, 
     if (ov) status |= kOverflow;
   }
   st.n_friction = V.nfric;
+  {
+    const double gap_prev = P.gap0[e];  // d_min at the start of the previous step (0: unknown)
+    __syncthreads();                    // read by every thread before it is replaced
+    if (threadIdx.x == 0) P.gap0[e] = dmin_start;
+    if (cont) {
+      const double closed = (gap_prev >= E.dhat && dmin_start > 0.0) ? fmax(0.0, gap_prev - dmin_start) : 0.0;
+      fac = m_cur / fmax(m_prev - closed, 0.25 * m_prev);
+    }
+  }
   bool direct = false;  // the warm start is feasible at q_s: one solve, no intermediate poses
   if (fac > 0.0 && !(status & kOverflow) && dmin_start > 0.0) {
     // take the warm start only if it is feasible at q_{s-1}: J > 0 and d > 0
-    for (int j = threadIdx.x; j < n; j += blockDim.x) V.x[j] = V.g1[j];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) V.x[j] = fma(fac, V.g1[j], V.xprev[j]);
     __syncthreads();
     int feas = 1;
     elem_eval(V, V.x, V.p, 0.0, V.g1, V.diag, *s.T, feas);

@@ -11,6 +11,7 @@ from scipy.optimize import minimize
 from oracle.geometry import slerp_pose
 from oracle.newton import newton_solve
 from oracle.pncg import pncg_solve
+from oracle.problem import StepProblem
 from oracle.sim import build, simulate
 from scenes.configs import micro_press
 
@@ -190,3 +191,39 @@ def test_pncg_reference_reaches_the_newton_minimiser(pressed):
     r = simulate(mesh, ind, env, mode="pncg", tol=1e-10)
     assert np.abs(r.x[-1] - res.x[-1]).max() < 1e-8
     assert np.abs(r.markers[-1] - res.markers[-1]).max() < 1e-8
+
+
+def test_preconditioner_diagonal_clamps_negative_pair_entries():
+    """precond_diag is the exact diagonal with each contact pair's contribution
+    clamped at zero: equal to diag without contact, never below it, positive on
+    the free DOFs, and different from it where a close pair's b' grad^2 d term
+    makes the exact entry smaller (edge-edge pairs of a pressed plate)."""
+    from oracle.sim import build, simulate
+    from scenes.configs import micro_press
+    q = np.array([0.99996192, 0.00610865, 0.00436331, 0.0])
+    w = micro_press(mesh="micro3", indenter="plate", depth=0.08, n_steps=2, xy=(0.1, -0.05),
+                    q=tuple(q / np.linalg.norm(q)))
+    env = w.envs[0]
+    r = simulate(w.meshes[env.mesh], w.indenters[env.indenter], env, mode="newton", tol=1e-12)
+    gel, _, prob = build(w.meshes[env.mesh], w.indenters[env.indenter], env)
+    free = ~gel.fixed
+    prob.set_pose(env.poses[0])                       # clear of the gel: no pair
+    assert np.array_equal(prob.precond_diag(gel.X), prob.diag(gel.X))
+    # the pressed state with the plate lowered by 0.7 d_min: every pair much
+    # closer than at equilibrium (a state a solve passes through)
+    x = r.x[-1]
+    prob.set_pose(env.poses[-1])
+    pose = env.poses[-1].copy()
+    pose[2] -= 0.7 * prob.d_min(x)
+    prob.set_pose(pose)
+    assert len(prob.active(x)[0]["idx"]) > 0 and prob.d_min(x) > 0.0
+    dg, pd = prob.diag(x), prob.precond_diag(x)
+    assert np.all(pd >= dg - 1e-12 * np.abs(dg).max())
+    assert np.all(pd[free] > 0.0)
+    assert np.any(pd[free] > dg[free] + 1e-9 * np.abs(dg).max())   # the clamp binds
+    # what is left after removing the elastic part is a sum of clamped pair entries
+    el = StepProblem(prob.gel, prob.ind, 1.0, 0.25, 0.0, prob.eps_v, prob.dhat, prob.kappa)
+    el.mu, el.lam = prob.mu, prob.lam
+    el.set_pose(np.array([0.0, 0.0, 1e3, 1.0, 0.0, 0.0, 0.0]))     # indenter far away
+    assert len(el.active(x)[0]["idx"]) == 0
+    assert np.all(pd - el.diag(x) >= -1e-12 * np.abs(dg).max())
