@@ -79,7 +79,8 @@ enum {
 typedef struct { double E, nu, mu_f, eps_v, dhat, kappa; } t2r_material;
 
 /* Solver options.
- *   tol           stop a solve when |P g|_inf <= tol (mm), P = diag(H)^-1
+ *   tol           stop a solve when |P g|_inf <= tol (mm), P = diag(H)^-1 (each
+ *                 contact pair's contribution to an entry clamped at zero)
  *   substep_tol   tolerance of intermediate continuation solves (<= 0: use tol)
  *   max_iters     PNCG iterations per solve
  *   max_substeps  continuation solves per load step
@@ -92,8 +93,11 @@ typedef struct { double E, nu, mu_f, eps_v, dhat, kappa; } t2r_material;
  *                 per CU, for few large envs); 0 = automatic: 512 while the envs
  *                 do not outnumber the compute units, else 256
  *   warm_start    1: when a load step continues the previous step's indenter
- *                 motion, start from x_{s-1} + f (x_{s-1} - x_{s-2}) (f = ratio of
- *                 the motions) if that point is feasible; 0: start from x_{s-1} */
+ *                 motion, start from x_{s-1} + f (x_{s-1} - x_{s-2}) if that point
+ *                 is feasible (f = this step's motion over the previous one's,
+ *                 less the gap it closed when it started out of contact), and
+ *                 solve directly at the final pose when that start is clear of
+ *                 the indenter there; 0: start from x_{s-1} */
 typedef struct {
   double tol;
   double substep_tol;
@@ -241,8 +245,9 @@ t2r_status t2r_step_sequence(t2r_ctx* ctx, int32_t n_steps, const double* d_pose
  * d_x_lag is not NULL, and the energy is evaluated at (d_x, pose).
  *   d_x, d_x_lag, d_p    device [n_v][3]; d_p may be NULL (curvature then 0)
  *   pose, pose_lag       host [7]
- *   d_grad, d_diag       device [n_v][3] or NULL: gradient and exact diagonal of
- *                        the Hessian (fixed vertices: 0 and 1)
+ *   d_grad, d_diag       device [n_v][3] or NULL: gradient, and the diagonal of the
+ *                        Hessian with each contact pair's contribution clamped at
+ *                        zero (the Jacobi preconditioner's; fixed vertices: 0 and 1)
  *   d_scalars            device [8] or NULL: Pi, p^T H p, d_min, active pairs,
  *                        feasible (1/0), candidate pairs, friction pairs, Pi_elastic
  * Synchronises the stream before returning. Returns T2R_E_NOMEM (outputs not
