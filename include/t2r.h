@@ -318,6 +318,13 @@ t2r_status t2r_record(t2r_ctx* ctx, int32_t max_steps);
 /* Load steps on the tape (-1: not recording). */
 t2r_status t2r_tape_length(const t2r_ctx* ctx, int32_t* n_steps);
 
+/* Copies tape entry `entry` (0: the state when recording started; k: after
+ * the k-th recorded load step) into d_state, device [t2r_state_size] in the
+ * layout of t2r_get_state (per env: positions [n_v][3], then the pose [7]).
+ * Errors: T2R_E_STATE without a tape, T2R_E_ARG for an entry outside
+ * [0, t2r_tape_length]. Asynchronous. */
+t2r_status t2r_tape_read(t2r_ctx* ctx, int32_t entry, double* d_state);
+
 /* Gradient of a loss L on the marker displacements of the last n_steps
  * recorded load steps with respect to each env's theta (as t2r_backward; the
  * pose offset applies to every pose of the window, including the lag pose of

@@ -1183,6 +1183,19 @@ t2r_status t2r_record(t2r_ctx* c, int32_t max_steps) {
   return T2R_OK;
 }
 
+t2r_status t2r_tape_read(t2r_ctx* c, int32_t entry, double* d_state) {
+  if (!c || !d_state) return T2R_E_ARG;
+  if (!c->d_tape_x) return fail(c, T2R_E_STATE, "no tape: call t2r_record before the load steps");
+  if (entry < 0 || entry > c->tape_len)
+    return fail(c, T2R_E_ARG, "entry must be in [0, %d], got %d", c->tape_len, entry);
+  StepParams P = step_params(c);
+  P.x = c->d_tape_x + (size_t)entry * (size_t)c->total_dofs;
+  P.pose_prev = c->d_tape_q + (size_t)entry * 7 * c->envs.size();
+  HIP_TRY(c, t2r_launch_pack_state(&P, nullptr, d_state, c->d_state_off, 1, c->stream));
+  c->err.clear();
+  return T2R_OK;
+}
+
 t2r_status t2r_tape_length(const t2r_ctx* c, int32_t* n_steps) {
   if (!c || !n_steps) return T2R_E_ARG;
   *n_steps = c->d_tape_x ? c->tape_len : -1;

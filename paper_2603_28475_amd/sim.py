@@ -90,6 +90,21 @@ class Sim:
         state (0 stops recording); see t2r_record."""
         self.ctx.record(max_steps)
 
+    def tape_state(self, entry):
+        """Positions (sum n_v, 3) and poses (n_env, 7) of tape entry `entry` (see
+        t2r_tape_read), as host arrays (synchronises this Sim's stream)."""
+        import numpy as np
+        st = torch.empty(self.ctx.state_size(), dtype=torch.float64, device=self.device)
+        self.ctx.tape_read(entry, st)
+        self.stream.synchronize()
+        a = st.cpu().numpy()
+        xs, qs, off = [], [], 0
+        for nv in self.n_v:
+            xs.append(a[off:off + 3 * nv].reshape(nv, 3))
+            qs.append(a[off + 3 * nv:off + 3 * nv + 7])
+            off += 3 * nv + 7
+        return np.concatenate(xs), np.stack(qs)
+
     def backward_sequence(self, dL_du):
         """dL/dtheta (n_env, 9) of a loss on the markers of the last S recorded load
         steps; dL_du: (S, sum n_m, 3), oldest step first (see t2r_backward_sequence).

@@ -81,6 +81,7 @@ SIGNATURES = [
     ("t2r_record", C.c_int32, [_P, C.c_int32]),
     ("t2r_tape_length", C.c_int32, [_P, C.POINTER(C.c_int32)]),
     ("t2r_backward_sequence", C.c_int32, [_P, C.c_int32, _P, _P]),
+    ("t2r_tape_read", C.c_int32, [_P, C.c_int32, _P]),
 ]
 
 
@@ -267,6 +268,9 @@ class Context:
         n = C.c_int32(0)
         self.check(lib.t2r_tape_length(self.handle, C.byref(n)))
         return n.value
+
+    def tape_read(self, entry, d_state):
+        self.check(lib.t2r_tape_read(self.handle, int(entry), _tptr(d_state)))
 
     def backward_sequence(self, n_steps, d_dL_du, d_grad):
         self.check(lib.t2r_backward_sequence(self.handle, int(n_steps), _tptr(d_dL_du), _tptr(d_grad)))

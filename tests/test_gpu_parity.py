@@ -611,6 +611,83 @@ def test_c5_sampled_gradients_match_oracle_at_full_size():
         assert np.all(np.abs(g[e] - ref) <= 1e-6 * np.maximum(np.abs(ref), 1e-3 * scale)), (e, g[e], ref)
 
 
+def _newton_correction(prob, x):
+    """|H^-1 g|_inf at x with the oracle's projected Hessian: the size of the
+    oracle's Newton step from x, a bound on the distance to its equilibrium
+    that does not depend on the GPU's stopping rule."""
+    import scipy.sparse.linalg as spla
+    free = np.repeat(~prob.gel.fixed, 3)
+    H = prob.hessian(x, project=True).tocsc()[free][:, free]
+    g = prob.gradient(x).ravel()[free]
+    return float(np.abs(spla.spsolve(H, g)).max())
+
+
+def _certify_sampled(w, sim, markers, envs, k_prev, k_last, bar):
+    """Oracle checks of sampled envs at tape entry k_last (lag at k_prev): the
+    oracle's marker map of the GPU positions equals the GPU markers, the state is
+    feasible, and the oracle's Newton correction is within `bar` mm."""
+    x_prev, q_prev = sim.tape_state(k_prev)
+    x_last, q_last = sim.tape_state(k_last)
+    off_v = np.cumsum([0] + list(sim.n_v))
+    off_m = np.cumsum([0] + list(sim.n_m))
+    for e in envs:
+        env = w.envs[e]
+        print(f"{w.name} env {e} ({env.mesh}, {env.indenter}): oracle certificate", flush=True)
+        gel, ind, prob = _oracle_problem(w, env)
+        xp, xl = x_prev[off_v[e]:off_v[e + 1]], x_last[off_v[e]:off_v[e + 1]]
+        assert np.allclose(q_last[e], env.poses[-1], atol=1e-12)
+        prob.set_lag(xp, q_prev[e])
+        prob.set_pose(q_last[e])
+        assert np.abs(gel.markers(xl) - markers[off_m[e]:off_m[e + 1]]).max() <= 1e-12
+        assert prob.feasible(xl)
+        assert len(prob.active(xl)[0]["idx"]) > 0
+        corr = _newton_correction(prob, xl)
+        assert corr <= bar, (e, corr)
+
+
+def _bench_shape_run(sim, w):
+    """The bench's launch shape: load step 1 in one launch, then steps 2..S in one
+    recorded launch; returns the last step's markers."""
+    poses = np.stack([e.poses for e in w.envs])
+    sim.step_sequence(poses[:, 1:2].transpose(1, 0, 2))
+    S = poses.shape[1] - 2
+    sim.record(S)
+    m, st = sim.step_sequence(np.ascontiguousarray(poses[:, 2:].transpose(1, 0, 2)))
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() & 1)
+    return m[-1].cpu().numpy(), S
+
+
+def test_c3_full_size_sampled_envs_are_oracle_equilibria():
+    """The headline workload at full size in the bench's launch shape (2048 envs of
+    the 5k gel, peg, friction, mixed precision, tol 1e-6 mm, 256-thread
+    workgroups): every env converges, and three sampled envs' final states are
+    certified by the oracle (markers, feasibility, Newton correction within the
+    1e-3 mm mixed-precision bar, friction lag at the GPU's previous state)."""
+    t2r = _gpu()
+    from scenes.configs import peg_batch_5k
+    w = peg_batch_5k(n_envs=2048)
+    print("C3 2048x5k bench-shape launch", flush=True)
+    sim = _build(t2r, w, tol=1e-6, precision=1, block_size=256)
+    m, S = _bench_shape_run(sim, w)
+    _certify_sampled(w, sim, m, (0, 1023, 2047), S - 1, S, 1e-3)
+
+
+def test_c4_full_size_sampled_envs_are_oracle_equilibria():
+    """The uneven batch at full size in the bench's launch shape (512 envs over the
+    2k, 5k and 12k gels and three indenters, mixed precision, 512-thread
+    workgroups as the autotuner picks): every env converges, and one env of each
+    gel class is certified by the oracle as in the headline test."""
+    t2r = _gpu()
+    from scenes.configs import mixed_batch
+    w = mixed_batch(n_envs=512)
+    print("C4 512 mixed bench-shape launch", flush=True)
+    sim = _build(t2r, w, tol=1e-6, precision=1, block_size=512)
+    m, S = _bench_shape_run(sim, w)
+    first = [next(i for i, e in enumerate(w.envs) if e.mesh == k) for k in ("2k", "5k", "12k")]
+    _certify_sampled(w, sim, m, first, S - 1, S, 1e-3)
+
+
 def _certify_equilibrium(w, env, pose, x, bound=1e-6):
     """The oracle's Newton started from x must not move: x is a minimiser of Pi."""
     from oracle.newton import newton_solve
