@@ -58,10 +58,15 @@ def parse():
     return ap.parse_args()
 
 
+KERNEL_SOURCES = ("t2r_internal.h", "t2r_kernels.hip", "t2r_math.h")
+
+
 def source_hash() -> str:
+    """Hash of the sources the device code is compiled from: a traffic profile
+    stays valid while they are unchanged (host-only changes do not move it)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_28475_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
