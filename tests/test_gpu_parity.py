@@ -688,6 +688,38 @@ def test_c4_full_size_sampled_envs_are_oracle_equilibria():
     _certify_sampled(w, sim, m, first, S - 1, S, 1e-3)
 
 
+def test_c2_full_size_press_and_shear_certified_by_oracle():
+    """The single large env at full size (12,177-vertex gel, tilted peg, 20 press
+    steps to 0.8 mm then 20 shear steps of 0.5 mm with friction 0.5, FP64, tol
+    1e-6 mm) in one recorded launch: every step converges, and the last press
+    step and the last shear step are certified by the oracle (marker map,
+    feasibility, Newton correction within 1e-4 mm, friction lag at the GPU's
+    previous state)."""
+    t2r = _gpu()
+    from scenes.configs import peg_press_shear_12k
+    w = peg_press_shear_12k()
+    env = w.envs[0]
+    print("C2 12k press + shear, one launch", flush=True)
+    sim = _build(t2r, w, tol=1e-6, precision=0, max_iters=100000)
+    S = env.poses.shape[0] - 1
+    sim.record(S)
+    m, st = sim.step_sequence(np.ascontiguousarray(env.poses[1:][:, None, :]))
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() & 1)
+    m = m.cpu().numpy()
+    for k in (20, S):
+        wk = _cut_schedule(w, k)
+        _certify_sampled(wk, sim, m[k - 1], (0,), k - 1, k, 1e-4)
+
+
+def _cut_schedule(w, k):
+    """The workload with its env's schedule cut after load step k (so that the
+    certificate's pose check refers to step k)."""
+    import dataclasses
+    e = w.envs[0]
+    return dataclasses.replace(w, envs=[dataclasses.replace(e, poses=e.poses[:k + 1])])
+
+
 def _certify_equilibrium(w, env, pose, x, bound=1e-6):
     """The oracle's Newton started from x must not move: x is a minimiser of Pi."""
     from oracle.newton import newton_solve
