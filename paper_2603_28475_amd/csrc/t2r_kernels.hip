@@ -69,6 +69,10 @@ union Tile {
     double g[3][kTileVerts];
     double d[3][kTileVerts];
   };
+  struct {                     // curvature pass, mixed precision: x and p rounded to float
+    float fx[3][kTileVerts];
+    float fp[3][kTileVerts];
+  };
   struct {
     double gx[3][kGelSlots];   // gel slot positions
     double gq[3][kGelSlots];   // gradient sums (eval) or p (curvature, CCD)
@@ -400,6 +404,20 @@ __device__ __forceinline__ double elem_eval(const View& V, const double* x, cons
                  : elem_eval_impl<false>(V, x, p, alpha, gout, dout, T, feasible);
 }
 
+// Stages one vertex coordinate of x and p for the curvature pass: as float in
+// mixed precision (p^T H p only sets the trial step; float positions of a
+// ~10 mm gel are within 1e-6 mm), else as double.
+template <bool MIXED>
+__device__ __forceinline__ void stage_xp(Tile& T, int c, int i, double xv, double pv) {
+  if constexpr (MIXED) {
+    T.fx[c][i] = (float)xv;
+    T.fp[c][i] = (float)pv;
+  } else {
+    T.x[c][i] = xv;
+    T.p[c][i] = pv;
+  }
+}
+
 // p^T H_elastic p at x (thread partial); same pipeline as the eval pass.
 template <bool MIXED>
 __device__ __forceinline__ double elem_curv_impl(const View& V, const double* x, const double* p, Tile& T) {
@@ -428,10 +446,7 @@ __device__ __forceinline__ double elem_curv_impl(const View& V, const double* x,
   for (int s = 0; s < kSlots; ++s)
     if (cur.fl[s] >= 0)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        T.x[c][threadIdx.x + s * B] = a[s][c];
-        T.p[c][threadIdx.x + s * B] = b[s][c];
-      }
+      for (int c = 0; c < 3; ++c) stage_xp<MIXED>(T, c, threadIdx.x + s * B, a[s][c], b[s][c]);
   __syncthreads();
   for (int tile = 0; tile < NT; ++tile) {
     const int t0 = G.tile_tet[tile], t1 = G.tile_tet[tile + 1];
@@ -455,8 +470,13 @@ __device__ __forceinline__ double elem_curv_impl(const View& V, const double* x,
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          Ds[r * 3 + k] = (Rl)(T.x[r][l[k + 1]] - T.x[r][l[0]]);
-          dDs[r * 3 + k] = (Rl)(T.p[r][l[k + 1]] - T.p[r][l[0]]);
+          if constexpr (MIXED) {
+            Ds[r * 3 + k] = T.fx[r][l[k + 1]] - T.fx[r][l[0]];
+            dDs[r * 3 + k] = T.fp[r][l[k + 1]] - T.fp[r][l[0]];
+          } else {
+            Ds[r * 3 + k] = T.x[r][l[k + 1]] - T.x[r][l[0]];
+            dDs[r * 3 + k] = T.p[r][l[k + 1]] - T.p[r][l[0]];
+          }
         }
       curv += (double)tet_curvature<Rl>(Ds, dDs, tc.Dm, tc.vol, (Rl)E.mu, (Rl)E.lam);
       tc = tn;
@@ -468,10 +488,7 @@ __device__ __forceinline__ double elem_curv_impl(const View& V, const double* x,
       for (int s = 0; s < kSlots; ++s)
         if (nxt.fl[s] >= 0)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            T.x[c][threadIdx.x + s * B] = a[s][c];
-            T.p[c][threadIdx.x + s * B] = b[s][c];
-          }
+          for (int c = 0; c < 3; ++c) stage_xp<MIXED>(T, c, threadIdx.x + s * B, a[s][c], b[s][c]);
       __syncthreads();
     }
     cur = nxt;
