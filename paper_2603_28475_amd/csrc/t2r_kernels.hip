@@ -1261,27 +1261,71 @@ __device__ __forceinline__ double ind_motion(const double a[7], const double b[7
 
 // Largest surface-vertex displacement since each snapshot and largest |p| on the
 // surface (p may be null): out = {outer, inner, p}.
+// Motion of the gel surface relative to the indenter since each list was built
+// (out[0]: outer list, out[1]: inner list) and max |p| over the surface
+// (out[2]). A surface vertex's relative motion is its distance from its
+// snapshot position carried along with the indenter's rigid motion since the
+// build, M (g - t_b) + t (M = R R_b^T). For a gel point g and an indenter
+// point y at distance D at the build, their distance changes by at most that
+// motion (a convex combination over the primitive's vertices) plus
+// |(M - I)(y - g)| <= theta D, theta the rotation angle since the build; a
+// pair beyond the list radius r then stays beyond r - (motion + theta r), so
+// theta r is added to each list's figure.
 __device__ __forceinline__ void surf_motion(Solver& s, const double* x, const double* p, double out[3]) {
   const GelDev& G = *s.V.G;
   const int nv = G.n_v, ns = G.n_sv;
+  const Shared& S = *s.S;
+  double Mo[9], Mi[9], to[3], ti[3];
+  double th[2];
+  {
+    const double* pb[2] = {s.L->pose_o, s.L->pose_i};
+    double* Mx[2] = {Mo, Mi};
+    double* tx[2] = {to, ti};
+    for (int l = 0; l < 2; ++l) {
+      double Rb[9];
+      quat_to_R(pb[l] + 3, Rb);
+      #pragma unroll
+      for (int r = 0; r < 3; ++r)
+        #pragma unroll
+        for (int c = 0; c < 3; ++c)
+          Mx[l][r * 3 + c] = S.R[r * 3 + 0] * Rb[c * 3 + 0] + S.R[r * 3 + 1] * Rb[c * 3 + 1] +
+                             S.R[r * 3 + 2] * Rb[c * 3 + 2];
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) tx[l][c] = pb[l][c];
+      double qa = 0.0, na = 0.0, nb = 0.0;
+      for (int i = 3; i < 7; ++i) { qa += pb[l][i] * S.pose[i]; na += pb[l][i] * pb[l][i]; nb += S.pose[i] * S.pose[i]; }
+      th[l] = 2.0 * acos(fmin(1.0, fabs(qa) / sqrt(na * nb)));
+    }
+  }
   double m[3] = {0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < ns; i += blockDim.x) {
     const int v = G.surf_v[i];
-    double a = 0.0, b = 0.0, c2 = 0.0;
+    double go[3], gi[3], xv[3];
+    double c2 = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double xv = x[c * nv + v];
-      const double da = xv - s.xs_o[c * ns + i], db = xv - s.xs_i[c * ns + i];
+      xv[c] = x[c * nv + v];
+      go[c] = s.xs_o[c * ns + i] - to[c];
+      gi[c] = s.xs_i[c * ns + i] - ti[c];
+      if (p) { const double pv = p[c * nv + v]; c2 += pv * pv; }
+    }
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const double da = xv[r] - (Mo[r * 3 + 0] * go[0] + Mo[r * 3 + 1] * go[1] + Mo[r * 3 + 2] * go[2] + S.t[r]);
+      const double db = xv[r] - (Mi[r * 3 + 0] * gi[0] + Mi[r * 3 + 1] * gi[1] + Mi[r * 3 + 2] * gi[2] + S.t[r]);
       a += da * da;
       b += db * db;
-      if (p) { const double pv = p[c * nv + v]; c2 += pv * pv; }
     }
     m[0] = fmax(m[0], a);
     m[1] = fmax(m[1], b);
     m[2] = fmax(m[2], c2);
   }
   block_reduce<0, 3>(m, *s.S);
-  for (int k = 0; k < 3; ++k) out[k] = sqrt(m[k]);
+  const double dh = s.V.E->dhat;
+  out[0] = sqrt(m[0]) + th[0] * (dh + s.buffer_out);
+  out[1] = sqrt(m[1]) + th[1] * (dh + s.buffer);
+  out[2] = sqrt(m[2]);
 }
 
 __device__ __forceinline__ void snapshot(Solver& s, const double* x, double* dst) {
@@ -1441,11 +1485,9 @@ __device__ __forceinline__ bool refilter(Solver& s, const double* x) {
 // Makes both lists valid at (x, current pose) for a coming motion of at most
 // `step` of any surface point. Returns false on a list overflow.
 __device__ __forceinline__ bool ensure_lists(Solver& s, const double* x, double step, const double m[2]) {
-  View& V = s.V;
-  const double r_max = V.I->r_max;
   const int vo = s.L->valid_o, vi = s.L->valid_i;
-  const double mo = vo ? m[0] + ind_motion(s.L->pose_o, s.S->pose, r_max) : kInf;
-  const double mi = vi ? m[1] + ind_motion(s.L->pose_i, s.S->pose, r_max) : kInf;
+  const double mo = vo ? m[0] : kInf;  // relative motions since the builds (surf_motion)
+  const double mi = vi ? m[1] : kInf;
   __syncthreads();
   if (!(mo + step <= s.buffer_out - s.buffer)) {
     if (!rebuild_outer(s, x)) return false;
