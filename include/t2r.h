@@ -287,7 +287,7 @@ t2r_status t2r_set_opts(t2r_ctx* ctx, const t2r_solver_opts* opts);
  * coefficient and a rigid offset of the indenter that moves every indenter
  * point y to exp([dw]x)(y - t) + t + dt (t the indenter origin at the current
  * pose), taken at dt = dw = 0. Implicit differentiation at the equilibrium
- * (the spec adjoint; the paper itself calibrates without gradients):
+ * (the paper itself calibrates without gradients):
  *   H lambda = dL/dx  (exact Hessian of the step energy, free DOFs; Jacobi-
  *                      preconditioned CG to a relative residual of 1e-10, at
  *                      most max_iters iterations, matrix-free on the GPU),
