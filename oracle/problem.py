@@ -72,6 +72,23 @@ class StepProblem:
         self.pose = None
         self.Yw = None
         self.lag = None
+        self.inertia = None
+
+    # ---------------------------------------------------------------- inertia
+    def set_inertia(self, w, xhat):
+        """Dynamic form (Supp. A, eq. ipc_energy with its inertia term): adds
+        1/2 sum_v w_v |x_v - xhat_v|^2, w_v = m_v / h^2 with the lumped mass m_v
+        and xhat = x^t + h v^t the inertial prediction. None turns it off."""
+        self.inertia = None if w is None else (np.asarray(w, dtype=np.float64),
+                                               np.asarray(xhat, dtype=np.float64))
+
+    def _inertia_energy(self, x):
+        if self.inertia is None:
+            return 0.0
+        w, xh = self.inertia
+        free = ~self.gel.fixed
+        r = (x - xh)[free]
+        return 0.5 * float(np.sum(w[free] * np.einsum("nd,nd->n", r, r)))
 
     # ---------------------------------------------------------------- pose / lag
     def set_pose(self, pose):
@@ -221,7 +238,7 @@ class StepProblem:
         if self.lag is not None and len(self.lag["lam"]):
             _, _, _, s = self._friction_terms(x)
             Ef = self.mu_f * np.sum(self.lag["lam"] * mollifier(s, self.eps_v))
-        return float(Ee.sum() + Eb + Ef)
+        return float(Ee.sum() + Eb + Ef + self._inertia_energy(x))
 
     def energy_parts(self, x):
         g = self.gel
@@ -254,6 +271,9 @@ class StepProblem:
             w = self.mu_f * self.lag["lam"] * fos
             contrib = (w[:, None, None] * self.lag["a"][:, :, None] * TD[:, None, :]) * gel_pt[:, :, None]
             np.add.at(out, gid, contrib)
+        if self.inertia is not None:
+            wi, xh = self.inertia
+            out += wi[:, None] * (x - xh)
         out[self.gel.fixed] = 0.0
         return out
 
@@ -297,6 +317,11 @@ class StepProblem:
                 Hf = psd_project(Hf)
             dof = (3 * gid[:, :, None] + np.arange(3)).reshape(-1, 12)
             yield "friction", dof, Hf
+        if self.inertia is not None:
+            wi, _ = self.inertia
+            free = np.nonzero(~g.fixed)[0]
+            dof = 3 * free[:, None] + np.arange(3)[None, :]
+            yield "inertia", dof, wi[free][:, None, None] * np.eye(3)[None]
 
     def hessian(self, x, project=True):
         n = 3 * self.nv

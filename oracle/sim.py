@@ -54,16 +54,32 @@ def continuation_increment(prob, x, pose_a, pose_b, tau, d_min):
     return 0.5 * min(prob.dhat, d_min) / rate
 
 
+def lumped_mass(gel):
+    """Per-vertex volume share sum_{e contains v} V_e / 4 (the lumped mass over the density)."""
+    m = np.zeros(gel.n_v)
+    np.add.at(m, gel.tets, np.repeat(gel.vol[:, None] / 4.0, 4, axis=1))
+    return m
+
+
 def simulate(gel_mesh, indenter, env, mode="newton", tol=None, n_steps=None,
-             max_substeps=10000, pncg_kw=None, x_start=None, verbose=False):
-    """Run the load steps of `env` (a scenes.EnvSpec). mode: 'newton' or 'pncg'."""
+             max_substeps=10000, pncg_kw=None, x_start=None, verbose=False, dynamic=None):
+    """Run the load steps of `env` (a scenes.EnvSpec). mode: 'newton' or 'pncg'.
+    dynamic: None (quasi-static) or dict(density=rho, dt=h) for the implicit-Euler
+    form: each step adds 1/2 |x - xhat|^2_M / h^2 with the lumped mass M = rho V/4
+    per vertex and xhat = x^t + h v^t, and then v = (x - x^t) / h (v^0 = 0)."""
     gel, ind, prob = build(gel_mesh, indenter, env)
     poses = np.asarray(env.poses, dtype=np.float64)
     S = poses.shape[0] - 1 if n_steps is None else n_steps
     x = gel.X.copy() if x_start is None else np.array(x_start, dtype=np.float64)
     out = SimResult()
+    vel = np.zeros_like(x)
+    if dynamic is not None:
+        w_dyn = dynamic["density"] * lumped_mass(gel) / dynamic["dt"] ** 2
     for s in range(1, S + 1):
         q0, q1 = poses[s - 1], poses[s]
+        x_t = x.copy()
+        if dynamic is not None:
+            prob.set_inertia(w_dyn, x_t + dynamic["dt"] * vel)
         prob.set_lag(x, q0)
         tau, nsub, iters = 0.0, 0, 0
         while tau < 1.0:
@@ -82,6 +98,9 @@ def simulate(gel_mesh, indenter, env, mode="newton", tol=None, n_steps=None,
                 print(f"step {s} tau={tau:.4f} iters={info['iters']} conv={info['converged']}")
             if nsub >= max_substeps:
                 raise RuntimeError("too many substeps")
+        if dynamic is not None:
+            vel = (x - x_t) / dynamic["dt"]
+            vel[gel.fixed] = 0.0
         out.x.append(x.copy())
         out.markers.append(gel.markers(x))
         out.substeps.append(nsub)
