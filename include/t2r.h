@@ -97,7 +97,17 @@ typedef struct { double E, nu, mu_f, eps_v, dhat, kappa; } t2r_material;
  *                 is feasible (f = this step's motion over the previous one's,
  *                 less the gap it closed when it started out of contact), and
  *                 solve directly at the final pose when that start is clear of
- *                 the indenter there; 0: start from x_{s-1} */
+ *                 the indenter there; 0: start from x_{s-1}
+ *   dynamic       1: implicit-Euler form (Supp. A, eq. ipc_energy with its
+ *                 inertia term): each load step is one time step dt and adds
+ *                 1/2 sum_v m_v / dt^2 |x_v - xhat_v|^2, m_v = density x the
+ *                 vertex's share sum V_e / 4 of its tets' rest volumes,
+ *                 xhat = x^t + dt v^t; after the step v = (x - x^t) / dt (v = 0
+ *                 after t2r_create, t2r_reset_envs and t2r_set_state). 0: the
+ *                 quasi-static form. The adjoint and t2r_eval cover the
+ *                 quasi-static form only.
+ *   dt, density   time step (s) and mass density (t/mm^3, so that forces are in
+ *                 N: 1,100 kg/m^3 = 1.1e-9) of the dynamic form */
 typedef struct {
   double tol;
   double substep_tol;
@@ -108,6 +118,9 @@ typedef struct {
   int32_t armijo;
   int32_t block_size;
   int32_t warm_start;
+  int32_t dynamic;
+  double dt;
+  double density;
 } t2r_solver_opts;
 
 /* Per-environment counters of the last launch (t2r_step or t2r_step_sequence;
@@ -139,7 +152,8 @@ typedef struct {
 } t2r_env_stats;
 
 /* Fills *o with the defaults: tol 1e-6, substep_tol 1e-4, max_iters 20000,
- * max_substeps 1000, precision 0, pair_capacity 0, armijo 1, block_size 0, warm_start 1. */
+ * max_substeps 1000, precision 0, pair_capacity 0, armijo 1, block_size 0, warm_start 1,
+ * dynamic 0, dt 1/60, density 1.1e-9. */
 void t2r_default_opts(t2r_solver_opts* o);
 
 /* Creates a context bound to `hip_stream` (a hipStream_t, or NULL for the null

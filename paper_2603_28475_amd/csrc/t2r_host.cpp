@@ -102,6 +102,7 @@ struct t2r_ctx {
   double* d_pose_lag = nullptr;
   double* d_adj = nullptr;
   double* d_gap = nullptr;  // [n_env] d_min at the start of each env's previous load step
+  double* d_vel = nullptr;  // [sum 3 n_v] velocities of the dynamic form
   bool stepped = false;
   // trajectory tape (t2r_record): tape_cap recorded steps at most, tape_len so far
   double *d_tape_x = nullptr, *d_tape_q = nullptr;
@@ -292,6 +293,9 @@ void t2r_default_opts(t2r_solver_opts* o) {
   o->armijo = 1;
   o->block_size = 0;
   o->warm_start = 1;
+  o->dynamic = 0;
+  o->dt = 1.0 / 60.0;
+  o->density = 1.1e-9;
 }
 
 static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
@@ -303,6 +307,9 @@ static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
   if (o->block_size != 0 && o->block_size != 256 && o->block_size != 512)
     return fail(c, T2R_E_ARG, "block_size must be 0 (256), 256 or 512");
   if (o->warm_start != 0 && o->warm_start != 1) return fail(c, T2R_E_ARG, "warm_start must be 0 or 1");
+  if (o->dynamic != 0 && o->dynamic != 1) return fail(c, T2R_E_ARG, "dynamic must be 0 or 1");
+  if (o->dynamic && (!(o->dt > 0.0) || !isfinite(o->dt) || !(o->density > 0.0) || !isfinite(o->density)))
+    return fail(c, T2R_E_ARG, "the dynamic form needs dt > 0 and density > 0");
   return T2R_OK;
 }
 
@@ -886,6 +893,9 @@ static StepParams step_params(t2r_ctx* c) {
   P.armijo = c->opts.armijo;
   P.warm_start = c->opts.warm_start;
   P.gap0 = c->d_gap;
+  P.vel = c->d_vel;
+  P.inertia_w = c->opts.dynamic ? c->opts.density / (c->opts.dt * c->opts.dt) : 0.0;
+  P.dt = c->opts.dt;
   return P;
 }
 
@@ -1008,6 +1018,7 @@ t2r_status t2r_eval(t2r_ctx* c, int32_t env, const double* d_x, const double* d_
   if (he != hipSuccess) { tfree(); return fail(c, T2R_E_HIP, "eval setup: %s", hipGetErrorString(he)); }
   EvalParams Q{};
   Q.sp = step_params(c);
+  Q.sp.inertia_w = 0.0;  // t2r_eval evaluates the quasi-static energy
   Q.sp.envs = senv;
   Q.sp.n_env = 1;
   Q.sp.x = sx;
@@ -1089,6 +1100,7 @@ t2r_status t2r_set_state(t2r_ctx* c, const double* d_state) {
   // positions changed arbitrarily: every neighbour list must be rebuilt
   HIP_TRY(c, hipMemsetAsync(c->d_lists, 0, c->envs.size() * sizeof(ListState), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_gap, 0, c->envs.size() * sizeof(double), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_vel, 0, (size_t)c->total_dofs * sizeof(double), c->stream));
   s = tape_seed(c);
   if (s != T2R_OK) return s;
   c->err.clear();
@@ -1113,6 +1125,7 @@ t2r_status t2r_reset_envs(t2r_ctx* c, const int32_t* ids, int32_t n) {
                               hipMemcpyHostToDevice, c->stream));  // no motion history
     HIP_TRY(c, hipMemsetAsync(c->d_lists + ids[i], 0, sizeof(ListState), c->stream));
     HIP_TRY(c, hipMemsetAsync(c->d_gap + ids[i], 0, sizeof(double), c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d_vel + ed.voff, 0, 3 * (size_t)g.n_v * sizeof(double), c->stream));
   }
   s = tape_seed(c);
   if (s != T2R_OK) return s;
@@ -1203,6 +1216,7 @@ t2r_status t2r_tape_length(const t2r_ctx* c, int32_t* n_steps) {
 }
 
 static t2r_status launch_adjoint(t2r_ctx* c, StepParams& P, const double* d_dL_du, double* d_grad) {
+  if (c->opts.dynamic) return fail(c, T2R_E_UNSUPPORTED, "the adjoint covers the quasi-static form (dynamic = 0)");
   P.dL_du = d_dL_du;
   P.grad_out = d_grad;
   P.markers_stride = 3 * c->total_markers;
@@ -1278,6 +1292,12 @@ t2r_status upload_gel(t2r_ctx* c, GelHost& g) {
   UP(tile_vstart, g.tile_vstart); UP(tile_verts, g.tile_verts); UP(tile_flags, g.tile_flags);
   UP(surf_v, g.surf_v); UP(surf_e, g.surf_e); UP(surf_f, g.surf_f); UP(marker_tri, g.marker_tri);
   UP(marker_w, g.marker_w);
+  {
+    std::vector<double> vm(g.n_v, 0.0);
+    for (int e = 0; e < g.n_t; ++e)
+      for (int k = 0; k < 4; ++k) vm[g.tet[k * g.n_t + e]] += 0.25 * g.vol[e];
+    UP(vmass, vm);
+  }
 #undef UP
   return T2R_OK;
 }
@@ -1469,7 +1489,8 @@ t2r_status commit(t2r_ctx* c) {
   c->d_pose_lag = alloc_n<double>(c, 7 * c->envs.size());
   c->d_adj = alloc_n<double>(c, nd);
   c->d_gap = alloc_n<double>(c, c->envs.size());
-  if (!c->d_gap || !c->d_x || !c->d_xprev || !c->d_g0 || !c->d_g1 || !c->d_diag || !c->d_p || !c->d_pose_prev ||
+  c->d_vel = alloc_n<double>(c, nd);
+  if (!c->d_vel || !c->d_gap || !c->d_x || !c->d_xprev || !c->d_g0 || !c->d_g1 || !c->d_diag || !c->d_p || !c->d_pose_prev ||
       !c->d_pairs || !c->d_pair_d || !c->d_outer || !c->d_lists || !c->d_xsnap || !c->d_fric ||
       !c->d_vmap || !c->d_oslot || !c->d_pslot || !c->d_slot_v || !c->d_imap || !c->d_islot_v ||
       !c->d_stats || !c->d_order || !c->d_motion || !c->d_pose_lag || !c->d_adj) {
@@ -1488,6 +1509,7 @@ t2r_status commit(t2r_ctx* c) {
   HIP_TRY(c, hipMemsetAsync(c->d_stats, 0, c->envs.size() * sizeof(EnvStats), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_motion, 0, c->envs.size() * sizeof(double), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_gap, 0, c->envs.size() * sizeof(double), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_vel, 0, nd * sizeof(double), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_lists, 0, c->envs.size() * sizeof(ListState), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_vmap, 0, (size_t)vtot * sizeof(int), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_imap, 0, (size_t)std::max(imtot, 1LL) * sizeof(int), c->stream));

@@ -85,6 +85,7 @@ struct GelDev {
   const T2R_G int* surf_f;       // [3][n_sf]
   const T2R_G int* marker_tri;   // [3][n_m]
   const T2R_G double* marker_w;  // [3][n_m]
+  const T2R_G double* vmass;     // [n_v] sum of V_e / 4 over the vertex's tets (lumped mass / density)
 };
 
 struct IndDev {
@@ -182,6 +183,9 @@ struct StepParams {
   int max_iters, max_substeps, precision, armijo;
   int warm_start;                // extrapolate the previous load step's displacement
   T2R_G double* gap0;            // [n_env] d_min at the start of the env's previous load step (0: unknown)
+  T2R_G double* vel;             // [sum 3 n_v] velocities of the dynamic form
+  double inertia_w;              // density / dt^2 (0: quasi-static)
+  double dt;                     // time step of the dynamic form
   // trajectory tape: entry k holds every env's positions ([sum 3 n_v], the
   // layout of x) and pose ([n_env][7]) after the k-th recorded load step
   // (entry 0: the state when recording started)

@@ -51,6 +51,8 @@ struct Shared {
   double bc[8];               // broadcast results
   int count, overflow, flag;
   int pad;
+  T2R_G double* vel;          // this env's velocities (dynamic form)
+  double iw, dt;              // inertia weight density / dt^2 (0: quasi-static), time step
   unsigned long long tacc[10];  // wall-clock ticks per phase (thread 0)
 };
 
@@ -1576,6 +1578,46 @@ __device__ __forceinline__ double dmin_all(Solver& s, const double* x, int& nact
 }
 
 // Evaluates Pi, grad (-> g) and diag at x + alpha p. Returns energy; feasible in flag.
+// Inertia term of the dynamic form (Supp. A, eq. ipc_energy): at x + alpha p,
+// 1/2 w_v |x_v - xhat_v|^2 with w_v = m_v / dt^2 and xhat = x^t + dt v^t
+// (x^t = xprev during a load step); its gradient and diagonal are added to
+// g and dg (free DOFs; every earlier pass's sums are in place). Returns the
+// thread's energy partial.
+__device__ __forceinline__ double inertia_eval(const View& V, const Shared& S, const double* x, const double* p,
+                                               double alpha, double* g, double* dg) {
+  const GelDev& G = *V.G;
+  const int nv = G.n_v, n = 3 * nv;
+  double e = 0.0;
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const int v = j >= 2 * nv ? j - 2 * nv : (j >= nv ? j - nv : j);
+    if (G.fixed[v]) continue;
+    const double w = S.iw * G.vmass[v];
+    const double xt = p ? fma(alpha, p[j], x[j]) : x[j];
+    const double r = xt - fma(S.dt, S.vel[j], V.xprev[j]);
+    g[j] += w * r;
+    dg[j] += w;
+    e += 0.5 * w * r * r;
+  }
+  return e;
+}
+
+// p^T (inertia Hessian) p: sum over free DOFs of w_v p^2 (thread partial).
+__device__ __forceinline__ double inertia_curv(const View& V, const Shared& S, const double* p) {
+  const GelDev& G = *V.G;
+  const int nv = G.n_v, n = 3 * nv;
+  double c = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const int v = j >= 2 * nv ? j - 2 * nv : (j >= nv ? j - nv : j);
+    if (G.fixed[v]) continue;
+    c += S.iw * G.vmass[v] * p[j] * p[j];
+  }
+  return c;
+}
+
+// INERTIA = false leaves the dynamic form's term out of the code (kernels that
+// evaluate the quasi-static energy only).
+template <bool INERTIA = true>
 __device__ __forceinline__ double eval_all(Solver& s, const double* x, const double* p, double alpha, double* g,
                            double* dg, int& feasible, int& nactive, double* e_el = nullptr) {
   View& V = s.V;
@@ -1597,6 +1639,8 @@ __device__ __forceinline__ double eval_all(Solver& s, const double* x, const dou
     v[0] += pairs_eval<false>(V, S, T, x, p, alpha, g, dg, feas, nact);
     if (V.nfric > 0) v[0] += fric_eval<false>(V, S, T, x, p, alpha, g, dg);
   }
+  if constexpr (INERTIA)
+    if (S.iw > 0.0) v[0] += inertia_eval(V, S, x, p, alpha, g, dg);
   v[1] = (double)nact;
   v[2] = feas ? 0.0 : 1.0;  // max -> any infeasible
   double w[4] = {v[0], v[1], eel, v[2]};
@@ -1624,6 +1668,7 @@ __device__ __forceinline__ double curvature_all(Solver& s, const double* x, cons
     c += pairs_curv<false>(V, S, T, x, p);
     if (V.nfric > 0) c += fric_curv<false>(V, S, T, x, p);
   }
+  if (S.iw > 0.0) c += inertia_curv(V, S, p);
   double w[1] = {c};
   block_reduce<1, 0>(w, *s.S);
   tock(*s.S, 3, t0);
@@ -1802,6 +1847,12 @@ __device__ __forceinline__ void init_solver(Solver& s, const StepParams& P, Shar
   s.guard = kEnergyGuard * E.mu * G.vol_total;
   s.buffer = E.dhat;
   s.buffer_out = 6.0 * E.dhat;
+  if (threadIdx.x == 0) {
+    S.vel = P.vel ? P.vel + E.voff : nullptr;
+    S.iw = P.vel ? P.inertia_w : 0.0;
+    S.dt = P.dt;
+  }
+  __syncthreads();
   s.armijo = P.armijo;
   s.pair_cap = E.pair_cap;
   s.fric_cap = E.fric_cap;
@@ -1974,9 +2025,18 @@ __device__ __forceinline__ int load_step(const StepParams& P, int e, Solver& s, 
     // roll back to x_{s-1}; the previous pose is kept
     for (int j = threadIdx.x; j < n; j += blockDim.x) V.x[j] = V.xprev[j];
     __syncthreads();
-  } else if (threadIdx.x == 0) {
-    #pragma unroll
-    for (int i = 0; i < 7; ++i) pose_prev[i] = q1[i];
+  } else {
+    if (threadIdx.x == 0) {
+      #pragma unroll
+      for (int i = 0; i < 7; ++i) pose_prev[i] = q1[i];
+    }
+    if (S.iw > 0.0) {  // dynamic form: v = (x - x^t) / dt
+      const double idt = 1.0 / S.dt;
+      for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const int v = j >= 2 * G.n_v ? j - 2 * G.n_v : (j >= G.n_v ? j - G.n_v : j);
+        S.vel[j] = G.fixed[v] ? 0.0 : (V.x[j] - V.xprev[j]) * idt;
+      }
+    }
   }
   __syncthreads();
   {
@@ -2801,7 +2861,7 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_backward_ke
     // Jacobi preconditioner at x_s (the gradient output is scratch)
     V.nfric = muf > 0.0 ? nfric : 0;
     int feas, nact;
-    eval_all(s, xs, V.p, 0.0, Ad, V.diag, feas, nact);
+    eval_all<false>(s, xs, V.p, 0.0, Ad, V.diag, feas, nact);
     double a2[2] = {0.0, 0.0};
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
       const int v = j >= 2 * nv ? j - 2 * nv : (j >= nv ? j - nv : j);
@@ -2947,7 +3007,7 @@ __global__ void __launch_bounds__(256) t2r_eval_kernel(EvalParams Q) {
   if (threadIdx.x == 0) P.stats[0].status = 0;
   int feas, nact;
   double eel = 0.0;
-  const double Etot = eval_all(s, V.x, V.p, 0.0, V.g0, V.diag, feas, nact, &eel);
+  const double Etot = eval_all<false>(s, V.x, V.p, 0.0, V.g0, V.diag, feas, nact, &eel);
   double curv = 0.0;
   if (Q.has_p) curv = curvature_all(s, V.x, V.p);
   int na2 = 0;

@@ -29,7 +29,8 @@ class SolverOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("substep_tol", C.c_double), ("max_iters", C.c_int32),
                 ("max_substeps", C.c_int32), ("precision", C.c_int32),
                 ("pair_capacity", C.c_int32), ("armijo", C.c_int32), ("block_size", C.c_int32),
-                ("warm_start", C.c_int32)]
+                ("warm_start", C.c_int32), ("dynamic", C.c_int32), ("dt", C.c_double),
+                ("density", C.c_double)]
 
 
 class EnvStats(C.Structure):

@@ -112,11 +112,14 @@ def test_invalid_inputs_are_rejected_on_the_host():
 
 def test_invalid_options_are_rejected():
     t2r = _t2r()
-    for kw in ({"tol": 0.0}, {"precision": 3}, {"block_size": 100}, {"block_size": 1024}, {"max_substeps": 0}):
+    for kw in ({"tol": 0.0}, {"precision": 3}, {"block_size": 100}, {"block_size": 1024}, {"max_substeps": 0},
+               {"dynamic": 2}, {"dynamic": 1, "dt": 0.0}, {"dynamic": 1, "density": -1.0}):
         with pytest.raises(t2r.T2RError):
             t2r.Context(t2r.default_opts(**kw))
     o = t2r.default_opts()
     assert o.tol == 1e-6 and o.armijo == 1 and o.max_iters > 0
+    assert o.dynamic == 0 and o.dt > 0.0 and o.density == 1.1e-9
+    t2r.Context(t2r.default_opts(dynamic=1, dt=1e-3, density=1e-9))   # a valid dynamic set
 
 
 def test_workload_classes_build_on_the_host():

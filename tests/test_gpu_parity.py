@@ -720,6 +720,40 @@ def _cut_schedule(w, k):
     return dataclasses.replace(w, envs=[dataclasses.replace(e, poses=e.poses[:k + 1])])
 
 
+def test_dynamic_form_matches_oracle():
+    """The implicit-Euler form (inertia with lumped masses, a density large
+    enough for the term to move the markers by > 1e-4 mm) against the oracle's
+    Newton with the same term, per-step launches and one multi-step launch
+    (the velocity carried inside the launch); the adjoint refuses the form."""
+    t2r = _gpu()
+    from oracle.sim import simulate
+    from scenes.configs import micro_press
+    w = micro_press(mesh="micro3", indenter="sphere_small", depth=0.15, n_steps=4, mu_f=0.5,
+                    shear=(0.05, 0.02), n_shear=2)
+    env = w.envs[0]
+    dyn = dict(density=1e-3, dt=1e-2)
+    ref = simulate(w.meshes[env.mesh], w.indenters[env.indenter], env, mode="newton", tol=1e-12, dynamic=dyn)
+    qs = simulate(w.meshes[env.mesh], w.indenters[env.indenter], env, mode="newton", tol=1e-12)
+    assert max(np.abs(a - b).max() for a, b in zip(ref.markers, qs.markers)) > 1e-4
+    opts = dict(tol=1e-10, substep_tol=1e-10, max_iters=400000, dynamic=1, dt=dyn["dt"], density=dyn["density"])
+    sim = _build(t2r, w, **opts)
+    for s in range(1, env.poses.shape[0]):
+        m, st = sim.step(env.poses[s][None], want_x=True)
+        torch.cuda.synchronize()
+        assert int(st.cpu()[0]) & 1
+        assert np.abs(sim.x.cpu().numpy() - ref.x[s - 1]).max() <= 1e-6, s
+        assert np.abs(m.cpu().numpy() - ref.markers[s - 1]).max() <= 1e-6, s
+    with pytest.raises(t2r.T2RError) as e:
+        sim.backward(np.zeros((len(ref.markers[0]), 3)))
+    assert e.value.code == t2r.T2R_E_UNSUPPORTED
+    sim2 = _build(t2r, w, **opts)
+    m2, st2 = sim2.step_sequence(np.ascontiguousarray(env.poses[1:][:, None, :]))
+    torch.cuda.synchronize()
+    assert np.all(st2.cpu().numpy() & 1)
+    for s in range(len(ref.markers)):
+        assert np.abs(m2[s].cpu().numpy() - ref.markers[s]).max() <= 1e-6, s
+
+
 def _certify_equilibrium(w, env, pose, x, bound=1e-6):
     """The oracle's Newton started from x must not move: x is a minimiser of Pi."""
     from oracle.newton import newton_solve
