@@ -42,6 +42,11 @@ def parse():
     ap.add_argument("--envs", type=int, default=0, help="0: the workload's own count")
     ap.add_argument("--precision", choices=["f64", "mixed"], default="mixed")
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--dynamic", action="store_true",
+                    help="the implicit-Euler form (inertia with lumped masses; one time step per load step)")
+    ap.add_argument("--dt", type=float, default=1.0 / 60.0, help="time step of the dynamic form (s)")
+    ap.add_argument("--density", type=float, default=1.1e-9,
+                    help="mass density of the dynamic form (t/mm^3; 1.1e-9 = 1,100 kg/m^3)")
     ap.add_argument("--plain-envs", type=int, default=4, help="envs timed one launch each (0: skip)")
     ap.add_argument("--launch", choices=["sequence", "per-step"], default="sequence",
                     help="sequence: the K timed load steps of every env in one launch; per-step: one launch per load step")
@@ -220,7 +225,8 @@ def main():
         print(f"warmup + steps must be <= {workload.n_steps}", file=sys.stderr)
         sys.exit(1)
     prec = 0 if args.precision == "f64" else 1
-    opts = t2r.default_opts(tol=args.tol, precision=prec, block_size=args.block)
+    opts = t2r.default_opts(tol=args.tol, precision=prec, block_size=args.block, dynamic=int(args.dynamic),
+                            dt=args.dt, density=args.density)
     t_build = time.perf_counter()
     sim = Sim.from_workload(workload, opts)
     poses = torch.as_tensor(np.stack([e.poses for e in workload.envs]), dtype=torch.float64,
@@ -293,7 +299,7 @@ def main():
     # by a 1 GiB copy), valid only for the kernel source they were taken with
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"t2r_step_kernel_{workload.name}_traffic.json")
-    if os.path.exists(tfile) and args.launch == "sequence" and W == 1 and K == 19:
+    if os.path.exists(tfile) and args.launch == "sequence" and W == 1 and K == 19 and not args.dynamic:
         with open(tfile) as fh:
             tr = json.load(fh)
         if (tr.get("source_hash") == source_hash() and tr.get("envs") == args.envs
@@ -352,6 +358,8 @@ def main():
                    "indenters": sorted(workload.indenters),
                    "load_steps_timed": f"{W + 1}..{W + K} of 20", "tol_mm": args.tol,
                    "precision": args.precision, "all_converged": bool(status_ok),
+                   "form": (f"dynamic (dt {args.dt:g} s, density {args.density:g} t/mm^3)" if args.dynamic
+                            else "quasi-static"),
                    "pncg_iters_per_env_step": iters_mean, "launch": args.launch,
                    "block_size": sim.ctx.get_opts().block_size or 256,
                    "autotune_trial_ms": tuned["trial_ms"] if tuned else None},
