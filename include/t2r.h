@@ -199,6 +199,15 @@ t2r_status t2r_gel_info(const t2r_ctx* ctx, int32_t gel_id, int32_t* out10);
 t2r_status t2r_gel_markers(const t2r_ctx* ctx, int32_t gel_id, int32_t* marker_tri,
                            double* marker_w);
 
+/* Replaces a gel class's marker map with any linear one: marker m's
+ * displacement is sum_k weight[m][k] (x - X) at vertex[m][k], k < 3 (host
+ * arrays [n_m][3]; e.g. the k-nearest-neighbour map of Sec. 3.1 with k <= 3).
+ * Before the first GPU call only (T2R_E_STATE after). Errors: T2R_E_ARG for a
+ * bad gel id, n_m < 0, vertex ids out of range or non-finite weights. Host
+ * only. */
+t2r_status t2r_set_gel_markers(t2r_ctx* ctx, int32_t gel_id, int32_t n_m, const int32_t* vertex,
+                               const double* weight);
+
 /* Adds a rigid indenter class: n_v local vertices Y[n_v][3] (mm) and n_f
  * triangles tris[n_f][3] of a closed surface. Edges are derived. Host only. */
 t2r_status t2r_add_indenter(t2r_ctx* ctx, int32_t n_v, const double* Y, int32_t n_f,

@@ -677,6 +677,31 @@ t2r_status t2r_gel_markers(const t2r_ctx* c, int32_t id, int32_t* tri, double* w
   return T2R_OK;
 }
 
+t2r_status t2r_set_gel_markers(t2r_ctx* c, int32_t id, int32_t n_m, const int32_t* vertex,
+                               const double* weight) {
+  if (!c) return T2R_E_ARG;
+  if (id < 0 || id >= (int)c->gels.size()) return fail(c, T2R_E_ARG, "bad gel id %d", id);
+  if (c->committed) return fail(c, T2R_E_STATE, "markers can only change before the first GPU call");
+  if (n_m < 0 || (n_m > 0 && (!vertex || !weight))) return fail(c, T2R_E_ARG, "bad marker arrays");
+  GelHost& g = c->gels[id];
+  for (int m = 0; m < n_m; ++m)
+    for (int k = 0; k < 3; ++k) {
+      const int v = vertex[3 * m + k];
+      if (v < 0 || v >= g.n_v) return fail(c, T2R_E_ARG, "marker %d: vertex %d out of range", m, v);
+      if (!isfinite(weight[3 * m + k])) return fail(c, T2R_E_ARG, "marker %d: weight not finite", m);
+    }
+  g.n_m = n_m;
+  g.marker_tri.assign((size_t)3 * n_m, 0);
+  g.marker_w.assign((size_t)3 * n_m, 0.0);
+  for (int m = 0; m < n_m; ++m)
+    for (int k = 0; k < 3; ++k) {
+      g.marker_tri[(size_t)k * n_m + m] = vertex[3 * m + k];
+      g.marker_w[(size_t)k * n_m + m] = weight[3 * m + k];
+    }
+  c->err.clear();
+  return T2R_OK;
+}
+
 t2r_status t2r_add_indenter(t2r_ctx* c, int32_t n_v, const double* Y, int32_t n_f, const int32_t* tris,
                             int32_t* ind_id) {
   if (!c) return T2R_E_ARG;

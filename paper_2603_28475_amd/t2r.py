@@ -83,6 +83,7 @@ SIGNATURES = [
     ("t2r_tape_length", C.c_int32, [_P, C.POINTER(C.c_int32)]),
     ("t2r_backward_sequence", C.c_int32, [_P, C.c_int32, _P, _P]),
     ("t2r_tape_read", C.c_int32, [_P, C.c_int32, _P]),
+    ("t2r_set_gel_markers", C.c_int32, [_P, C.c_int32, C.c_int32, _PI, _PD]),
 ]
 
 
@@ -173,6 +174,12 @@ class Context:
         w = np.zeros((n_m, 3), np.float64)
         self.check(lib.t2r_gel_markers(self.handle, gid, _dptr(tri, C.c_int32), _dptr(w, C.c_double)))
         return tri, w
+
+    def set_gel_markers(self, gid, vertex, weight):
+        vertex = np.ascontiguousarray(vertex, dtype=np.int32).reshape(-1, 3)
+        weight = np.ascontiguousarray(weight, dtype=np.float64).reshape(-1, 3)
+        self.check(lib.t2r_set_gel_markers(self.handle, gid, len(vertex), _dptr(vertex, C.c_int32),
+                                           _dptr(weight, C.c_double)))
 
     def add_indenter(self, Y, tris) -> int:
         Y = np.ascontiguousarray(Y, dtype=np.float64)

@@ -155,3 +155,28 @@ def test_options_roundtrip_and_capacity_rule():
         assert info["pair_capacity"] == max(8192, 3 * (info["n_sv"] + info["n_se"] + info["n_sf"]))
     ctx.set_pair_capacity(5000)
     assert ctx.gel_info(gid)["pair_capacity"] == 5000
+
+
+def test_marker_map_replacement_and_knn_map():
+    """t2r_set_gel_markers validates and replaces a gel's map before the first GPU
+    call; the kNN map's weights sum to 1 and a marker on a node takes it alone."""
+    t2r = _t2r()
+    from paper_2603_28475_amd.markers import knn_marker_map
+    g = mesh_class("c1")
+    ctx = t2r.Context()
+    gid = ctx.add_gel(g.X, g.tets, g.fixed, g.markers)
+    top = np.nonzero(np.isclose(g.X[:, 2], g.X[:, 2].max()))[0]
+    M = np.asarray(g.markers)
+    vert, wt = knn_marker_map(g.X, top, M, k=3)
+    assert np.allclose(wt.sum(axis=1), 1.0) and np.all(wt >= 0.0)
+    d = np.linalg.norm(g.X[vert][:, :, :2] - M[:, None, :], axis=2)
+    assert np.all(d[:, 0] <= d[:, 1] + 1e-15) and np.all(d[:, 1] <= d[:, 2] + 1e-15)
+    on = knn_marker_map(g.X, top, g.X[top[:1], :2], k=3)
+    assert on[0][0, 0] == top[0] and on[1][0, 0] == 1.0 and on[1][0, 1:].sum() == 0.0
+    ctx.set_gel_markers(gid, vert, wt)
+    tri2, w2 = ctx.gel_markers(gid)
+    assert np.array_equal(tri2, vert) and np.allclose(w2, wt)
+    for bad in ((vert + g.n_verts, wt), (vert, wt * np.nan)):
+        with pytest.raises(t2r.T2RError) as e:
+            ctx.set_gel_markers(gid, *bad)
+        assert e.value.code == t2r.T2R_E_ARG

@@ -819,6 +819,33 @@ def test_calibration_recovers_hidden_parameters():
     assert abs(vals[1] - star[1]) <= 0.01 * star[1] and abs(vals[2] - star[2]) <= 0.05 * star[2], vals
 
 
+def test_knn_marker_map_matches_oracle_positions():
+    """The paper's k-nearest-neighbour marker map (k = 3, inverse-distance
+    weights) set through t2r_set_gel_markers: the GPU markers equal the map
+    applied to the oracle's Newton positions within 1e-6 mm."""
+    t2r = _gpu()
+    from oracle.sim import simulate
+    from paper_2603_28475_amd.markers import knn_marker_map
+    from scenes.configs import micro_press
+    w = micro_press(mesh="micro3", indenter="sphere_small", depth=0.15, n_steps=3, xy=(0.12, -0.07))
+    env = w.envs[0]
+    g = w.meshes[env.mesh]
+    top = np.nonzero(np.isclose(g.X[:, 2], g.X[:, 2].max()))[0]
+    vert, wt = knn_marker_map(g.X, top, np.asarray(g.markers), k=3)
+    sim = _build(t2r, w, tol=1e-10, substep_tol=1e-10, max_iters=400000)
+    sim.ctx.set_gel_markers(sim.gel_ids[env.mesh], vert, wt)
+    ref = simulate(g, w.indenters[env.indenter], env, mode="newton", tol=1e-12)
+    for s in range(1, env.poses.shape[0]):
+        m, st = sim.step(env.poses[s][None])
+        torch.cuda.synchronize()
+        assert int(st.cpu()[0]) & 1
+        u = np.einsum("mk,mkd->md", wt, (ref.x[s - 1] - g.X)[vert])
+        assert np.abs(m.cpu().numpy() - u).max() <= 1e-6, s
+    with pytest.raises(t2r.T2RError) as e:
+        sim.ctx.set_gel_markers(sim.gel_ids[env.mesh], vert, wt)
+    assert e.value.code == t2r.T2R_E_STATE
+
+
 def _certify_equilibrium(w, env, pose, x, bound=1e-6):
     """The oracle's Newton started from x must not move: x is a minimiser of Pi."""
     from oracle.newton import newton_solve
