@@ -116,17 +116,20 @@ def sphere_press_484v(n_envs: int = 1, n_steps: int = 10) -> Workload:
 
 
 def peg_press_484v(tilt_deg: float = 1.0, depth: float = 0.3, n_steps: int = 3, mu_f: float = 0.0,
-                   shear=(0.0, 0.0), n_shear: int = 0) -> Workload:
+                   shear=(0.0, 0.0), n_shear: int = 0, mesh: str = "c1") -> Workload:
     """Small parity scene with every pair kind active: the 8x8x2 mm gel (484 v)
     pressed by the end-on peg r=4 mm, tilted a little so that its flat face, its
-    rim edges and its rim vertices all come within dhat of the gel."""
-    g = mesh_class("c1")
+    rim edges and its rim vertices all come within dhat of the gel. mesh "c1u":
+    the same gel tetrahedralised unstructured."""
+    assert mesh in ("c1", "c1u")
+    g = mesh_class(mesh)
     ind = INDENTERS["peg4"]()
     q = _yaw_tilt(0.3, np.deg2rad(tilt_deg))
     poses = press_schedule(ind, q, (0.5, -0.3), depth, g.thickness, n_steps, shear=shear,
                            n_shear=n_shear)
-    env = EnvSpec("c1", "peg4", 0.3, NU, mu_f, poses)
-    return Workload("peg_press_484v", 6, {"c1": g}, {"peg4": ind}, [env], "f64", 1e-6,
+    env = EnvSpec(mesh, "peg4", 0.3, NU, mu_f, poses)
+    return Workload("peg_press_484v" + ("u" if mesh == "c1u" else ""), 6, {mesh: g}, {"peg4": ind}, [env],
+                    "f64", 1e-6,
                     "1 env, 484-vertex gel, slightly tilted end-on peg")
 
 
@@ -149,10 +152,13 @@ def peg_press_shear_12k(n_envs: int = 1) -> Workload:
                     "1 env, 12k-vertex gel, tilted peg, 0.8 mm press + 0.5 mm shear, friction 0.5")
 
 
-def peg_batch_5k(n_envs: int = 2048, n_steps: int = 20, precision: str = "mixed") -> Workload:
+def peg_batch_5k(n_envs: int = 2048, n_steps: int = 20, precision: str = "mixed",
+                 mesh: str = "5k") -> Workload:
     """Uniform batch: n_envs x 5k-vertex gels (4,914 v, 24,000 t), peg at xy U[-2,2]^2 mm,
-    yaw U[0,360) deg, 20 press steps to depth U[0.3,1.0] mm, E U[0.2,0.5], mu U[0.3,0.8]."""
-    g = mesh_class("5k")
+    yaw U[0,360) deg, 20 press steps to depth U[0.3,1.0] mm, E U[0.2,0.5], mu U[0.3,0.8].
+    mesh "5ku": the same box and points tetrahedralised unstructured (27,063 t)."""
+    assert mesh in ("5k", "5ku")
+    g = mesh_class(mesh)
     ind = INDENTERS["peg4"]()
     envs = []
     for e in range(n_envs):
@@ -163,9 +169,10 @@ def peg_batch_5k(n_envs: int = 2048, n_steps: int = 20, precision: str = "mixed"
         E = r.uniform(0.2, 0.5)
         mu = r.uniform(0.3, 0.8)
         poses = press_schedule(ind, _yaw_tilt(yaw, 0.0), xy, depth, g.thickness, n_steps)
-        envs.append(EnvSpec("5k", "peg4", E, NU, mu, poses))
-    return Workload(f"peg_batch_{n_envs}x5k", 3, {"5k": g}, {"peg4": ind}, envs, precision, 1e-6,
-                    f"{n_envs} envs, 5k-vertex gels, peg, {n_steps} press steps")
+        envs.append(EnvSpec(mesh, "peg4", E, NU, mu, poses))
+    return Workload(f"peg_batch_{n_envs}x{mesh}", 3, {mesh: g}, {"peg4": ind}, envs, precision, 1e-6,
+                    f"{n_envs} envs, 5k-vertex gels ({'unstructured' if mesh == '5ku' else 'Kuhn'}), "
+                    f"peg, {n_steps} press steps")
 
 
 def mixed_batch(n_envs: int = 512, n_steps: int = 20, precision: str = "mixed") -> Workload:

@@ -1,4 +1,5 @@
-"""Tetrahedral gel pads: a hex grid split into six Kuhn tetrahedra per hex.
+"""Tetrahedral gel pads: a hex grid split into six Kuhn tetrahedra per hex, or
+an unstructured Delaunay tetrahedralisation of the same box.
 
 The paper meshes the sensor gel with tetrahedra (Supp. A, first paragraph)
 and reports a "pseudo-structured" mesh for its throughput figure (Sec. 5.1,
@@ -119,6 +120,62 @@ def marker_grid(size_xy, counts) -> np.ndarray:
     return np.stack([Xg.ravel(), Yg.ravel()], axis=1).astype(np.float64)
 
 
+def delaunay_gel(size, cells, markers_xy=(7, 7), seed: int = 0, jitter: float = 0.3,
+                 q_min: float = 0.1, max_rounds: int = 100, name: str = "") -> GelMesh:
+    """Unstructured box gel: the Delaunay tetrahedralisation of a jittered point
+    set, with a lower bound on tet quality.
+
+    The paper contrasts its pseudo-structured mesh with an unstructured one
+    (Sec. 5.1, "Parallel Performance"). This builds the latter kind without a
+    mesh generator: the (nx+1)(ny+1)(nz+1) grid points of `cells` over the box
+    are moved by independent uniform offsets of up to `jitter` cells along
+    every axis in which they are interior (box corners stay, edge points move
+    along their edge, face points within their face), so the box faces stay
+    planar, and scipy's Delaunay tetrahedralises them. Tets whose normalised
+    volume-to-edge quality 6 sqrt(2) V / l_rms^3 (1 for a regular tet) is
+    below `q_min` are slivers: their movable points are drawn again and the
+    point set re-triangulated until none is left (at most `max_rounds` times,
+    else ValueError). Every tet is returned positively oriented.
+    """
+    from scipy.spatial import Delaunay
+
+    W, D, T = (float(s) for s in size)
+    nx, ny, nz = (int(n) for n in cells)
+    n = np.array([nx, ny, nz])
+    h = np.array([W / nx, D / ny, T / nz])
+    kk, jj, ii = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    ijk = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)   # x fastest, like hex_kuhn_gel
+    movable = (ijk > 0) & (ijk < n)
+    P0 = ijk * h + np.array([-W / 2, -D / 2, 0.0])
+    rng = np.random.default_rng(seed)
+    J = rng.uniform(-jitter, jitter, P0.shape)
+    for _ in range(max_rounds):
+        X = P0 + J * h * movable
+        tets = Delaunay(X).simplices.astype(np.int64)
+        q = tet_quality(X, tets)
+        bad = np.abs(q) < q_min
+        if not bad.any():
+            break
+        vs = np.unique(tets[bad])
+        J[vs] = rng.uniform(-jitter, jitter, (len(vs), 3))
+    else:
+        raise ValueError(f"no sliver-free tetrahedralisation after {max_rounds} rounds")
+    neg = q < 0
+    tets[neg] = tets[neg][:, [0, 1, 3, 2]]
+    fixed = (np.abs(X[:, 2]) < 1e-12).astype(np.uint8)
+    return GelMesh(X=X, tets=tets.astype(np.int32), fixed=fixed, size=(W, D, T), cells=(nx, ny, nz),
+                   markers=marker_grid((W, D), markers_xy), name=name)
+
+
+def tet_quality(X, tets) -> np.ndarray:
+    """Signed 6 sqrt(2) V / l_rms^3 per tet: 1 for a regular tet, 0 when flat."""
+    P = np.asarray(X)[np.asarray(tets)]
+    e = [P[:, a] - P[:, b] for a, b in ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))]
+    l_rms = np.sqrt(np.mean([np.einsum("ij,ij->i", v, v) for v in e], axis=0))
+    vol = np.einsum("ij,ij->i", P[:, 1] - P[:, 0], np.cross(P[:, 2] - P[:, 0], P[:, 3] - P[:, 0])) / 6.0
+    return 6.0 * np.sqrt(2.0) * vol / l_rms ** 3
+
+
 # Mesh classes used by the workloads: (size mm, hexes, marker grid).
 MESH_CLASSES = {
     "c1": ((8.0, 8.0, 2.0), (10, 10, 3), (7, 7)),
@@ -131,6 +188,16 @@ MESH_CLASSES = {
 }
 
 
+# Unstructured classes "<name>u": the same box, grid and markers as class
+# <name>, tetrahedralised by delaunay_gel (seed 0) instead of the Kuhn split.
+_UNSTRUCTURED = {}
+
+
 def mesh_class(name: str) -> GelMesh:
+    if name.endswith("u") and name[:-1] in MESH_CLASSES:
+        if name not in _UNSTRUCTURED:
+            size, cells, mk = MESH_CLASSES[name[:-1]]
+            _UNSTRUCTURED[name] = delaunay_gel(size, cells, mk, seed=0, name=name)
+        return _UNSTRUCTURED[name]
     size, cells, mk = MESH_CLASSES[name]
     return hex_kuhn_gel(size, cells, mk, name=name)

@@ -56,7 +56,24 @@ def peg_press_friction():
     print(f"peg_press_484v_friction: {time.time() - t:.1f}s, active {r.n_active}")
 
 
+def peg_press_friction_unstructured():
+    """The same scene on the unstructured (Delaunay) version of the 484-vertex
+    gel; the mesh itself is stored too, so that a test can check that it
+    regenerates bit for bit."""
+    w = peg_press_484v(mu_f=0.5, shear=(0.1, 0.05), n_shear=2, mesh="c1u")
+    env = w.envs[0]
+    g = w.meshes["c1u"]
+    t = time.time()
+    r = simulate(g, w.indenters["peg4"], env, mode="newton")
+    np.savez_compressed(os.path.join(HERE, "peg_press_484v_unstructured_friction_newton.npz"),
+                        x=np.array(r.x), markers=np.array(r.markers), poses=env.poses,
+                        n_active=np.array(r.n_active), d_min=np.array(r.d_min),
+                        mesh_X=g.X, mesh_tets=g.tets)
+    print(f"peg_press_484v_unstructured_friction: {time.time() - t:.1f}s, active {r.n_active}")
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["micro_friction", "sphere_press", "peg_press_friction"]
+    which = sys.argv[1:] or ["micro_friction", "sphere_press", "peg_press_friction",
+                             "peg_press_friction_unstructured"]
     for name in which:
         globals()[name]()

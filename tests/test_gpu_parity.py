@@ -846,6 +846,74 @@ def test_knn_marker_map_matches_oracle_positions():
     assert e.value.code == t2r.T2R_E_STATE
 
 
+def test_unstructured_peg_friction_sequence_matches_newton_oracle():
+    """The tilted-peg friction scene on the unstructured (Delaunay) version of
+    the 484-vertex gel: three press steps and two shear steps against the
+    oracle's Newton minimiser, which was run on the same mesh (checked to
+    regenerate bit for bit)."""
+    t2r = _gpu()
+    from scenes.configs import peg_press_484v
+    w = peg_press_484v(mu_f=0.5, shear=(0.1, 0.05), n_shear=2, mesh="c1u")
+    gold = np.load(os.path.join(HERE, "golden", "peg_press_484v_unstructured_friction_newton.npz"))
+    g = w.meshes["c1u"]
+    assert np.array_equal(g.X, gold["mesh_X"]) and np.array_equal(g.tets, gold["mesh_tets"])
+    sim = _build(t2r, w, tol=1e-10, substep_tol=1e-8, max_iters=400000)
+    poses = np.stack([e.poses for e in w.envs])
+    m, x, st = _run_steps(sim, poses, want_x=True)
+    assert np.all(st & 1), st
+    assert np.abs(x - gold["x"]).max() <= 1e-6
+    assert np.abs(m - gold["markers"]).max() <= 1e-6
+
+
+def test_c3_unstructured_full_size_sampled_envs_are_oracle_equilibria():
+    """The headline batch on the unstructured 5k gel (4,914 v, 27,063 t) at full
+    size in the bench's launch shape: every env converges and three sampled
+    envs are certified by the oracle as in the structured case."""
+    t2r = _gpu()
+    from scenes.configs import peg_batch_5k
+    w = peg_batch_5k(n_envs=2048, mesh="5ku")
+    print("C3 2048x5ku bench-shape launch", flush=True)
+    sim = _build(t2r, w, tol=1e-6, precision=1, block_size=256)
+    m, S = _bench_shape_run(sim, w)
+    _certify_sampled(w, sim, m, (0, 1023, 2047), S - 1, S, 1e-3)
+
+
+def test_plugin_velocity_driven_observation_matches_oracle():
+    """The physics-engine plugin: engine steps given as linear and angular
+    velocities (a press, then a slide with a twist, two load steps each) drive a
+    gel with a 7 x 9 marker grid; every engine step's observation equals the
+    in-plane marker field of the oracle's Newton solve along the same poses
+    within 1e-6 mm."""
+    t2r = _gpu()
+    from oracle.sim import simulate
+    from paper_2603_28475_amd.plugin import TactilePlugin, advance_pose
+    from scenes.configs import DHAT, INDENTERS, EnvSpec, Workload, pose_at_depth
+    from scenes.mesh import hex_kuhn_gel
+    g = hex_kuhn_gel((3.0, 3.0, 1.0), (3, 3, 1), (7, 9), name="micro3_7x9")
+    ind = INDENTERS["sphere_small"]()
+    dt, sub = 1.0 / 60.0, 2
+    p0 = pose_at_depth(ind, (1.0, 0.0, 0.0, 0.0), (0.1, -0.05), -2.0 * DHAT, g.thickness)
+    motion = [((0, 0, -0.06 / dt), (0, 0, 0))] * 3 + [((0.03 / dt, 0.01 / dt, 0), (0, 0, 0.05 / dt))] * 2
+    poses, p = [p0], p0
+    for v, om in motion:
+        poses += [advance_pose(p, v, om, dt * (k + 1) / sub) for k in range(sub)]
+        p = poses[-1]
+    env = EnvSpec("micro3_7x9", "sphere_small", 0.3, 0.45, 0.5, np.stack(poses))
+    w = Workload("plugin_micro3", 0, {"micro3_7x9": g}, {"sphere_small": ind}, [env], "f64", 1e-10)
+    ref = simulate(g, ind, env, mode="newton", tol=1e-12)
+    sim = _build(t2r, w, tol=1e-11, substep_tol=1e-8, max_iters=200000)
+    plug = TactilePlugin(sim, p0[None], grid=(7, 9), substeps=sub)
+    for k, (v, om) in enumerate(motion):
+        obs, st = plug.step_velocity(np.array([v], dtype=np.float64), np.array([om], dtype=np.float64), dt)
+        torch.cuda.synchronize()
+        assert np.all(st.cpu().numpy() & 1)
+        u = ref.markers[sub * (k + 1) - 1]                     # (63, 3), x fastest
+        expect = u[:, :2].reshape(9, 7, 2).transpose(1, 0, 2)
+        assert obs.shape == (1, 7, 9, 2)
+        assert np.abs(obs[0].cpu().numpy() - expect).max() <= 1e-6, k
+    assert np.abs(ref.markers[-1]).max() > 1e-3                 # the gel did deform
+
+
 def _certify_equilibrium(w, env, pose, x, bound=1e-6):
     """The oracle's Newton started from x must not move: x is a minimiser of Pi."""
     from oracle.newton import newton_solve

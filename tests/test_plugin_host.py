@@ -1,0 +1,102 @@
+"""Host-side pins of the physics-engine plugin surface: the velocities of a
+pose change and their integration are inverse to each other and agree with
+closed forms, and the observation is the in-plane marker field laid out as
+the n_x x n_y marker grid."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2603_28475_amd.plugin import TactilePlugin, advance_pose, observation, relative_velocity  # noqa: E402
+from scenes.indenters import quat_from_axis_angle, quat_mul  # noqa: E402
+from scenes.mesh import marker_grid  # noqa: E402
+
+
+def _random_poses(rng, n):
+    t = rng.uniform(-2, 2, (n, 3))
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    return np.concatenate([t, q], axis=1)
+
+
+def _same_rotation(qa, qb):
+    return np.all(np.abs(np.abs(np.sum(qa * qb, axis=-1)) - 1.0) < 1e-12)
+
+
+def test_velocity_integration_inverts_the_velocity_of_a_pose_change():
+    rng = np.random.default_rng(3)
+    p0, p1 = _random_poses(rng, 50), _random_poses(rng, 50)
+    dt = 0.0125
+    v, w = relative_velocity(p0, p1, dt)
+    p = advance_pose(p0, v, w, dt)
+    assert np.allclose(p[:, :3], p1[:, :3], atol=1e-12)
+    assert _same_rotation(p[:, 3:], p1[:, 3:])
+    # the shortest rotation: |w| dt <= pi, and q1 given as -q1 changes nothing
+    assert np.all(np.linalg.norm(w, axis=1) * dt <= np.pi + 1e-12)
+    v2, w2 = relative_velocity(p0, np.concatenate([p1[:, :3], -p1[:, 3:]], axis=1), dt)
+    assert np.allclose(v2, v) and np.allclose(w2, w, atol=1e-12)
+
+
+def test_velocities_of_closed_form_motions():
+    dt = 0.02
+    q0 = quat_from_axis_angle((0, 1, 0), 0.3)
+    p0 = np.array([0.1, -0.2, 3.0, *q0])
+    # a turn by 0.05 rad about the world z axis and a slide along x
+    q1 = quat_mul(quat_from_axis_angle((0, 0, 1), 0.05), q0)
+    p1 = np.array([0.15, -0.2, 2.9, *q1])
+    v, w = relative_velocity(p0, p1, dt)
+    assert np.allclose(v, [0.05 / dt, 0.0, -0.1 / dt], atol=1e-12)
+    assert np.allclose(w, [0.0, 0.0, 0.05 / dt], atol=1e-10)
+    # no motion, no velocity
+    v0, w0 = relative_velocity(p0, p0, dt)
+    assert np.all(v0 == 0) and np.allclose(w0, 0.0, atol=1e-15)
+    with pytest.raises(ValueError):
+        relative_velocity(p0, p1, 0.0)
+
+
+def test_two_half_steps_equal_one_step():
+    rng = np.random.default_rng(8)
+    p0 = _random_poses(rng, 10)
+    v, w = rng.standard_normal((10, 3)), rng.standard_normal((10, 3))
+    a = advance_pose(advance_pose(p0, v, w, 0.05), v, w, 0.05)
+    b = advance_pose(p0, v, w, 0.1)
+    assert np.allclose(a[:, :3], b[:, :3], atol=1e-13) and _same_rotation(a[:, 3:], b[:, 3:])
+
+
+def test_observation_is_the_in_plane_field_on_the_marker_grid():
+    n_env, grid = 3, (7, 9)
+    xy = marker_grid((8.0, 9.0), grid)                          # x fastest
+    m = np.concatenate([np.concatenate([xy + 100 * e, np.full((63, 1), -1.0)], axis=1)
+                        for e in range(n_env)])
+    obs = observation(torch.as_tensor(m), n_env, grid)
+    assert tuple(obs.shape) == (n_env, 7, 9, 2)
+    for e in range(n_env):
+        for i in range(7):
+            for j in range(9):
+                assert np.array_equal(obs[e, i, j].numpy(), m[e * 63 + j * 7 + i, :2])
+    # x grows along the first grid axis, y along the second
+    assert np.all(np.diff(obs[0, :, 0, 0].numpy()) > 0) and np.all(np.diff(obs[0, 0, :, 1].numpy()) > 0)
+    with pytest.raises(ValueError):
+        observation(torch.zeros((62, 3)), 1, grid)
+
+
+class _FakeSim:
+    def __init__(self, n_env, n_m):
+        self.n_env, self.n_m = n_env, [n_m] * n_env
+
+
+def test_plugin_substeps_follow_the_constant_velocity_motion():
+    rng = np.random.default_rng(1)
+    p0 = _random_poses(rng, 4)
+    p1 = _random_poses(rng, 4)
+    plug = TactilePlugin(_FakeSim(4, 63), p0, substeps=5)
+    v, w = relative_velocity(p0, p1, 0.1)
+    poses = plug.substep_poses(v, w, 0.1)
+    assert poses.shape == (5, 4, 7)
+    assert np.allclose(poses[-1, :, :3], p1[:, :3], atol=1e-12) and _same_rotation(poses[-1, :, 3:], p1[:, 3:])
+    assert np.allclose(poses[2], advance_pose(p0, v, w, 0.06), atol=1e-14)
+    with pytest.raises(ValueError):
+        TactilePlugin(_FakeSim(2, 49), p0[:2])
+    with pytest.raises(ValueError):
+        TactilePlugin(_FakeSim(2, 63), p0[:2], substeps=0)
