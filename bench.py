@@ -40,8 +40,6 @@ def parse():
                     help="peg_batch_5k: uniform 2048 x 5k gels (headline); mixed_batch: 512 envs over "
                          "three gel sizes and three indenters")
     ap.add_argument("--envs", type=int, default=0, help="0: the workload's own count")
-    ap.add_argument("--mesh", choices=["structured", "unstructured"], default="structured",
-                    help="peg_batch_5k gel: the Kuhn-split box or its unstructured Delaunay version")
     ap.add_argument("--precision", choices=["f64", "mixed"], default="mixed")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--dynamic", action="store_true",
@@ -222,11 +220,7 @@ def main():
     if args.envs <= 0:
         args.envs = 2048 if args.workload == "peg_batch_5k" else 512
     make = peg_batch_5k if args.workload == "peg_batch_5k" else mixed_batch
-    kw = {"mesh": "5ku"} if args.mesh == "unstructured" else {}
-    if kw and args.workload != "peg_batch_5k":
-        print("--mesh unstructured applies to peg_batch_5k only", file=sys.stderr)
-        sys.exit(1)
-    workload = make(n_envs=args.envs, n_steps=20, precision=args.precision, **kw)
+    workload = make(n_envs=args.envs, n_steps=20, precision=args.precision)
     if n_steps > workload.n_steps:
         print(f"warmup + steps must be <= {workload.n_steps}", file=sys.stderr)
         sys.exit(1)
@@ -363,7 +357,7 @@ def main():
                    "gel_tets": sorted({int(m.n_tets) for m in workload.meshes.values()}),
                    "indenters": sorted(workload.indenters),
                    "load_steps_timed": f"{W + 1}..{W + K} of 20", "tol_mm": args.tol,
-                   "precision": args.precision, "mesh": args.mesh, "all_converged": bool(status_ok),
+                   "precision": args.precision, "all_converged": bool(status_ok),
                    "form": (f"dynamic (dt {args.dt:g} s, density {args.density:g} t/mm^3)" if args.dynamic
                             else "quasi-static"),
                    "pncg_iters_per_env_step": iters_mean, "launch": args.launch,
