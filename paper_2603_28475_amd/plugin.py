@@ -6,7 +6,7 @@ to the sensor at the start and at the end of the step; that motion, as a
 linear and an angular velocity, drives the tactile simulation, whose marker
 displacement field is handed back as part of the observation (Sec. 3.3,
 "Integrating to Physics Engine"). The policy sees the field of one finger as
-a 7 x 9 grid of in-plane displacements (Sec. 5, online RL).
+a 7 x 9 grid of in-plane displacements (Sec. 5.3, online RL).
 
 Poses are (t_x, t_y, t_z, q_w, q_x, q_y, q_z) of the indenter (the object) in
 the gel's frame, as everywhere in this package. The velocity integration is
