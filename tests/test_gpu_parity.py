@@ -865,9 +865,9 @@ def test_unstructured_peg_friction_sequence_matches_newton_oracle():
     assert np.abs(m - gold["markers"]).max() <= 1e-6
 
 
-@pytest.mark.skip(reason="a batch of 256 or more unstructured 5k envs did not finish its first load "
-                         "step within minutes, even with iterations and substeps capped, while 4 envs "
-                         "converge in 0.45 s; the cause is not found, so the case stays off the GPU")
+@pytest.mark.skip(reason="a batch of 256 unstructured 5k envs did not finish its first load step "
+                         "within three minutes (also with iterations and substeps capped) while 4 envs "
+                         "converge in 0.45 s; the cause is not shown, so the case stays off the GPU")
 def test_c3_unstructured_full_size_sampled_envs_are_oracle_equilibria():
     """The headline batch on the unstructured 5k gel (4,914 v, 27,063 t) at full
     size in the bench's launch shape: every env converges and three sampled
