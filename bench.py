@@ -4,9 +4,12 @@
 Workload (default): 2048 environments, each a 20x16x4 mm gel meshed with
 25x20x8 hexes (4,914 vertices, 24,000 tets) pressed by an end-on peg
 (r = 4 mm, 2,048 triangles) at a seeded pose, 20 press steps to a seeded
-depth; all envs advance one load step per launch of the persistent kernel.
-A "step" is one such load step of every env: continuation, culling, every
+depth. A "step" is one load step of every env: continuation, culling, every
 PNCG iteration to tolerance and the marker output.
+
+Timing: W warmup load steps of the schedule are run and discarded, every env
+is put back at rest, and load steps 1..K of the 20-step schedule (K <= 20,
+load step 1 from rest included) are timed in one persistent launch.
 
 Prints one JSON line: env-steps/s of the batched launch, the roofline of the
 step kernel from HIP-event timings, the unbatched ("plain") solver on the
@@ -34,8 +37,10 @@ BYTES_PER_VERT_ITER = 384  # 16 vector passes x 3 coords x 8 B per PNCG iteratio
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=19)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="load steps timed, 1..20 of the press schedule, from rest")
+    ap.add_argument("--warmup", type=int, default=2,
+                    help="untimed load steps of the schedule before the timed run (envs reset after)")
     ap.add_argument("--workload", choices=["peg_batch_5k", "mixed_batch"], default="peg_batch_5k",
                     help="peg_batch_5k: uniform 2048 x 5k gels (headline); mixed_batch: 512 envs over "
                          "three gel sizes and three indenters")
@@ -54,8 +59,8 @@ def parse():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--adjoint", action="store_true",
-                    help="time the adjoint instead: 64 envs of the 5k gel, frictionless, 20 load steps "
-                         "forward, then one t2r_backward launch (prints its own JSON line)")
+                    help="time the adjoint instead: 64 envs of the 5k gel with friction, 20 load steps "
+                         "recorded forward, then one t2r_backward_sequence launch (prints its own JSON line)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the block-shape / pair-capacity autotuner (setup, not timed)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -82,34 +87,82 @@ def log(args, *a):
         print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(args, workload, iters_per_env_step):
-    """The oracle's PNCG reference (one thread) on env 0, timed per iteration.
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    A full load step takes the numpy oracle tens of minutes at this mesh size,
-    so it runs as many iterations of the first solve of load step 1 as fit in
-    the budget, and the per-iteration time is scaled by the GPU run's mean
-    PNCG iterations per env-step (same algorithm and tolerance)."""
-    from oracle.geometry import slerp_pose  # noqa: F401
+
+def _oracle_worker(job):
+    """One env of the workload, load step 1 from rest, through the oracle's PNCG
+    reference (numpy FP64, BLAS threads 1) with the same continuation rule as the
+    GPU path, until `seconds` have passed. Returns (iterations, seconds spent in
+    solves that iterated)."""
+    workload, env_id, seconds, tol = job
+    from oracle.geometry import slerp_pose
     from oracle.pncg import pncg_solve
-    from oracle.sim import build
-    env = workload.envs[0]
+    from oracle.sim import build, continuation_increment
+    env = workload.envs[env_id]
     gel, ind, prob = build(workload.meshes[env.mesh], workload.indenters[env.indenter], env)
-    prob.set_lag(gel.X, env.poses[0])
-    prob.set_pose(env.poses[1])
+    q0, q1 = env.poses[0], env.poses[1]
+    x = gel.X.copy()
+    prob.set_lag(x, q0)
+    deadline = time.perf_counter() + seconds
+    iters, spent, tau = 0, 0.0, 0.0
+    while tau < 1.0 and time.perf_counter() < deadline:
+        prob.set_pose(slerp_pose(q0, q1, tau))
+        dtau = continuation_increment(prob, x, q0, q1, tau, prob.d_min(x))
+        tau = min(1.0, tau + dtau)
+        prob.set_pose(slerp_pose(q0, q1, tau))
+        t0 = time.perf_counter()
+        x, info = pncg_solve(prob, x, tol=tol, deadline=deadline)
+        if info["iters"] > 0:  # solves out of contact converge at once
+            iters += info["iters"]
+            spent += time.perf_counter() - t0
+    return iters, spent
+
+
+def cpu_baseline_measure(args, workload):
+    """Times the oracle's PNCG reference on the host's cores: one env per process
+    (envs 0..P-1 of the workload, P = the usable cores, at most 16), each running
+    load step 1 from rest for about args.cpu_seconds. Returns the per-iteration
+    time of one process; the caller scales it by the GPU run's PNCG iterations
+    per env-step (same algorithm and tolerance). Runs before the GPU is touched,
+    so that the pool's processes fork from a process without a HIP context."""
+    import multiprocessing as mp
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16, len(workload.envs)))
+    jobs = [(workload, i, args.cpu_seconds, args.tol) for i in range(cores)]
     t0 = time.perf_counter()
-    pncg_solve(prob, gel.X, tol=args.tol, max_iters=1)
-    t1 = time.perf_counter() - t0
-    n = max(2, int(args.cpu_seconds / max(t1, 1e-3)))
-    t0 = time.perf_counter()
-    _, info = pncg_solve(prob, gel.X, tol=args.tol, max_iters=n)
-    dt = time.perf_counter() - t0
-    done = max(1, info["iters"])
-    per_iter = dt / done
-    return {"value": 1.0 / (per_iter * iters_per_env_step), "unit": "env-steps/s", "cores": 1,
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    iters = sum(r[0] for r in res)
+    busy = sum(r[1] for r in res)
+    return {"cores": cores, "iters": iters, "busy_s": busy, "wall_s": wall,
+            "s_per_iter": busy / max(iters, 1), "cpu_model": _cpu_model()}
+
+
+def cpu_baseline(meas, iters_per_env_step, workload_name):
+    """env-steps/s of the oracle on the measured cores: every process solves its
+    own env, so the rate is cores / (seconds per iteration x iterations per env-step)."""
+    per_step = meas["s_per_iter"] * iters_per_env_step
+    return {"value": meas["cores"] / per_step, "unit": "env-steps/s", "cores": meas["cores"],
             "kind": "oracle",
-            "sample": f"env 0, first solve of load step 1: {done} PNCG iterations of the numpy FP64 "
-                      f"oracle in {dt:.1f} s ({per_iter:.2f} s/iteration, one thread), scaled by "
-                      f"{iters_per_env_step:.0f} iterations per env-step (GPU run mean)"}
+            "cpu_model": meas["cpu_model"],
+            "sample": (f"{workload_name}: envs 0..{meas['cores'] - 1}, one per process (numpy FP64 PNCG "
+                       f"reference, BLAS threads 1), load step 1 from rest for {meas['busy_s'] / meas['cores']:.0f} s "
+                       f"each: {meas['iters']} PNCG iterations, {meas['s_per_iter']:.2f} s per iteration and "
+                       f"process; extrapolated to whole env-steps with the GPU run's "
+                       f"{iters_per_env_step:.0f} PNCG iterations per env-step (same algorithm and tolerance)")}
 
 
 def adjoint_bench(args):
@@ -185,6 +238,9 @@ def adjoint_bench(args):
     print(json.dumps(line), flush=True)
 
 
+SCHEDULE_STEPS = 20  # load steps of every workload's press schedule
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -192,16 +248,17 @@ def main():
               "environments across GPUs with no exchange inside a step; see DESIGN.md.",
               file=sys.stderr)
         sys.exit(2)
+    W, K = args.warmup, args.steps
+    if not 1 <= K <= SCHEDULE_STEPS or W < 0:
+        print(f"--steps must be in 1..{SCHEDULE_STEPS} (the load steps of the press schedule, timed from "
+              f"rest) and --warmup >= 0; got --steps {K} --warmup {W}", file=sys.stderr)
+        sys.exit(2)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         os.environ[k] = "1"
     import numpy as np
     import torch
 
-    from paper_2603_28475_amd import t2r
-    from paper_2603_28475_amd.sim import Sim
-    from scenes.configs import mixed_batch, peg_batch_5k
-
-    if not torch.cuda.is_available():
+    if torch.cuda.device_count() < 1:  # counts devices without creating a HIP context
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     if args.adjoint:
@@ -215,15 +272,23 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8}))
         return
-    W, K = args.warmup, args.steps
-    n_steps = W + K
+
+    from scenes.configs import mixed_batch, peg_batch_5k
     if args.envs <= 0:
         args.envs = 2048 if args.workload == "peg_batch_5k" else 512
     make = peg_batch_5k if args.workload == "peg_batch_5k" else mixed_batch
-    workload = make(n_envs=args.envs, n_steps=20, precision=args.precision)
-    if n_steps > workload.n_steps:
-        print(f"warmup + steps must be <= {workload.n_steps}", file=sys.stderr)
-        sys.exit(1)
+    workload = make(n_envs=args.envs, n_steps=SCHEDULE_STEPS, precision=args.precision)
+
+    # the CPU oracle runs first, in processes forked before this one creates a HIP context
+    cpu_meas = None
+    if args.cpu_seconds > 0:
+        cpu_meas = cpu_baseline_measure(args, workload)
+        log(args, f"cpu oracle: {cpu_meas['cores']} processes, {cpu_meas['iters']} iterations, "
+                  f"{cpu_meas['s_per_iter']:.2f} s/iteration")
+
+    from paper_2603_28475_amd import t2r
+    from paper_2603_28475_amd.sim import Sim
+
     prec = 0 if args.precision == "f64" else 1
     opts = t2r.default_opts(tol=args.tol, precision=prec, block_size=args.block, dynamic=int(args.dynamic),
                             dt=args.dt, density=args.density)
@@ -231,14 +296,29 @@ def main():
     sim = Sim.from_workload(workload, opts)
     poses = torch.as_tensor(np.stack([e.poses for e in workload.envs]), dtype=torch.float64,
                             device="cuda:0")
-    pose_steps = [poses[:, s].contiguous() for s in range(n_steps + 1)]
     log(args, f"built {args.envs} envs in {time.perf_counter() - t_build:.1f}s")
     stream = torch.cuda.current_stream()
     nv_env = np.array([workload.meshes[e.mesh].n_verts for e in workload.envs], dtype=np.float64)
     nt_env = np.array([workload.meshes[e.mesh].n_tets for e in workload.envs], dtype=np.float64)
+    all_envs = list(range(args.envs))
 
-    def seq(a, b):  # poses of load steps a..b-1 as (steps, n_env, 7)
-        return poses[:, a:b].transpose(0, 1).contiguous()
+    def seq(a, b, envs=slice(None)):  # poses of load steps a..b-1 as (steps, n_env, 7)
+        return poses[envs, a:b].transpose(0, 1).contiguous()
+
+    def warmup(sm, envs):
+        """W load steps of the schedule from rest (in launches of at most the whole
+        schedule), then every env back at rest."""
+        left = W
+        while left > 0:
+            n = min(left, SCHEDULE_STEPS)
+            if args.launch == "sequence":
+                sm.step_sequence(seq(1, n + 1, envs))
+            else:
+                for s in range(1, n + 1):
+                    sm.step(poses[envs, s].contiguous())
+            sm.ctx.reset_envs(list(range(sm.n_env)))
+            left -= n
+        torch.cuda.synchronize()
 
     tuned = None
     if not args.no_autotune and args.block == 0:
@@ -246,64 +326,60 @@ def main():
         tuned = sim.autotune(seq(1, 2), target_steps=K if args.launch == "sequence" else 1)
         log(args, f"autotune: {tuned}")
 
-    if W > 0:
-        if args.launch == "sequence":
-            sim.step_sequence(seq(1, W + 1))
-        else:
-            for s in range(1, W + 1):
-                sim.step(pose_steps[s])
-        torch.cuda.synchronize()
-        st = sim.stats()
-        log(args, f"warmup ({W} load steps): iters/env {np.mean([x['iters'] for x in st]):.0f}")
+    warmup(sim, slice(None))
+    log(args, f"warmup: {W} load steps, envs back at rest")
 
+    # output buffers exist before the timed region (no allocation or fill inside it)
+    n_m = sum(sim.n_m)
+    markers = torch.zeros((K, n_m, 3), dtype=torch.float64, device="cuda:0")
+    status = torch.zeros((K, args.envs), dtype=torch.int32, device="cuda:0")
+    pose_seq = seq(1, K + 1)
     torch.cuda.synchronize()
     iters = []          # per launch: PNCG iterations of every env
     launch_ms = []
-    status_ok = True
     t0 = time.perf_counter()
     if args.launch == "sequence":
         start = torch.cuda.Event(enable_timing=True)
         end = torch.cuda.Event(enable_timing=True)
         start.record(stream)
-        _, status = sim.step_sequence(seq(W + 1, W + K + 1))
+        sim.ctx.step_sequence(K, pose_seq, None, markers, None, status)
         end.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         launch_ms.append(start.elapsed_time(end))
         st = sim.stats()
         iters.append(np.array([x["iters"] for x in st], dtype=np.int64))
-        status_ok = bool(((status.cpu().numpy() & t2r.ENV_CONVERGED) != 0).all())
-        log(args, f"load steps {W + 1}..{W + K} in one launch: {launch_ms[0]:.1f} ms, iters/env-step mean "
+        log(args, f"load steps 1..{K} in one launch: {launch_ms[0]:.1f} ms, iters/env-step mean "
                   f"{iters[0].mean() / K:.0f}, env total max {iters[0].max()}")
     else:
         starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
         ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+        per_step = [pose_seq[k] for k in range(K)]
         for k in range(K):
-            s = W + 1 + k
             starts[k].record(stream)
-            sim.step(pose_steps[s])
+            sim.ctx.step(per_step[k], None, markers[k], None, status[k])
             ends[k].record(stream)
             st = sim.stats()  # synchronises; needed for the per-launch iteration counts
             iters.append(np.array([x["iters"] for x in st], dtype=np.int64))
-            status_ok &= all(x["status"] & t2r.ENV_CONVERGED for x in st)
-            log(args, f"step {s}: {starts[k].elapsed_time(ends[k]):.1f} ms, iters/env mean "
+            log(args, f"step {k + 1}: {starts[k].elapsed_time(ends[k]):.1f} ms, iters/env mean "
                       f"{iters[-1].mean():.0f} max {iters[-1].max()}")
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         launch_ms = [starts[k].elapsed_time(ends[k]) for k in range(K)]
+    status_ok = bool(((status.cpu().numpy() & t2r.ENV_CONVERGED) != 0).all())
     value = args.envs * K / wall
     # roofline of the step kernel: algorithmic vector bytes per launch / launch time
     bytes_per_launch = [float((it * nv_env).sum()) * BYTES_PER_VERT_ITER for it in iters]
     achieved = float(np.mean([b / (t * 1e-3) for b, t in zip(bytes_per_launch, launch_ms)]))
     # HBM bytes of the same launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled
-    # by a 1 GiB copy), valid only for the kernel source they were taken with
+    # by a 1 GiB copy), valid only for the kernel source and launch they were taken with
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"t2r_step_kernel_{workload.name}_traffic.json")
-    if os.path.exists(tfile) and args.launch == "sequence" and W == 1 and K == 19 and not args.dynamic:
+    if os.path.exists(tfile) and args.launch == "sequence" and not args.dynamic:
         with open(tfile) as fh:
             tr = json.load(fh)
         if (tr.get("source_hash") == source_hash() and tr.get("envs") == args.envs
-                and tr.get("precision") == args.precision):
+                and tr.get("precision") == args.precision and tr.get("load_steps") == K):
             traffic = tr.get("bytes_per_launch")
     # FP64-vector view of the same launch: element flops per iteration under the
     # reference schedule (about 350 per tet for energy, gradient and diagonal,
@@ -321,24 +397,22 @@ def main():
         n = min(args.plain_envs, args.envs)
         sims = [Sim.from_workload(workload, opts, envs=[i]) for i in range(n)]
         for i_, sm in enumerate(sims):
-            if W > 0:
-                sm.step_sequence(poses[i_:i_ + 1, 1:W + 1].transpose(0, 1).contiguous())
-        torch.cuda.synchronize()
+            warmup(sm, slice(i_, i_ + 1))
         tp = time.perf_counter()
         for i_, sm in enumerate(sims):
             if args.launch == "sequence":
-                sm.step_sequence(poses[i_:i_ + 1, W + 1:W + K + 1].transpose(0, 1).contiguous())
+                sm.step_sequence(seq(1, K + 1, slice(i_, i_ + 1)))
             else:
-                for s in range(W + 1, W + K + 1):
+                for s in range(1, K + 1):
                     sm.step(poses[i_:i_ + 1, s].contiguous())
         torch.cuda.synchronize()
         dtp = time.perf_counter() - tp
         plain = {"value": n * K / dtp, "unit": "env-steps/s",
-                 "sample": f"envs 0..{n - 1}, load steps {W + 1}..{W + K}, one env per launch",
+                 "sample": f"envs 0..{n - 1}, load steps 1..{K} from rest, one env per launch",
                  "batched_over_plain": value / (n * K / dtp)}
 
     iters_mean = float(sum(it.sum() for it in iters)) / (args.envs * K)
-    cpu = cpu_baseline(args, workload, iters_mean) if args.cpu_seconds > 0 else None
+    cpu = cpu_baseline(cpu_meas, iters_mean, workload.name) if cpu_meas else None
     line = {
         "metric": "env-steps/s at fixed PNCG tol (batched)",
         "value": value,
@@ -356,7 +430,7 @@ def main():
                    "gel_verts": sorted({int(m.n_verts) for m in workload.meshes.values()}),
                    "gel_tets": sorted({int(m.n_tets) for m in workload.meshes.values()}),
                    "indenters": sorted(workload.indenters),
-                   "load_steps_timed": f"{W + 1}..{W + K} of 20", "tol_mm": args.tol,
+                   "load_steps_timed": f"1..{K} of {SCHEDULE_STEPS}, from rest", "tol_mm": args.tol,
                    "precision": args.precision, "all_converged": bool(status_ok),
                    "form": (f"dynamic (dt {args.dt:g} s, density {args.density:g} t/mm^3)" if args.dynamic
                             else "quasi-static"),

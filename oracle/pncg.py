@@ -30,6 +30,8 @@ From Supp. A (eqs. dk_direction and step_size) with these readings:
 
 from __future__ import annotations
 
+import time
+
 import numpy as np
 
 from .ccd import ccd_step
@@ -49,8 +51,10 @@ def _precond(prob, x, free):
     return P
 
 
-def pncg_solve(prob, x0, tol=1e-6, max_iters=100000, armijo=True, record=None):
-    """Run PNCG from the feasible x0. Returns (x, info). `record` collects per-iteration data."""
+def pncg_solve(prob, x0, tol=1e-6, max_iters=100000, armijo=True, record=None, deadline=None):
+    """Run PNCG from the feasible x0. Returns (x, info). `record` collects per-iteration data.
+    deadline: a time.perf_counter() value after which no further iteration starts
+    (for bounded timing runs; info["timed_out"] is then set)."""
     x = np.array(x0, dtype=np.float64)
     free = ~prob.gel.fixed
     E = prob.energy(x)
@@ -67,6 +71,9 @@ def pncg_solve(prob, x0, tol=1e-6, max_iters=100000, armijo=True, record=None):
             info["converged"] = True
             break
         if k == max_iters:
+            break
+        if deadline is not None and time.perf_counter() > deadline:
+            info["timed_out"] = True
             break
         pinf = float(np.abs(p).max())
         gp = float(np.sum(g * p))
