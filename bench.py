@@ -7,9 +7,12 @@ Workload (default): 2048 environments, each a 20x16x4 mm gel meshed with
 depth. A "step" is one load step of every env: continuation, culling, every
 PNCG iteration to tolerance and the marker output.
 
-Timing: W warmup load steps of the schedule are run and discarded, every env
-is put back at rest, and load steps 1..K of the 20-step schedule (K <= 20,
-load step 1 from rest included) are timed in one persistent launch.
+Timing: warmup runs ceil(W / K) untimed launches of the timed sequence itself
+(load steps 1..K of the 20-step schedule from rest, so at least W load steps),
+each followed by a reset of every env to rest; then load steps 1..K (K <= 20,
+load step 1 from rest included) are timed in one persistent launch. Every
+launch of the step kernel in a run therefore has the timed launch's shape, and
+a profiler's per-kernel average equals the timed launch's duration.
 
 Prints one JSON line: env-steps/s of the batched launch, the roofline of the
 step kernel from HIP-event timings, the unbatched ("plain") solver on the
@@ -40,7 +43,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20,
                     help="load steps timed, 1..20 of the press schedule, from rest")
     ap.add_argument("--warmup", type=int, default=2,
-                    help="untimed load steps of the schedule before the timed run (envs reset after)")
+                    help="untimed load steps before the timed run: ceil(W/K) launches of the timed "
+                         "sequence, envs reset to rest after each")
     ap.add_argument("--workload", choices=["peg_batch_5k", "mixed_batch"], default="peg_batch_5k",
                     help="peg_batch_5k: uniform 2048 x 5k gels (headline); mixed_batch: 512 envs over "
                          "three gel sizes and three indenters")
@@ -61,8 +65,10 @@ def parse():
     ap.add_argument("--adjoint", action="store_true",
                     help="time the adjoint instead: 64 envs of the 5k gel with friction, 20 load steps "
                          "recorded forward, then one t2r_backward_sequence launch (prints its own JSON line)")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="skip the block-shape / pair-capacity autotuner (setup, not timed)")
+    ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
+                    help="block-shape / pair-capacity autotuner (setup, not timed); auto: on for the "
+                         "uneven mixed_batch, off for the uniform batch (whose shape the automatic rule "
+                         "picks: 256 threads when the envs outnumber the compute units)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -88,6 +94,15 @@ def log(args, *a):
 
 
 def _cpu_model() -> str:
+    """The CPU model as lscpu reports it (else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
@@ -96,6 +111,13 @@ def _cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
+
+
+def _nproc() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
 
 def _oracle_worker(job):
@@ -135,11 +157,8 @@ def cpu_baseline_measure(args, workload):
     per env-step (same algorithm and tolerance). Runs before the GPU is touched,
     so that the pool's processes fork from a process without a HIP context."""
     import multiprocessing as mp
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16, len(workload.envs)))
+    nproc = _nproc()
+    cores = max(1, min(nproc, 16, len(workload.envs)))
     jobs = [(workload, i, args.cpu_seconds, args.tol) for i in range(cores)]
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
@@ -148,7 +167,7 @@ def cpu_baseline_measure(args, workload):
     iters = sum(r[0] for r in res)
     busy = sum(r[1] for r in res)
     return {"cores": cores, "iters": iters, "busy_s": busy, "wall_s": wall,
-            "s_per_iter": busy / max(iters, 1), "cpu_model": _cpu_model()}
+            "s_per_iter": busy / max(iters, 1), "cpu_model": _cpu_model(), "nproc": nproc}
 
 
 def cpu_baseline(meas, iters_per_env_step, workload_name):
@@ -157,7 +176,7 @@ def cpu_baseline(meas, iters_per_env_step, workload_name):
     per_step = meas["s_per_iter"] * iters_per_env_step
     return {"value": meas["cores"] / per_step, "unit": "env-steps/s", "cores": meas["cores"],
             "kind": "oracle",
-            "cpu_model": meas["cpu_model"],
+            "cpu_model": meas["cpu_model"], "nproc": meas["nproc"],
             "sample": (f"{workload_name}: envs 0..{meas['cores'] - 1}, one per process (numpy FP64 PNCG "
                        f"reference, BLAS threads 1), load step 1 from rest for {meas['busy_s'] / meas['cores']:.0f} s "
                        f"each: {meas['iters']} PNCG iterations, {meas['s_per_iter']:.2f} s per iteration and "
@@ -306,28 +325,26 @@ def main():
         return poses[envs, a:b].transpose(0, 1).contiguous()
 
     def warmup(sm, envs):
-        """W load steps of the schedule from rest (in launches of at most the whole
-        schedule), then every env back at rest."""
-        left = W
-        while left > 0:
-            n = min(left, SCHEDULE_STEPS)
+        """ceil(W / K) untimed runs of the timed sequence (load steps 1..K from rest),
+        every env back at rest after each."""
+        for _ in range(-(-W // K)):
             if args.launch == "sequence":
-                sm.step_sequence(seq(1, n + 1, envs))
+                sm.step_sequence(seq(1, K + 1, envs))
             else:
-                for s in range(1, n + 1):
+                for s in range(1, K + 1):
                     sm.step(poses[envs, s].contiguous())
             sm.ctx.reset_envs(list(range(sm.n_env)))
-            left -= n
         torch.cuda.synchronize()
 
     tuned = None
-    if not args.no_autotune and args.block == 0:
+    use_tuner = args.autotune == "on" or (args.autotune == "auto" and args.workload == "mixed_batch")
+    if use_tuner and args.block == 0:
         # setup (not timed): trial the first load step with each block shape, state restored
         tuned = sim.autotune(seq(1, 2), target_steps=K if args.launch == "sequence" else 1)
         log(args, f"autotune: {tuned}")
 
     warmup(sim, slice(None))
-    log(args, f"warmup: {W} load steps, envs back at rest")
+    log(args, f"warmup: {-(-W // K)} launch(es) of load steps 1..{K}, envs back at rest")
 
     # output buffers exist before the timed region (no allocation or fill inside it)
     n_m = sum(sim.n_m)

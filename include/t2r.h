@@ -66,8 +66,13 @@ enum {
   T2R_ENV_NONFINITE = 8,      /* NaN/Inf pose or state; the env was not advanced */
   T2R_ENV_PAIR_OVERFLOW = 16, /* contact pair list overflowed; env rolled back */
   T2R_ENV_LINESEARCH = 32,    /* 30 halvings found no acceptable step */
-  T2R_ENV_SUBSTEPS = 64,      /* continuation hit max_substeps before the target */
-  T2R_ENV_SKIPPED = 128       /* masked out by the caller; state unchanged */
+  T2R_ENV_SUBSTEPS = 64,      /* continuation hit max_substeps before the target pose: the
+                                 env keeps the equilibrium of the last pose it reached, which
+                                 becomes its pose (t2r_get_state) */
+  T2R_ENV_SKIPPED = 128,      /* masked out by the caller; state unchanged */
+  T2R_ENV_BUDGET = 256        /* the env used up max_evals in this launch: the load step is
+                                 rolled back (with T2R_ENV_MAXITER), the env keeps its last
+                                 completed step's state and pose for the rest of the launch */
 };
 
 /* Material and contact parameters of one environment.
@@ -107,7 +112,13 @@ typedef struct { double E, nu, mu_f, eps_v, dhat, kappa; } t2r_material;
  *                 quasi-static form. The adjoint and t2r_eval cover the
  *                 quasi-static form only.
  *   dt, density   time step (s) and mass density (t/mm^3, so that forces are in
- *                 N: 1,100 kg/m^3 = 1.1e-9) of the dynamic form */
+ *                 N: 1,100 kg/m^3 = 1.1e-9) of the dynamic form
+ *   max_evals     work budget of one env in one launch: energy (line-search trial)
+ *                 plus curvature evaluation passes over its mesh and contact list;
+ *                 0 = no limit. Every loop of a solve is bounded (max_iters, 30
+ *                 halvings, max_substeps), but those bounds multiply; this one caps
+ *                 the product, so a launch ends after at most about max_evals passes
+ *                 of its slowest env (T2R_ENV_BUDGET) */
 typedef struct {
   double tol;
   double substep_tol;
@@ -121,6 +132,7 @@ typedef struct {
   int32_t dynamic;
   double dt;
   double density;
+  int32_t max_evals;
 } t2r_solver_opts;
 
 /* Per-environment counters of the last launch (t2r_step or t2r_step_sequence;
@@ -149,11 +161,13 @@ typedef struct {
                             and friction, [7] vector passes, [8] the whole launch, [9] friction lag */
   double list_fill;      /* largest (list length / capacity) of the inner, outer and friction
                             lists during the launch; > 1 means a list overflowed */
+  int32_t evals;         /* energy and curvature evaluation passes of the launch (see max_evals) */
+  int32_t reserved;
 } t2r_env_stats;
 
 /* Fills *o with the defaults: tol 1e-6, substep_tol 1e-4, max_iters 20000,
  * max_substeps 1000, precision 0, pair_capacity 0, armijo 1, block_size 0, warm_start 1,
- * dynamic 0, dt 1/60, density 1.1e-9. */
+ * dynamic 0, dt 1/60, density 1.1e-9, max_evals 200000. */
 void t2r_default_opts(t2r_solver_opts* o);
 
 /* Creates a context bound to `hip_stream` (a hipStream_t, or NULL for the null
@@ -296,6 +310,14 @@ t2r_status t2r_reset_envs(t2r_ctx* ctx, const int32_t* env_ids, int32_t n);
  * call this reallocates the pair lists (positions and poses are kept; the lists
  * are rebuilt on the next step). T2R_E_NOMEM leaves the old capacity. */
 t2r_status t2r_set_pair_capacity(t2r_ctx* ctx, int32_t capacity);
+
+/* Generation counter of the context's launch layout: it changes whenever the
+ * parameters or device buffers a launch captures change (the first GPU call,
+ * t2r_set_pair_capacity, t2r_set_opts, t2r_set_materials, t2r_record). A
+ * caller that replays a captured t2r_step (a HIP graph) must capture again
+ * after it changes: the old capture may refer to freed buffers or stale
+ * options. Host only. */
+t2r_status t2r_layout_generation(const t2r_ctx* ctx, int64_t* gen);
 
 /* Reads / replaces the solver options. Every field may change between steps
  * (block_size picks the workgroup shape of the next launch; a new

@@ -107,6 +107,9 @@ struct t2r_ctx {
   // trajectory tape (t2r_record): tape_cap recorded steps at most, tape_len so far
   double *d_tape_x = nullptr, *d_tape_q = nullptr;
   int tape_cap = 0, tape_len = 0;
+  // bumped whenever a launch's parameters or device buffers change (allocation,
+  // relayout, options, tape, materials): a captured launch is stale after a bump
+  int64_t layout_gen = 0;
   // two-entry tape of the single-step adjoint (x_{s-1}, x_s)
   double *d_bw_x = nullptr, *d_bw_q = nullptr;
   uint64_t* d_oslot = nullptr;
@@ -296,6 +299,7 @@ void t2r_default_opts(t2r_solver_opts* o) {
   o->dynamic = 0;
   o->dt = 1.0 / 60.0;
   o->density = 1.1e-9;
+  o->max_evals = 200000;
 }
 
 static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
@@ -304,6 +308,7 @@ static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
   if (o->max_iters < 0 || o->max_substeps < 1) return fail(c, T2R_E_ARG, "max_iters >= 0 and max_substeps >= 1 required");
   if (o->precision != 0 && o->precision != 1) return fail(c, T2R_E_ARG, "precision must be 0 or 1");
   if (o->pair_capacity < 0) return fail(c, T2R_E_ARG, "pair_capacity must be >= 0");
+  if (o->max_evals < 0) return fail(c, T2R_E_ARG, "max_evals must be >= 0 (0: no limit)");
   if (o->block_size != 0 && o->block_size != 256 && o->block_size != 512)
     return fail(c, T2R_E_ARG, "block_size must be 0 (256), 256 or 512");
   if (o->warm_start != 0 && o->warm_start != 1) return fail(c, T2R_E_ARG, "warm_start must be 0 or 1");
@@ -805,6 +810,7 @@ t2r_status t2r_set_materials(t2r_ctx* c, int32_t n, const int32_t* env_ids, cons
     if (!valid_material(mats[i])) return fail(c, T2R_E_ARG, "env %d: invalid material", env_ids[i]);
   }
   if (c->committed) HIP_TRY(c, hipStreamSynchronize(c->stream));  // earlier work may read the descriptors
+  ++c->layout_gen;
   for (int i = 0; i < n; ++i) {
     const int e = env_ids[i];
     c->envs[e].mat = mats[i];
@@ -914,6 +920,7 @@ static StepParams step_params(t2r_ctx* c) {
   P.substep_tol = c->opts.substep_tol;
   P.max_iters = c->opts.max_iters;
   P.max_substeps = c->opts.max_substeps;
+  P.max_evals = c->opts.max_evals;
   P.precision = c->opts.precision;
   P.armijo = c->opts.armijo;
   P.warm_start = c->opts.warm_start;
@@ -1164,6 +1171,7 @@ t2r_status t2r_set_pair_capacity(t2r_ctx* c, int32_t cap) {
   if (cap > (1 << 24)) return fail(c, T2R_E_ARG, "pair capacity too large");
   const int32_t old = c->opts.pair_capacity;
   c->opts.pair_capacity = cap;
+  ++c->layout_gen;
   if (c->committed && cap != old) {
     const t2r_status s = relayout_lists(c);
     if (s != T2R_OK) { c->opts.pair_capacity = old; return s; }
@@ -1187,7 +1195,14 @@ t2r_status t2r_set_opts(t2r_ctx* c, const t2r_solver_opts* o) {
     if (s != T2R_OK) return s;
   }
   c->opts = *o;
+  ++c->layout_gen;
   c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_layout_generation(const t2r_ctx* c, int64_t* gen) {
+  if (!c || !gen) return T2R_E_ARG;
+  *gen = c->layout_gen;
   return T2R_OK;
 }
 
@@ -1201,6 +1216,7 @@ t2r_status t2r_record(t2r_ctx* c, int32_t max_steps) {
   dev_free(c, c->d_tape_q);
   c->d_tape_x = c->d_tape_q = nullptr;
   c->tape_cap = c->tape_len = 0;
+  ++c->layout_gen;
   if (max_steps == 0) {
     c->err.clear();
     return T2R_OK;
@@ -1365,6 +1381,7 @@ int pair_cap_of(const t2r_ctx* c, const GelHost& g) {
 // and every env's lists are marked invalid.
 t2r_status relayout_lists(t2r_ctx* c) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  ++c->layout_gen;
   std::vector<EnvDev> he = c->h_envs;
   long long poff = 0, foff = 0, ooff = 0;
   for (size_t i = 0; i < he.size(); ++i) {
@@ -1412,6 +1429,7 @@ t2r_status relayout_lists(t2r_ctx* c) {
 
 t2r_status commit(t2r_ctx* c) {
   if (c->committed) return T2R_OK;
+  ++c->layout_gen;
   int dev_count = 0;
   if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count == 0)
     return fail(c, T2R_E_HIP, "no HIP device available");

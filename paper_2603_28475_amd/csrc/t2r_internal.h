@@ -137,6 +137,7 @@ struct EnvStats {
   double d_min, residual, energy;
   double phase_ms[10];     // see t2r_env_stats
   double list_fill;        // largest list length / capacity seen in the launch
+  int evals, reserved;     // evaluation passes (energy + curvature) of the launch
 };
 
 struct StepParams {
@@ -181,6 +182,7 @@ struct StepParams {
   double clock_khz;        // wall-clock counter rate (phase timers)
   double tol, substep_tol;
   int max_iters, max_substeps, precision, armijo;
+  long long max_evals;           // energy + curvature passes per env per launch (<= 0: no limit)
   int warm_start;                // extrapolate the previous load step's displacement
   T2R_G double* gap0;            // [n_env] d_min at the start of the env's previous load step (0: unknown)
   T2R_G double* vel;             // [sum 3 n_v] velocities of the dynamic form

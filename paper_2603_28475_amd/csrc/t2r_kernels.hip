@@ -38,7 +38,7 @@ constexpr double kSqrt3 = 1.7320508075688772;
 
 // Status bits (mirror T2R_ENV_* in t2r.h).
 constexpr int kConverged = 1, kMaxIter = 2, kInfeasible = 4, kNonFinite = 8, kOverflow = 16,
-              kLineSearch = 32, kSubsteps = 64, kSkipped = 128;
+              kLineSearch = 32, kSubsteps = 64, kSkipped = 128, kBudget = 256;
 
 // ---------------------------------------------------------------------------
 // Workgroup shared state
@@ -351,7 +351,7 @@ __device__ __forceinline__ double elem_eval_impl(const View& V, const double* x,
       bool ok;
       if constexpr (MIXED) {
         ok = tet_grad_diag_mixed(Ds, tc.Dm, tc.vol, E.mu, E.lam, ed,
-                                 [&](int k, int c, float gv, float dv) {
+                                 [&](int k, int c, auto gv, auto dv) {
                                    atomicAdd(&T.g[c][l[k]], (double)gv);
                                    atomicAdd(&T.d[c][l[k]], (double)dv);
                                  });
@@ -480,7 +480,33 @@ __device__ __forceinline__ double elem_curv_impl(const View& V, const double* x,
             dDs[r * 3 + k] = T.p[r][l[k + 1]] - T.p[r][l[0]];
           }
         }
-      curv += (double)tet_curvature<Rl>(Ds, dDs, tc.Dm, tc.vol, (Rl)E.mu, (Rl)E.lam);
+      if constexpr (MIXED) {
+        // a tet squashed below kMixedMinJ: FP64 from the global positions
+        // (FP32 cofactors lose the sign of det F as J -> 0)
+        const float J32 = Ds[0] * (Ds[4] * Ds[8] - Ds[5] * Ds[7]) - Ds[1] * (Ds[3] * Ds[8] - Ds[5] * Ds[6]) +
+                          Ds[2] * (Ds[3] * Ds[7] - Ds[4] * Ds[6]);
+        const float Jref = 6.0f * tc.vol;  // det Ds at rest = 6 V
+        if (!(J32 > (float)kMixedMinJ * Jref)) {
+          double Ds64[9], dDs64[9], Dm64[9];
+          int gv[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) gv[k] = G.tet[k * G.n_t + e];
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              Ds64[r * 3 + k] = x[r * nv + gv[k + 1]] - x[r * nv + gv[0]];
+              dDs64[r * 3 + k] = p[r * nv + gv[k + 1]] - p[r * nv + gv[0]];
+            }
+#pragma unroll
+          for (int k = 0; k < 9; ++k) Dm64[k] = (double)tc.Dm[k];
+          curv += tet_curvature<double>(Ds64, dDs64, Dm64, (double)tc.vol, E.mu, E.lam);
+        } else {
+          curv += (double)tet_curvature<Rl>(Ds, dDs, tc.Dm, tc.vol, (Rl)E.mu, (Rl)E.lam);
+        }
+      } else {
+        curv += (double)tet_curvature<Rl>(Ds, dDs, tc.Dm, tc.vol, (Rl)E.mu, (Rl)E.lam);
+      }
       tc = tn;
     }
     if (t0 + (int)threadIdx.x >= t1) load_tet<MIXED>(G, first_tet(G, tile + 1), tc);
@@ -1211,6 +1237,8 @@ struct Solver {
   // stats
   int reculls, restarts, halvings, ncand, outer_builds;
   double fill;        // largest list length / capacity seen
+  // work budget: energy and curvature evaluation passes of this env in this launch
+  long long evals, max_evals;
 };
 
 // Inner candidate list from the outer one: exact distance of every coarse pair,
@@ -1623,6 +1651,7 @@ __device__ __forceinline__ double eval_all(Solver& s, const double* x, const dou
   View& V = s.V;
   int feas = 1, nact = 0;
   double v[3];
+  ++s.evals;
   unsigned long long t0 = tick();
   v[0] = elem_eval(V, x, p, alpha, g, dg, *s.T, feas);
   tock(*s.S, 5, t0);
@@ -1654,6 +1683,7 @@ __device__ __forceinline__ double eval_all(Solver& s, const double* x, const dou
 
 __device__ __forceinline__ double curvature_all(Solver& s, const double* x, const double* p) {
   View& V = s.V;
+  ++s.evals;
   unsigned long long t0 = tick();
   double c = elem_curv(V, x, p, *s.T);
   tock(*s.S, 2, t0);
@@ -1704,6 +1734,7 @@ __device__ __forceinline__ int pncg(Solver& s, double tol, int max_iters, int& i
   double* x = V.x;
   double* g0 = V.g0;
   double* g1 = V.g1;
+  if (s.evals >= s.max_evals) { iters = 0; return kMaxIter | kBudget; }
   if (!ensure_lists(s, x, 0.0)) return kOverflow;
   int feas, nact;
   unsigned long long t0;
@@ -1719,6 +1750,7 @@ __device__ __forceinline__ int pncg(Solver& s, double tol, int max_iters, int& i
   for (;; ++k) {
     if (res <= tol) { status = kConverged; break; }
     if (k >= max_iters) { status = kMaxIter; break; }
+    if (s.evals >= s.max_evals) { status = kMaxIter | kBudget; break; }
     const double a_up = dh / (2.0 * pinf);
     const double curv = curvature_all(s, x, V.p);
     const double a_bar = (curv > 0.0) ? -gp / curv : kInf;
@@ -1862,6 +1894,8 @@ __device__ __forceinline__ void init_solver(Solver& s, const StepParams& P, Shar
   s.xs_i = P.xsnap + E.snoff + 3 * (long long)G.n_sv;
   s.reculls = s.restarts = s.halvings = s.ncand = s.outer_builds = 0;
   s.fill = 0.0;
+  s.evals = 0;
+  s.max_evals = P.max_evals > 0 ? P.max_evals : (1ll << 62);
 }
 
 
@@ -2014,21 +2048,27 @@ __device__ __forceinline__ int load_step(const StepParams& P, int e, Solver& s, 
       ++sub;
       tau = tau_new;
       if (stt & (kOverflow | kInfeasible)) { status_acc = stt; break; }
+      if (stt & kBudget) { status_acc = stt; break; }  // the env stops: rolled back below
       if (!(stt & kConverged)) status_acc = (status_acc & ~kConverged) | stt;
       int na2 = 0;
       dmin = dmin_all(s, V.x, na2);
     }
-    if (tau < 1.0 && !(status_acc & (kOverflow | kInfeasible))) status_acc = (status_acc & ~kConverged) | kSubsteps;
+    if (tau < 1.0 && !(status_acc & (kOverflow | kInfeasible | kBudget)))
+      status_acc = (status_acc & ~kConverged) | kSubsteps;
   }
   status |= status_acc;
-  if (status & (kOverflow | kInfeasible)) {
+  if (status & (kOverflow | kInfeasible | kBudget)) {
     // roll back to x_{s-1}; the previous pose is kept
     for (int j = threadIdx.x; j < n; j += blockDim.x) V.x[j] = V.xprev[j];
     __syncthreads();
   } else {
     if (threadIdx.x == 0) {
+      // the pose x is in equilibrium with: q1, or the last continuation pose
+      // reached when max_substeps ended the step early (T2R_ENV_SUBSTEPS)
+      double q[7];
+      if (tau < 1.0) interp_pose(q0, q1, tau, q);
       #pragma unroll
-      for (int i = 0; i < 7; ++i) pose_prev[i] = q1[i];
+      for (int i = 0; i < 7; ++i) pose_prev[i] = tau < 1.0 ? q[i] : q1[i];
     }
     if (S.iw > 0.0) {  // dynamic form: v = (x - x^t) / dt
       const double idt = 1.0 / S.dt;
@@ -2097,6 +2137,7 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
   st.d_min = kInf; st.residual = 0.0; st.energy = 0.0;
   for (int k = 0; k < 10; ++k) st.phase_ms[k] = 0.0;
   st.list_fill = 0.0;
+  st.evals = 0; st.reserved = 0;
   const bool skip = P.env_mask && P.env_mask[e] == 0;
   load_lists(s);
   for (int k = 0; k < P.n_steps; ++k) {
@@ -2130,6 +2171,7 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
   st.n_candidates = s.ncand;
   st.n_outer = V.nouter;
   st.list_fill = s.fill;
+  st.evals = (int)min(s.evals, (long long)INT32_MAX);
   if (P.x_out) {
     T2R_G double* xo = P.x_out + 3 * P.x_out_off[e];
     for (int j = threadIdx.x; j < 3 * nv; j += blockDim.x) {
@@ -2540,7 +2582,7 @@ __device__ __forceinline__ void fric_hvp(const View& V, const Shared& S, Tile& T
 // parameters w move with the points by the implicit-function theorem on the
 // closest-point optimality D^T r = 0: (D^T D) dw = -sum_i (Cw_i r + c_i D) dz_i.
 // Global-memory path (one pass per load step).
-__device__ void fric_adjoint(const View& V, const Shared& S, Tile& T, const double* xs, const double* xp,
+__device__ __forceinline__ void fric_adjoint(const View& V, const Shared& S, Tile& T, const double* xs, const double* xp,
                              const double* lam, const double qp[7], double mrec, double acc[7],
                              double* carry) {
   const GelDev& G = *V.G;
@@ -2806,6 +2848,7 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_backward_ke
   st.outer_builds = 0; st.n_outer = 0; st.d_min = 0.0; st.residual = 0.0; st.energy = 0.0;
   for (int k = 0; k < 10; ++k) st.phase_ms[k] = 0.0;
   st.list_fill = 0.0;
+  st.evals = 0; st.reserved = 0;
   const unsigned long long t_start = tick();
   load_lists(s);
   const double muf = E.mu_f;

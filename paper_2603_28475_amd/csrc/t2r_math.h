@@ -101,13 +101,30 @@ __device__ __forceinline__ bool tet_grad_diag64(const double Ds[9], const double
   return true;
 }
 
+// Below this volume ratio J the mixed path computes a tet's element terms in
+// FP64. FP32 element terms lose about cond(F) x 2^-24 in relative accuracy, and
+// a tet squashed towards zero volume has cond(F) ~ 1/J: near J = 1e-7 the FP32
+// cofactors no longer carry the sign of det F, the stress points the wrong way
+// and the search direction stops being a descent direction for the FP64 energy
+// (a collapsed surface tet under a flat indenter stalled a solve that way). At
+// J >= 0.1 the FP32 terms stay within about 1e-6 relative.
+constexpr double kMixedMinJ = 0.1;
+
 // Mixed tet: F, J, ln J and the energy in double (the line search compares
-// energies), gradient and diagonal in float from the rounded F.
+// energies), gradient and diagonal in float from the rounded F, or in double
+// when J < kMixedMinJ. emit receives float or double values.
 template <typename Emit>
 __device__ __forceinline__ bool tet_grad_diag_mixed(const double Ds[9], const float Dm[9], float V, double mu,
                                                     double lam, double& energy, Emit&& emit) {
   double F[9], lnJ;
   if (!tet_F_energy(Ds, Dm, (double)V, mu, lam, F, lnJ, energy)) return false;
+  if (lnJ < log(kMixedMinJ)) {
+    double Dm64[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Dm64[k] = (double)Dm[k];
+    tet_grad_diag_from_F<double>(F, Dm64, (double)V, mu, lam, lnJ, emit);
+    return true;
+  }
   float F32[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) F32[k] = (float)F[k];

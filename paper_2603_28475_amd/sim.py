@@ -24,6 +24,7 @@ class Sim:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = t2r.Context(opts, self.stream.cuda_stream)
         self._graph = None
+        self._graph_gen = -1
         self.mats = []
         self.gel_ids = {}
         self.ind_ids = {}
@@ -122,8 +123,13 @@ class Sim:
         the step kernel) on this Sim's stream; later calls copy `poses` into the
         captured pose buffer and replay. Needs a non-default stream. Returns
         (markers, status) like step(), not synchronised."""
+        if self.ctx.tape_length() >= 0:
+            raise RuntimeError("graph_step cannot record a tape (a replay would rewrite one entry); "
+                               "stop recording with record(0) or use step()")
         p = torch.as_tensor(np.asarray(poses, dtype=np.float64) if not torch.is_tensor(poses) else poses,
                             dtype=torch.float64, device=self.device)
+        if self._graph is not None and self._graph_gen != self.ctx.layout_generation():
+            self._graph = None  # buffers or options changed since the capture: capture again
         with torch.cuda.stream(self.stream):
             if self._graph is None:
                 self._pose_buf = p.clone().contiguous()
@@ -133,6 +139,7 @@ class Sim:
                 with torch.cuda.graph(graph, stream=self.stream):
                     self.ctx.step(self._pose_buf, None, self.markers, None, self.status)
                 self._graph = graph
+                self._graph_gen = self.ctx.layout_generation()
             else:
                 self._pose_buf.copy_(p)
                 self._graph.replay()

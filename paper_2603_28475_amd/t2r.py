@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libt2r.so")
 T2R_OK, T2R_E_ARG, T2R_E_NOMEM, T2R_E_HIP, T2R_E_STATE, T2R_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 ENV_CONVERGED, ENV_MAXITER, ENV_INFEASIBLE, ENV_NONFINITE = 1, 2, 4, 8
 ENV_PAIR_OVERFLOW, ENV_LINESEARCH, ENV_SUBSTEPS, ENV_SKIPPED = 16, 32, 64, 128
+ENV_BUDGET = 256
 
 
 class Material(C.Structure):
@@ -30,7 +31,7 @@ class SolverOpts(C.Structure):
                 ("max_substeps", C.c_int32), ("precision", C.c_int32),
                 ("pair_capacity", C.c_int32), ("armijo", C.c_int32), ("block_size", C.c_int32),
                 ("warm_start", C.c_int32), ("dynamic", C.c_int32), ("dt", C.c_double),
-                ("density", C.c_double)]
+                ("density", C.c_double), ("max_evals", C.c_int32)]
 
 
 class EnvStats(C.Structure):
@@ -39,7 +40,8 @@ class EnvStats(C.Structure):
                 ("n_candidates", C.c_int32), ("n_active", C.c_int32), ("n_friction", C.c_int32),
                 ("max_solve_iters", C.c_int32), ("outer_builds", C.c_int32),
                 ("n_outer", C.c_int32), ("d_min", C.c_double), ("residual", C.c_double),
-                ("energy", C.c_double), ("phase_ms", C.c_double * 10), ("list_fill", C.c_double)]
+                ("energy", C.c_double), ("phase_ms", C.c_double * 10), ("list_fill", C.c_double),
+                ("evals", C.c_int32), ("reserved", C.c_int32)]
 
 
 class T2RError(RuntimeError):
@@ -84,6 +86,7 @@ SIGNATURES = [
     ("t2r_backward_sequence", C.c_int32, [_P, C.c_int32, _P, _P]),
     ("t2r_tape_read", C.c_int32, [_P, C.c_int32, _P]),
     ("t2r_set_gel_markers", C.c_int32, [_P, C.c_int32, C.c_int32, _PI, _PD]),
+    ("t2r_layout_generation", C.c_int32, [_P, C.POINTER(C.c_int64)]),
 ]
 
 
@@ -215,6 +218,11 @@ class Context:
     def state_size(self) -> int:
         n = C.c_int64()
         self.check(lib.t2r_state_size(self.handle, C.byref(n)))
+        return n.value
+
+    def layout_generation(self) -> int:
+        n = C.c_int64()
+        self.check(lib.t2r_layout_generation(self.handle, C.byref(n)))
         return n.value
 
     def set_pair_capacity(self, cap):

@@ -180,3 +180,20 @@ def test_marker_map_replacement_and_knn_map():
         with pytest.raises(t2r.T2RError) as e:
             ctx.set_gel_markers(gid, *bad)
         assert e.value.code == t2r.T2R_E_ARG
+
+
+def test_device_code_has_no_function_calls():
+    """Every device function of the kernels is force-inlined, so the compiled
+    kernels contain no calls. A call is the one place where a kernel's private
+    state crosses a calling convention (caller-saved registers, a callee stack
+    frame in scratch); the adjoint kernel's result once changed with the layout
+    of its private state while one helper was a real call, and matched the
+    oracle again once that helper was inlined."""
+    csrc = os.path.join(ROOT, "paper_2603_28475_amd", "csrc")
+    for f in ("t2r_kernels.hip", "t2r_math.h"):
+        src = open(os.path.join(csrc, f)).read()
+        for m in re.finditer(r"^[^\n/]*__device__[^\n;{]*\(", src, re.M):
+            decl = m.group(0)
+            if "__global__" in decl or "constexpr" in decl:
+                continue
+            assert "__forceinline__" in decl, f"{f}: {decl.strip()}"
