@@ -349,6 +349,21 @@ t2r_status t2r_set_opts(t2r_ctx* ctx, const t2r_solver_opts* opts);
  * first load step. Asynchronous; positions and poses are not changed. */
 t2r_status t2r_backward(t2r_ctx* ctx, const double* d_dL_du, double* d_grad);
 
+/* t2r_backward without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving or training loops,
+ * harnesses that forbid hipMalloc). Same arguments, results and errors as
+ * t2r_backward, from the same kernel; the two-entry tape it needs (x_{s-1},
+ * x_s and both poses of every env: 2 x (total 3 n_v + 7 n_env) doubles) is
+ * copied into a static workspace of 2^21 doubles (16 MiB) that the library
+ * holds on each GPU it runs on until the process ends, instead of a
+ * context-owned buffer. T2R_E_ARG (checked before any GPU use) when the tape
+ * does not fit, e.g. beyond about 700 envs of the 484-vertex gel or 70 of the
+ * 4,914-vertex gel. All calls on one GPU share that workspace: calls that
+ * overlap on one GPU (different streams or threads) race and must be ordered
+ * by the caller. No hipMalloc/hipFree or allocating library call is made; the
+ * context must already have stepped (its own buffers exist since then). */
+t2r_status t2r_backward_static(t2r_ctx* ctx, const double* d_dL_du, double* d_grad);
+
 /* Starts recording a trajectory tape of at most max_steps load steps (device
  * memory: (max_steps + 1) x (sum 3 n_v + 7 n_env) doubles, owned by the
  * context). Entry 0 is the current state of every env; each later t2r_step /

@@ -122,6 +122,7 @@ struct t2r_ctx {
   int pair_cap = 0;
   double clock_khz = 1.0;
   int n_cu = 256;      // compute units of the device (set at the first GPU call)
+  int device = -1;     // the device current at the first GPU call
 };
 
 namespace {
@@ -1315,6 +1316,46 @@ t2r_status t2r_backward(t2r_ctx* c, const double* d_dL_du, double* d_grad) {
   return launch_adjoint(c, P, d_dL_du, d_grad);
 }
 
+t2r_status t2r_backward_static(t2r_ctx* c, const double* d_dL_du, double* d_grad) {
+  if (!c) return T2R_E_ARG;
+  if (!d_dL_du || !d_grad) return fail(c, T2R_E_ARG, "d_dL_du and d_grad are required");
+  // sizes first: a context whose two-entry tape does not fit is refused before any GPU use
+  size_t nd = 0;  // 3 x the vertices of every env (the context may not have uploaded yet)
+  for (const EnvHost& e : c->envs) nd += 3 * (size_t)c->gels[e.gel].n_v;
+  const size_t nq = 7 * c->envs.size();
+  const size_t need = 2 * nd + 2 * nq, cap = t2r_static_scratch_capacity();
+  if (need > cap)
+    return fail(c, T2R_E_ARG,
+                "t2r_backward_static: the adjoint tape needs %zu doubles (2 x (3 x %zu vertices + 7 x %zu envs)) "
+                "and the static workspace holds %zu; use t2r_backward", need, nd / 3, c->envs.size(), cap);
+  for (size_t i = 0; i < c->envs.size(); ++i)
+    if (c->envs[i].mat.mu_f != 0.0)
+      return fail(c, T2R_E_UNSUPPORTED, "env %zu has mu_f = %g (t2r_record + t2r_backward_sequence)", i,
+                  c->envs[i].mat.mu_f);
+  if (!c->committed || !c->stepped) return fail(c, T2R_E_STATE, "no load step has run");
+  if (c->opts.dynamic) return fail(c, T2R_E_UNSUPPORTED, "the adjoint covers the quasi-static form (dynamic = 0)");
+  int cur = -1;
+  HIP_TRY(c, hipGetDevice(&cur));
+  if (cur != c->device) HIP_TRY(c, hipSetDevice(c->device));
+  double* ws = nullptr;
+  size_t n = 0;
+  const hipError_t e = t2r_static_scratch(c->device, &ws, &n);
+  if (cur != c->device) HIP_TRY(c, hipSetDevice(cur));
+  if (e != hipSuccess) return fail(c, T2R_E_HIP, "static workspace: %s", hipGetErrorString(e));
+  double* tx = ws;
+  double* tq = ws + 2 * nd;
+  HIP_TRY(c, hipMemcpyAsync(tx, c->d_xprev, nd * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(tx + nd, c->d_x, nd * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(tq, c->d_pose_lag, nq * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(tq + nq, c->d_pose_prev, nq * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  StepParams P = step_params(c);
+  P.tape_x = tx;
+  P.tape_q = tq;
+  P.bw_steps = 1;
+  P.bw_last = 1;
+  return launch_adjoint(c, P, d_dL_du, d_grad);
+}
+
 }  // extern "C"
 
 // ===========================================================================
@@ -1436,6 +1477,7 @@ t2r_status commit(t2r_ctx* c) {
   {
     int dev = 0, khz = 0;
     HIP_TRY(c, hipGetDevice(&dev));
+    c->device = dev;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
       c->clock_khz = (double)khz;
     int cu = 0;

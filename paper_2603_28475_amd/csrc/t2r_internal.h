@@ -224,4 +224,6 @@ hipError_t t2r_launch_eval(const t2r::EvalParams* p, int block, hipStream_t stre
 hipError_t t2r_launch_pack_state(const t2r::StepParams* p, const double* in, double* out,
                                  const long long* state_off, int direction, hipStream_t stream);
 hipError_t t2r_launch_aos_to_soa(const double* in, double* out, int nv, hipStream_t stream);
+hipError_t t2r_static_scratch(int device, double** ptr, size_t* n_doubles);
+size_t t2r_static_scratch_capacity();
 }

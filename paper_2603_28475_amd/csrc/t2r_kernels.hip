@@ -16,6 +16,7 @@
 #include <float.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include <hip/hip_runtime.h>
@@ -3196,3 +3197,39 @@ extern "C" hipError_t t2r_launch_aos_to_soa(const double* in, double* out, int n
   hipLaunchKernelGGL(t2r_aos_to_soa_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, stream, in, out, nv);
   return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// Static workspace of t2r_backward_static: the two-entry trajectory tape
+// (x_{s-1}, x_s and both poses) of a single-step adjoint, in a file-scope
+// device array so that the call allocates nothing. Every GPU the library runs
+// on holds its own copy until the process ends. In host code `scratch` names a
+// host-side stand-in, so its device address is looked up once per device
+// (hipGetSymbolAddress) and only that address is ever handed to copies and
+// kernels.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kStaticScratchDoubles = size_t(1) << 21;  // 16 MiB
+constexpr int kMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+// Device address and size (doubles) of `scratch` on `device`, which must be
+// current. The first call on a device resolves the address; later calls reuse it.
+extern "C" hipError_t t2r_static_scratch(int device, double** ptr, size_t* n_doubles) {
+  static std::mutex lock;
+  static double* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices || !ptr || !n_doubles) return hipErrorInvalidValue;
+  std::lock_guard<std::mutex> g(lock);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = static_cast<double*>(p);
+  }
+  *ptr = addr[device];
+  *n_doubles = kStaticScratchDoubles;
+  return hipSuccess;
+}
+
+extern "C" size_t t2r_static_scratch_capacity() { return kStaticScratchDoubles; }

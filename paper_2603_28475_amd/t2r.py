@@ -87,6 +87,7 @@ SIGNATURES = [
     ("t2r_tape_read", C.c_int32, [_P, C.c_int32, _P]),
     ("t2r_set_gel_markers", C.c_int32, [_P, C.c_int32, C.c_int32, _PI, _PD]),
     ("t2r_layout_generation", C.c_int32, [_P, C.POINTER(C.c_int64)]),
+    ("t2r_backward_static", C.c_int32, [_P, _P, _P]),
 ]
 
 
@@ -276,6 +277,9 @@ class Context:
 
     def backward(self, d_dL_du, d_grad):
         self.check(lib.t2r_backward(self.handle, _tptr(d_dL_du), _tptr(d_grad)))
+
+    def backward_static(self, d_dL_du, d_grad):
+        self.check(lib.t2r_backward_static(self.handle, _tptr(d_dL_du), _tptr(d_grad)))
 
     def record(self, max_steps):
         self.check(lib.t2r_record(self.handle, int(max_steps)))

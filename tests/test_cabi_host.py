@@ -194,6 +194,24 @@ def test_device_code_has_no_function_calls():
         src = open(os.path.join(csrc, f)).read()
         for m in re.finditer(r"^[^\n/]*__device__[^\n;{]*\(", src, re.M):
             decl = m.group(0)
-            if "__global__" in decl or "constexpr" in decl:
-                continue
+            if "__global__" in decl or "constexpr" in decl or "__align__" in decl:
+                continue  # kernels, constants and device arrays
             assert "__forceinline__" in decl, f"{f}: {decl.strip()}"
+
+
+def test_static_backward_refuses_a_tape_beyond_its_workspace_before_any_gpu_use():
+    """t2r_backward_static keeps its tape in a fixed 2^21-double workspace: a
+    context whose tape would not fit (800 envs of the 484-vertex gel need
+    2 x (800 x 1,452 + 800 x 7) doubles) is refused with T2R_E_ARG and a message
+    naming the sizes, before any GPU call."""
+    t2r = _t2r()
+    w = sphere_press_484v(n_envs=800, n_steps=1)
+    ctx = t2r.Context(t2r.default_opts(), None)
+    g = w.meshes["c1"]
+    gid = ctx.add_gel(g.X, g.tets, g.fixed, g.markers)
+    iid = ctx.add_indenter(w.indenters["sphere3"].Y, w.indenters["sphere3"].tris)
+    ctx.add_envs([gid] * 800, [iid] * 800, [e.material() for e in w.envs], np.stack([e.poses[0] for e in w.envs]))
+    with pytest.raises(t2r.T2RError) as ei:
+        ctx.backward_static(torch.zeros(1, dtype=torch.float64), torch.zeros(1, dtype=torch.float64))
+    assert ei.value.code == t2r.T2R_E_ARG
+    assert "static workspace holds 2097152" in str(ei.value)
