@@ -429,6 +429,14 @@ def main():
                  "batched_over_plain": value / (n * K / dtp)}
 
     iters_mean = float(sum(it.sum() for it in iters)) / (args.envs * K)
+    # per-phase wall time of an env's workgroup per PNCG iteration (in-kernel clocks,
+    # last launch), at the launch's occupancy
+    st_last = sim.stats()
+    it_tot = max(1, sum(x["iters"] for x in st_last))
+    phase_names = ("outer_cull", "filter", "curv_elem", "curv_pairs", "ccd", "eval_elem", "eval_pairs",
+                   "vector", "launch", "friction_lag")
+    phase_us = {n: 1e3 * sum(x["phase_ms"][k] for x in st_last) / it_tot for k, n in enumerate(phase_names)}
+    evals_per_iter = sum(x["evals"] for x in st_last) / it_tot
     cpu = cpu_baseline(cpu_meas, iters_mean, workload.name) if cpu_meas else None
     line = {
         "metric": "env-steps/s at fixed PNCG tol (batched)",
@@ -452,6 +460,8 @@ def main():
                    "form": (f"dynamic (dt {args.dt:g} s, density {args.density:g} t/mm^3)" if args.dynamic
                             else "quasi-static"),
                    "pncg_iters_per_env_step": iters_mean, "launch": args.launch,
+                   "phase_us_per_env_iter": {k: round(v, 2) for k, v in phase_us.items()},
+                   "eval_passes_per_iter": round(evals_per_iter, 3),
                    "block_size": sim.ctx.get_opts().block_size or 256,
                    "autotune_trial_ms": tuned["trial_ms"] if tuned else None},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
