@@ -196,7 +196,6 @@ def adjoint_bench(args):
     import numpy as np
     import torch
     from paper_2603_28475_amd import t2r
-    from paper_2603_28475_amd.autograd import offset_poses
     from paper_2603_28475_amd.sim import Sim
     from scenes.configs import adjoint_peg_5k
     n = args.envs if args.envs > 0 else 64
@@ -213,11 +212,13 @@ def adjoint_bench(args):
         return th
 
     def run(th, record):
-        sim.ctx.set_materials(list(range(n)), [(th[i, 0], th[i, 1], th[i, 2], *sim.mats[i][3:]) for i in range(n)])
-        sim.ctx.reset_envs(list(range(n)))
+        ids = list(range(n))
+        sim.ctx.set_materials(ids, [(th[i, 0], th[i, 1], th[i, 2], *sim.mats[i][3:]) for i in range(n)])
+        sim.ctx.set_pose_offsets(ids, th[:, 3:9])  # the rigid pose offset, applied by the library
+        sim.ctx.reset_envs(ids)
         if record:
             sim.record(S)
-        return sim.step_sequence(offset_poses(poses, th))
+        return sim.step_sequence(poses)
 
     rng = np.random.default_rng(5)
     m_star, st_star = run(theta_of("theta_star"), False)

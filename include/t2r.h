@@ -222,6 +222,22 @@ t2r_status t2r_gel_markers(const t2r_ctx* ctx, int32_t gel_id, int32_t* marker_t
 t2r_status t2r_set_gel_markers(t2r_ctx* ctx, int32_t gel_id, int32_t n_m, const int32_t* vertex,
                                const double* weight);
 
+/* Replaces a gel class's marker map with the k-nearest-neighbour map of
+ * Sec. 3.2 (Tactile Representation: marker displacements interpolated from the
+ * k nearest mesh nodes of each marker in the initial mesh, with weights; the
+ * paper gives neither k nor the weights). Read here as: the k <= 3 top-face
+ * vertices (vertices of the top-face triangles) nearest to the marker's rest xy
+ * position, ties by vertex id, weighted by 1 / distance^power normalised to sum
+ * 1; a marker within 1e-12 mm of a vertex takes that vertex alone (weight 1).
+ * Unused slots repeat the nearest vertex with weight 0.
+ *   n_m, markers_xy[n_m][2] marker rest xy (host, mm)
+ *   k                   1, 2 or 3;  power > 0 (1: inverse distance)
+ * Before the first GPU call only (T2R_E_STATE after). Errors: T2R_E_ARG for a
+ * bad gel id, k, power or non-finite markers. Host only; the map is read back
+ * with t2r_gel_markers. */
+t2r_status t2r_set_gel_markers_knn(t2r_ctx* ctx, int32_t gel_id, int32_t n_m, const double* markers_xy,
+                                   int32_t k, double power);
+
 /* Adds a rigid indenter class: n_v local vertices Y[n_v][3] (mm) and n_f
  * triangles tris[n_f][3] of a closed surface. Edges are derived. Host only. */
 t2r_status t2r_add_indenter(t2r_ctx* ctx, int32_t n_v, const double* Y, int32_t n_f,
@@ -276,6 +292,41 @@ t2r_status t2r_step(t2r_ctx* ctx, const double* d_pose, const int32_t* d_env_mas
 t2r_status t2r_step_sequence(t2r_ctx* ctx, int32_t n_steps, const double* d_poses,
                              const int32_t* d_env_mask, double* d_markers, double* d_x,
                              int32_t* d_status);
+
+/* Load steps driven by the indenter's motion instead of target poses (the
+ * physics-engine input of Sec. 3.3: per engine step the object's pose relative
+ * to the sensor, or its velocity, drives the tactile simulation). Every env
+ * starts from its current pose q_0 = (t_0, r_0) and moves at a constant linear
+ * velocity v and world-frame angular velocity w over one engine step of length
+ * dt, cut into n_steps load steps: load step k (1-based) targets
+ *   t = t_0 + v dt k / n_steps,   r = exp([w dt k / n_steps]x) r_0,
+ * all in one persistent launch (otherwise as t2r_step_sequence: markers, x,
+ * status and the tape as there; pose offsets do not apply, the motion is
+ * relative to the env's own pose).
+ *   t2r_step_velocity: d_vel device [n_env][6] = (v, w) in mm/s and rad/s;
+ *                      dt > 0 in s.
+ *   t2r_step_relative: d_rel0, d_rel1 device [n_env][7] = the object's pose
+ *                      relative to the sensor at the start and at the end of
+ *                      the engine step; the motion is (t_1 - t_0) and the
+ *                      shortest rotation r_1 r_0^-1 (dt cancels).
+ * Errors: T2R_E_ARG for NULL inputs, n_steps < 1 or dt <= 0. Asynchronous. */
+t2r_status t2r_step_velocity(t2r_ctx* ctx, int32_t n_steps, double dt, const double* d_vel,
+                             const int32_t* d_env_mask, double* d_markers, double* d_x, int32_t* d_status);
+t2r_status t2r_step_relative(t2r_ctx* ctx, int32_t n_steps, const double* d_rel0, const double* d_rel1,
+                             const int32_t* d_env_mask, double* d_markers, double* d_x, int32_t* d_status);
+
+/* Sets a rigid offset per env (host arrays; offsets[n][6] = translation dt in
+ * mm and rotation vector dw in rad): from now on every target pose the env
+ * receives from t2r_step / t2r_step_sequence, and its start pose at
+ * t2r_reset_envs (and at the first GPU call), is moved so that each indenter
+ * point R y + t becomes exp([dw]x) R y + t + dt. The current state is not
+ * changed (reset to start from the offset start pose). The adjoints
+ * (t2r_backward, t2r_backward_sequence) then report the pose part of dL/dtheta
+ * with respect to this offset, dL/d(dt) and dL/d(dw) (through the left
+ * Jacobian of SO(3)); with no offset set they are the derivatives at zero.
+ * Zero offsets clear it. Errors: T2R_E_ARG for bad ids or non-finite values.
+ * Synchronises the context's stream. */
+t2r_status t2r_set_pose_offsets(t2r_ctx* ctx, int32_t n, const int32_t* env_ids, const double* offsets);
 
 /* Diagnostic evaluation of one env's step energy at given positions, without
  * touching its state: the friction lag is taken at (d_x_lag, pose_lag) when

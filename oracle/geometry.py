@@ -152,3 +152,85 @@ class IndenterGeometry:
     def world(self, pose) -> np.ndarray:
         R = quat_to_matrix(pose[3:])
         return self.Y @ R.T + np.asarray(pose[:3], dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Indenter motion from a physics engine (Sec. 3.3, Integrating to Physics
+# Engine): per engine step the object's pose relative to the sensor at its
+# start and end gives a constant linear and angular velocity.
+# ---------------------------------------------------------------------------
+def _qmul(a, b):
+    w1, x1, y1, z1 = np.moveaxis(a, -1, 0)
+    w2, x2, y2, z2 = np.moveaxis(b, -1, 0)
+    return np.stack([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2], axis=-1)
+
+
+def relative_velocity(p0, p1, dt):
+    """Constant linear and world-frame angular velocity (rad/s) carrying pose p0
+    to p1 in time dt: v = (t1 - t0) / dt, w = axis * angle / dt of the shortest
+    rotation q1 q0^-1. Shapes (..., 7) -> ((..., 3), (..., 3))."""
+    p0 = np.asarray(p0, dtype=np.float64)
+    p1 = np.asarray(p1, dtype=np.float64)
+    if not dt > 0:
+        raise ValueError("dt must be positive")
+    v = (p1[..., :3] - p0[..., :3]) / dt
+    q0 = p0[..., 3:] / np.linalg.norm(p0[..., 3:], axis=-1, keepdims=True)
+    q1 = p1[..., 3:] / np.linalg.norm(p1[..., 3:], axis=-1, keepdims=True)
+    dq = _qmul(q1, q0 * np.array([1.0, -1.0, -1.0, -1.0]))
+    dq = np.where(dq[..., :1] < 0, -dq, dq)
+    s = np.linalg.norm(dq[..., 1:], axis=-1, keepdims=True)
+    angle = 2.0 * np.arctan2(s, dq[..., :1])
+    axis = np.divide(dq[..., 1:], s, out=np.zeros_like(dq[..., 1:]), where=s > 0)
+    return v, axis * angle / dt
+
+
+def advance_pose(p0, v, w, tau):
+    """Pose after moving p0 for time tau at linear velocity v and world-frame
+    angular velocity w: t = t0 + v tau, q = exp(w tau) q0."""
+    p0 = np.asarray(p0, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    t = p0[..., :3] + v * tau
+    rate = np.linalg.norm(w, axis=-1, keepdims=True)
+    half = 0.5 * rate * tau
+    axis = np.divide(w, rate, out=np.zeros_like(w), where=rate > 0)
+    dq = np.concatenate([np.cos(half), np.sin(half) * axis], axis=-1)
+    q = _qmul(dq, p0[..., 3:] / np.linalg.norm(p0[..., 3:], axis=-1, keepdims=True))
+    return np.concatenate([t, q / np.linalg.norm(q, axis=-1, keepdims=True)], axis=-1)
+
+
+def top_face_vertices(X, surface_tris):
+    """Ascending ids of the vertices of the boundary triangles that lie on the
+    top face (largest z)."""
+    X = np.asarray(X, dtype=np.float64)
+    tris = np.asarray(surface_tris)
+    zt = X[:, 2].max()
+    on = np.all(np.abs(X[tris, 2] - zt) <= 1e-9 * (1.0 + abs(zt)), axis=1)
+    return np.unique(tris[on])
+
+
+def knn_marker_map(X, top_vertices, markers_xy, k=3, power=1.0):
+    """The k-nearest-neighbour marker map (Sec. 3.2: marker displacements from the
+    k nearest nodes of the initial mesh, with weights; k and the weights are not
+    given). Reading: the k <= 3 top-face vertices nearest to the marker's rest xy
+    (ties by vertex id) with weights 1 / distance^power summing to 1; a marker on
+    a vertex (within 1e-12 mm) takes that vertex alone. Returns vertex and weight
+    arrays [n_m][3]; unused slots repeat the nearest vertex with weight 0."""
+    X = np.asarray(X, dtype=np.float64)
+    top = np.sort(np.asarray(top_vertices, dtype=np.int64))
+    M = np.asarray(markers_xy, dtype=np.float64).reshape(-1, 2)
+    vertex = np.zeros((len(M), 3), dtype=np.int32)
+    weight = np.zeros((len(M), 3))
+    for m, (mx, my) in enumerate(M):
+        d = np.hypot(X[top, 0] - mx, X[top, 1] - my)
+        order = sorted(range(len(top)), key=lambda j: (d[j], top[j]))[:k]
+        vertex[m, :] = top[order[0]]
+        if d[order[0]] <= 1e-12:
+            weight[m, 0] = 1.0
+            continue
+        w = np.array([1.0 / d[j] ** power for j in order])
+        vertex[m, :k] = top[order]
+        weight[m, :k] = w / w.sum()
+    return vertex, weight
+

@@ -38,6 +38,7 @@ struct GelHost {
   std::vector<int> tile_tet, tile_vstart, tile_verts;
   std::vector<uint8_t> tile_flags;
   std::vector<int> surf_v, surf_e, surf_f;  // SoA
+  std::vector<int> top_v;         // vertices of the top-face triangles (ascending)
   int n_sv = 0, n_se = 0, n_sf = 0, n_top = 0, n_fixed = 0;
   std::vector<int> marker_tri;    // [3][n_m]
   std::vector<double> marker_w;   // [3][n_m]
@@ -65,7 +66,29 @@ struct EnvHost {
   int gel, ind;
   t2r_material mat;
   double pose0[7];
+  int has_off = 0;
+  double off[6] = {0, 0, 0, 0, 0, 0};  // rigid pose offset (dt, dw)
 };
+
+// pose0 moved by the env's rigid offset: q <- exp([dw]x) q (normalised),
+// t <- t + dt (the same composition as the kernels' for every step pose)
+void start_pose(const EnvHost& e, double out[7]) {
+  for (int k = 0; k < 7; ++k) out[k] = e.pose0[k];
+  if (!e.has_off) return;
+  const double* w = e.off + 3;
+  const double a = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  const double sc = a > 1e-12 ? sin(0.5 * a) / a : 0.5 - a * a / 48.0;
+  const double ex[4] = {cos(0.5 * a), sc * w[0], sc * w[1], sc * w[2]};
+  double qn = 0.0;
+  for (int k = 3; k < 7; ++k) qn += e.pose0[k] * e.pose0[k];
+  qn = sqrt(qn);
+  const double q[4] = {e.pose0[3] / qn, e.pose0[4] / qn, e.pose0[5] / qn, e.pose0[6] / qn};
+  out[3] = ex[0] * q[0] - ex[1] * q[1] - ex[2] * q[2] - ex[3] * q[3];
+  out[4] = ex[0] * q[1] + ex[1] * q[0] + ex[2] * q[3] - ex[3] * q[2];
+  out[5] = ex[0] * q[2] - ex[1] * q[3] + ex[2] * q[0] + ex[3] * q[1];
+  out[6] = ex[0] * q[3] + ex[1] * q[2] - ex[2] * q[1] + ex[3] * q[0];
+  for (int k = 0; k < 3; ++k) out[k] = e.pose0[k] + e.off[k];
+}
 
 }  // namespace
 
@@ -486,6 +509,9 @@ t2r_status t2r_add_gel(t2r_ctx* c, int32_t n_v, const double* X, int32_t n_t, co
           fabs(X[3 * (size_t)t[2] + 2] - ztop) <= ztol)
         top.push_back(t);
     g.n_top = (int)top.size();
+    for (auto& t : top) g.top_v.insert(g.top_v.end(), t.begin(), t.end());
+    std::sort(g.top_v.begin(), g.top_v.end());
+    g.top_v.erase(std::unique(g.top_v.begin(), g.top_v.end()), g.top_v.end());
     g.marker_tri.resize(3 * (size_t)n_m);
     g.marker_w.resize(3 * (size_t)n_m);
     for (int m = 0; m < n_m; ++m) {
@@ -922,6 +948,10 @@ static StepParams step_params(t2r_ctx* c) {
   P.max_iters = c->opts.max_iters;
   P.max_substeps = c->opts.max_substeps;
   P.max_evals = c->opts.max_evals;
+  P.motion_mode = 0;
+  P.motion_in = nullptr;
+  P.motion_in2 = nullptr;
+  P.motion_dt = 0.0;
   P.precision = c->opts.precision;
   P.armijo = c->opts.armijo;
   P.warm_start = c->opts.warm_start;
@@ -932,11 +962,15 @@ static StepParams step_params(t2r_ctx* c) {
   return P;
 }
 
-t2r_status t2r_step_sequence(t2r_ctx* c, int32_t n_steps, const double* d_poses, const int32_t* d_mask,
-                             double* d_markers, double* d_x, int32_t* d_status) {
+// One persistent launch of n_steps load steps; the targets come from poses
+// (mode 0), velocities (1) or a relative motion (2); see StepParams.
+static t2r_status launch_steps(t2r_ctx* c, int32_t n_steps, int mode, const double* in, const double* in2,
+                               double dt, const int32_t* d_mask, double* d_markers, double* d_x,
+                               int32_t* d_status) {
   if (!c) return T2R_E_ARG;
-  if (!d_poses) return fail(c, T2R_E_ARG, "d_poses is NULL");
+  if (!in || (mode == 2 && !in2)) return fail(c, T2R_E_ARG, "the step's input array is NULL");
   if (n_steps < 1) return fail(c, T2R_E_ARG, "n_steps must be >= 1 (got %d)", n_steps);
+  if (mode == 1 && !(dt > 0.0 && isfinite(dt))) return fail(c, T2R_E_ARG, "dt must be positive and finite");
   if (c->envs.empty()) return fail(c, T2R_E_STATE, "no environments");
   t2r_status s = commit(c);
   if (s != T2R_OK) return s;
@@ -950,7 +984,14 @@ t2r_status t2r_step_sequence(t2r_ctx* c, int32_t n_steps, const double* d_poses,
     P.tape_q = c->d_tape_q;
     P.tape_k0 = c->tape_len;
   }
-  P.pose_in = d_poses;
+  P.motion_mode = mode;
+  if (mode == 0) {
+    P.pose_in = in;
+  } else {
+    P.motion_in = in;
+    P.motion_in2 = in2;
+    P.motion_dt = dt;
+  }
   P.env_mask = d_mask;
   P.markers_out = d_markers;
   P.markers_stride = 3 * c->total_markers;
@@ -966,6 +1007,89 @@ t2r_status t2r_step_sequence(t2r_ctx* c, int32_t n_steps, const double* d_poses,
   if (c->d_tape_x) c->tape_len += n_steps;
   c->err.clear();
   return T2R_OK;
+}
+
+t2r_status t2r_step_sequence(t2r_ctx* c, int32_t n_steps, const double* d_poses, const int32_t* d_mask,
+                             double* d_markers, double* d_x, int32_t* d_status) {
+  return launch_steps(c, n_steps, 0, d_poses, nullptr, 0.0, d_mask, d_markers, d_x, d_status);
+}
+
+t2r_status t2r_step_velocity(t2r_ctx* c, int32_t n_steps, double dt, const double* d_vel, const int32_t* d_mask,
+                             double* d_markers, double* d_x, int32_t* d_status) {
+  return launch_steps(c, n_steps, 1, d_vel, nullptr, dt, d_mask, d_markers, d_x, d_status);
+}
+
+t2r_status t2r_step_relative(t2r_ctx* c, int32_t n_steps, const double* d_rel0, const double* d_rel1,
+                             const int32_t* d_mask, double* d_markers, double* d_x, int32_t* d_status) {
+  return launch_steps(c, n_steps, 2, d_rel0, d_rel1, 0.0, d_mask, d_markers, d_x, d_status);
+}
+
+t2r_status t2r_set_pose_offsets(t2r_ctx* c, int32_t n, const int32_t* env_ids, const double* offsets) {
+  if (!c) return T2R_E_ARG;
+  if (n < 0 || (n > 0 && (!env_ids || !offsets))) return fail(c, T2R_E_ARG, "bad arguments");
+  for (int i = 0; i < n; ++i) {
+    if (env_ids[i] < 0 || env_ids[i] >= (int)c->envs.size()) return fail(c, T2R_E_ARG, "bad env id %d", env_ids[i]);
+    for (int k = 0; k < 6; ++k)
+      if (!isfinite(offsets[6 * (size_t)i + k])) return fail(c, T2R_E_ARG, "env %d: non-finite offset", env_ids[i]);
+  }
+  if (c->committed) HIP_TRY(c, hipStreamSynchronize(c->stream));  // earlier work may read the descriptors
+  ++c->layout_gen;
+  for (int i = 0; i < n; ++i) {
+    EnvHost& e = c->envs[env_ids[i]];
+    bool any = false;
+    for (int k = 0; k < 6; ++k) {
+      e.off[k] = offsets[6 * (size_t)i + k];
+      any |= e.off[k] != 0.0;
+    }
+    e.has_off = any ? 1 : 0;
+    if (c->committed) {
+      EnvDev& d = c->h_envs[env_ids[i]];
+      d.has_off = e.has_off;
+      for (int k = 0; k < 6; ++k) d.off[k] = e.off[k];
+      HIP_TRY(c, hipMemcpyAsync(c->d_envs + env_ids[i], &d, sizeof(EnvDev), hipMemcpyHostToDevice, c->stream));
+    }
+  }
+  if (c->committed) HIP_TRY(c, hipStreamSynchronize(c->stream));  // host copies are pageable
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_set_gel_markers_knn(t2r_ctx* c, int32_t id, int32_t n_m, const double* markers_xy, int32_t k,
+                                   double power) {
+  if (!c) return T2R_E_ARG;
+  if (id < 0 || id >= (int)c->gels.size()) return fail(c, T2R_E_ARG, "bad gel id %d", id);
+  if (k < 1 || k > 3) return fail(c, T2R_E_ARG, "k must be 1, 2 or 3 (three nodes per marker), got %d", k);
+  if (!(power > 0.0) || !isfinite(power)) return fail(c, T2R_E_ARG, "power must be positive");
+  if (n_m < 0 || (n_m > 0 && !markers_xy)) return fail(c, T2R_E_ARG, "bad marker array");
+  const GelHost& g = c->gels[id];
+  if ((int)g.top_v.size() < k) return fail(c, T2R_E_ARG, "the top face has fewer than %d vertices", k);
+  std::vector<int32_t> vert(3 * (size_t)n_m);
+  std::vector<double> wt(3 * (size_t)n_m, 0.0);
+  std::vector<std::pair<double, int>> dist(g.top_v.size());
+  for (int m = 0; m < n_m; ++m) {
+    const double mx = markers_xy[2 * (size_t)m], my = markers_xy[2 * (size_t)m + 1];
+    if (!isfinite(mx) || !isfinite(my)) return fail(c, T2R_E_ARG, "non-finite marker %d", m);
+    for (size_t j = 0; j < g.top_v.size(); ++j) {
+      const int v = g.top_v[j];
+      const double dx = g.X[v] - mx, dy = g.X[g.n_v + v] - my;
+      dist[j] = {sqrt(dx * dx + dy * dy), v};
+    }
+    // the k nearest, ties by vertex id
+    std::partial_sort(dist.begin(), dist.begin() + k, dist.end());
+    for (int j = 0; j < 3; ++j) vert[3 * (size_t)m + j] = dist[0].second;
+    if (dist[0].first <= 1e-12) {
+      wt[3 * (size_t)m] = 1.0;  // a marker on a node takes that node alone
+    } else {
+      double sum = 0.0;
+      for (int j = 0; j < k; ++j) {
+        vert[3 * (size_t)m + j] = dist[j].second;
+        wt[3 * (size_t)m + j] = 1.0 / pow(dist[j].first, power);
+        sum += wt[3 * (size_t)m + j];
+      }
+      for (int j = 0; j < k; ++j) wt[3 * (size_t)m + j] /= sum;
+    }
+  }
+  return t2r_set_gel_markers(c, id, n_m, vert.data(), wt.data());
 }
 
 t2r_status t2r_step(t2r_ctx* c, const double* d_pose, const int32_t* d_mask, double* d_markers, double* d_x,
@@ -1152,10 +1276,13 @@ t2r_status t2r_reset_envs(t2r_ctx* c, const int32_t* ids, int32_t n) {
     const EnvDev& ed = c->h_envs[ids[i]];
     HIP_TRY(c, hipMemcpyAsync(c->d_x + ed.voff, g.dev.X, 3 * (size_t)g.n_v * sizeof(double),
                               hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->d_pose_prev + 7 * (size_t)ids[i], e.pose0, 7 * sizeof(double),
+    double q0[7];
+    start_pose(e, q0);
+    HIP_TRY(c, hipMemcpyAsync(c->d_pose_prev + 7 * (size_t)ids[i], q0, 7 * sizeof(double),
                               hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->d_pose_lag + 7 * (size_t)ids[i], e.pose0, 7 * sizeof(double),
+    HIP_TRY(c, hipMemcpyAsync(c->d_pose_lag + 7 * (size_t)ids[i], q0, 7 * sizeof(double),
                               hipMemcpyHostToDevice, c->stream));  // no motion history
+    HIP_TRY(c, hipStreamSynchronize(c->stream));  // q0 is a pageable stack copy
     HIP_TRY(c, hipMemsetAsync(c->d_lists + ids[i], 0, sizeof(ListState), c->stream));
     HIP_TRY(c, hipMemsetAsync(c->d_gap + ids[i], 0, sizeof(double), c->stream));
     HIP_TRY(c, hipMemsetAsync(c->d_vel + ed.voff, 0, 3 * (size_t)g.n_v * sizeof(double), c->stream));
@@ -1509,6 +1636,8 @@ t2r_status commit(t2r_ctx* c) {
     d.gel = e.gel;
     d.ind = e.ind;
     material_to_dev(e.mat, d);
+    d.has_off = e.has_off;
+    for (int k = 0; k < 6; ++k) d.off[k] = e.off[k];
     const int cap = pair_cap_of(c, g);
     d.pair_cap = cap;
     d.fric_cap = std::max(1024, cap / 2);
@@ -1588,7 +1717,7 @@ t2r_status commit(t2r_ctx* c) {
     const GelHost& g = c->gels[c->envs[i].gel];
     HIP_TRY(c, hipMemcpyAsync(c->d_x + c->h_envs[i].voff, g.dev.X, 3 * (size_t)g.n_v * sizeof(double),
                               hipMemcpyDeviceToDevice, c->stream));
-    for (int k = 0; k < 7; ++k) pose[7 * i + k] = c->envs[i].pose0[k];
+    start_pose(c->envs[i], &pose[7 * i]);
   }
   HIP_TRY(c, hipMemsetAsync(c->d_p, 0, nd * sizeof(double), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_stats, 0, c->envs.size() * sizeof(EnvStats), c->stream));

@@ -110,6 +110,8 @@ struct EnvDev {
   long long vtxoff;        // vertex offset (voff / 3) of its vertex map
   long long imoff;         // offset of its indenter vertex map
   int pair_cap, fric_cap, outer_cap;
+  int has_off;             // a rigid pose offset is set (t2r_set_pose_offsets)
+  double off[6];           // its translation dt (mm) and rotation vector dw (rad)
 };
 
 struct FricPair {          // lagged friction data of one pair (Supp. A, eq. friction_energy)
@@ -170,7 +172,16 @@ struct StepParams {
   T2R_G EnvStats* stats;         // [n_env]
   const T2R_G int* order;        // [n_env] env of each workgroup (longest expected first) or null
   // inputs / outputs
-  const T2R_G double* pose_in;   // [n_steps][n_env][7]
+  const T2R_G double* pose_in;   // [n_steps][n_env][7] (motion_mode 0)
+  // motion_mode 1: motion_in [n_env][6] = linear and world-frame angular
+  // velocity, applied for motion_dt over the launch's n_steps load steps from
+  // each env's pose at the launch start; 2: motion_in and motion_in2 [n_env][7]
+  // = poses at the start and end of a motion whose relative displacement
+  // (t1 - t0, q1 q0^-1) is applied the same way
+  int motion_mode;
+  const T2R_G double* motion_in;
+  const T2R_G double* motion_in2;
+  double motion_dt;
   const T2R_G int* env_mask;     // [n_env] or null
   T2R_G double* markers_out;     // [n_steps][sum n_m][3] or null
   long long markers_stride;      // doubles per load step in markers_out (3 sum n_m)

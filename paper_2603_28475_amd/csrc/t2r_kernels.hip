@@ -163,6 +163,96 @@ __device__ __forceinline__ void interp_pose(const double p0[7], const double p1[
   for (int i = 0; i < 4; ++i) out[3 + i] /= n;
 }
 
+// Quaternion product a b (w, x, y, z).
+__device__ __forceinline__ void quat_mul(const double a[4], const double b[4], double o[4]) {
+  o[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+  o[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+  o[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+  o[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+}
+
+// Unit quaternion of the rotation by the rotation vector w: exp([w]x).
+__device__ __forceinline__ void quat_exp(const double w[3], double q[4]) {
+  const double a = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  const double s = a > 1e-12 ? sin(0.5 * a) / a : 0.5 - a * a / 48.0;
+  q[0] = cos(0.5 * a);
+  q[1] = s * w[0];
+  q[2] = s * w[1];
+  q[3] = s * w[2];
+}
+
+// A pose moved rigidly by (dt, dw): every indenter point R y + t becomes
+// exp([dw]x) R y + t + dt, i.e. q <- exp(dw) q (normalised), t <- t + dt.
+__device__ __forceinline__ void move_pose(const double in[7], const double dt[3], const double dw[3],
+                                          double out[7]) {
+  double qn = 0.0;
+  #pragma unroll
+  for (int i = 3; i < 7; ++i) qn += in[i] * in[i];
+  qn = sqrt(qn);
+  const double q[4] = {in[3] / qn, in[4] / qn, in[5] / qn, in[6] / qn};
+  double e[4], r[4];
+  quat_exp(dw, e);
+  quat_mul(e, q, r);
+  #pragma unroll
+  for (int i = 0; i < 3; ++i) out[i] = in[i] + dt[i];
+  #pragma unroll
+  for (int i = 0; i < 4; ++i) out[3 + i] = r[i];
+}
+
+// Rotation vector of the shortest rotation q1 q0^-1 (unit or not).
+__device__ __forceinline__ void quat_log_rel(const double q0_in[4], const double q1_in[4], double w[3]) {
+  double n0 = 0.0, n1 = 0.0;
+  #pragma unroll
+  for (int i = 0; i < 4; ++i) { n0 += q0_in[i] * q0_in[i]; n1 += q1_in[i] * q1_in[i]; }
+  n0 = sqrt(n0); n1 = sqrt(n1);
+  const double c0[4] = {q0_in[0] / n0, -q0_in[1] / n0, -q0_in[2] / n0, -q0_in[3] / n0};
+  const double q1[4] = {q1_in[0] / n1, q1_in[1] / n1, q1_in[2] / n1, q1_in[3] / n1};
+  double d[4];
+  quat_mul(q1, c0, d);
+  if (d[0] < 0.0) for (int i = 0; i < 4; ++i) d[i] = -d[i];
+  const double s = sqrt(d[1] * d[1] + d[2] * d[2] + d[3] * d[3]);
+  const double ang = 2.0 * atan2(s, d[0]);
+  const double f = s > 1e-300 ? ang / s : 2.0;
+  #pragma unroll
+  for (int i = 0; i < 3; ++i) w[i] = f * d[1 + i];
+}
+
+// Target pose of load step k (0-based) of a launch of n load steps: the
+// caller's pose (moved by the env's rigid offset, if one is set), or the pose
+// reached after (k + 1) / n of the launch's motion from the launch-start pose qb.
+__device__ __forceinline__ void target_pose(const StepParams& P, const EnvDev& E, int e, int k,
+                                            const double qb[7], double q1[7]) {
+  if (P.motion_mode == 0) {
+    double q[7];
+    #pragma unroll
+    for (int i = 0; i < 7; ++i) q[i] = P.pose_in[((long long)k * P.n_env + e) * 7 + i];
+    if (E.has_off) move_pose(q, E.off, E.off + 3, q1);
+    else
+      #pragma unroll
+      for (int i = 0; i < 7; ++i) q1[i] = q[i];
+    return;
+  }
+  double dt[3], dw[3];
+  if (P.motion_mode == 1) {
+    #pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      dt[i] = P.motion_in[6 * e + i] * P.motion_dt;
+      dw[i] = P.motion_in[6 * e + 3 + i] * P.motion_dt;
+    }
+  } else {
+    const T2R_G double* a = P.motion_in + 7 * e;
+    const T2R_G double* b = P.motion_in2 + 7 * e;
+    const double qa[4] = {a[3], a[4], a[5], a[6]}, qbb[4] = {b[3], b[4], b[5], b[6]};
+    #pragma unroll
+    for (int i = 0; i < 3; ++i) dt[i] = b[i] - a[i];
+    quat_log_rel(qa, qbb, dw);
+  }
+  const double f = (double)(k + 1) / (double)P.n_steps;
+  #pragma unroll
+  for (int i = 0; i < 3; ++i) { dt[i] *= f; dw[i] *= f; }
+  move_pose(qb, dt, dw, q1);
+}
+
 __device__ __forceinline__ void set_pose(Shared& S, const IndDev& I, const double pose[7]) {
   for (int i = 0; i < 7; ++i) S.pose[i] = pose[i];
   quat_to_R(pose + 3, S.R);
@@ -2141,14 +2231,15 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
   st.evals = 0; st.reserved = 0;
   const bool skip = P.env_mask && P.env_mask[e] == 0;
   load_lists(s);
+  double qb[7];  // the env's pose at the launch start (motion modes)
+  #pragma unroll
+  for (int i = 0; i < 7; ++i) qb[i] = P.pose_prev[7 * e + i];
   for (int k = 0; k < P.n_steps; ++k) {
     double q1[7];
+    target_pose(P, *V.E, e, k, qb, q1);
     bool bad = false;
     #pragma unroll
-    for (int i = 0; i < 7; ++i) {
-      q1[i] = P.pose_in[((long long)k * P.n_env + e) * 7 + i];
-      bad |= !isfinite(q1[i]);
-    }
+    for (int i = 0; i < 7; ++i) bad |= !isfinite(q1[i]);
     int status;
     if (skip || bad) {
       status = skip ? kSkipped : kNonFinite;
@@ -2991,6 +3082,26 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_backward_ke
     grad[1] = -(acc[0] * dmu_dnu + acc[1] * dlam_dnu);
     grad[2] = -acc[2];
     for (int k = 0; k < 6; ++k) grad[3 + k] = -acc[3 + k];
+    if (E.has_off) {
+      // the kernel's rotation gradient is for an incremental rotation d applied
+      // after the env's offset exp(dw); exp([dw + e]x) = exp([J_l(dw) e]x) exp([dw]x)
+      // to first order, so dL/d(dw) = J_l(dw)^T dL/dd
+      const double* w = E.off + 3;
+      const double a2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2], a = sqrt(a2);
+      const double c1 = a > 1e-6 ? (1.0 - cos(a)) / a2 : 0.5 - a2 / 24.0;
+      const double c2 = a > 1e-6 ? (a - sin(a)) / (a2 * a) : 1.0 / 6.0 - a2 / 120.0;
+      const double K[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
+      double J[9];
+      for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) {
+          double kk = 0.0;
+          for (int m = 0; m < 3; ++m) kk += K[r * 3 + m] * K[m * 3 + cc];
+          J[r * 3 + cc] = (r == cc ? 1.0 : 0.0) + c1 * K[r * 3 + cc] + c2 * kk;
+        }
+      double gr[3];
+      for (int cc = 0; cc < 3; ++cc) gr[cc] = J[0 * 3 + cc] * grad[6] + J[1 * 3 + cc] * grad[7] + J[2 * 3 + cc] * grad[8];
+      for (int cc = 0; cc < 3; ++cc) grad[6 + cc] = gr[cc];
+    }
     if (status & (kMaxIter | kNonFinite)) status &= ~kConverged;
   }
   if (threadIdx.x < 9) P.grad_out[9 * e + threadIdx.x] = grad[threadIdx.x];
@@ -3137,14 +3248,12 @@ __global__ void __launch_bounds__(1024) t2r_order_kernel(StepParams P, int* orde
     unsigned long long k = ~0ull;
     if (i < n) {
       const double r_max = P.inds[P.envs[i].ind].r_max;
-      double m = 0.0, q0[7], q1[7];
-      for (int c = 0; c < 7; ++c) q0[c] = P.pose_prev[7 * i + c];
+      double m = 0.0, q0[7], q1[7], qb[7];
+      for (int c = 0; c < 7; ++c) q0[c] = qb[c] = P.pose_prev[7 * i + c];
       for (int s = 0; s < P.n_steps; ++s) {
+        target_pose(P, P.envs[i], i, s, qb, q1);
         bool fin = true;
-        for (int c = 0; c < 7; ++c) {
-          q1[c] = P.pose_in[((long long)s * n + i) * 7 + c];
-          fin &= isfinite(q1[c]);
-        }
+        for (int c = 0; c < 7; ++c) fin &= isfinite(q1[c]);
         if (!fin) continue;
         m += ind_motion(q0, q1, r_max);
         for (int c = 0; c < 7; ++c) q0[c] = q1[c];

@@ -10,19 +10,49 @@ library. Typical use:
 
 from __future__ import annotations
 
+import atexit
+import weakref
+
 import numpy as np
 import torch
 
 from . import t2r
 
 
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # contexts still open at exit give their memory back to torch's allocator
+    # while torch is still there
+    for sim in list(_LIVE):
+        sim.close()
+
+
 class Sim:
-    def __init__(self, opts: t2r.SolverOpts | None = None, device: str | int = "cuda:0", stream=None):
+    def __init__(self, opts: t2r.SolverOpts | None = None, device: str | int = "cuda:0", stream=None,
+                 torch_memory: bool = True):
         """stream: the torch stream the library enqueues on (default: the current
-        stream; graph_step needs a non-default one, e.g. torch.cuda.Stream())."""
+        stream; graph_step needs a non-default one, e.g. torch.cuda.Stream()).
+        torch_memory: every device allocation of the library comes from torch's
+        caching allocator on that stream (t2r_set_allocator), so torch owns all
+        device memory; False lets the library call hipMalloc itself."""
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = t2r.Context(opts, self.stream.cuda_stream)
+        if torch_memory:
+            dev = self.device.index if self.device.index is not None else torch.cuda.current_device()
+            stream_handle = self.stream.cuda_stream
+
+            def alloc(nbytes):
+                try:
+                    return torch.cuda.caching_allocator_alloc(nbytes, dev, stream_handle)
+                except RuntimeError:
+                    return 0  # out of memory: the library reports T2R_E_NOMEM
+
+            self.ctx.set_allocator(alloc, torch.cuda.caching_allocator_delete)
+        _LIVE.add(self)
         self._graph = None
         self._graph_gen = -1
         self.mats = []
@@ -34,10 +64,10 @@ class Sim:
 
     @classmethod
     def from_workload(cls, workload, opts: t2r.SolverOpts | None = None, device="cuda:0",
-                      envs=None, stream=None):
+                      envs=None, stream=None, torch_memory: bool = True):
         """Builds every gel and indenter class of a scenes.Workload and its envs
         (all of them, or the listed indices)."""
-        sim = cls(opts, device, stream)
+        sim = cls(opts, device, stream, torch_memory=torch_memory)
         for name, g in workload.meshes.items():
             sim.gel_ids[name] = sim.ctx.add_gel(g.X, g.tets, g.fixed, g.markers)
         for name, ind in workload.indenters.items():
@@ -191,6 +221,11 @@ class Sim:
         self.stream.synchronize()
         return {"block_size": opts.block_size, "pair_capacity": opts.pair_capacity, "trial_ms": trial_ms,
                 "predicted_ms": predicted, "list_fill": used * grow}
+
+    def close(self):
+        """Releases the library's device memory (back to torch's allocator)."""
+        self._graph = None
+        self.ctx.close()
 
     def split_markers(self, markers=None):
         markers = self.markers if markers is None else markers

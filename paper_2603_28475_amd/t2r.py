@@ -88,6 +88,10 @@ SIGNATURES = [
     ("t2r_set_gel_markers", C.c_int32, [_P, C.c_int32, C.c_int32, _PI, _PD]),
     ("t2r_layout_generation", C.c_int32, [_P, C.POINTER(C.c_int64)]),
     ("t2r_backward_static", C.c_int32, [_P, _P, _P]),
+    ("t2r_set_gel_markers_knn", C.c_int32, [_P, C.c_int32, C.c_int32, _PD, C.c_int32, C.c_double]),
+    ("t2r_step_velocity", C.c_int32, [_P, C.c_int32, C.c_double, _P, _P, _P, _P, _P]),
+    ("t2r_step_relative", C.c_int32, [_P, C.c_int32, _P, _P, _P, _P, _P, _P]),
+    ("t2r_set_pose_offsets", C.c_int32, [_P, C.c_int32, _PI, _PD]),
 ]
 
 
@@ -125,6 +129,10 @@ def default_opts(**kw) -> SolverOpts:
     return o
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class Context:
     """Owns one t2r context; methods mirror the C entry points."""
 
@@ -139,6 +147,16 @@ class Context:
         if self.handle:
             lib.t2r_destroy(self.handle)
             self.handle = C.c_void_p()
+        self._alloc_cbs = None
+
+    def set_allocator(self, alloc, free):
+        """Routes every device allocation of the context through alloc(nbytes) -> int
+        pointer (0 on failure) and free(ptr) (t2r_set_allocator); before the first
+        GPU call. The callbacks live as long as the context."""
+        a = _ALLOC_FN(lambda n, user: alloc(int(n)))
+        f = _FREE_FN(lambda ptr, user: free(int(ptr)) if ptr else None)
+        self.check(lib.t2r_set_allocator(self.handle, C.cast(a, C.c_void_p), C.cast(f, C.c_void_p), None))
+        self._alloc_cbs = (a, f)
 
     def __del__(self):
         try:
@@ -184,6 +202,11 @@ class Context:
         weight = np.ascontiguousarray(weight, dtype=np.float64).reshape(-1, 3)
         self.check(lib.t2r_set_gel_markers(self.handle, gid, len(vertex), _dptr(vertex, C.c_int32),
                                            _dptr(weight, C.c_double)))
+
+    def set_gel_markers_knn(self, gid, markers_xy, k=3, power=1.0):
+        m = np.ascontiguousarray(markers_xy, dtype=np.float64).reshape(-1, 2)
+        self.check(lib.t2r_set_gel_markers_knn(self.handle, gid, len(m), _dptr(m, C.c_double), int(k),
+                                               float(power)))
 
     def add_indenter(self, Y, tris) -> int:
         Y = np.ascontiguousarray(Y, dtype=np.float64)
@@ -245,6 +268,19 @@ class Context:
     def step_sequence(self, n_steps, d_poses, d_mask=None, d_markers=None, d_x=None, d_status=None):
         self.check(lib.t2r_step_sequence(self.handle, int(n_steps), _tptr(d_poses), _tptr(d_mask),
                                          _tptr(d_markers), _tptr(d_x), _tptr(d_status)))
+
+    def step_velocity(self, n_steps, dt, d_vel, d_mask=None, d_markers=None, d_x=None, d_status=None):
+        self.check(lib.t2r_step_velocity(self.handle, int(n_steps), float(dt), _tptr(d_vel), _tptr(d_mask),
+                                         _tptr(d_markers), _tptr(d_x), _tptr(d_status)))
+
+    def step_relative(self, n_steps, d_rel0, d_rel1, d_mask=None, d_markers=None, d_x=None, d_status=None):
+        self.check(lib.t2r_step_relative(self.handle, int(n_steps), _tptr(d_rel0), _tptr(d_rel1), _tptr(d_mask),
+                                         _tptr(d_markers), _tptr(d_x), _tptr(d_status)))
+
+    def set_pose_offsets(self, env_ids, offsets):
+        ids = np.ascontiguousarray(env_ids, dtype=np.int32)
+        off = np.ascontiguousarray(offsets, dtype=np.float64).reshape(-1, 6)
+        self.check(lib.t2r_set_pose_offsets(self.handle, len(ids), _dptr(ids, C.c_int32), _dptr(off, C.c_double)))
 
     def eval(self, env, d_x, pose, d_p=None, d_x_lag=None, pose_lag=None, d_grad=None, d_diag=None,
              d_scalars=None):

@@ -79,8 +79,10 @@ def pose_at_depth(ind: Indenter, q, xy, depth: float, thickness: float) -> np.nd
 
 
 def press_schedule(ind, q, xy, depth, thickness, n_press, dhat=DHAT,
-                   shear=(0.0, 0.0), n_shear=0) -> np.ndarray:
-    poses = [pose_at_depth(ind, q, xy, -2.0 * dhat, thickness)]
+                   shear=(0.0, 0.0), n_shear=0, clearance=None) -> np.ndarray:
+    """Pose 0 `clearance` above the gel (default 2 dhat), then n_press steps to
+    `depth`, then n_shear in-plane steps adding up to `shear`."""
+    poses = [pose_at_depth(ind, q, xy, -(2.0 * dhat if clearance is None else clearance), thickness)]
     for s in range(1, n_press + 1):
         poses.append(pose_at_depth(ind, q, xy, depth * s / n_press, thickness))
     last = poses[-1].copy()
@@ -230,8 +232,11 @@ def adjoint_peg_5k(n_envs: int = 64) -> Workload:
         mu = r.uniform(0.3, 0.8)
         dt = r.uniform(-0.2, 0.2, 3)
         dw = np.deg2rad(r.uniform(-2.0, 2.0, 3))
+        # pose 0 starts 0.6 mm above the gel: the rigid offsets (|dt_z| <= 0.3 mm,
+        # tilts of up to 3 deg over the 4 mm peg radius) move every pose,
+        # the start pose included, and it must stay clear of the gel
         poses = press_schedule(ind, (1.0, 0, 0, 0), (0.0, 0.0), 0.6, g.thickness, 10,
-                               shear=(0.5, 0.0), n_shear=10)
+                               shear=(0.5, 0.0), n_shear=10, clearance=0.6)
         theta_star = dict(E=E, nu=nu, mu=mu, dt=dt, dw=dw)
         theta0 = dict(E=1.2 * E, nu=nu - 0.02, mu=mu + 0.1, dt=dt + 0.1, dw=dw + np.deg2rad(1.0))
         envs.append(EnvSpec("5k", "peg4", theta0["E"], theta0["nu"], theta0["mu"], poses,

@@ -159,20 +159,38 @@ def test_options_roundtrip_and_capacity_rule():
 
 def test_marker_map_replacement_and_knn_map():
     """t2r_set_gel_markers validates and replaces a gel's map before the first GPU
-    call; the kNN map's weights sum to 1 and a marker on a node takes it alone."""
+    call. t2r_set_gel_markers_knn builds the paper's k-nearest-neighbour map in
+    the library; it equals the oracle's kNN map (same vertices, weights to
+    1e-15) for k = 1, 2, 3 and two weight powers, its weights sum to 1 in
+    order of distance, and a marker on a node takes it alone."""
     t2r = _t2r()
-    from paper_2603_28475_amd.markers import knn_marker_map
+    from oracle.geometry import GelGeometry, knn_marker_map, top_face_vertices
     g = mesh_class("c1")
+    top = top_face_vertices(g.X, GelGeometry(g.X, g.tets, g.fixed, g.markers).boundary_tris_all)
+    rng = np.random.default_rng(4)
+    M = np.concatenate([np.asarray(g.markers), g.X[top[:2], :2], rng.uniform(-3.9, 3.9, (20, 2))])
+    for k in (1, 2, 3):
+        for power in (1.0, 2.0):
+            ctx = t2r.Context()
+            gid = ctx.add_gel(g.X, g.tets, g.fixed, g.markers)
+            ctx.set_gel_markers_knn(gid, M, k=k, power=power)
+            vert, wt = ctx.gel_markers(gid)
+            ov, ow = knn_marker_map(g.X, top, M, k=k, power=power)
+            assert np.array_equal(vert, ov), (k, power)
+            assert np.abs(wt - ow).max() <= 1e-15, (k, power)
+            assert np.allclose(wt.sum(axis=1), 1.0) and np.all(wt >= 0.0)
+            d = np.linalg.norm(g.X[vert][:, :, :2] - M[:, None, :], axis=2)
+            if k == 3:
+                assert np.all(d[:, 0] <= d[:, 1] + 1e-15) and np.all(d[:, 1] <= d[:, 2] + 1e-15)
+            on = len(g.markers)  # the two markers placed on nodes
+            assert np.all(wt[on:on + 2, 0] == 1.0) and np.all(vert[on:on + 2, 0] == top[:2])
     ctx = t2r.Context()
     gid = ctx.add_gel(g.X, g.tets, g.fixed, g.markers)
-    top = np.nonzero(np.isclose(g.X[:, 2], g.X[:, 2].max()))[0]
-    M = np.asarray(g.markers)
-    vert, wt = knn_marker_map(g.X, top, M, k=3)
-    assert np.allclose(wt.sum(axis=1), 1.0) and np.all(wt >= 0.0)
-    d = np.linalg.norm(g.X[vert][:, :, :2] - M[:, None, :], axis=2)
-    assert np.all(d[:, 0] <= d[:, 1] + 1e-15) and np.all(d[:, 1] <= d[:, 2] + 1e-15)
-    on = knn_marker_map(g.X, top, g.X[top[:1], :2], k=3)
-    assert on[0][0, 0] == top[0] and on[1][0, 0] == 1.0 and on[1][0, 1:].sum() == 0.0
+    for bad in (dict(k=0), dict(k=4), dict(power=0.0)):
+        with pytest.raises(t2r.T2RError) as e:
+            ctx.set_gel_markers_knn(gid, M, **{"k": 3, "power": 1.0, **bad})
+        assert e.value.code == t2r.T2R_E_ARG
+    vert, wt = knn_marker_map(g.X, top, np.asarray(g.markers), k=3)
     ctx.set_gel_markers(gid, vert, wt)
     tri2, w2 = ctx.gel_markers(gid)
     assert np.array_equal(tri2, vert) and np.allclose(w2, wt)

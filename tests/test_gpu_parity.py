@@ -573,20 +573,24 @@ def test_c5_sampled_gradients_match_oracle_at_full_size():
     (all sliding, friction lag active) of two sampled envs against the oracle's
     sparse-solve sequence adjoint at the GPU's own states."""
     t2r = _gpu()
-    from oracle.adjoint import adjoint_sequence
-    from paper_2603_28475_amd.autograd import offset_poses
+    from oracle.adjoint import adjoint_sequence, offset_pose
     from scenes.configs import adjoint_peg_5k
     w = adjoint_peg_5k(n_envs=64)
     sim = _build(t2r, w, tol=1e-8, precision=0, max_iters=50000)
     n = len(w.envs)
     th0 = np.array([[e.E, e.nu, e.mu_f, *e.extra["theta0"]["dt"], *e.extra["theta0"]["dw"]] for e in w.envs])
-    seq = offset_poses(np.stack([e.poses for e in w.envs])[:, 1:].transpose(1, 0, 2), th0)
+    # the rigid pose offsets theta0 are applied by the library (t2r_set_pose_offsets);
+    # the oracle gets the offset poses themselves
+    sim.ctx.set_pose_offsets(list(range(n)), th0[:, 3:9])
+    raw = np.stack([e.poses for e in w.envs])[:, 1:].transpose(1, 0, 2)
+    seq = np.array([[offset_pose(raw[s, e], th0[e, 3:6], th0[e, 6:9]) for e in range(n)]
+                    for s in range(raw.shape[0])])
     S = seq.shape[0]
     print("C5 64x5k forward with tape", flush=True)
     sim.record(S)
     xs = []
     for s in range(S):
-        _, st = sim.step(seq[s], want_x=True)
+        _, st = sim.step(raw[s], want_x=True)
         torch.cuda.synchronize()
         assert np.all(st.cpu().numpy() & 1), s
         xs.append(sim.x.cpu().numpy().copy())
@@ -607,8 +611,20 @@ def test_c5_sampled_gradients_match_oracle_at_full_size():
         states = [xs[k][e * nv:(e + 1) * nv] for k in range(S - W - 1, S)]
         poses = seq[S - W - 1:S, e]
         ref = adjoint_sequence(prob, states, poses, du[:, e * n_m:(e + 1) * n_m])
+        ref[6:9] = _left_jacobian(th0[e, 6:9]).T @ ref[6:9]  # incremental rotation -> d/d(dw)
         scale = np.abs(ref).max()
         assert np.all(np.abs(g[e] - ref) <= 1e-6 * np.maximum(np.abs(ref), 1e-3 * scale)), (e, g[e], ref)
+
+
+def _left_jacobian(w):
+    """J_l(w) of SO(3): exp([w + d]x) = exp([J_l(w) d]x) exp([w]x) to first order
+    (I + (1 - cos a)/a^2 K + (a - sin a)/a^3 K^2, K = [w]x, a = |w|)."""
+    w = np.asarray(w, dtype=np.float64)
+    a = float(np.linalg.norm(w))
+    K = np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
+    if a < 1e-8:
+        return np.eye(3) + 0.5 * K
+    return np.eye(3) + (1.0 - np.cos(a)) / a ** 2 * K + (a - np.sin(a)) / a ** 3 * (K @ K)
 
 
 def _newton_correction(prob, x):
@@ -821,19 +837,20 @@ def test_calibration_recovers_hidden_parameters():
 
 def test_knn_marker_map_matches_oracle_positions():
     """The paper's k-nearest-neighbour marker map (k = 3, inverse-distance
-    weights) set through t2r_set_gel_markers: the GPU markers equal the map
-    applied to the oracle's Newton positions within 1e-6 mm."""
+    weights) built by the library (t2r_set_gel_markers_knn): the GPU markers
+    equal the oracle's kNN map applied to the oracle's Newton positions within
+    1e-6 mm."""
     t2r = _gpu()
+    from oracle.geometry import GelGeometry, knn_marker_map, top_face_vertices
     from oracle.sim import simulate
-    from paper_2603_28475_amd.markers import knn_marker_map
     from scenes.configs import micro_press
     w = micro_press(mesh="micro3", indenter="sphere_small", depth=0.15, n_steps=3, xy=(0.12, -0.07))
     env = w.envs[0]
     g = w.meshes[env.mesh]
-    top = np.nonzero(np.isclose(g.X[:, 2], g.X[:, 2].max()))[0]
-    vert, wt = knn_marker_map(g.X, top, np.asarray(g.markers), k=3)
+    top = top_face_vertices(g.X, GelGeometry(g.X, g.tets, g.fixed, g.markers).boundary_tris_all)
+    vert, wt = knn_marker_map(g.X, top, np.asarray(g.markers), k=3)   # the oracle's map
     sim = _build(t2r, w, tol=1e-10, substep_tol=1e-10, max_iters=400000)
-    sim.ctx.set_gel_markers(sim.gel_ids[env.mesh], vert, wt)
+    sim.ctx.set_gel_markers_knn(sim.gel_ids[env.mesh], np.asarray(g.markers), k=3)  # the library's
     ref = simulate(g, w.indenters[env.indenter], env, mode="newton", tol=1e-12)
     for s in range(1, env.poses.shape[0]):
         m, st = sim.step(env.poses[s][None])
@@ -842,7 +859,7 @@ def test_knn_marker_map_matches_oracle_positions():
         u = np.einsum("mk,mkd->md", wt, (ref.x[s - 1] - g.X)[vert])
         assert np.abs(m.cpu().numpy() - u).max() <= 1e-6, s
     with pytest.raises(t2r.T2RError) as e:
-        sim.ctx.set_gel_markers(sim.gel_ids[env.mesh], vert, wt)
+        sim.ctx.set_gel_markers_knn(sim.gel_ids[env.mesh], np.asarray(g.markers), k=3)
     assert e.value.code == t2r.T2R_E_STATE
 
 
@@ -896,8 +913,9 @@ def test_plugin_velocity_driven_observation_matches_oracle():
     in-plane marker field of the oracle's Newton solve along the same poses
     within 1e-6 mm."""
     t2r = _gpu()
+    from oracle.geometry import advance_pose
     from oracle.sim import simulate
-    from paper_2603_28475_amd.plugin import TactilePlugin, advance_pose
+    from paper_2603_28475_amd.plugin import TactilePlugin
     from scenes.configs import DHAT, INDENTERS, EnvSpec, Workload, pose_at_depth
     from scenes.mesh import hex_kuhn_gel
     g = hex_kuhn_gel((3.0, 3.0, 1.0), (3, 3, 1), (7, 9), name="micro3_7x9")
@@ -913,7 +931,7 @@ def test_plugin_velocity_driven_observation_matches_oracle():
     w = Workload("plugin_micro3", 0, {"micro3_7x9": g}, {"sphere_small": ind}, [env], "f64", 1e-10)
     ref = simulate(g, ind, env, mode="newton", tol=1e-12)
     sim = _build(t2r, w, tol=1e-11, substep_tol=1e-8, max_iters=200000)
-    plug = TactilePlugin(sim, p0[None], grid=(7, 9), substeps=sub)
+    plug = TactilePlugin(sim, grid=(7, 9), substeps=sub)
     for k, (v, om) in enumerate(motion):
         obs, st = plug.step_velocity(np.array([v], dtype=np.float64), np.array([om], dtype=np.float64), dt)
         torch.cuda.synchronize()
@@ -921,6 +939,16 @@ def test_plugin_velocity_driven_observation_matches_oracle():
         u = ref.markers[sub * (k + 1) - 1]                     # (63, 3), x fastest
         expect = u[:, :2].reshape(9, 7, 2).transpose(1, 0, 2)
         assert obs.shape == (1, 7, 9, 2)
+        assert np.abs(obs[0].cpu().numpy() - expect).max() <= 1e-6, k
+    # the same engine steps given as the poses at their start and end (t2r_step_relative)
+    sim2 = _build(t2r, w, tol=1e-11, substep_tol=1e-8, max_iters=200000)
+    plug2 = TactilePlugin(sim2, grid=(7, 9), substeps=sub)
+    for k in range(len(motion)):
+        obs, st = plug2.step_relative(np.array([poses[sub * k]]), np.array([poses[sub * (k + 1)]]))
+        torch.cuda.synchronize()
+        assert np.all(st.cpu().numpy() & 1)
+        u = ref.markers[sub * (k + 1) - 1]
+        expect = u[:, :2].reshape(9, 7, 2).transpose(1, 0, 2)
         assert np.abs(obs[0].cpu().numpy() - expect).max() <= 1e-6, k
     assert np.abs(ref.markers[-1]).max() > 1e-3                 # the gel did deform
 

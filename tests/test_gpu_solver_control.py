@@ -348,3 +348,34 @@ def test_graph_step_matches_newton_oracle_and_recaptures_after_layout_change():
     sim.record(2)
     with pytest.raises(RuntimeError):
         sim.graph_step(env.poses[10][None])
+
+
+def test_library_memory_comes_from_torch_caching_allocator():
+    """Sim routes the library's device allocations through torch's caching
+    allocator (t2r_set_allocator): torch's allocated-bytes counter grows by the
+    library's buffers at the first GPU call and drops back when the Sim is
+    closed; a Sim with torch_memory=False allocates outside torch and steps to
+    the same markers."""
+    t2r = _gpu()
+    from paper_2603_28475_amd.sim import Sim
+    from scenes.configs import peg_batch_5k
+    w = peg_batch_5k(n_envs=8, n_steps=2)
+    poses = np.stack([e.poses for e in w.envs])
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    sim = Sim.from_workload(w, t2r.default_opts(tol=1e-8, precision=0))
+    m, st = sim.step(poses[:, 1])
+    torch.cuda.synchronize()
+    grown = torch.cuda.memory_allocated() - base
+    assert grown > 20e6, grown  # pair lists, friction records, state vectors of 8 envs (about 38 MB)
+    assert np.all(st.cpu().numpy() & t2r.ENV_CONVERGED)
+    m_torch = m.cpu().numpy().copy()
+    sim.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() - base < 5e6  # the Sim's own output tensors remain
+    plain = Sim.from_workload(w, t2r.default_opts(tol=1e-8, precision=0), torch_memory=False)
+    before = torch.cuda.memory_allocated()
+    m2, st2 = plain.step(poses[:, 1])
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() - before < 10e6  # only the outputs are torch's
+    assert np.abs(m2.cpu().numpy() - m_torch).max() <= 1e-6
