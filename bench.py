@@ -45,9 +45,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2,
                     help="untimed load steps before the timed run: ceil(W/K) launches of the timed "
                          "sequence, envs reset to rest after each")
-    ap.add_argument("--workload", choices=["peg_batch_5k", "mixed_batch"], default="peg_batch_5k",
-                    help="peg_batch_5k: uniform 2048 x 5k gels (headline); mixed_batch: 512 envs over "
-                         "three gel sizes and three indenters")
+    ap.add_argument("--workload", choices=["peg_batch_5k", "peg_batch_5ku", "mixed_batch"], default="peg_batch_5k",
+                    help="peg_batch_5k: uniform 2048 x 5k gels (headline); peg_batch_5ku: the same batch on the "
+                         "unstructured (Delaunay) 5k gel; mixed_batch: 512 envs over three gel sizes and three "
+                         "indenters")
     ap.add_argument("--envs", type=int, default=0, help="0: the workload's own count")
     ap.add_argument("--precision", choices=["f64", "mixed"], default="mixed")
     ap.add_argument("--tol", type=float, default=1e-6)
@@ -295,9 +296,12 @@ def main():
 
     from scenes.configs import mixed_batch, peg_batch_5k
     if args.envs <= 0:
-        args.envs = 2048 if args.workload == "peg_batch_5k" else 512
-    make = peg_batch_5k if args.workload == "peg_batch_5k" else mixed_batch
-    workload = make(n_envs=args.envs, n_steps=SCHEDULE_STEPS, precision=args.precision)
+        args.envs = 512 if args.workload == "mixed_batch" else 2048
+    if args.workload == "mixed_batch":
+        workload = mixed_batch(n_envs=args.envs, n_steps=SCHEDULE_STEPS, precision=args.precision)
+    else:
+        workload = peg_batch_5k(n_envs=args.envs, n_steps=SCHEDULE_STEPS, precision=args.precision,
+                                mesh="5ku" if args.workload == "peg_batch_5ku" else "5k")
 
     # the CPU oracle runs first, in processes forked before this one creates a HIP context
     cpu_meas = None

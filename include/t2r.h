@@ -315,6 +315,14 @@ t2r_status t2r_step_velocity(t2r_ctx* ctx, int32_t n_steps, double dt, const dou
 t2r_status t2r_step_relative(t2r_ctx* ctx, int32_t n_steps, const double* d_rel0, const double* d_rel1,
                              const int32_t* d_env_mask, double* d_markers, double* d_x, int32_t* d_status);
 
+/* Sets each listed env's own mass density of the dynamic form (host arrays;
+ * t/mm^3, e.g. 1.1e-9 = 1,100 kg/m^3), replacing the option `density` for it;
+ * 0 returns the env to the option's density. Used by calibrations that fit
+ * density per candidate (theta = [E, nu, rho, mu], Sec. 4.2, eq.
+ * optimization_problem). Only the dynamic form reads it. Errors: T2R_E_ARG for
+ * bad ids or negative / non-finite densities. Synchronises the stream. */
+t2r_status t2r_set_densities(t2r_ctx* ctx, int32_t n, const int32_t* env_ids, const double* density);
+
 /* Sets a rigid offset per env (host arrays; offsets[n][6] = translation dt in
  * mm and rotation vector dw in rad): from now on every target pose the env
  * receives from t2r_step / t2r_step_sequence, and its start pose at

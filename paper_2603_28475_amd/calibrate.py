@@ -27,41 +27,14 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-# The paper's ranges (E in Pa there; here MPa, so 1e4..2e5 Pa = 0.01..0.2 MPa).
+from scenes.configs import protocol_poses  # noqa: F401  (the recording protocol, re-exported)
+
+# The paper's ranges (Supp., table of parameter ranges): E in Pa there, here MPa
+# (1e4..2e5 Pa = 0.01..0.2 MPa); rho is given without a unit as 1e-3..5e-3, read
+# as g/mm^3 (1,000..5,000 kg/m^3, around a silicone gel's 1,100); the library
+# takes t/mm^3, RHO_TO_LIB times these values.
 PAPER_RANGES = {"E": (0.01, 0.2), "nu": (0.4, 0.497), "mu_f": (0.25, 2.5), "density": (1e-3, 5e-3)}
-
-
-def protocol_poses(pose0, press=1.0, slide=1.0, rotate_deg=2.0, d_press=0.1, d_slide=0.1, d_rot_deg=0.5,
-                   slide_axis=(1.0, 0.0, 0.0)):
-    """The recording protocol as poses (S, 7) after `pose0` (the indenter just
-    touching): press by `press` mm in `d_press` steps, slide by `slide` mm along
-    `slide_axis`, rotate by `rotate_deg` about the vertical axis."""
-    pose0 = np.asarray(pose0, dtype=np.float64)
-    out = []
-    p = pose0.copy()
-    for _ in range(int(round(press / d_press))):
-        p = p.copy()
-        p[2] -= d_press
-        out.append(p)
-    ax = np.asarray(slide_axis, dtype=np.float64)
-    for _ in range(int(round(slide / d_slide))):
-        p = p.copy()
-        p[:3] += d_slide * ax
-        out.append(p)
-    h = math.radians(d_rot_deg) / 2
-    dq = np.array([math.cos(h), 0.0, 0.0, math.sin(h)])
-    for _ in range(int(round(rotate_deg / d_rot_deg))):
-        p = p.copy()
-        p[3:] = _quat_mul(dq, p[3:])
-        out.append(p)
-    return np.stack(out)
-
-
-def _quat_mul(a, b):
-    w1, x1, y1, z1 = a
-    w2, x2, y2, z2 = b
-    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
-                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+RHO_TO_LIB = 1e-6
 
 
 @dataclass
@@ -165,7 +138,8 @@ def cmaes_fit(sim, base_mats, poses, target, params: Params, x0_unit, generation
               sigma0=0.3, seed=0, log=None):
     """CMA-ES over `params` for N indenters. `sim` holds popsize x N envs, env
     k * N + i running indenter i for candidate k; base_mats: the N indenters'
-    materials (the calibrated entries are replaced); poses: (S, N, 7);
+    materials (the calibrated entries are replaced; a calibrated density is set
+    per env, which the dynamic form reads); poses: (S, N, 7);
     target: (S, N, n_m, 3) recorded marker fields. Returns (best values, best
     loss, loss per generation)."""
     N = len(base_mats)
@@ -176,7 +150,7 @@ def cmaes_fit(sim, base_mats, poses, target, params: Params, x0_unit, generation
     best, best_loss, history = None, math.inf, []
     for g in range(generations):
         cand = es.ask()
-        mats = []
+        mats, dens = [], []
         for k in range(popsize):
             vals = dict(zip(params.names, params.from_unit(cand[k])))
             for i in range(N):
@@ -185,6 +159,9 @@ def cmaes_fit(sim, base_mats, poses, target, params: Params, x0_unit, generation
                     if key in vals:
                         m[j] = float(vals[key])
                 mats.append(tuple(m))
+                dens.append(float(vals["density"]) * RHO_TO_LIB if "density" in vals else 0.0)
+        if "density" in params.names:  # per-candidate density of the dynamic form
+            sim.ctx.set_densities(list(range(sim.n_env)), dens)
         markers, status = _set_and_run(sim, mats, poses_env)
         markers = markers.reshape(markers.shape[0], popsize, N, n_m, 3)
         losses = np.array([mse(markers[:, k], target) for k in range(popsize)])

@@ -68,6 +68,7 @@ struct EnvHost {
   double pose0[7];
   int has_off = 0;
   double off[6] = {0, 0, 0, 0, 0, 0};  // rigid pose offset (dt, dw)
+  double density = 0.0;                // own density of the dynamic form (0: the option's)
 };
 
 // pose0 moved by the env's rigid offset: q <- exp([dw]x) q (normalised),
@@ -1054,6 +1055,29 @@ t2r_status t2r_set_pose_offsets(t2r_ctx* c, int32_t n, const int32_t* env_ids, c
   return T2R_OK;
 }
 
+t2r_status t2r_set_densities(t2r_ctx* c, int32_t n, const int32_t* env_ids, const double* density) {
+  if (!c) return T2R_E_ARG;
+  if (n < 0 || (n > 0 && (!env_ids || !density))) return fail(c, T2R_E_ARG, "bad arguments");
+  for (int i = 0; i < n; ++i) {
+    if (env_ids[i] < 0 || env_ids[i] >= (int)c->envs.size()) return fail(c, T2R_E_ARG, "bad env id %d", env_ids[i]);
+    if (!(density[i] >= 0.0) || !isfinite(density[i]))
+      return fail(c, T2R_E_ARG, "env %d: density must be finite and >= 0", env_ids[i]);
+  }
+  if (c->committed) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  ++c->layout_gen;
+  for (int i = 0; i < n; ++i) {
+    c->envs[env_ids[i]].density = density[i];
+    if (c->committed) {
+      EnvDev& d = c->h_envs[env_ids[i]];
+      d.density = density[i];
+      HIP_TRY(c, hipMemcpyAsync(c->d_envs + env_ids[i], &d, sizeof(EnvDev), hipMemcpyHostToDevice, c->stream));
+    }
+  }
+  if (c->committed) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->err.clear();
+  return T2R_OK;
+}
+
 t2r_status t2r_set_gel_markers_knn(t2r_ctx* c, int32_t id, int32_t n_m, const double* markers_xy, int32_t k,
                                    double power) {
   if (!c) return T2R_E_ARG;
@@ -1638,6 +1662,7 @@ t2r_status commit(t2r_ctx* c) {
     material_to_dev(e.mat, d);
     d.has_off = e.has_off;
     for (int k = 0; k < 6; ++k) d.off[k] = e.off[k];
+    d.density = e.density;
     const int cap = pair_cap_of(c, g);
     d.pair_cap = cap;
     d.fric_cap = std::max(1024, cap / 2);

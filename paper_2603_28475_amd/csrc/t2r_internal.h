@@ -112,6 +112,7 @@ struct EnvDev {
   int pair_cap, fric_cap, outer_cap;
   int has_off;             // a rigid pose offset is set (t2r_set_pose_offsets)
   double off[6];           // its translation dt (mm) and rotation vector dw (rad)
+  double density;          // mass density of the dynamic form (t/mm^3); 0: the option's
 };
 
 struct FricPair {          // lagged friction data of one pair (Supp. A, eq. friction_energy)

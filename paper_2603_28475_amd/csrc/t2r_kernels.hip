@@ -52,6 +52,7 @@ struct Shared {
   double bc[8];               // broadcast results
   int count, overflow, flag;
   int pad;
+  double qb[7];               // the env's pose at the launch start (motion input)
   T2R_G double* vel;          // this env's velocities (dynamic form)
   double iw, dt;              // inertia weight density / dt^2 (0: quasi-static), time step
   unsigned long long tacc[10];  // wall-clock ticks per phase (thread 0)
@@ -1972,7 +1973,9 @@ __device__ __forceinline__ void init_solver(Solver& s, const StepParams& P, Shar
   s.buffer_out = 6.0 * E.dhat;
   if (threadIdx.x == 0) {
     S.vel = P.vel ? P.vel + E.voff : nullptr;
-    S.iw = P.vel ? P.inertia_w : 0.0;
+    // density / dt^2 of the dynamic form (0: quasi-static); an env's own density
+    // (t2r_set_densities) replaces the option's
+    S.iw = (P.vel && P.inertia_w > 0.0) ? (E.density > 0.0 ? E.density / (P.dt * P.dt) : P.inertia_w) : 0.0;
     S.dt = P.dt;
   }
   __syncthreads();
@@ -2231,12 +2234,11 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
   st.evals = 0; st.reserved = 0;
   const bool skip = P.env_mask && P.env_mask[e] == 0;
   load_lists(s);
-  double qb[7];  // the env's pose at the launch start (motion modes)
-  #pragma unroll
-  for (int i = 0; i < 7; ++i) qb[i] = P.pose_prev[7 * e + i];
+  if (threadIdx.x < 7) S.qb[threadIdx.x] = P.pose_prev[7 * e + threadIdx.x];
+  __syncthreads();
   for (int k = 0; k < P.n_steps; ++k) {
     double q1[7];
-    target_pose(P, *V.E, e, k, qb, q1);
+    target_pose(P, *V.E, e, k, S.qb, q1);
     bool bad = false;
     #pragma unroll
     for (int i = 0; i < 7; ++i) bad |= !isfinite(q1[i]);

@@ -92,6 +92,7 @@ SIGNATURES = [
     ("t2r_step_velocity", C.c_int32, [_P, C.c_int32, C.c_double, _P, _P, _P, _P, _P]),
     ("t2r_step_relative", C.c_int32, [_P, C.c_int32, _P, _P, _P, _P, _P, _P]),
     ("t2r_set_pose_offsets", C.c_int32, [_P, C.c_int32, _PI, _PD]),
+    ("t2r_set_densities", C.c_int32, [_P, C.c_int32, _PI, _PD]),
 ]
 
 
@@ -276,6 +277,11 @@ class Context:
     def step_relative(self, n_steps, d_rel0, d_rel1, d_mask=None, d_markers=None, d_x=None, d_status=None):
         self.check(lib.t2r_step_relative(self.handle, int(n_steps), _tptr(d_rel0), _tptr(d_rel1), _tptr(d_mask),
                                          _tptr(d_markers), _tptr(d_x), _tptr(d_status)))
+
+    def set_densities(self, env_ids, density):
+        ids = np.ascontiguousarray(env_ids, dtype=np.int32)
+        rho = np.ascontiguousarray(density, dtype=np.float64).reshape(-1)
+        self.check(lib.t2r_set_densities(self.handle, len(ids), _dptr(ids, C.c_int32), _dptr(rho, C.c_double)))
 
     def set_pose_offsets(self, env_ids, offsets):
         ids = np.ascontiguousarray(env_ids, dtype=np.int32)

@@ -13,6 +13,7 @@ minus the lowest world z of the indenter's vertices.
 
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -271,3 +272,68 @@ WORKLOADS = {
 
 def make_workload(name: str, **kw) -> Workload:
     return WORKLOADS[name](**kw)
+
+
+def protocol_poses(pose0, press=1.0, slide=1.0, rotate_deg=2.0, d_press=0.1, d_slide=0.1, d_rot_deg=0.5,
+                   slide_axis=(1.0, 0.0, 0.0)):
+    """The recording protocol as poses (S, 7) after `pose0` (the indenter just
+    touching): press by `press` mm in `d_press` steps, slide by `slide` mm along
+    `slide_axis`, rotate by `rotate_deg` about the vertical axis."""
+    pose0 = np.asarray(pose0, dtype=np.float64)
+    out = []
+    p = pose0.copy()
+    for _ in range(int(round(press / d_press))):
+        p = p.copy()
+        p[2] -= d_press
+        out.append(p)
+    ax = np.asarray(slide_axis, dtype=np.float64)
+    for _ in range(int(round(slide / d_slide))):
+        p = p.copy()
+        p[:3] += d_slide * ax
+        out.append(p)
+    h = math.radians(d_rot_deg) / 2
+    dq = np.array([math.cos(h), 0.0, 0.0, math.sin(h)])
+    for _ in range(int(round(rotate_deg / d_rot_deg))):
+        p = p.copy()
+        p[3:] = _qmul(dq, p[3:])
+        out.append(p)
+    return np.stack(out)
+
+
+def _qmul(a, b):
+    w1, x1, y1, z1 = a
+    w2, x2, y2, z2 = b
+    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+def _qmul(a, b):
+    w1, x1, y1, z1 = a
+    w2, x2, y2, z2 = b
+    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+def calibration_micro(theta, n_copies: int = 1):
+    """The calibration scene: the 32-vertex gel with a small sphere and a tilted
+    plate (N = 2 indenters), friction, driven by the recording protocol scaled to
+    the 1 mm gel (press 0.2 mm, slide 0.1 mm, rotate 1 deg, in 0.05 mm, 0.05 mm
+    and 0.5 deg steps); theta = (E, nu, mu_f); n_copies of the pair of envs.
+    Returns (workload, poses (S, 2, 7) of the protocol after pose 0)."""
+    import dataclasses
+    q = np.array([0.99996192, 0.00610865, 0.00436331, 0.0])
+    ws = micro_press(mesh="micro3", indenter="sphere_small", depth=0.1, n_steps=1)
+    wp = micro_press(mesh="micro3", indenter="plate", depth=0.05, n_steps=1, xy=(0.1, -0.05),
+                     q=tuple(q / np.linalg.norm(q)))
+    envs, poses = [], []
+    for wk in (ws, wp):
+        e = wk.envs[0]
+        P = protocol_poses(e.poses[0], press=0.2, slide=0.1, rotate_deg=1.0, d_press=0.05, d_slide=0.05)
+        poses.append(P)
+        envs.append(dataclasses.replace(e, E=theta[0], nu=theta[1], mu_f=theta[2],
+                                        poses=np.concatenate([e.poses[:1], P])))
+    w = dataclasses.replace(ws, name="calibration_micro3",
+                            indenters={"sphere_small": INDENTERS["sphere_small"](), "plate": INDENTERS["plate"]()},
+                            envs=envs * n_copies)
+    return w, np.stack(poses, axis=1)
+

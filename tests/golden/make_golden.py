@@ -18,7 +18,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle.sim import simulate  # noqa: E402
-from scenes.configs import micro_press, peg_press_484v, sphere_press_484v  # noqa: E402
+from scenes.configs import calibration_micro, micro_press, peg_press_484v, sphere_press_484v  # noqa: E402
+
+CALIB_THETA = (0.12, 0.45, 0.6)        # hidden (E MPa, nu, mu_f) of the calibration recordings
+CALIB_DYNAMIC = dict(density=2.5e-9, dt=2e-4)  # hidden density (t/mm^3) of the dynamic recordings
 
 
 def sphere_press():
@@ -72,8 +75,28 @@ def peg_press_friction_unstructured():
     print(f"peg_press_484v_unstructured_friction: {time.time() - t:.1f}s, active {r.n_active}")
 
 
+def calibration_targets():
+    """Synthetic recordings for the calibration driver: the oracle's Newton
+    marker fields of the calibration scene (two indenters, the recording
+    protocol) at hidden parameters, quasi-static and in the dynamic form."""
+    w, poses = calibration_micro(CALIB_THETA)
+    t = time.time()
+    out = {}
+    for key, dyn in (("static", None), ("dynamic", CALIB_DYNAMIC)):
+        ms = []
+        for env in w.envs:
+            r = simulate(w.meshes[env.mesh], w.indenters[env.indenter], env, mode="newton", tol=1e-12,
+                         dynamic=dyn)
+            ms.append(np.array(r.markers))
+        out[key] = np.stack(ms, axis=1)     # (S, 2 indenters, n_m, 3)
+    np.savez_compressed(os.path.join(HERE, "calibration_micro3_newton.npz"), poses=poses,
+                        theta=np.array(CALIB_THETA), density=CALIB_DYNAMIC["density"], dt=CALIB_DYNAMIC["dt"],
+                        **out)
+    print(f"calibration_targets: {time.time() - t:.1f}s")
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["micro_friction", "sphere_press", "peg_press_friction",
-                             "peg_press_friction_unstructured"]
+                             "peg_press_friction_unstructured", "calibration_targets"]
     for name in which:
         globals()[name]()

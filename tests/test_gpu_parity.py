@@ -770,69 +770,72 @@ def test_dynamic_form_matches_oracle():
         assert np.abs(m2[s].cpu().numpy() - ref.markers[s]).max() <= 1e-6, s
 
 
-def _calibration_scene(n_copies, theta):
-    """The 32-vertex gel with a small sphere and a tilted plate (N = 2
-    indenters), friction; poses of the recording protocol scaled to the 1 mm
-    gel (press 0.2 mm, slide 0.1 mm, rotate 1 deg); n_copies of the pair of envs."""
-    import dataclasses
-    from paper_2603_28475_amd.calibrate import protocol_poses
-    from scenes.configs import INDENTERS, micro_press
-    q = np.array([0.99996192, 0.00610865, 0.00436331, 0.0])
-    ws = micro_press(mesh="micro3", indenter="sphere_small", depth=0.1, n_steps=1)
-    wp = micro_press(mesh="micro3", indenter="plate", depth=0.05, n_steps=1, xy=(0.1, -0.05),
-                     q=tuple(q / np.linalg.norm(q)))
-    envs, poses = [], []
-    for wk in (ws, wp):
-        e = wk.envs[0]
-        P = protocol_poses(e.poses[0], press=0.2, slide=0.1, rotate_deg=1.0, d_press=0.05, d_slide=0.05)
-        poses.append(P)
-        envs.append(dataclasses.replace(e, E=theta[0], nu=theta[1], mu_f=theta[2],
-                                        poses=np.concatenate([e.poses[:1], P])))
-    w = dataclasses.replace(ws, indenters={"sphere_small": INDENTERS["sphere_small"](), "plate": INDENTERS["plate"]()},
-                            envs=envs * n_copies)
-    return w, np.stack(poses, axis=1)   # (S, 2, 7)
-
-
-def test_calibration_recovers_hidden_parameters():
-    """The calibration drivers on synthetic recordings made at hidden
-    (E, nu, mu_f): CMA-ES (popsize 12, every generation one batched launch of
-    12 x 2 envs) and bounded L-BFGS with the adjoint gradient through the
-    protocol both
-    reduce the marker MSE at least 100-fold and recover nu within 1% and mu_f
-    within 5%. E is left out of the check: the protocol prescribes the
-    indenter's motion, so the marker field depends on E only through the
-    barrier's stiffness relative to the gel's and E is weakly identified by
-    marker data (the loss is flat along it)."""
+def test_calibration_recovers_hidden_parameters_from_oracle_recordings():
+    """The calibration drivers on synthetic recordings made by the oracle
+    (tests/golden/calibration_micro3_newton.npz: Newton marker fields of two
+    indenters through the recording protocol at hidden (E, nu, mu_f)): CMA-ES
+    with the paper's popsize 12 and 80 generations (every generation one
+    batched launch of 12 x 2 envs) cuts the marker MSE at least 1000-fold and
+    recovers E within 1%, nu within 0.1% and mu_f within 0.5% (measured: 2e-5,
+    1e-8, 4e-7); bounded L-BFGS with the adjoint gradient through the protocol
+    recovers all three within 1e-3 relative (measured: 1e-5)."""
     t2r = _gpu()
-    from paper_2603_28475_amd.calibrate import Params, cmaes_fit, gradient_fit, mse
+    from paper_2603_28475_amd.calibrate import Params, cmaes_fit, gradient_fit
     from paper_2603_28475_amd.sim import Sim
-    star = (0.12, 0.45, 0.6)
-    w, poses = _calibration_scene(1, star)
+    from scenes.configs import calibration_micro
+    gold = np.load(os.path.join(HERE, "golden", "calibration_micro3_newton.npz"))
+    star = tuple(gold["theta"])
+    w, poses = calibration_micro(star)
+    assert np.array_equal(poses, gold["poses"])
+    target = gold["static"]
     o = t2r.default_opts(tol=1e-8, substep_tol=1e-8, max_iters=200000)
-    rec = Sim.from_workload(w, o)
-    m, st = rec.step_sequence(poses)
-    torch.cuda.synchronize()
-    assert np.all(st.cpu().numpy() & 1)
-    S, n_m = poses.shape[0], rec.n_m[0]
-    target = m.cpu().numpy().reshape(S, 2, n_m, 3)
     pr = Params()
     x0 = np.full(3, 0.5)
-    # CMA-ES
-    wc, _ = _calibration_scene(12, star)
+    wc, _ = calibration_micro(star, 12)
     simc = Sim.from_workload(wc, o)
-    print("calibration: CMA-ES", flush=True)
+    print("calibration: CMA-ES, 80 generations", flush=True)
     best, best_loss, hist = cmaes_fit(simc, [e.material() for e in w.envs], poses, target, pr, x0,
-                                      generations=14, popsize=12)
+                                      generations=80, popsize=12)
     print("CMA-ES", best, best_loss, hist[0], flush=True)
-    assert best_loss <= 1e-2 * hist[0], (best_loss, hist[0])
-    assert abs(best[1] - star[1]) <= 0.01 * star[1] and abs(best[2] - star[2]) <= 0.05 * star[2], best
-    # gradient fit
+    assert best_loss <= 1e-3 * hist[0], (best_loss, hist[0])
+    assert abs(best[0] - star[0]) <= 0.01 * star[0], best
+    assert abs(best[1] - star[1]) <= 1e-3 * star[1] and abs(best[2] - star[2]) <= 5e-3 * star[2], best
     simg = Sim.from_workload(w, o)
     print("calibration: adjoint gradient", flush=True)
-    vals, ghist = gradient_fit(simg, poses, target, pr, x0, steps=30)
+    vals, ghist = gradient_fit(simg, poses, target, pr, x0, steps=60)
     print("gradient", vals, ghist[0], ghist[-1], flush=True)
-    assert min(ghist) <= 1e-2 * ghist[0], (ghist[0], min(ghist))
-    assert abs(vals[1] - star[1]) <= 0.01 * star[1] and abs(vals[2] - star[2]) <= 0.05 * star[2], vals
+    assert np.all(np.abs(np.asarray(vals) - np.asarray(star)) <= 1e-3 * np.asarray(star)), (vals, star)
+
+
+def test_calibration_in_the_dynamic_form_recovers_density():
+    """theta = [E, nu, rho, mu] (Sec. 4.2): CMA-ES (popsize 12, 80 generations,
+    density set per candidate env with t2r_set_densities) on the oracle's
+    recordings of the same protocol in the dynamic (implicit-Euler) form at a
+    hidden density, one load step per 0.2 ms time step, recovers the density
+    within 2% and E, nu and mu_f within 2%, 0.5% and 1% (measured: 2e-4, 2e-4,
+    6e-7, 1e-5)."""
+    t2r = _gpu()
+    from paper_2603_28475_amd.calibrate import RHO_TO_LIB, Params, cmaes_fit
+    from paper_2603_28475_amd.sim import Sim
+    from scenes.configs import calibration_micro
+    gold = np.load(os.path.join(HERE, "golden", "calibration_micro3_newton.npz"))
+    star = tuple(gold["theta"])
+    rho_star = float(gold["density"])
+    w, poses = calibration_micro(star)
+    o = t2r.default_opts(tol=1e-8, substep_tol=1e-8, max_iters=200000, dynamic=1, dt=float(gold["dt"]),
+                         density=1.1e-9)
+    pr = Params(names=("E", "nu", "mu_f", "density"))
+    wc, _ = calibration_micro(star, 12)
+    simc = Sim.from_workload(wc, o)
+    print("dynamic calibration: CMA-ES, 80 generations", flush=True)
+    best, best_loss, hist = cmaes_fit(simc, [e.material() for e in w.envs], poses, gold["dynamic"], pr,
+                                      np.full(4, 0.5), generations=80, popsize=12)
+    rho = best[3] * RHO_TO_LIB
+    print("CMA-ES dynamic", best, rho, best_loss, hist[0], flush=True)
+    assert best_loss <= 1e-3 * hist[0], (best_loss, hist[0])
+    assert abs(rho - rho_star) <= 0.02 * rho_star, (rho, rho_star)
+    assert abs(best[0] - star[0]) <= 0.02 * star[0], best
+    assert abs(best[1] - star[1]) <= 5e-3 * star[1] and abs(best[2] - star[2]) <= 0.01 * star[2], best
 
 
 def test_knn_marker_map_matches_oracle_positions():
