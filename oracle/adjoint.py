@@ -84,11 +84,7 @@ def _pose_mixed_terms(prob, x, lam_x):
     out = np.zeros(6)
     if len(pairs["idx"]) == 0:
         return out
-    d, grad, Hd = distance_derivatives(res["Z"], res["c"], res["Cw"], res["k"])
-    b1 = barrier_d1(d, prob.dhat)
-    b2 = barrier_d2(d, prob.dhat)
-    gf = grad.reshape(-1, 12)
-    Hb = prob.kappa * (b2[:, None, None] * np.einsum("ni,nj->nij", gf, gf) + b1[:, None, None] * Hd)
+    _, _, Hb = prob.pair_terms(pairs, res, order=2)
     gel_pt = pairs["idx"] < prob.nv
     P1 = np.where(gel_pt[:, :, None], lam_x[np.where(gel_pt, pairs["idx"], 0)], 0.0).reshape(-1, 12)
     t = prob.pose[:3]

@@ -7,7 +7,9 @@ over the free vertices (the bottom face stays at rest).
 
 C(x) holds every gel-surface/indenter pair closer than dhat: gel vertex vs
 indenter triangle, indenter vertex vs gel triangle, gel edge vs indenter edge.
-Shared-feature duplicates are kept (plain IPC enumeration, no mollifier).
+Shared-feature duplicates are kept (plain IPC enumeration). With the option
+ee_mollifier the edge-edge terms are kappa m(c) b(d), m the edge-edge mollifier
+of barrier.py (smooth as the edges turn parallel); without it kappa b(d).
 
 Friction (Supp. A, eqs. friction_energy, friction_mollifier) is lagged once per
 load step at the previous equilibrium (x_{s-1}, q_{s-1}): for each pair active
@@ -23,7 +25,9 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .barrier import barrier, barrier_d1, barrier_d2, mollifier, mollifier_d1, mollifier_d2
+from .barrier import (EDGE_MOLLIFIER_REL, barrier, barrier_d1, barrier_d2, edge_cross_derivatives,
+                      edge_mollifier, edge_mollifier_d1, edge_mollifier_d2, mollifier, mollifier_d1,
+                      mollifier_d2)
 from .distance import distance_derivatives, edge_edge, point_triangle
 from .elastic import (element_energy, element_gradient, element_hessian, lame, psd_project)
 from .geometry import GelGeometry, IndenterGeometry
@@ -55,8 +59,9 @@ class StepProblem:
     """Energy of one load step at a fixed indenter pose (and fixed friction lag)."""
 
     def __init__(self, gel: GelGeometry, ind: IndenterGeometry, E, nu, mu_f=0.0,
-                 eps_v=1e-3, dhat=0.05, kappa=1e3):
+                 eps_v=1e-3, dhat=0.05, kappa=1e3, ee_mollifier=False):
         self.gel, self.ind = gel, ind
+        self.ee_mollifier = bool(ee_mollifier)
         self.mu, self.lam = lame(E, nu)
         self.mu_f, self.eps_v, self.dhat, self.kappa = mu_f, eps_v, dhat, kappa
         self.nv = gel.n_v
@@ -210,6 +215,47 @@ class StepProblem:
             return np.inf
         return float(self.pair_geometry(x, pairs)["d"].min())
 
+    def pair_terms(self, pairs, res, order=2):
+        """Per active pair: the barrier potential kappa b(d) (edge-edge pairs:
+        kappa m(c) b(d) with the mollifier on), its gradient (n, 12) and Hessian
+        (n, 12, 12) with respect to the pair's four points (gel and indenter),
+        up to derivative `order`."""
+        d = res["d"]
+        n = len(d)
+        val = self.kappa * barrier(d, self.dhat)
+        if order == 0 and not self.ee_mollifier:
+            return val, None, None
+        _, grad, Hd = distance_derivatives(res["Z"], res["c"], res["Cw"], res["k"])
+        b1 = barrier_d1(d, self.dhat)
+        g = grad.reshape(n, 12)
+        G = self.kappa * b1[:, None] * g
+        H = None
+        if order >= 2:
+            b2 = barrier_d2(d, self.dhat)
+            H = self.kappa * (b2[:, None, None] * np.einsum("ni,nj->nij", g, g) + b1[:, None, None] * Hd)
+        if self.ee_mollifier:
+            ee = np.nonzero(pairs["kind"] == EE)[0]
+            if len(ee):
+                idx = pairs["idx"][ee]
+                ar = self.gel.X[idx[:, 1]] - self.gel.X[idx[:, 0]]
+                br = self.ind.Y[idx[:, 3] - self.nv] - self.ind.Y[idx[:, 2] - self.nv]
+                eps = EDGE_MOLLIFIER_REL * np.einsum("nd,nd->n", ar, ar) * np.einsum("nd,nd->n", br, br)
+                c, gc, Hc = edge_cross_derivatives(res["Z"][ee])
+                m, m1, m2 = edge_mollifier(c, eps), edge_mollifier_d1(c, eps), edge_mollifier_d2(c, eps)
+                b = barrier(d[ee], self.dhat)
+                be1 = b1[ee]
+                ge = g[ee]
+                if H is not None:
+                    He = H[ee]
+                    H[ee] = (m[:, None, None] * He
+                             + self.kappa * (m1 * be1)[:, None, None] * (np.einsum("ni,nj->nij", gc, ge)
+                                                                         + np.einsum("ni,nj->nij", ge, gc))
+                             + self.kappa * (m2 * b)[:, None, None] * np.einsum("ni,nj->nij", gc, gc)
+                             + self.kappa * (m1 * b)[:, None, None] * Hc)
+                G[ee] = m[:, None] * G[ee] + self.kappa * (m1 * b)[:, None] * gc
+                val[ee] = m * val[ee]
+        return val, G, H
+
     # ---------------------------------------------------------------- friction
     def _friction_terms(self, x):
         L = self.lag
@@ -230,10 +276,10 @@ class StepProblem:
         Ee = element_energy(x, g.tets, g.Dm_inv, g.vol, self.mu, self.lam)
         if not np.all(np.isfinite(Ee)):
             return np.inf
-        _, res = self.active(x)
+        pairs, res = self.active(x)
         if np.any(res["d"] <= 0):
             return np.inf
-        Eb = self.kappa * barrier(res["d"], self.dhat).sum()
+        Eb = self.pair_terms(pairs, res, order=0)[0].sum()
         Ef = 0.0
         if self.lag is not None and len(self.lag["lam"]):
             _, _, _, s = self._friction_terms(x)
@@ -243,8 +289,8 @@ class StepProblem:
     def energy_parts(self, x):
         g = self.gel
         Ee = element_energy(x, g.tets, g.Dm_inv, g.vol, self.mu, self.lam).sum()
-        _, res = self.active(x)
-        Eb = self.kappa * barrier(res["d"], self.dhat).sum()
+        pairs, res = self.active(x)
+        Eb = self.pair_terms(pairs, res, order=0)[0].sum()
         Ef = 0.0
         if self.lag is not None and len(self.lag["lam"]):
             _, _, _, s = self._friction_terms(x)
@@ -258,10 +304,9 @@ class StepProblem:
         np.add.at(out, g.tets, ge)
         pairs, res = self.active(x)
         if len(pairs["idx"]):
-            d, grad, _ = distance_derivatives(res["Z"], res["c"], res["Cw"], res["k"])
-            coef = self.kappa * barrier_d1(d, self.dhat)
+            _, G, _ = self.pair_terms(pairs, res, order=1)
             gel_pt = pairs["idx"] < self.nv
-            contrib = coef[:, None, None] * grad * gel_pt[:, :, None]
+            contrib = G.reshape(-1, 4, 3) * gel_pt[:, :, None]
             np.add.at(out, np.where(gel_pt, pairs["idx"], 0), contrib)
         if self.lag is not None and len(self.lag["lam"]):
             gel_pt, gid, TD, s = self._friction_terms(x)
@@ -288,11 +333,7 @@ class StepProblem:
         yield "elastic", dof, He
         pairs, res = self.active(x)
         if len(pairs["idx"]):
-            d, grad, Hd = distance_derivatives(res["Z"], res["c"], res["Cw"], res["k"])
-            b1 = barrier_d1(d, self.dhat)
-            b2 = barrier_d2(d, self.dhat)
-            gf = grad.reshape(-1, 12)
-            Hb = self.kappa * (b2[:, None, None] * np.einsum("ni,nj->nij", gf, gf) + b1[:, None, None] * Hd)
+            _, _, Hb = self.pair_terms(pairs, res, order=2)
             gel_pt = pairs["idx"] < self.nv
             mask = np.repeat(gel_pt, 3, axis=1).astype(np.float64)
             Hb = Hb * mask[:, :, None] * mask[:, None, :]
