@@ -118,7 +118,14 @@ typedef struct { double E, nu, mu_f, eps_v, dhat, kappa; } t2r_material;
  *                 0 = no limit. Every loop of a solve is bounded (max_iters, 30
  *                 halvings, max_substeps), but those bounds multiply; this one caps
  *                 the product, so a launch ends after at most about max_evals passes
- *                 of its slowest env (T2R_ENV_BUDGET) */
+ *                 of its slowest env (T2R_ENV_BUDGET)
+ *   ee_mollifier  1: weight each gel-edge / indenter-edge barrier by IPC's
+ *                 parallel-edge mollifier m(c) (the contact model of Supp. A
+ *                 follows IPC), c = |a x b|^2 of the two edge vectors,
+ *                 m(c) = (c/e)(2 - c/e) below e = 1e-3 |a_rest|^2 |b_rest|^2 and
+ *                 1 above, so the edge-edge potential stays smooth as two edges
+ *                 turn parallel; the friction lag keeps the unweighted barrier
+ *                 force. 0: the plain barrier on every pair */
 typedef struct {
   double tol;
   double substep_tol;
@@ -133,6 +140,7 @@ typedef struct {
   double dt;
   double density;
   int32_t max_evals;
+  int32_t ee_mollifier;
 } t2r_solver_opts;
 
 /* Per-environment counters of the last launch (t2r_step or t2r_step_sequence;
@@ -167,7 +175,7 @@ typedef struct {
 
 /* Fills *o with the defaults: tol 1e-6, substep_tol 1e-4, max_iters 20000,
  * max_substeps 1000, precision 0, pair_capacity 0, armijo 1, block_size 0, warm_start 1,
- * dynamic 0, dt 1/60, density 1.1e-9, max_evals 200000. */
+ * dynamic 0, dt 1/60, density 1.1e-9, max_evals 200000, ee_mollifier 0. */
 void t2r_default_opts(t2r_solver_opts* o);
 
 /* Creates a context bound to `hip_stream` (a hipStream_t, or NULL for the null
@@ -215,7 +223,7 @@ t2r_status t2r_gel_markers(const t2r_ctx* ctx, int32_t gel_id, int32_t* marker_t
 
 /* Replaces a gel class's marker map with any linear one: marker m's
  * displacement is sum_k weight[m][k] (x - X) at vertex[m][k], k < 3 (host
- * arrays [n_m][3]; e.g. the k-nearest-neighbour map of Sec. 3.1 with k <= 3).
+ * arrays [n_m][3]; e.g. the k-nearest-neighbour map of Sec. 3.2 with k <= 3).
  * Before the first GPU call only (T2R_E_STATE after). Errors: T2R_E_ARG for a
  * bad gel id, n_m < 0, vertex ids out of range or non-finite weights. Host
  * only. */
@@ -273,7 +281,7 @@ t2r_status t2r_step(t2r_ctx* ctx, const double* d_pose, const int32_t* d_env_mas
                     double* d_markers, double* d_x, int32_t* d_status);
 
 /* Advances every environment through n_steps consecutive load steps in one
- * launch (a scripted indenter trajectory, Sec. 3.1: the simulator replays the
+ * launch (a scripted indenter trajectory, Sec. 4.2: the simulator replays the
  * recorded press and shear poses): load step k moves the indenter to
  * d_poses[k][env][7], exactly as n_steps calls of t2r_step would. Each env's
  * workgroup keeps its env for all steps, so the uneven cost of individual

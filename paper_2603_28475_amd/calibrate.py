@@ -2,7 +2,7 @@
 
 The paper fits (E, nu, rho, mu) by minimising the mean squared error between
 simulated and recorded marker displacement fields over K frames of N
-indenters (Sec. 3.2, eqs. loss_function and optimization_problem) with
+indenters (Sec. 4.2, eqs. loss_function and optimization_problem) with
 CMA-ES, popsize 12, the parameters normalised to [0, 1] over fixed ranges
 (Supp., Results for Parameters Calibration). Two drivers over the batched
 solver:

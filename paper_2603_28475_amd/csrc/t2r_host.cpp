@@ -325,6 +325,7 @@ void t2r_default_opts(t2r_solver_opts* o) {
   o->dt = 1.0 / 60.0;
   o->density = 1.1e-9;
   o->max_evals = 200000;
+  o->ee_mollifier = 0;
 }
 
 static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
@@ -334,6 +335,7 @@ static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
   if (o->precision != 0 && o->precision != 1) return fail(c, T2R_E_ARG, "precision must be 0 or 1");
   if (o->pair_capacity < 0) return fail(c, T2R_E_ARG, "pair_capacity must be >= 0");
   if (o->max_evals < 0) return fail(c, T2R_E_ARG, "max_evals must be >= 0 (0: no limit)");
+  if (o->ee_mollifier != 0 && o->ee_mollifier != 1) return fail(c, T2R_E_ARG, "ee_mollifier must be 0 or 1");
   if (o->block_size != 0 && o->block_size != 256 && o->block_size != 512)
     return fail(c, T2R_E_ARG, "block_size must be 0 (256), 256 or 512");
   if (o->warm_start != 0 && o->warm_start != 1) return fail(c, T2R_E_ARG, "warm_start must be 0 or 1");
@@ -954,6 +956,7 @@ static StepParams step_params(t2r_ctx* c) {
   P.motion_in2 = nullptr;
   P.motion_dt = 0.0;
   P.precision = c->opts.precision;
+  P.ee_moll = c->opts.ee_mollifier;
   P.armijo = c->opts.armijo;
   P.warm_start = c->opts.warm_start;
   P.gap0 = c->d_gap;

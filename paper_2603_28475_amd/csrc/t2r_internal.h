@@ -194,6 +194,7 @@ struct StepParams {
   double clock_khz;        // wall-clock counter rate (phase timers)
   double tol, substep_tol;
   int max_iters, max_substeps, precision, armijo;
+  int ee_moll;                   // weight edge-edge barriers by the parallel-edge mollifier
   long long max_evals;           // energy + curvature passes per env per launch (<= 0: no limit)
   int warm_start;                // extrapolate the previous load step's displacement
   T2R_G double* gap0;            // [n_env] d_min at the start of the env's previous load step (0: unknown)

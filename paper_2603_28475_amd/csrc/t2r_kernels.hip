@@ -304,6 +304,7 @@ struct View {
   int npairs, nfric, nouter;
   int nslots, nislots, slots_ok;
   int mixed;
+  int moll;              // edge-edge mollifier on
 };
 
 // ---------------------------------------------------------------------------
@@ -726,6 +727,58 @@ __device__ __forceinline__ double pair_distance(const PairPts& P, const Feature&
   return sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
 }
 
+// Edge-edge mollifier of pair P (edge vectors a = z1 - z0 of the gel edge and
+// b = z3 - z2 of the indenter edge): false unless the option is on, P is an
+// edge-edge pair and c = |a x b|^2 lies below e = kEdgeMollRel |a_rest|^2
+// |b_rest|^2 (rest gel positions, local indenter positions). With c as a
+// function of the four points: dc/dz1 = -dc/dz0 = ga = 2 (|b|^2 a - (a.b) b),
+// dc/dz3 = -dc/dz2 = gb = 2 (|a|^2 b - (a.b) a), d2c/da2 = 2 (|b|^2 I - b b^T)
+// and d2c/da db = 4 a b^T - 2 b a^T - 2 (a.b) I.
+struct EdgeMoll {
+  double m, m1, m2;       // m(c), m'(c), m''(c)
+  double a[3], b[3];
+  double aa, bb, ab;
+};
+
+template <bool LDS>
+__device__ __forceinline__ bool edge_moll(const View& V, int2 pr, uint64_t rec, const PairPts& P, EdgeMoll& M) {
+  if (!V.moll || P.kind != kEE) return false;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    M.a[c] = P.z[1][c] - P.z[0][c];
+    M.b[c] = P.z[3][c] - P.z[2][c];
+  }
+  const double w[3] = {M.a[1] * M.b[2] - M.a[2] * M.b[1], M.a[2] * M.b[0] - M.a[0] * M.b[2],
+                       M.a[0] * M.b[1] - M.a[1] * M.b[0]};
+  const double cx = dot3(w, w);
+  const GelDev& G = *V.G;
+  const IndDev& I = *V.I;
+  int id[4];
+  if constexpr (LDS) {
+    id[0] = V.slot_v[rec_slot(rec, 0)];
+    id[1] = V.slot_v[rec_slot(rec, 1)];
+    id[2] = V.islot_v[rec_slot(rec, 2)];
+    id[3] = V.islot_v[rec_slot(rec, 3)];
+  } else {
+    pair_point_ids(G, I, pr, id);
+  }
+  double ar = 0.0, br = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double u = G.X[c * G.n_v + id[1]] - G.X[c * G.n_v + id[0]];
+    const double v = I.Y[c * I.n_v + id[3]] - I.Y[c * I.n_v + id[2]];
+    ar += u * u;
+    br += v * v;
+  }
+  const double e = kEdgeMollRel * ar * br;
+  if (!(cx < e)) return false;
+  edge_mollifier3(cx, e, M.m, M.m1, M.m2);
+  M.aa = dot3(M.a, M.a);
+  M.bb = dot3(M.b, M.b);
+  M.ab = dot3(M.a, M.b);
+  return true;
+}
+
 // Stages the slot points of the env for a pair pass. what: 0 positions x;
 // 1 positions x and p (in gq); 2 positions x + alpha p, |p|^2 (in pn), cleared
 // gradient/diagonal sums (p not null for 1 and 2). The indenter points are
@@ -834,7 +887,14 @@ __device__ __forceinline__ double pairs_eval(const View& V, const Shared& S, Til
     ++nactive;
     double b, b1, b2;
     barrier3(d, dh, b, b1, b2);
-    energy += kap * b;
+    EdgeMoll M;
+    const bool mol = edge_moll<LDS>(V, pr, rec, P, M);
+    double ga[3] = {0.0, 0.0, 0.0};
+    if (mol) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ga[c] = 2.0 * (M.bb * M.a[c] - M.ab * M.b[c]);
+    }
+    energy += kap * (mol ? M.m * b : b);
     const double invd = 1.0 / d;
     double n[3] = {r[0] * invd, r[1] * invd, r[2] * invd};
     double D[2][3] = {{0, 0, 0}, {0, 0, 0}};
@@ -861,7 +921,14 @@ __device__ __forceinline__ double pairs_eval(const View& V, const Shared& S, Til
         const double hdd = (ci * ci - uMu) * invd - gi * gi * invd;
         // preconditioner diagonal: the pair's contribution clamped at zero (b' < 0
         // makes it negative in directions tangent to a close contact)
-        const double gval = kap * b1 * gi, dval = kap * fmax(0.0, b2 * gi * gi + b1 * hdd);
+        double gval = kap * b1 * gi, hval = b2 * gi * gi + b1 * hdd;
+        if (mol) {  // gel points of an edge-edge pair: k = 0, 1
+          const double gc = k == 0 ? -ga[c] : ga[c];
+          const double hc = 2.0 * (M.bb - M.b[c] * M.b[c]);
+          gval = kap * (M.m * b1 * gi + M.m1 * b * gc);
+          hval = M.m * hval + 2.0 * M.m1 * b1 * gi * gc + M.m2 * b * gc * gc + M.m1 * b * hc;
+        }
+        const double dval = kap * fmax(0.0, hval);
         if constexpr (LDS) {
           atomicAdd(&T.gq[c][v], gval);
           atomicAdd(&T.gd[c][v], dval);
@@ -909,7 +976,7 @@ __device__ __forceinline__ double pairs_curv(const View& V, const Shared& S, con
         D[w][c] = cw_of(f, 0, w) * P.z[0][c] + cw_of(f, 1, w) * P.z[1][c] + cw_of(f, 2, w) * P.z[2][c] + cw_of(f, 3, w) * P.z[3][c];
     double Mi[2][2];
     gram_inverse(D, f.k, Mi);
-    double q[3] = {0, 0, 0}, vv[2] = {0, 0};
+    double q[3] = {0, 0, 0}, vv[2] = {0, 0}, da[3] = {0, 0, 0};
     #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = P.gid[k];
@@ -919,6 +986,10 @@ __device__ __forceinline__ double pairs_curv(const View& V, const Shared& S, con
       for (int c = 0; c < 3; ++c) pk[c] = LDS ? T.gq[c][v] : p[c * nv + v];  // p = 0 on fixed vertices
       #pragma unroll
       for (int c = 0; c < 3; ++c) q[c] += f.c[k] * pk[c];
+      if (k < 2) {  // p_1 - p_0 of an edge-edge pair's gel edge
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) da[c] += k == 0 ? -pk[c] : pk[c];
+      }
       const double rp = dot3(r, pk);
       #pragma unroll
       for (int w = 0; w < 2; ++w) if (w < f.k) vv[w] += cw_of(f, k, w) * rp + f.c[k] * dot3(D[w], pk);
@@ -926,7 +997,15 @@ __device__ __forceinline__ double pairs_curv(const View& V, const Shared& S, con
     const double nq = dot3(n, q);
     const double vMv = vv[0] * (Mi[0][0] * vv[0] + Mi[0][1] * vv[1]) + vv[1] * (Mi[1][0] * vv[0] + Mi[1][1] * vv[1]);
     const double pHp = (dot3(q, q) - vMv) * invd - nq * nq * invd;
-    curv += kap * (b2 * nq * nq + b1 * pHp);
+    double cv = b2 * nq * nq + b1 * pHp;
+    EdgeMoll M;
+    if (edge_moll<LDS>(V, pr, rec, P, M)) {
+      const double bd = dot3(M.b, da);
+      const double cp = 2.0 * (M.bb * dot3(M.a, da) - M.ab * bd);   // grad c . p
+      const double pHc = 2.0 * (M.bb * dot3(da, da) - bd * bd);      // p^T (d2c) p
+      cv = M.m * cv + 2.0 * M.m1 * b1 * nq * cp + M.m2 * b * cp * cp + M.m1 * b * pHc;
+    }
+    curv += kap * cv;
   }
   return curv;
 }
@@ -1960,6 +2039,7 @@ __device__ __forceinline__ void make_view(const StepParams& P, int e, View& V) {
   V.nislots = 0;
   V.slots_ok = 0;
   V.mixed = P.precision;
+  V.moll = P.ee_moll;
 }
 
 __device__ __forceinline__ void init_solver(Solver& s, const StepParams& P, Shared& S, Tile& T) {
@@ -2493,7 +2573,7 @@ __device__ __forceinline__ void pairs_hvp(const View& V, const Shared& S, Tile& 
         D[w][c] = cw_of(f, 0, w) * P.z[0][c] + cw_of(f, 1, w) * P.z[1][c] + cw_of(f, 2, w) * P.z[2][c] + cw_of(f, 3, w) * P.z[3][c];
     double Mi[2][2];
     gram_inverse(D, f.k, Mi);
-    double q[3] = {0, 0, 0}, vv[2] = {0, 0};
+    double q[3] = {0, 0, 0}, vv[2] = {0, 0}, da[3] = {0, 0, 0};
     #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int g = P.gid[k];
@@ -2503,12 +2583,28 @@ __device__ __forceinline__ void pairs_hvp(const View& V, const Shared& S, Tile& 
       for (int c = 0; c < 3; ++c) pk[c] = LDS ? T.gq[c][g] : v[c * nv + g];
       #pragma unroll
       for (int c = 0; c < 3; ++c) q[c] += f.c[k] * pk[c];
+      if (k < 2) {  // v_1 - v_0 of an edge-edge pair's gel edge
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) da[c] += k == 0 ? -pk[c] : pk[c];
+      }
       const double rp = dot3(r, pk);
       #pragma unroll
       for (int w = 0; w < 2; ++w) if (w < f.k) vv[w] += cw_of(f, k, w) * rp + f.c[k] * dot3(D[w], pk);
     }
     const double wv[2] = {Mi[0][0] * vv[0] + Mi[0][1] * vv[1], Mi[1][0] * vv[0] + Mi[1][1] * vv[1]};
     const double nq = dot3(n, q);
+    EdgeMoll M;
+    const bool mol = edge_moll<LDS>(V, pr, rec, P, M);
+    double ga[3] = {0, 0, 0}, hcv[3] = {0, 0, 0}, cp = 0.0;
+    if (mol) {
+      const double bd = dot3(M.b, da);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        ga[c] = 2.0 * (M.bb * M.a[c] - M.ab * M.b[c]);
+        hcv[c] = 2.0 * (M.bb * da[c] - M.b[c] * bd);   // (d2c/da2) (v_1 - v_0)
+      }
+      cp = dot3(ga, da);
+    }
     #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int g = P.gid[k];
@@ -2521,7 +2617,13 @@ __device__ __forceinline__ void pairs_hvp(const View& V, const Shared& S, Tile& 
         #pragma unroll
         for (int w = 0; w < 2; ++w)
           if (w < f.k) hv -= (cw_of(f, k, w) * r[c] + ci * D[w][c]) * wv[w];
-        const double o = kap * (b2 * nq * ci * n[c] + b1 * hv * invd);
+        double hb = b2 * nq * ci * n[c] + b1 * hv * invd;
+        if (mol) {  // gel points of an edge-edge pair: k = 0, 1
+          const double sg = k == 0 ? -1.0 : 1.0;
+          hb = M.m * hb + M.m1 * b1 * (cp * ci * n[c] + nq * sg * ga[c]) + M.m2 * b * cp * sg * ga[c]
+               + M.m1 * b * sg * hcv[c];
+        }
+        const double o = kap * hb;
         if constexpr (LDS) atomicAdd(&T.gd[c][g], o);
         else atomicAdd(&out[c * nv + g], o);
       }
@@ -2564,7 +2666,7 @@ __device__ __forceinline__ void pairs_pose(const View& V, const Shared& S, const
     double Mi[2][2];
     gram_inverse(D, f.k, Mi);
     // gel side (lambda)
-    double q1[3] = {0, 0, 0}, v1[2] = {0, 0};
+    double q1[3] = {0, 0, 0}, v1[2] = {0, 0}, da[3] = {0, 0, 0};
     #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int g = P.gid[k];
@@ -2574,15 +2676,27 @@ __device__ __forceinline__ void pairs_pose(const View& V, const Shared& S, const
       for (int c = 0; c < 3; ++c) pk[c] = LDS ? T.gq[c][g] : lv[c * nv + g];
       #pragma unroll
       for (int c = 0; c < 3; ++c) q1[c] += f.c[k] * pk[c];
+      if (k < 2) {  // lambda_1 - lambda_0 of an edge-edge pair's gel edge
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) da[c] += k == 0 ? -pk[c] : pk[c];
+      }
       const double rp = dot3(r, pk);
       #pragma unroll
       for (int w = 0; w < 2; ++w) if (w < f.k) v1[w] += cw_of(f, k, w) * rp + f.c[k] * dot3(D[w], pk);
     }
     const double n1 = dot3(n, q1);
     const double m1[2] = {Mi[0][0] * v1[0] + Mi[0][1] * v1[1], Mi[1][0] * v1[0] + Mi[1][1] * v1[1]};
+    EdgeMoll M;
+    const bool mol = edge_moll<LDS>(V, pr, rec, P, M);
+    double c1 = 0.0, aD = 0.0, bD = 0.0;
+    if (mol) {
+      aD = dot3(M.a, da);
+      bD = dot3(M.b, da);
+      c1 = 2.0 * (M.bb * aD - M.ab * bD);   // grad c . lambda
+    }
     #pragma unroll
     for (int a = 0; a < 6; ++a) {
-      double q2[3] = {0, 0, 0}, v2[2] = {0, 0};
+      double q2[3] = {0, 0, 0}, v2[2] = {0, 0}, db[3] = {0, 0, 0};
       #pragma unroll
       for (int k = 0; k < 4; ++k) {
         if (P.gid[k] >= 0) continue;
@@ -2600,13 +2714,24 @@ __device__ __forceinline__ void pairs_pose(const View& V, const Shared& S, const
         }
         #pragma unroll
         for (int c = 0; c < 3; ++c) q2[c] += f.c[k] * dy[c];
+        if (k >= 2) {  // dy_3 - dy_2 of an edge-edge pair's indenter edge
+          #pragma unroll
+          for (int c = 0; c < 3; ++c) db[c] += k == 2 ? -dy[c] : dy[c];
+        }
         const double rp = dot3(r, dy);
         #pragma unroll
         for (int w = 0; w < 2; ++w) if (w < f.k) v2[w] += cw_of(f, k, w) * rp + f.c[k] * dot3(D[w], dy);
       }
       const double n2 = dot3(n, q2);
       const double hd = (dot3(q1, q2) - (m1[0] * v2[0] + m1[1] * v2[1])) * invd - n1 * n2 * invd;
-      acc[a] += kap * (b2 * n1 * n2 + b1 * hd);
+      double hb = b2 * n1 * n2 + b1 * hd;
+      if (mol) {
+        const double ab2 = dot3(M.a, db), bb2 = dot3(M.b, db);
+        const double c2 = 2.0 * (M.aa * bb2 - M.ab * ab2);                             // grad c . dy
+        const double cx = 4.0 * aD * bb2 - 2.0 * bD * ab2 - 2.0 * M.ab * dot3(da, db);  // lambda^T (d2c/da db) dy
+        hb = M.m * hb + M.m1 * b1 * (c1 * n2 + n1 * c2) + M.m2 * b * c1 * c2 + M.m1 * b * cx;
+      }
+      acc[a] += kap * hb;
     }
   }
 }

@@ -189,6 +189,18 @@ __device__ __forceinline__ void barrier3(double d, double dh, double& b, double&
   b2 = -2.0 * l - 4.0 * e / d + (e * e) / (d * d);
 }
 
+// Edge-edge mollifier (option; IPC, whose contact model Supp. A follows): the
+// barrier of a gel-edge / indenter-edge pair is weighted by m(c), c = |a x b|^2
+// of the two edge vectors, m(c) = (c/e)(2 - c/e) below e and 1 above, with
+// e = kEdgeMollRel |a_rest|^2 |b_rest|^2; m, m' and m'' at c < e.
+constexpr double kEdgeMollRel = 1e-3;
+__device__ __forceinline__ void edge_mollifier3(double c, double e, double& m, double& m1, double& m2) {
+  const double ie = 1.0 / e, s = c * ie;
+  m = s * (2.0 - s);
+  m1 = 2.0 * ie * (1.0 - s);
+  m2 = -2.0 * ie * ie;
+}
+
 // Friction mollifier (Supp. A, eq. friction_mollifier) pieces at s >= 0:
 //   f(s), f'(s)/s, and (f''(s) - f'(s)/s)/s^2 * s^2 / s  written as `corr` so that
 //   Hess_Delta = mulam [ fos T + corr uhat uhat^T ] with uhat = T Delta / s.

@@ -4,7 +4,7 @@ Each indenter is a closed, outward-oriented triangle mesh. Its local origin is
 the rotation centre used by the pose: world point = R(q) y_local + t.
 The shapes follow the workloads the paper uses (a sphere-like indenter, an
 end-on cylindrical peg and a hexagonal nut; Sec. 5.2 and the RL tasks of
-Sec. 5.4).
+Sec. 5.3).
 """
 
 from __future__ import annotations

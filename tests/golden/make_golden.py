@@ -75,6 +75,34 @@ def peg_press_friction_unstructured():
     print(f"peg_press_484v_unstructured_friction: {time.time() - t:.1f}s, active {r.n_active}")
 
 
+def peg_press_mollified():
+    """The tilted peg scene with lagged friction and shear, edge-edge barriers
+    weighted by the parallel-edge mollifier; per step, the number of edge-edge
+    pairs below the mollifier's threshold is stored too."""
+    from oracle.barrier import EDGE_MOLLIFIER_REL, edge_cross_derivatives
+    from oracle.problem import EE
+    from oracle.sim import build
+    w = peg_press_484v(mu_f=0.5, shear=(0.1, 0.05), n_shear=2)
+    env = w.envs[0]
+    t = time.time()
+    r = simulate(w.meshes["c1"], w.indenters["peg4"], env, mode="newton", ee_mollifier=True)
+    gel, ind, prob = build(w.meshes["c1"], w.indenters["peg4"], env, ee_mollifier=True)
+    n_moll = []
+    for s, x in enumerate(r.x):
+        prob.set_pose(env.poses[s + 1])
+        pairs, res = prob.active(x)
+        ee = np.nonzero(pairs["kind"] == EE)[0]
+        idx = pairs["idx"][ee]
+        ar = gel.X[idx[:, 1]] - gel.X[idx[:, 0]]
+        br = ind.Y[idx[:, 3] - prob.nv] - ind.Y[idx[:, 2] - prob.nv]
+        eps = EDGE_MOLLIFIER_REL * np.sum(ar * ar, 1) * np.sum(br * br, 1)
+        n_moll.append(int(np.sum(edge_cross_derivatives(res["Z"][ee])[0] < eps)))
+    np.savez_compressed(os.path.join(HERE, "peg_press_484v_mollifier_friction_newton.npz"),
+                        x=np.array(r.x), markers=np.array(r.markers), poses=env.poses,
+                        n_active=np.array(r.n_active), d_min=np.array(r.d_min), n_mollified=np.array(n_moll))
+    print(f"peg_press_484v_mollifier_friction: {time.time() - t:.1f}s, active {r.n_active}, mollified {n_moll}")
+
+
 def calibration_targets():
     """Synthetic recordings for the calibration driver: the oracle's Newton
     marker fields of the calibration scene (two indenters, the recording
@@ -97,6 +125,6 @@ def calibration_targets():
 
 if __name__ == "__main__":
     which = sys.argv[1:] or ["micro_friction", "sphere_press", "peg_press_friction",
-                             "peg_press_friction_unstructured", "calibration_targets"]
+                             "peg_press_friction_unstructured", "calibration_targets", "peg_press_mollified"]
     for name in which:
         globals()[name]()
