@@ -62,6 +62,8 @@ def parse():
                     help="sequence: the K timed load steps of every env in one launch; per-step: one launch per load step")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle budget (0: skip)")
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--outer-radius", type=float, default=0.0,
+                    help="coarse candidate list margin in multiples of dhat (0: the library default)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--adjoint", action="store_true",
                     help="time the adjoint instead: 64 envs of the 5k gel with friction, 20 load steps "
@@ -315,7 +317,7 @@ def main():
 
     prec = 0 if args.precision == "f64" else 1
     opts = t2r.default_opts(tol=args.tol, precision=prec, block_size=args.block, dynamic=int(args.dynamic),
-                            dt=args.dt, density=args.density)
+                            dt=args.dt, density=args.density, outer_radius=args.outer_radius)
     t_build = time.perf_counter()
     sim = Sim.from_workload(workload, opts)
     poses = torch.as_tensor(np.stack([e.poses for e in workload.envs]), dtype=torch.float64,
@@ -442,6 +444,7 @@ def main():
                    "vector", "launch", "friction_lag")
     phase_us = {n: 1e3 * sum(x["phase_ms"][k] for x in st_last) / it_tot for k, n in enumerate(phase_names)}
     evals_per_iter = sum(x["evals"] for x in st_last) / it_tot
+    lists_per_step = {k: sum(x[k] for x in st_last) / (args.envs * K) for k in ("outer_builds", "reculls")}
     cpu = cpu_baseline(cpu_meas, iters_mean, workload.name) if cpu_meas else None
     line = {
         "metric": "env-steps/s at fixed PNCG tol (batched)",
@@ -467,6 +470,8 @@ def main():
                    "pncg_iters_per_env_step": iters_mean, "launch": args.launch,
                    "phase_us_per_env_iter": {k: round(v, 2) for k, v in phase_us.items()},
                    "eval_passes_per_iter": round(evals_per_iter, 3),
+                   "outer_radius_dhat": args.outer_radius if args.outer_radius > 0 else 6.0,
+                   "list_builds_per_env_step": {k: round(v, 3) for k, v in lists_per_step.items()},
                    "block_size": sim.ctx.get_opts().block_size or 256,
                    "autotune_trial_ms": tuned["trial_ms"] if tuned else None},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",

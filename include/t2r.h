@@ -125,7 +125,14 @@ typedef struct { double E, nu, mu_f, eps_v, dhat, kappa; } t2r_material;
  *                 m(c) = (c/e)(2 - c/e) below e = 1e-3 |a_rest|^2 |b_rest|^2 and
  *                 1 above, so the edge-edge potential stays smooth as two edges
  *                 turn parallel; the friction lag keeps the unweighted barrier
- *                 force. 0: the plain barrier on every pair */
+ *                 force. 0: the plain barrier on every pair
+ *   outer_radius  margin of the coarse candidate list beyond dhat, in multiples
+ *                 of dhat (0: 6; else >= 2, at most 64). The inner list keeps a
+ *                 margin of one dhat; the coarse list is rebuilt from the
+ *                 indenter grids once the surface and the indenter have moved by
+ *                 the difference of the margins since its last build. A wider
+ *                 margin rebuilds less often and filters more pairs each time;
+ *                 results do not depend on it */
 typedef struct {
   double tol;
   double substep_tol;
@@ -141,6 +148,7 @@ typedef struct {
   double density;
   int32_t max_evals;
   int32_t ee_mollifier;
+  double outer_radius;
 } t2r_solver_opts;
 
 /* Per-environment counters of the last launch (t2r_step or t2r_step_sequence;
@@ -175,7 +183,7 @@ typedef struct {
 
 /* Fills *o with the defaults: tol 1e-6, substep_tol 1e-4, max_iters 20000,
  * max_substeps 1000, precision 0, pair_capacity 0, armijo 1, block_size 0, warm_start 1,
- * dynamic 0, dt 1/60, density 1.1e-9, max_evals 200000, ee_mollifier 0. */
+ * dynamic 0, dt 1/60, density 1.1e-9, max_evals 200000, ee_mollifier 0, outer_radius 0. */
 void t2r_default_opts(t2r_solver_opts* o);
 
 /* Creates a context bound to `hip_stream` (a hipStream_t, or NULL for the null

@@ -326,6 +326,7 @@ void t2r_default_opts(t2r_solver_opts* o) {
   o->density = 1.1e-9;
   o->max_evals = 200000;
   o->ee_mollifier = 0;
+  o->outer_radius = 0.0;
 }
 
 static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
@@ -336,6 +337,8 @@ static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
   if (o->pair_capacity < 0) return fail(c, T2R_E_ARG, "pair_capacity must be >= 0");
   if (o->max_evals < 0) return fail(c, T2R_E_ARG, "max_evals must be >= 0 (0: no limit)");
   if (o->ee_mollifier != 0 && o->ee_mollifier != 1) return fail(c, T2R_E_ARG, "ee_mollifier must be 0 or 1");
+  if (!(o->outer_radius == 0.0 || (o->outer_radius >= 2.0 && o->outer_radius <= 64.0)))
+    return fail(c, T2R_E_ARG, "outer_radius must be 0 or in [2, 64] (got %g)", o->outer_radius);
   if (o->block_size != 0 && o->block_size != 256 && o->block_size != 512)
     return fail(c, T2R_E_ARG, "block_size must be 0 (256), 256 or 512");
   if (o->warm_start != 0 && o->warm_start != 1) return fail(c, T2R_E_ARG, "warm_start must be 0 or 1");
@@ -671,6 +674,27 @@ t2r_status t2r_add_gel(t2r_ctx* c, int32_t n_v, const double* X, int32_t n_t, co
     }
     close_tile(n_t);
     const int ntiles = (int)g.tile_tet.size() - 1;
+    // number each tile's vertices in ascending global order, so that the
+    // slot-parallel loads and stores of a tile's positions and sums touch as few
+    // cache lines per wavefront as the mesh numbering allows
+    for (int t = 0; t < ntiles; ++t) {
+      const int e0 = g.tile_tet[t], e1 = g.tile_tet[t + 1];
+      const int v0 = g.tile_vstart[t], nvt = g.tile_vstart[t + 1] - v0;
+      std::vector<int> rank(nvt), nid(nvt);
+      for (int l = 0; l < nvt; ++l) rank[l] = l;
+      std::sort(rank.begin(), rank.end(),
+                [&](int a, int b) { return g.tile_verts[v0 + a] < g.tile_verts[v0 + b]; });
+      for (int r = 0; r < nvt; ++r) nid[rank[r]] = r;
+      for (int i = e0; i < e1; ++i) {
+        uint64_t loc = 0;
+        for (int k = 0; k < 4; ++k)
+          loc |= (uint64_t)nid[(int)((g.tet_local[i] >> (16 * k)) & 0xffff)] << (16 * k);
+        g.tet_local[i] = loc;
+      }
+      std::vector<int> tv(nvt);
+      for (int l = 0; l < nvt; ++l) tv[nid[l]] = g.tile_verts[v0 + l];
+      std::copy(tv.begin(), tv.end(), g.tile_verts.begin() + v0);
+    }
     std::vector<int> first(n_v, -1), last(n_v, -1);
     for (int t = 0; t < ntiles; ++t)
       for (int j = g.tile_vstart[t]; j < g.tile_vstart[t + 1]; ++j) {
@@ -957,6 +981,7 @@ static StepParams step_params(t2r_ctx* c) {
   P.motion_dt = 0.0;
   P.precision = c->opts.precision;
   P.ee_moll = c->opts.ee_mollifier;
+  P.outer_mult = c->opts.outer_radius > 0.0 ? c->opts.outer_radius : 6.0;
   P.armijo = c->opts.armijo;
   P.warm_start = c->opts.warm_start;
   P.gap0 = c->d_gap;

@@ -2050,7 +2050,7 @@ __device__ __forceinline__ void init_solver(Solver& s, const StepParams& P, Shar
   s.floor_d = kDiagFloor * E.mu * G.diag_rest_max;
   s.guard = kEnergyGuard * E.mu * G.vol_total;
   s.buffer = E.dhat;
-  s.buffer_out = 6.0 * E.dhat;
+  s.buffer_out = P.outer_mult * E.dhat;
   if (threadIdx.x == 0) {
     S.vel = P.vel ? P.vel + E.voff : nullptr;
     // density / dt^2 of the dynamic form (0: quasi-static); an env's own density

@@ -113,13 +113,30 @@ def test_invalid_inputs_are_rejected_on_the_host():
 def test_invalid_options_are_rejected():
     t2r = _t2r()
     for kw in ({"tol": 0.0}, {"precision": 3}, {"block_size": 100}, {"block_size": 1024}, {"max_substeps": 0},
-               {"dynamic": 2}, {"dynamic": 1, "dt": 0.0}, {"dynamic": 1, "density": -1.0}):
+               {"dynamic": 2}, {"dynamic": 1, "dt": 0.0}, {"dynamic": 1, "density": -1.0}, {"ee_mollifier": 2},
+               {"outer_radius": 1.5}, {"outer_radius": 65.0}, {"outer_radius": float("nan")}):
         with pytest.raises(t2r.T2RError):
             t2r.Context(t2r.default_opts(**kw))
     o = t2r.default_opts()
     assert o.tol == 1e-6 and o.armijo == 1 and o.max_iters > 0
     assert o.dynamic == 0 and o.dt > 0.0 and o.density == 1.1e-9
+    assert o.max_evals == 200000 and o.ee_mollifier == 0 and o.outer_radius == 0.0
     t2r.Context(t2r.default_opts(dynamic=1, dt=1e-3, density=1e-9))   # a valid dynamic set
+    t2r.Context(t2r.default_opts(ee_mollifier=1, outer_radius=10.0))
+
+
+def test_options_struct_layout_matches_the_library():
+    """t2r_default_opts writes every field of the C struct: into a buffer larger
+    than the binding's struct, it leaves the bytes past the binding's size alone
+    and sets the last field the binding knows."""
+    import ctypes
+    t2r = _t2r()
+    n = ctypes.sizeof(t2r.SolverOpts)
+    buf = (ctypes.c_ubyte * (n + 64))(*([0xA5] * (n + 64)))
+    t2r.lib.t2r_default_opts(ctypes.cast(buf, ctypes.POINTER(t2r.SolverOpts)))
+    assert bytes(buf[n:]) == bytes([0xA5] * 64)
+    o = t2r.SolverOpts.from_buffer(buf)
+    assert o.outer_radius == 0.0 and o.max_evals == 200000
 
 
 def test_workload_classes_build_on_the_host():
