@@ -132,7 +132,18 @@ typedef struct { double E, nu, mu_f, eps_v, dhat, kappa; } t2r_material;
  *                 indenter grids once the surface and the indenter have moved by
  *                 the difference of the margins since its last build. A wider
  *                 margin rebuilds less often and filters more pairs each time;
- *                 results do not depend on it */
+ *                 results do not depend on it
+ *   deterministic 1: every sum of per-element and per-pair terms into per-vertex
+ *                 totals, and every candidate and friction list, is built in a
+ *                 fixed order (those passes run on one thread of the env's
+ *                 workgroup, in index order; the lists are rebuilt at the start
+ *                 of every load step), so a step's results depend only on its
+ *                 inputs and its starting state (t2r_save_checkpoint) and repeat
+ *                 bit for bit, also after t2r_load_checkpoint and in any batch,
+ *                 at equal block_size. Much slower: for tests and debugging.
+ *                 The adjoint entry points keep their atomic sums. 0: sums in
+ *                 LDS / global atomics, whose order varies from run to run in
+ *                 the last bits */
 typedef struct {
   double tol;
   double substep_tol;
@@ -149,6 +160,7 @@ typedef struct {
   int32_t max_evals;
   int32_t ee_mollifier;
   double outer_radius;
+  int32_t deterministic;
 } t2r_solver_opts;
 
 /* Per-environment counters of the last launch (t2r_step or t2r_step_sequence;
@@ -183,7 +195,8 @@ typedef struct {
 
 /* Fills *o with the defaults: tol 1e-6, substep_tol 1e-4, max_iters 20000,
  * max_substeps 1000, precision 0, pair_capacity 0, armijo 1, block_size 0, warm_start 1,
- * dynamic 0, dt 1/60, density 1.1e-9, max_evals 200000, ee_mollifier 0, outer_radius 0. */
+ * dynamic 0, dt 1/60, density 1.1e-9, max_evals 200000, ee_mollifier 0, outer_radius 0,
+ * deterministic 0. */
 void t2r_default_opts(t2r_solver_opts* o);
 
 /* Creates a context bound to `hip_stream` (a hipStream_t, or NULL for the null
@@ -377,6 +390,21 @@ t2r_status t2r_get_stats(t2r_ctx* ctx, void* host_out, size_t bytes);
 t2r_status t2r_state_size(const t2r_ctx* ctx, int64_t* n_doubles);
 t2r_status t2r_get_state(t2r_ctx* ctx, double* d_state);
 t2r_status t2r_set_state(t2r_ctx* ctx, const double* d_state);
+
+/* Checkpoint of everything a later load step reads besides its inputs: per
+ * env its positions x_s and x_{s-1}, velocities (dynamic form), poses q_s and
+ * q_{s-1}, and the smallest distance at the start of its last load step (the
+ * warm start's motion estimate). The buffer (device, t2r_checkpoint_size
+ * doubles, caller-owned) is opaque: the library's own array order, valid for
+ * contexts built with the same meshes and envs. t2r_load_checkpoint restores
+ * it, clears the neighbour lists (rebuilt at the next step) and restarts a
+ * recording as t2r_set_state does. In deterministic mode the steps after a
+ * load repeat those after the save bit for bit; in atomic mode they agree to
+ * the last bits of the atomic sums. Both are asynchronous on the context's
+ * stream. Errors: T2R_E_ARG for NULL. */
+t2r_status t2r_checkpoint_size(const t2r_ctx* ctx, int64_t* n_doubles);
+t2r_status t2r_save_checkpoint(t2r_ctx* ctx, double* d_buf);
+t2r_status t2r_load_checkpoint(t2r_ctx* ctx, const double* d_buf);
 
 /* Puts the listed envs (host ids) back at rest with their initial pose. */
 t2r_status t2r_reset_envs(t2r_ctx* ctx, const int32_t* env_ids, int32_t n);

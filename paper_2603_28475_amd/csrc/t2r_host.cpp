@@ -327,6 +327,7 @@ void t2r_default_opts(t2r_solver_opts* o) {
   o->max_evals = 200000;
   o->ee_mollifier = 0;
   o->outer_radius = 0.0;
+  o->deterministic = 0;
 }
 
 static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
@@ -337,6 +338,7 @@ static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
   if (o->pair_capacity < 0) return fail(c, T2R_E_ARG, "pair_capacity must be >= 0");
   if (o->max_evals < 0) return fail(c, T2R_E_ARG, "max_evals must be >= 0 (0: no limit)");
   if (o->ee_mollifier != 0 && o->ee_mollifier != 1) return fail(c, T2R_E_ARG, "ee_mollifier must be 0 or 1");
+  if (o->deterministic != 0 && o->deterministic != 1) return fail(c, T2R_E_ARG, "deterministic must be 0 or 1");
   if (!(o->outer_radius == 0.0 || (o->outer_radius >= 2.0 && o->outer_radius <= 64.0)))
     return fail(c, T2R_E_ARG, "outer_radius must be 0 or in [2, 64] (got %g)", o->outer_radius);
   if (o->block_size != 0 && o->block_size != 256 && o->block_size != 512)
@@ -982,6 +984,7 @@ static StepParams step_params(t2r_ctx* c) {
   P.precision = c->opts.precision;
   P.ee_moll = c->opts.ee_mollifier;
   P.outer_mult = c->opts.outer_radius > 0.0 ? c->opts.outer_radius : 6.0;
+  P.det = c->opts.deterministic;
   P.armijo = c->opts.armijo;
   P.warm_start = c->opts.warm_start;
   P.gap0 = c->d_gap;
@@ -1310,6 +1313,61 @@ t2r_status t2r_set_state(t2r_ctx* c, const double* d_state) {
   HIP_TRY(c, hipMemsetAsync(c->d_lists, 0, c->envs.size() * sizeof(ListState), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_gap, 0, c->envs.size() * sizeof(double), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_vel, 0, (size_t)c->total_dofs * sizeof(double), c->stream));
+  s = tape_seed(c);
+  if (s != T2R_OK) return s;
+  c->err.clear();
+  return T2R_OK;
+}
+
+// Checkpoint: positions x_s, x_{s-1}, velocities, poses q_s and q_{s-1} and the
+// warm start's starting distance, each as the whole array in device order.
+t2r_status t2r_checkpoint_size(const t2r_ctx* c, int64_t* n) {
+  if (!c || !n) return T2R_E_ARG;
+  int64_t dofs = 0;
+  for (auto& e : c->envs) dofs += 3 * (int64_t)c->gels[e.gel].n_v;
+  *n = 3 * dofs + 15 * (int64_t)c->envs.size();
+  return T2R_OK;
+}
+
+// The checkpoint's arrays in order: {device array, doubles}.
+static void checkpoint_parts(t2r_ctx* c, double* parts[6], size_t n[6]) {
+  const size_t dofs = (size_t)c->total_dofs, ne = c->envs.size();
+  parts[0] = c->d_x; n[0] = dofs;
+  parts[1] = c->d_xprev; n[1] = dofs;
+  parts[2] = c->d_vel; n[2] = dofs;
+  parts[3] = c->d_pose_prev; n[3] = 7 * ne;
+  parts[4] = c->d_pose_lag; n[4] = 7 * ne;
+  parts[5] = c->d_gap; n[5] = ne;
+}
+
+t2r_status t2r_save_checkpoint(t2r_ctx* c, double* d_buf) {
+  if (!c || !d_buf) return T2R_E_ARG;
+  t2r_status s = commit(c);
+  if (s != T2R_OK) return s;
+  double* parts[6];
+  size_t n[6], off = 0;
+  checkpoint_parts(c, parts, n);
+  for (int k = 0; k < 6; ++k) {
+    HIP_TRY(c, hipMemcpyAsync(d_buf + off, parts[k], n[k] * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    off += n[k];
+  }
+  c->err.clear();
+  return T2R_OK;
+}
+
+t2r_status t2r_load_checkpoint(t2r_ctx* c, const double* d_buf) {
+  if (!c || !d_buf) return T2R_E_ARG;
+  t2r_status s = commit(c);
+  if (s != T2R_OK) return s;
+  double* parts[6];
+  size_t n[6], off = 0;
+  checkpoint_parts(c, parts, n);
+  for (int k = 0; k < 6; ++k) {
+    HIP_TRY(c, hipMemcpyAsync(parts[k], d_buf + off, n[k] * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    off += n[k];
+  }
+  // neighbour lists are not part of a checkpoint: rebuilt at the next step
+  HIP_TRY(c, hipMemsetAsync(c->d_lists, 0, c->envs.size() * sizeof(ListState), c->stream));
   s = tape_seed(c);
   if (s != T2R_OK) return s;
   c->err.clear();

@@ -196,6 +196,7 @@ struct StepParams {
   int max_iters, max_substeps, precision, armijo;
   int ee_moll;                   // weight edge-edge barriers by the parallel-edge mollifier
   double outer_mult;             // coarse list margin beyond dhat, in multiples of dhat
+  int det;                       // deterministic summation and list order
   long long max_evals;           // energy + curvature passes per env per launch (<= 0: no limit)
   int warm_start;                // extrapolate the previous load step's displacement
   T2R_G double* gap0;            // [n_env] d_min at the start of the env's previous load step (0: unknown)

@@ -305,7 +305,17 @@ struct View {
   int nslots, nislots, slots_ok;
   int mixed;
   int moll;              // edge-edge mollifier on
+  int det;               // deterministic order: summing passes and list builds on one thread
 };
+
+// Item loops of the passes that sum into shared per-vertex slots or append to
+// lists: block-strided, or in deterministic mode all on thread 0 in index
+// order (every sum and every list then has a fixed order, so results repeat
+// bit for bit).
+__device__ __forceinline__ unsigned item_first(const View& V) {
+  return V.det ? (threadIdx.x == 0 ? 0u : 0x7fffffffu) : threadIdx.x;
+}
+__device__ __forceinline__ unsigned item_step(const View& V) { return V.det ? 1u : blockDim.x; }
 
 // ---------------------------------------------------------------------------
 // Element passes over LDS-staged tiles
@@ -429,9 +439,13 @@ __device__ __forceinline__ double elem_eval_impl(const View& V, const double* x,
       for (int c = 0; c < 3; ++c) a[s][c] = fma(alpha, p[c * nv + nxt.v[s]], x[c * nv + nxt.v[s]]);
     SlotIdx nn;
     fetch_idx(G, tile + 2, nn);
-    for (int e = t0 + threadIdx.x; e < t1; e += B) {
+    // deterministic mode: the tile's tets on thread 0, in tile order (its next
+    // tet is then e + 1, and after the tile the first tet of the next one)
+    const int e_first = V.det ? (threadIdx.x == 0 ? t0 : t1) : t0 + (int)threadIdx.x;
+    const int e_step = V.det ? 1 : B;
+    for (int e = e_first; e < t1; e += e_step) {
       TetIn<MIXED> tn;
-      const int en = (e + B < t1) ? e + B : first_tet(G, tile + 1);
+      const int en = (e + e_step < t1) ? e + e_step : first_tet(G, tile + 1);
       load_tet<MIXED>(G, en, tn);
       int l[4];
       tet_ids(tc.loc, l);
@@ -460,7 +474,7 @@ __device__ __forceinline__ double elem_eval_impl(const View& V, const double* x,
       tc = tn;
     }
     // a thread without a tet here fetches its first tet of the next tile
-    if (t0 + (int)threadIdx.x >= t1) load_tet<MIXED>(G, first_tet(G, tile + 1), tc);
+    if (e_first >= t1) load_tet<MIXED>(G, first_tet(G, tile + 1), tc);
     __syncthreads();
     // flush this tile's slots, clear them, stage the next tile's positions
 #pragma unroll
@@ -847,7 +861,7 @@ __device__ __forceinline__ double pairs_eval(const View& V, const Shared& S, Til
   const int nv = G.n_v;
   const double dh = E.dhat, kap = E.kappa;
   double energy = 0.0;
-  for (int i = threadIdx.x; i < V.npairs; i += blockDim.x) {
+  for (int i = item_first(V); i < V.npairs; i += item_step(V)) {
     int2 pr = make_int2(0, 0);
     uint64_t rec = 0;
     if constexpr (LDS) rec = V.pslot[i];
@@ -1157,7 +1171,7 @@ __device__ __forceinline__ double fric_eval(const View& V, const Shared& S, Tile
   const int nv = G.n_v;
   const double eps = V.E->eps_v;
   double energy = 0.0;
-  for (int i = threadIdx.x; i < V.nfric; i += blockDim.x) {
+  for (int i = item_first(V); i < V.nfric; i += item_step(V)) {
     const FricPair F = V.fric[i];
     double Dl[3];
     fric_delta<LDS>(V, S, T, F, x, p, alpha, Dl);
@@ -1297,7 +1311,7 @@ __device__ __forceinline__ double cull(View& V, Shared& S, const double* x, doub
   __syncthreads();
   double dmin = kInf;
   const int ntot = G.n_sv + G.n_se + G.n_sf;
-  for (int i = threadIdx.x; i < ntot; i += blockDim.x) {
+  for (int i = item_first(V); i < ntot; i += item_step(V)) {
     int kind, gp, gvid[3], ngv;
     if (i < G.n_sv) { kind = kVF; gvid[0] = G.surf_v[i]; gp = gvid[0]; ngv = 1; }  // VF pairs store the vertex id
     else if (i < G.n_sv + G.n_se) {
@@ -1410,6 +1424,8 @@ struct Solver {
   double fill;        // largest list length / capacity seen
   // work budget: energy and curvature evaluation passes of this env in this launch
   long long evals, max_evals;
+  int mixed0;         // configured precision (a solve's line-search fallback may switch to FP64)
+  int fallbacks;      // line-search fallbacks taken in the current solve
 };
 
 // Inner candidate list from the outer one: exact distance of every coarse pair,
@@ -1419,7 +1435,7 @@ __device__ __forceinline__ void filter_pairs(View& V, Shared& S, const Tile& T, 
                                              int cap) {
   if (threadIdx.x == 0) { S.count = 0; S.overflow = 0; }
   __syncthreads();
-  for (int i = threadIdx.x; i < V.nouter; i += blockDim.x) {
+  for (int i = item_first(V); i < V.nouter; i += item_step(V)) {
     const int2 pr = V.outer[i];
     const uint64_t rec = LDS ? V.oslot[i] : 0ull;
     PairPts P;
@@ -1724,7 +1740,7 @@ __device__ __forceinline__ double lag_pass(Solver& s, const double* x, int mode,
   if (threadIdx.x == 0) { S.count = 0; S.overflow = 0; }
   __syncthreads();
   double dmin = kInf;
-  for (int i = threadIdx.x; i < V.nouter; i += blockDim.x) {
+  for (int i = item_first(V); i < V.nouter; i += item_step(V)) {
     const int2 pr = V.outer[i];
     const uint64_t rec = LDS ? V.oslot[i] : 0ull;
     PairPts P;
@@ -1906,6 +1922,8 @@ __device__ __forceinline__ int pncg(Solver& s, double tol, int max_iters, int& i
   double* g0 = V.g0;
   double* g1 = V.g1;
   if (s.evals >= s.max_evals) { iters = 0; return kMaxIter | kBudget; }
+  V.mixed = s.mixed0;
+  s.fallbacks = 0;
   if (!ensure_lists(s, x, 0.0)) return kOverflow;
   int feas, nact;
   unsigned long long t0;
@@ -1955,7 +1973,19 @@ __device__ __forceinline__ int pncg(Solver& s, double tol, int max_iters, int& i
       ++s.halvings;
     }
     t0 = tick();
-    if (!ok) { status = kLineSearch; break; }
+    if (!ok) {
+      // one fallback per solve: restart along -P g at x; in mixed precision with
+      // FP64 element terms for the rest of the solve (FP32 rounding of the
+      // element gradient can leave no descent the FP64 energy test accepts)
+      if (s.fallbacks > 0) { status = kLineSearch; break; }
+      ++s.fallbacks;
+      V.mixed = 0;
+      E0 = eval_all(s, x, V.p, 0.0, g0, V.diag, feas, nact);
+      init_direction(s, g0, res, pinf, gp);
+      ++s.restarts;
+      tock(*s.S, 7, t0);
+      continue;
+    }
     nactive_out = nact;
     // dots: x += alpha p ; P1 ; y = g1 - g0
     double a[6] = {0, 0, 0, 0, 0, 0};  // gPy, yPy, yp, pg1, gPg | max|Pg1|
@@ -2040,6 +2070,7 @@ __device__ __forceinline__ void make_view(const StepParams& P, int e, View& V) {
   V.slots_ok = 0;
   V.mixed = P.precision;
   V.moll = P.ee_moll;
+  V.det = P.det;
 }
 
 __device__ __forceinline__ void init_solver(Solver& s, const StepParams& P, Shared& S, Tile& T) {
@@ -2047,6 +2078,8 @@ __device__ __forceinline__ void init_solver(Solver& s, const StepParams& P, Shar
   const GelDev& G = *s.V.G;
   s.S = &S;
   s.T = &T;
+  s.mixed0 = s.V.mixed;
+  s.fallbacks = 0;
   s.floor_d = kDiagFloor * E.mu * G.diag_rest_max;
   s.guard = kEnergyGuard * E.mu * G.vol_total;
   s.buffer = E.dhat;
@@ -2125,8 +2158,12 @@ __device__ __forceinline__ int load_step(const StepParams& P, int e, Solver& s, 
   }
   // friction lag and starting distance at (x_{s-1}, q_{s-1}), from the outer
   // list kept since the last step (rebuilt here if the motion since it was
-  // built exceeds its margin)
-  if (threadIdx.x == 0) set_pose(S, I, q0);
+  // built exceeds its margin; in deterministic mode always, so that a step's
+  // lists, and their order, depend on its starting state only)
+  if (threadIdx.x == 0) {
+    set_pose(S, I, q0);
+    if (V.det) { s.L->valid_o = 0; s.L->valid_i = 0; }
+  }
   __syncthreads();
   int status = 0;
   double dmin_start;
@@ -2289,7 +2326,9 @@ __device__ __forceinline__ void write_markers(const StepParams& P, int k, const 
 // One workgroup owns one env for the whole launch; workgroups take envs in
 // P.order (longest expected first).
 // Two workgroups of 256 threads (or one of 512) per CU: 2 waves per SIMD.
-template <int BLOCK>
+// DET: deterministic mode as a compile-time constant, so that the atomic-mode
+// instantiation carries none of its code.
+template <int BLOCK, bool DET>
 __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel(StepParams P) {
   __shared__ Shared S;
   __shared__ Tile T;
@@ -2297,6 +2336,7 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_step_kernel
   if (e >= P.n_env) return;
   Solver s;
   make_view(P, e, s.V);
+  s.V.det = DET ? 1 : 0;
   View& V = s.V;
   init_solver(s, P, S, T);
   const GelDev& G = *V.G;
@@ -3054,6 +3094,7 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_backward_ke
   if (e >= P.n_env) return;
   Solver s;
   make_view(P, e, s.V);
+  s.V.det = 0;  // the adjoint keeps its atomic sums
   View& V = s.V;
   init_solver(s, P, S, T);
   const GelDev& G = *V.G;
@@ -3348,10 +3389,14 @@ __global__ void t2r_aos_to_soa_kernel(const double* in, double* out, int nv) {
 }
 
 extern "C" hipError_t t2r_launch_step(const StepParams* p, int block, hipStream_t stream) {
-  if (block == 512)
-    hipLaunchKernelGGL(t2r_step_kernel<512>, dim3(p->n_env), dim3(512), 0, stream, *p);
+  if (block == 512 && p->det)
+    hipLaunchKernelGGL((t2r_step_kernel<512, true>), dim3(p->n_env), dim3(512), 0, stream, *p);
+  else if (block == 256 && p->det)
+    hipLaunchKernelGGL((t2r_step_kernel<256, true>), dim3(p->n_env), dim3(256), 0, stream, *p);
+  else if (block == 512)
+    hipLaunchKernelGGL((t2r_step_kernel<512, false>), dim3(p->n_env), dim3(512), 0, stream, *p);
   else if (block == 256)
-    hipLaunchKernelGGL(t2r_step_kernel<256>, dim3(p->n_env), dim3(256), 0, stream, *p);
+    hipLaunchKernelGGL((t2r_step_kernel<256, false>), dim3(p->n_env), dim3(256), 0, stream, *p);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

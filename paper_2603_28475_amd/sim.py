@@ -116,6 +116,17 @@ class Sim:
         self.ctx.backward(g, out)
         return out
 
+    def save_checkpoint(self):
+        """A device copy of everything later load steps read besides their inputs
+        (see t2r_save_checkpoint). Not synchronised."""
+        buf = torch.empty(self.ctx.checkpoint_size(), dtype=torch.float64, device=self.device)
+        self.ctx.save_checkpoint(buf)
+        return buf
+
+    def load_checkpoint(self, buf):
+        """Restores a save_checkpoint copy (same meshes and envs)."""
+        self.ctx.load_checkpoint(torch.as_tensor(buf, device=self.device).contiguous())
+
     def record(self, max_steps):
         """Starts a trajectory tape of at most max_steps load steps from the current
         state (0 stops recording); see t2r_record."""

@@ -32,7 +32,7 @@ class SolverOpts(C.Structure):
                 ("pair_capacity", C.c_int32), ("armijo", C.c_int32), ("block_size", C.c_int32),
                 ("warm_start", C.c_int32), ("dynamic", C.c_int32), ("dt", C.c_double),
                 ("density", C.c_double), ("max_evals", C.c_int32),
-                ("ee_mollifier", C.c_int32), ("outer_radius", C.c_double)]
+                ("ee_mollifier", C.c_int32), ("outer_radius", C.c_double), ("deterministic", C.c_int32)]
 
 
 class EnvStats(C.Structure):
@@ -76,6 +76,9 @@ SIGNATURES = [
     ("t2r_get_stats", C.c_int32, [_P, _P, C.c_size_t]),
     ("t2r_state_size", C.c_int32, [_P, C.POINTER(C.c_int64)]),
     ("t2r_get_state", C.c_int32, [_P, _P]),
+    ("t2r_checkpoint_size", C.c_int32, [_P, C.POINTER(C.c_int64)]),
+    ("t2r_save_checkpoint", C.c_int32, [_P, _P]),
+    ("t2r_load_checkpoint", C.c_int32, [_P, _P]),
     ("t2r_set_state", C.c_int32, [_P, _P]),
     ("t2r_reset_envs", C.c_int32, [_P, _PI, C.c_int32]),
     ("t2r_set_pair_capacity", C.c_int32, [_P, C.c_int32]),
@@ -313,6 +316,17 @@ class Context:
 
     def set_state(self, d_state):
         self.check(lib.t2r_set_state(self.handle, _tptr(d_state)))
+
+    def checkpoint_size(self) -> int:
+        n = C.c_int64()
+        self.check(lib.t2r_checkpoint_size(self.handle, C.byref(n)))
+        return n.value
+
+    def save_checkpoint(self, d_buf):
+        self.check(lib.t2r_save_checkpoint(self.handle, _tptr(d_buf)))
+
+    def load_checkpoint(self, d_buf):
+        self.check(lib.t2r_load_checkpoint(self.handle, _tptr(d_buf)))
 
     def reset_envs(self, ids):
         a = np.ascontiguousarray(ids, dtype=np.int32)
