@@ -549,8 +549,9 @@ __device__ __forceinline__ double elem_curv_impl(const View& V, const double* x,
       a[s][c] = x[c * nv + cur.v[s]];
       b[s][c] = p[c * nv + cur.v[s]];
     }
-  TetIn<MIXED> tc;
+  TetIn<MIXED> tc, tc1;  // tc1: the second tet of a pair (mixed precision)
   load_tet<MIXED>(G, first_tet(G, 0), tc);
+  if constexpr (MIXED) load_tet<MIXED>(G, min(first_tet(G, 0) + B, G.n_t - 1), tc1);
 #pragma unroll
   for (int s = 0; s < kSlots; ++s)
     if (cur.fl[s] >= 0)
@@ -568,55 +569,119 @@ __device__ __forceinline__ double elem_curv_impl(const View& V, const double* x,
       }
     SlotIdx nn;
     fetch_idx(G, tile + 2, nn);
-    for (int e = t0 + threadIdx.x; e < t1; e += B) {
-      TetIn<MIXED> tn;
-      const int en = (e + B < t1) ? e + B : first_tet(G, tile + 1);
-      load_tet<MIXED>(G, en, tn);
-      int l[4];
-      tet_ids(tc.loc, l);
-      Rl Ds[9], dDs[9];
+    if constexpr (MIXED) {
+      // a thread's tets of the tile in pairs (e, e + B): both tets' LDS reads and
+      // FP32 arithmetic sit in one block, so the two chains hide each other's
+      // latency; the next pair's tet data is in flight meanwhile
+      for (int e = t0 + threadIdx.x; e < t1; e += 2 * B) {
+        const bool two = e + B < t1;
+        const int en0 = (e + 2 * B < t1) ? e + 2 * B : first_tet(G, tile + 1);
+        TetIn<MIXED> tn, tn1;
+        load_tet<MIXED>(G, en0, tn);
+        load_tet<MIXED>(G, min(en0 + B, G.n_t - 1), tn1);
+        int la[4], lb[4];
+        tet_ids(tc.loc, la);
+        tet_ids(tc1.loc, lb);
+        float DsA[9], dDsA[9], DsB[9], dDsB[9];
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+        for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          if constexpr (MIXED) {
-            Ds[r * 3 + k] = T.fx[r][l[k + 1]] - T.fx[r][l[0]];
-            dDs[r * 3 + k] = T.fp[r][l[k + 1]] - T.fp[r][l[0]];
-          } else {
-            Ds[r * 3 + k] = T.x[r][l[k + 1]] - T.x[r][l[0]];
-            dDs[r * 3 + k] = T.p[r][l[k + 1]] - T.p[r][l[0]];
+          for (int k = 0; k < 3; ++k) {
+            DsA[r * 3 + k] = T.fx[r][la[k + 1]] - T.fx[r][la[0]];
+            dDsA[r * 3 + k] = T.fp[r][la[k + 1]] - T.fp[r][la[0]];
+            DsB[r * 3 + k] = T.fx[r][lb[k + 1]] - T.fx[r][lb[0]];
+            dDsB[r * 3 + k] = T.fp[r][lb[k + 1]] - T.fp[r][lb[0]];
           }
+        const float JA = DsA[0] * (DsA[4] * DsA[8] - DsA[5] * DsA[7]) - DsA[1] * (DsA[3] * DsA[8] - DsA[5] * DsA[6]) +
+                         DsA[2] * (DsA[3] * DsA[7] - DsA[4] * DsA[6]);
+        const float JB = DsB[0] * (DsB[4] * DsB[8] - DsB[5] * DsB[7]) - DsB[1] * (DsB[3] * DsB[8] - DsB[5] * DsB[6]) +
+                         DsB[2] * (DsB[3] * DsB[7] - DsB[4] * DsB[6]);
+        // det Ds at rest = 6 V; a tet squashed below kMixedMinJ takes FP64 from the
+        // global positions (FP32 cofactors lose the sign of det F as J -> 0)
+        const bool okA = JA > (float)kMixedMinJ * 6.0f * tc.vol;
+        const bool okB = !two || JB > (float)kMixedMinJ * 6.0f * tc1.vol;
+        if (okA && okB) {
+          const float cA = tet_curvature<float>(DsA, dDsA, tc.Dm, tc.vol, (float)E.mu, (float)E.lam);
+          const float cB = tet_curvature<float>(DsB, dDsB, tc1.Dm, tc1.vol, (float)E.mu, (float)E.lam);
+          curv += (double)cA + (two ? (double)cB : 0.0);
+        } else {
+          auto slow = [&](const TetIn<MIXED>& t, int et, const float* Ds, const float* dDs, bool ok) {
+            if (ok) return (double)tet_curvature<float>(Ds, dDs, t.Dm, t.vol, (float)E.mu, (float)E.lam);
+            double Ds64[9], dDs64[9], Dm64[9];
+            int gv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) gv[k] = G.tet[k * G.n_t + et];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                Ds64[r * 3 + k] = x[r * nv + gv[k + 1]] - x[r * nv + gv[0]];
+                dDs64[r * 3 + k] = p[r * nv + gv[k + 1]] - p[r * nv + gv[0]];
+              }
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Dm64[k] = (double)t.Dm[k];
+            return tet_curvature<double>(Ds64, dDs64, Dm64, (double)t.vol, E.mu, E.lam);
+          };
+          curv += slow(tc, e, DsA, dDsA, okA);
+          if (two) curv += slow(tc1, e + B, DsB, dDsB, JB > (float)kMixedMinJ * 6.0f * tc1.vol);
         }
-      if constexpr (MIXED) {
-        // a tet squashed below kMixedMinJ: FP64 from the global positions
-        // (FP32 cofactors lose the sign of det F as J -> 0)
-        const float J32 = Ds[0] * (Ds[4] * Ds[8] - Ds[5] * Ds[7]) - Ds[1] * (Ds[3] * Ds[8] - Ds[5] * Ds[6]) +
-                          Ds[2] * (Ds[3] * Ds[7] - Ds[4] * Ds[6]);
-        const float Jref = 6.0f * tc.vol;  // det Ds at rest = 6 V
-        if (!(J32 > (float)kMixedMinJ * Jref)) {
-          double Ds64[9], dDs64[9], Dm64[9];
-          int gv[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) gv[k] = G.tet[k * G.n_t + e];
-#pragma unroll
-          for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              Ds64[r * 3 + k] = x[r * nv + gv[k + 1]] - x[r * nv + gv[0]];
-              dDs64[r * 3 + k] = p[r * nv + gv[k + 1]] - p[r * nv + gv[0]];
+        tc = tn;
+        tc1 = tn1;
+      }
+    } else {
+      for (int e = t0 + threadIdx.x; e < t1; e += B) {
+        TetIn<MIXED> tn;
+        const int en = (e + B < t1) ? e + B : first_tet(G, tile + 1);
+        load_tet<MIXED>(G, en, tn);
+        int l[4];
+        tet_ids(tc.loc, l);
+        Rl Ds[9], dDs[9];
+  #pragma unroll
+        for (int r = 0; r < 3; ++r)
+  #pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            if constexpr (MIXED) {
+              Ds[r * 3 + k] = T.fx[r][l[k + 1]] - T.fx[r][l[0]];
+              dDs[r * 3 + k] = T.fp[r][l[k + 1]] - T.fp[r][l[0]];
+            } else {
+              Ds[r * 3 + k] = T.x[r][l[k + 1]] - T.x[r][l[0]];
+              dDs[r * 3 + k] = T.p[r][l[k + 1]] - T.p[r][l[0]];
             }
-#pragma unroll
-          for (int k = 0; k < 9; ++k) Dm64[k] = (double)tc.Dm[k];
-          curv += tet_curvature<double>(Ds64, dDs64, Dm64, (double)tc.vol, E.mu, E.lam);
+          }
+        if constexpr (MIXED) {
+          // a tet squashed below kMixedMinJ: FP64 from the global positions
+          // (FP32 cofactors lose the sign of det F as J -> 0)
+          const float J32 = Ds[0] * (Ds[4] * Ds[8] - Ds[5] * Ds[7]) - Ds[1] * (Ds[3] * Ds[8] - Ds[5] * Ds[6]) +
+                            Ds[2] * (Ds[3] * Ds[7] - Ds[4] * Ds[6]);
+          const float Jref = 6.0f * tc.vol;  // det Ds at rest = 6 V
+          if (!(J32 > (float)kMixedMinJ * Jref)) {
+            double Ds64[9], dDs64[9], Dm64[9];
+            int gv[4];
+  #pragma unroll
+            for (int k = 0; k < 4; ++k) gv[k] = G.tet[k * G.n_t + e];
+  #pragma unroll
+            for (int r = 0; r < 3; ++r)
+  #pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                Ds64[r * 3 + k] = x[r * nv + gv[k + 1]] - x[r * nv + gv[0]];
+                dDs64[r * 3 + k] = p[r * nv + gv[k + 1]] - p[r * nv + gv[0]];
+              }
+  #pragma unroll
+            for (int k = 0; k < 9; ++k) Dm64[k] = (double)tc.Dm[k];
+            curv += tet_curvature<double>(Ds64, dDs64, Dm64, (double)tc.vol, E.mu, E.lam);
+          } else {
+            curv += (double)tet_curvature<Rl>(Ds, dDs, tc.Dm, tc.vol, (Rl)E.mu, (Rl)E.lam);
+          }
         } else {
           curv += (double)tet_curvature<Rl>(Ds, dDs, tc.Dm, tc.vol, (Rl)E.mu, (Rl)E.lam);
         }
-      } else {
-        curv += (double)tet_curvature<Rl>(Ds, dDs, tc.Dm, tc.vol, (Rl)E.mu, (Rl)E.lam);
+        tc = tn;
       }
-      tc = tn;
     }
-    if (t0 + (int)threadIdx.x >= t1) load_tet<MIXED>(G, first_tet(G, tile + 1), tc);
+    if (t0 + (int)threadIdx.x >= t1) {
+      load_tet<MIXED>(G, first_tet(G, tile + 1), tc);
+      if constexpr (MIXED) load_tet<MIXED>(G, min(first_tet(G, tile + 1) + B, G.n_t - 1), tc1);
+    }
     __syncthreads();
     if (tile + 1 < NT) {
 #pragma unroll

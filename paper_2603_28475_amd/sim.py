@@ -11,6 +11,7 @@ library. Typical use:
 from __future__ import annotations
 
 import atexit
+import os
 import weakref
 
 import numpy as np
@@ -20,6 +21,8 @@ from . import t2r
 
 
 _LIVE = weakref.WeakSet()
+# autotune results of this process, keyed by Sim.tune_key
+_TUNE_CACHE: dict = {}
 
 
 @atexit.register
@@ -59,6 +62,8 @@ class Sim:
         self.gel_ids = {}
         self.ind_ids = {}
         self.env_gel = []
+        self.env_ind = []
+        self.ind_sizes = {}
         self.n_m = []
         self.n_v = []
 
@@ -72,10 +77,12 @@ class Sim:
             sim.gel_ids[name] = sim.ctx.add_gel(g.X, g.tets, g.fixed, g.markers)
         for name, ind in workload.indenters.items():
             sim.ind_ids[name] = sim.ctx.add_indenter(ind.Y, ind.tris)
+            sim.ind_sizes[sim.ind_ids[name]] = (int(len(ind.Y)), int(len(ind.tris)))
         sel = workload.envs if envs is None else [workload.envs[i] for i in envs]
         sim.ctx.add_envs([sim.gel_ids[e.mesh] for e in sel], [sim.ind_ids[e.indenter] for e in sel],
                          [e.material() for e in sel], np.stack([e.poses[0] for e in sel]))
         sim.env_gel = [sim.gel_ids[e.mesh] for e in sel]
+        sim.env_ind = [sim.ind_ids[e.indenter] for e in sel]
         sim.mats = [e.material() for e in sel]
         for e in sel:
             info = sim.ctx.gel_info(sim.gel_ids[e.mesh])
@@ -186,8 +193,25 @@ class Sim:
                 self._graph.replay()
         return self.markers, self.status
 
-    def autotune(self, poses, blocks=(256, 512), target_steps=1):
+    def tune_key(self, target_steps=1) -> str:
+        """Cache key of an autotune result: the device, the launch length and the
+        batch's composition (count of envs per gel class and indenter class, each
+        class by its sizes)."""
+        import collections
+        comp = collections.Counter()
+        for g, i in zip(self.env_gel, self.env_ind):
+            info = self.ctx.gel_info(g)
+            comp[(info["n_v"], info["n_t"], info["n_sf"]) + tuple(self.ind_sizes.get(i, (0, 0)))] += 1
+        name = torch.cuda.get_device_name(self.device)
+        return repr((name, int(target_steps), sorted(comp.items())))
+
+    def autotune(self, poses, blocks=(256, 512), target_steps=1, cache=True, cache_path=None):
         """Picks the workgroup shape and pair-list capacity for this batch.
+
+        With cache, a batch of the same composition on the same device and launch
+        length reuses an earlier result without trial launches: from this process
+        (a module-level table) or from the JSON file cache_path (read if it
+        exists, written after a tuning run).
 
         Runs the trial load steps `poses` ((S, n_env, 7)) from the current state
         once per candidate block shape and keeps the faster one for launches of
@@ -199,7 +223,19 @@ class Sim:
         and restores the state (positions and poses). Tuning time is setup, not
         part of a timed step. Returns {"block_size", "pair_capacity",
         "trial_ms", "predicted_ms", "list_fill"}."""
+        import json
         import time
+        key = self.tune_key(target_steps) if cache else None
+        if cache and cache_path and key not in _TUNE_CACHE and os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                _TUNE_CACHE.update(json.load(fh))
+        if cache and key in _TUNE_CACHE:
+            hit = _TUNE_CACHE[key]
+            opts = self.ctx.get_opts()
+            opts.block_size = hit["block_size"]
+            opts.pair_capacity = hit["pair_capacity"]
+            self.ctx.set_opts(opts)
+            return dict(hit, cached=True)
         saved = torch.empty(self.ctx.state_size(), dtype=torch.float64, device=self.device)
         self.ctx.get_state(saved)
         opts = self.ctx.get_opts()
@@ -230,8 +266,14 @@ class Sim:
         self.ctx.set_opts(opts)
         self.ctx.set_state(saved)
         self.stream.synchronize()
-        return {"block_size": opts.block_size, "pair_capacity": opts.pair_capacity, "trial_ms": trial_ms,
-                "predicted_ms": predicted, "list_fill": used * grow}
+        out = {"block_size": opts.block_size, "pair_capacity": opts.pair_capacity, "trial_ms": trial_ms,
+               "predicted_ms": predicted, "list_fill": used * grow}
+        if cache:
+            _TUNE_CACHE[key] = out
+            if cache_path:
+                with open(cache_path, "w") as fh:
+                    json.dump(_TUNE_CACHE, fh, indent=1)
+        return dict(out, cached=False)
 
     def close(self):
         """Releases the library's device memory (back to torch's allocator)."""

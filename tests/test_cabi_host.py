@@ -250,3 +250,32 @@ def test_static_backward_refuses_a_tape_beyond_its_workspace_before_any_gpu_use(
         ctx.backward_static(torch.zeros(1, dtype=torch.float64), torch.zeros(1, dtype=torch.float64))
     assert ei.value.code == t2r.T2R_E_ARG
     assert "static workspace holds 2097152" in str(ei.value)
+
+
+def test_autotune_key_counts_batch_composition():
+    """The autotune cache key (Sim.tune_key) depends on the batch's composition
+    by gel and indenter class, not on the envs' order or poses. Host only: the
+    key is computed without any GPU call (device name stubbed)."""
+    import torch
+    from paper_2603_28475_amd.sim import Sim
+    from scenes.configs import uneven_small
+    w = uneven_small(n_steps=2)
+    orig = torch.cuda.get_device_name
+    torch.cuda.get_device_name = lambda dev=None: "stub"
+    try:
+        def key(order):
+            s = Sim.__new__(Sim)
+            s.ctx = _t2r().Context()
+            s.device = torch.device("cpu")
+            gid = {n: s.ctx.add_gel(g.X, g.tets, g.fixed, g.markers) for n, g in w.meshes.items()}
+            s.ind_sizes = {i: (len(w.indenters[n].Y), len(w.indenters[n].tris))
+                           for i, n in enumerate(w.indenters)}
+            iid = {n: i for i, n in enumerate(w.indenters)}
+            s.env_gel = [gid[w.envs[k].mesh] for k in order]
+            s.env_ind = [iid[w.envs[k].indenter] for k in order]
+            return s.tune_key(4)
+        assert key([0, 1, 2, 3]) == key([3, 2, 1, 0])
+        assert key([0, 1, 2, 3]) != key([0, 1, 2, 2])
+        assert key([0, 1, 2, 3]) != key([0, 1, 2])
+    finally:
+        torch.cuda.get_device_name = orig

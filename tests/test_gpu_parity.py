@@ -292,12 +292,26 @@ def test_autotune_restores_state_and_capacity_regrow_keeps_solving():
     torch.cuda.synchronize()
     before = torch.empty(sim.ctx.state_size(), dtype=torch.float64, device="cuda:0")
     sim.ctx.get_state(before)
-    res = sim.autotune(np.ascontiguousarray(poses[:, 2:4].transpose(1, 0, 2)))
-    assert res["block_size"] in (256, 512) and set(res["trial_ms"]) == {256, 512}
+    import tempfile
+    from paper_2603_28475_amd import sim as sim_mod
+    sim_mod._TUNE_CACHE.clear()
+    cache = os.path.join(tempfile.mkdtemp(), "tune.json")
+    res = sim.autotune(np.ascontiguousarray(poses[:, 2:4].transpose(1, 0, 2)), cache_path=cache)
+    assert res["block_size"] in (256, 512) and set(res["trial_ms"]) == {256, 512} and not res["cached"]
     after = torch.empty_like(before)
     sim.ctx.get_state(after)
     torch.cuda.synchronize()
     assert torch.equal(before, after)
+    # a second batch of the same composition reuses the result, from this
+    # process's table and from the file, without trial launches
+    for clear in (False, True):
+        if clear:
+            sim_mod._TUNE_CACHE.clear()
+        other = _build(t2r, w, tol=1e-10, substep_tol=1e-6, max_iters=200000)
+        hit = other.autotune(np.ascontiguousarray(poses[:, 2:4].transpose(1, 0, 2)), cache_path=cache)
+        assert hit["cached"] and hit["block_size"] == res["block_size"]
+        assert other.ctx.get_opts().block_size == res["block_size"]
+        other.close()
     sim.ctx.set_pair_capacity(2 * sim.ctx.gel_info(0)["pair_capacity"])
     for s in range(2, poses.shape[1]):
         m, st = sim.step(poses[:, s], want_x=True)
