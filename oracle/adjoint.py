@@ -261,7 +261,7 @@ def _lag_pairs(prob, x_prev, pose_prev):
     Yp = prob.ind.world(pose_prev)
     pairs = prob.candidates(x_prev, prob.dhat, Yw=Yp)
     res = prob.pair_geometry(x_prev, pairs, Yw=Yp)
-    act = res["d"] < prob.dhat
+    act = (res["d"] < prob.dhat) & (pairs["kind"] < 3)   # self-contact pairs carry no friction
     return pairs["idx"][act], pairs["kind"][act], res["Z"][act], Yp
 
 

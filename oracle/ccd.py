@@ -3,7 +3,8 @@
 Within one solve the indenter is static and gel vertex i moves along
 x_i + t dx_i. Every point of a primitive is a convex combination of its
 vertices, so the distance of a pair can shrink at most at rate
-l = max |dx_i| over the pair's gel vertices. Starting from d_0 and advancing
+l = max |dx_i| over the pair's gel vertices; for a self-contact pair, whose two
+primitives both move, at most at the sum of that maximum over each side. Starting from d_0 and advancing
 by t += (d(t) - g)/l therefore never brings the pair below the gap
 g = GAP_FRACTION * d_0: this is additive conservative advancement (the
 additive-CCD idea of codimensional IPC, cited by the paper for IPC).
@@ -28,8 +29,8 @@ def ccd_step(prob, x, dx, alpha_max, thr=None):
     L = float(np.linalg.norm(dx, axis=1).max()) if len(dx) else 0.0
     if L == 0.0 or alpha_max <= 0.0:
         return alpha_max
-    if thr is None:
-        thr = prob.dhat + 1.01 * alpha_max * L
+    if thr is None:  # self-contact pairs close at up to twice the largest speed
+        thr = prob.dhat + (2.02 if getattr(prob, "self_contact", False) else 1.01) * alpha_max * L
     pairs = prob.candidates(x, thr)
     if len(pairs["idx"]) == 0:
         return alpha_max
@@ -37,7 +38,12 @@ def ccd_step(prob, x, dx, alpha_max, thr=None):
     idx = pairs["idx"]
     gel_pt = idx < nv
     vel = np.where(gel_pt[:, :, None], dx[np.where(gel_pt, idx, 0)], 0.0)
-    lpair = np.linalg.norm(vel, axis=2).max(axis=1)
+    speed = np.linalg.norm(vel, axis=2)
+    lpair = speed.max(axis=1)
+    kind = pairs["kind"]
+    gvf, gee = kind == 3, kind == 4       # self-contact: both sides move
+    lpair[gvf] = speed[gvf, 0] + speed[gvf, 1:].max(axis=1)
+    lpair[gee] = speed[gee, :2].max(axis=1) + speed[gee, 2:].max(axis=1)
     d0 = prob.pair_geometry(x, pairs)["d"]
     if np.any(d0 <= 0):
         return 0.0
@@ -73,7 +79,7 @@ def _dist_at(prob, x, dx, pairs, t):
     idx = pairs["idx"]
     Z = pts[idx] + t[:, None, None] * vel[idx]
     d = np.zeros(len(idx))
-    pt = pairs["kind"] != 2  # point-triangle kinds; 2 is edge-edge
+    pt = ~np.isin(pairs["kind"], (2, 4))  # point-triangle kinds; 2 and 4 are edge-edge
     if np.any(pt):
         d[pt] = point_triangle(Z[pt, 0], Z[pt, 1], Z[pt, 2], Z[pt, 3])["d"]
     ee = ~pt

@@ -83,7 +83,9 @@ def newton_solve(prob, x0, tol=1e-12, max_iter=200, verbose=False):
             break
         L = float(np.linalg.norm(dx, axis=1).max())
         alpha = min(1.0, prob.dhat / L)
-        alpha = ccd_step(prob, x, dx, alpha, thr=prob.dhat + 1.01 * alpha * L)
+        # self-contact pairs close at up to twice the largest speed
+        rate = 2.02 if getattr(prob, "self_contact", False) else 1.01
+        alpha = ccd_step(prob, x, dx, alpha, thr=prob.dhat + rate * alpha * L)
         gdx = float(g @ dx.ravel())
         accepted = False
         for _ in range(80):

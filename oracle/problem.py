@@ -7,9 +7,13 @@ over the free vertices (the bottom face stays at rest).
 
 C(x) holds every gel-surface/indenter pair closer than dhat: gel vertex vs
 indenter triangle, indenter vertex vs gel triangle, gel edge vs indenter edge.
-Shared-feature duplicates are kept (plain IPC enumeration). With the option
-ee_mollifier the edge-edge terms are kappa m(c) b(d), m the edge-edge mollifier
-of barrier.py (smooth as the edges turn parallel); without it kappa b(d).
+With the option self_contact it also holds every pair of gel surface
+primitives closer than dhat that share no vertex: gel vertex vs gel triangle
+and gel edge vs gel edge (Supp. A applies the barrier between all surface
+primitives). Shared-feature duplicates are kept (plain IPC enumeration). With
+the option ee_mollifier the edge-edge terms are kappa m(c) b(d), m the
+edge-edge mollifier of barrier.py (smooth as the edges turn parallel);
+without it kappa b(d). Self-contact pairs carry no friction (reading).
 
 Friction (Supp. A, eqs. friction_energy, friction_mollifier) is lagged once per
 load step at the previous equilibrium (x_{s-1}, q_{s-1}): for each pair active
@@ -33,6 +37,8 @@ from .elastic import (element_energy, element_gradient, element_hessian, lame, p
 from .geometry import GelGeometry, IndenterGeometry
 
 VF, FV, EE = 0, 1, 2
+GVF, GEE = 3, 4      # gel vertex vs gel triangle, gel edge vs gel edge (self-contact)
+EDGE_KINDS = (EE, GEE)
 
 
 def _aabb(P):
@@ -59,9 +65,10 @@ class StepProblem:
     """Energy of one load step at a fixed indenter pose (and fixed friction lag)."""
 
     def __init__(self, gel: GelGeometry, ind: IndenterGeometry, E, nu, mu_f=0.0,
-                 eps_v=1e-3, dhat=0.05, kappa=1e3, ee_mollifier=False):
+                 eps_v=1e-3, dhat=0.05, kappa=1e3, ee_mollifier=False, self_contact=False):
         self.gel, self.ind = gel, ind
         self.ee_mollifier = bool(ee_mollifier)
+        self.self_contact = bool(self_contact)
         self.mu, self.lam = lame(E, nu)
         self.mu_f, self.eps_v, self.dhat, self.kappa = mu_f, eps_v, dhat, kappa
         self.nv = gel.n_v
@@ -108,7 +115,7 @@ class StepProblem:
         Yp = self.ind.world(pose_prev)
         pairs = self.candidates(x_prev, self.dhat, Yw=Yp)
         res = self.pair_geometry(x_prev, pairs, Yw=Yp)
-        act = res["d"] < self.dhat
+        act = (res["d"] < self.dhat) & (pairs["kind"] < GVF)   # self-contact pairs: no friction
         idx, kind = pairs["idx"][act], pairs["kind"][act]
         d, c = res["d"][act], res["c"][act]
         Z = res["Z"][act]
@@ -173,6 +180,25 @@ class StepProblem:
             idx = np.stack([se[i, 0], se[i, 1], nv + ie[j, 0], nv + ie[j, 1]], 1)
             out_idx.append(idx)
             out_kind.append(np.full(len(i), EE))
+        if self.self_contact:
+            # gel surface vertex vs gel surface triangle not containing it
+            sv, st = g.surf_verts, g.surf_tris
+            if len(sv) and len(st):
+                lo, hi = _aabb(x[st])
+                i, j = _pairs_by_aabb(x[sv], x[sv], lo, hi, thr)
+                keep = np.all(st[j] != sv[i][:, None], axis=1)
+                i, j = i[keep], j[keep]
+                out_idx.append(np.stack([sv[i], st[j, 0], st[j, 1], st[j, 2]], 1))
+                out_kind.append(np.full(len(i), GVF))
+            # gel surface edge pairs (each unordered pair once) sharing no vertex
+            se = g.surf_edges
+            if len(se) > 1:
+                lo, hi = _aabb(x[se])
+                i, j = _pairs_by_aabb(lo, hi, lo, hi, thr)
+                keep = (i < j) & np.all(se[i][:, :, None] != se[j][:, None, :], axis=(1, 2))
+                i, j = i[keep], j[keep]
+                out_idx.append(np.stack([se[i, 0], se[i, 1], se[j, 0], se[j, 1]], 1))
+                out_kind.append(np.full(len(i), GEE))
         if out_idx:
             idx = np.concatenate(out_idx).astype(np.int64)
             kind = np.concatenate(out_kind)
@@ -191,11 +217,11 @@ class StepProblem:
         c = np.zeros((n, 4))
         Cw = np.zeros((n, 4, 2))
         k = np.zeros(n, np.int64)
-        pt = kind != EE
+        ee = np.isin(kind, EDGE_KINDS)
+        pt = ~ee
         if np.any(pt):
             r = point_triangle(Z[pt, 0], Z[pt, 1], Z[pt, 2], Z[pt, 3])
             d[pt], c[pt], Cw[pt], k[pt] = r["d"], r["c"], r["Cw"], r["k"]
-        ee = kind == EE
         if np.any(ee):
             r = edge_edge(Z[ee, 0], Z[ee, 1], Z[ee, 2], Z[ee, 3])
             d[ee], c[ee], Cw[ee], k[ee] = r["d"], r["c"], r["Cw"], r["k"]
@@ -234,11 +260,14 @@ class StepProblem:
             b2 = barrier_d2(d, self.dhat)
             H = self.kappa * (b2[:, None, None] * np.einsum("ni,nj->nij", g, g) + b1[:, None, None] * Hd)
         if self.ee_mollifier:
-            ee = np.nonzero(pairs["kind"] == EE)[0]
+            ee = np.nonzero(np.isin(pairs["kind"], EDGE_KINDS))[0]
             if len(ee):
                 idx = pairs["idx"][ee]
-                ar = self.gel.X[idx[:, 1]] - self.gel.X[idx[:, 0]]
-                br = self.ind.Y[idx[:, 3] - self.nv] - self.ind.Y[idx[:, 2] - self.nv]
+                # rest positions: the gel's, or the indenter's local ones
+                rest = lambda i: np.where((i < self.nv)[:, None], self.gel.X[np.minimum(i, self.nv - 1)],
+                                          self.ind.Y[np.maximum(i - self.nv, 0)])
+                ar = rest(idx[:, 1]) - rest(idx[:, 0])
+                br = rest(idx[:, 3]) - rest(idx[:, 2])
                 eps = EDGE_MOLLIFIER_REL * np.einsum("nd,nd->n", ar, ar) * np.einsum("nd,nd->n", br, br)
                 c, gc, Hc = edge_cross_derivatives(res["Z"][ee])
                 m, m1, m2 = edge_mollifier(c, eps), edge_mollifier_d1(c, eps), edge_mollifier_d2(c, eps)

@@ -37,11 +37,11 @@ class SimResult:
     n_active: list = field(default_factory=list)
 
 
-def build(gel_mesh, indenter, env, ee_mollifier=False):
+def build(gel_mesh, indenter, env, ee_mollifier=False, self_contact=False):
     gel = GelGeometry(gel_mesh.X, gel_mesh.tets, gel_mesh.fixed, gel_mesh.markers)
     ind = IndenterGeometry(indenter.Y, indenter.tris)
     prob = StepProblem(gel, ind, env.E, env.nu, env.mu_f, env.eps_v, env.dhat, env.kappa,
-                       ee_mollifier=ee_mollifier)
+                       ee_mollifier=ee_mollifier, self_contact=self_contact)
     return gel, ind, prob
 
 
@@ -64,13 +64,14 @@ def lumped_mass(gel):
 
 def simulate(gel_mesh, indenter, env, mode="newton", tol=None, n_steps=None,
              max_substeps=10000, pncg_kw=None, x_start=None, verbose=False, dynamic=None,
-             ee_mollifier=False):
+             ee_mollifier=False, self_contact=False):
     """Run the load steps of `env` (a scenes.EnvSpec). mode: 'newton' or 'pncg'.
     dynamic: None (quasi-static) or dict(density=rho, dt=h) for the implicit-Euler
     form: each step adds 1/2 |x - xhat|^2_M / h^2 with the lumped mass M = rho V/4
     per vertex and xhat = x^t + h v^t, and then v = (x - x^t) / h (v^0 = 0).
-    ee_mollifier: weight edge-edge barriers by the parallel-edge mollifier."""
-    gel, ind, prob = build(gel_mesh, indenter, env, ee_mollifier=ee_mollifier)
+    ee_mollifier: weight edge-edge barriers by the parallel-edge mollifier;
+    self_contact: barriers between gel surface primitives too."""
+    gel, ind, prob = build(gel_mesh, indenter, env, ee_mollifier=ee_mollifier, self_contact=self_contact)
     poses = np.asarray(env.poses, dtype=np.float64)
     S = poses.shape[0] - 1 if n_steps is None else n_steps
     x = gel.X.copy() if x_start is None else np.array(x_start, dtype=np.float64)

@@ -20,7 +20,7 @@ import numpy as np
 
 from .indenters import (Indenter, end_on_peg, flat_plate, hex_nut, icosphere,
                         quat_from_axis_angle, quat_mul, rotation_matrix)
-from .mesh import GelMesh, mesh_class
+from .mesh import GelMesh, hex_kuhn_gel, marker_grid, mesh_class
 
 DHAT = 0.05      # mm
 KAPPA = 1.0e3    # N/mm
@@ -256,6 +256,34 @@ def micro_press(mesh: str = "micro2", indenter: str = "sphere_small", depth: flo
     env = EnvSpec(mesh, indenter, E, nu, mu_f, poses)
     return Workload(f"micro_{mesh}_{indenter}", 0, {mesh: g}, {indenter: ind}, [env], "f64", 1e-10,
                     "micro scene")
+
+
+def two_block_gel(size=(1.5, 1.5, 1.0), cells=(3, 3, 2), gap: float = 0.08, markers=(3, 3)) -> GelMesh:
+    """Two box gels side by side along x, `gap` mm apart, both fixed at the bottom:
+    one gel mesh whose surfaces can meet (self-contact scenes). Markers on the
+    first block's top face."""
+    a = hex_kuhn_gel(size, cells, markers)
+    off = np.array([size[0] / 2 + gap / 2, 0.0, 0.0])
+    X = np.concatenate([a.X - off, a.X + off])
+    tets = np.concatenate([a.tets, a.tets + a.n_verts]).astype(np.int32)
+    fixed = np.concatenate([a.fixed, a.fixed])
+    mk = marker_grid(size[:2], markers) - off[:2]
+    return GelMesh(X=X, tets=tets, fixed=fixed, size=(2 * size[0] + gap, size[1], size[2]), cells=cells,
+                   markers=mk, name="two_block")
+
+
+def self_contact_press(depth: float = 0.3, n_steps: int = 3, xy=(-0.3, 0.0), gap: float = 0.08,
+                       mu_f: float = 0.0, shear=(0.0, 0.0), n_shear: int = 0) -> Workload:
+    """Self-contact scene: a small sphere (r = 0.6 mm) presses the first of two
+    gel blocks next to the gap between them, so that the block's side wall bulges
+    towards the second block's."""
+    g = two_block_gel(gap=gap)
+    ind = INDENTERS["sphere_small"]()
+    poses = press_schedule(ind, (1.0, 0.0, 0.0, 0.0), xy, depth, g.thickness, n_steps, shear=shear,
+                           n_shear=n_shear)
+    env = EnvSpec("two_block", "sphere_small", 0.3, NU, mu_f, poses)
+    return Workload("self_contact_press", 0, {"two_block": g}, {"sphere_small": ind}, [env], "f64", 1e-6,
+                    "1 env, two gel blocks with a gap, small sphere pressing next to the gap")
 
 
 WORKLOADS = {

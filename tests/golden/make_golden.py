@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle.sim import simulate  # noqa: E402
-from scenes.configs import calibration_micro, micro_press, peg_press_484v, sphere_press_484v  # noqa: E402
+from scenes.configs import (calibration_micro, micro_press, peg_press_484v, self_contact_press,  # noqa: E402
+                            sphere_press_484v)
 
 CALIB_THETA = (0.12, 0.45, 0.6)        # hidden (E MPa, nu, mu_f) of the calibration recordings
 CALIB_DYNAMIC = dict(density=2.5e-9, dt=2e-4)  # hidden density (t/mm^3) of the dynamic recordings
@@ -103,6 +104,29 @@ def peg_press_mollified():
     print(f"peg_press_484v_mollifier_friction: {time.time() - t:.1f}s, active {r.n_active}, mollified {n_moll}")
 
 
+def self_contact_friction():
+    """Two gel blocks 0.08 mm apart; a small sphere presses the first next to
+    the gap and slides it towards the second with friction 0.8: gel surface
+    pairs of the two blocks come within dhat (self-contact on)."""
+    from oracle.problem import GEE, GVF
+    from oracle.sim import build
+    w = self_contact_press(depth=0.3, xy=(-0.45, 0.0), mu_f=0.8, shear=(0.25, 0.0), n_shear=3)
+    env = w.envs[0]
+    g = w.meshes["two_block"]
+    t = time.time()
+    r = simulate(g, w.indenters["sphere_small"], env, mode="newton", self_contact=True)
+    gel, ind, prob = build(g, w.indenters["sphere_small"], env, self_contact=True)
+    n_self = []
+    for s, x in enumerate(r.x):
+        prob.set_pose(env.poses[s + 1])
+        pairs, _ = prob.active(x)
+        n_self.append(int(np.isin(pairs["kind"], (GVF, GEE)).sum()))
+    np.savez_compressed(os.path.join(HERE, "self_contact_friction_newton.npz"),
+                        x=np.array(r.x), markers=np.array(r.markers), poses=env.poses,
+                        n_active=np.array(r.n_active), n_self=np.array(n_self))
+    print(f"self_contact_friction: {time.time() - t:.1f}s, active {r.n_active}, self {n_self}")
+
+
 def calibration_targets():
     """Synthetic recordings for the calibration driver: the oracle's Newton
     marker fields of the calibration scene (two indenters, the recording
@@ -125,6 +149,7 @@ def calibration_targets():
 
 if __name__ == "__main__":
     which = sys.argv[1:] or ["micro_friction", "sphere_press", "peg_press_friction",
-                             "peg_press_friction_unstructured", "calibration_targets", "peg_press_mollified"]
+                             "peg_press_friction_unstructured", "calibration_targets", "peg_press_mollified",
+                             "self_contact_friction"]
     for name in which:
         globals()[name]()
