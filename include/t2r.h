@@ -143,7 +143,16 @@ typedef struct { double E, nu, mu_f, eps_v, dhat, kappa; } t2r_material;
  *                 at equal block_size. Much slower: for tests and debugging.
  *                 The adjoint entry points keep their atomic sums. 0: sums in
  *                 LDS / global atomics, whose order varies from run to run in
- *                 the last bits */
+ *                 the last bits
+ *   self_contact  1: the barrier also acts between gel surface primitives that
+ *                 share no vertex (vertex / triangle and edge / edge pairs of the
+ *                 gel; Supp. A places it between all surface primitives), without
+ *                 friction. Such pairs are searched where the gel can deform:
+ *                 among the surface primitives whose vertices all lie within the
+ *                 coarse list's margin of the indenter (at most 512 vertices;
+ *                 beyond that the env reports T2R_ENV_PAIR_OVERFLOW). The step
+ *                 bound and the list margins count both sides' motion.
+ *                 0: gel / indenter pairs only */
 typedef struct {
   double tol;
   double substep_tol;
@@ -161,6 +170,7 @@ typedef struct {
   int32_t ee_mollifier;
   double outer_radius;
   int32_t deterministic;
+  int32_t self_contact;
 } t2r_solver_opts;
 
 /* Per-environment counters of the last launch (t2r_step or t2r_step_sequence;
@@ -196,7 +206,7 @@ typedef struct {
 /* Fills *o with the defaults: tol 1e-6, substep_tol 1e-4, max_iters 20000,
  * max_substeps 1000, precision 0, pair_capacity 0, armijo 1, block_size 0, warm_start 1,
  * dynamic 0, dt 1/60, density 1.1e-9, max_evals 200000, ee_mollifier 0, outer_radius 0,
- * deterministic 0. */
+ * deterministic 0, self_contact 0. */
 void t2r_default_opts(t2r_solver_opts* o);
 
 /* Creates a context bound to `hip_stream` (a hipStream_t, or NULL for the null

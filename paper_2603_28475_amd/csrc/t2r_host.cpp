@@ -328,6 +328,7 @@ void t2r_default_opts(t2r_solver_opts* o) {
   o->ee_mollifier = 0;
   o->outer_radius = 0.0;
   o->deterministic = 0;
+  o->self_contact = 0;
 }
 
 static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
@@ -339,6 +340,7 @@ static t2r_status check_opts(t2r_ctx* c, const t2r_solver_opts* o) {
   if (o->max_evals < 0) return fail(c, T2R_E_ARG, "max_evals must be >= 0 (0: no limit)");
   if (o->ee_mollifier != 0 && o->ee_mollifier != 1) return fail(c, T2R_E_ARG, "ee_mollifier must be 0 or 1");
   if (o->deterministic != 0 && o->deterministic != 1) return fail(c, T2R_E_ARG, "deterministic must be 0 or 1");
+  if (o->self_contact != 0 && o->self_contact != 1) return fail(c, T2R_E_ARG, "self_contact must be 0 or 1");
   if (!(o->outer_radius == 0.0 || (o->outer_radius >= 2.0 && o->outer_radius <= 64.0)))
     return fail(c, T2R_E_ARG, "outer_radius must be 0 or in [2, 64] (got %g)", o->outer_radius);
   if (o->block_size != 0 && o->block_size != 256 && o->block_size != 512)
@@ -985,6 +987,7 @@ static StepParams step_params(t2r_ctx* c) {
   P.ee_moll = c->opts.ee_mollifier;
   P.outer_mult = c->opts.outer_radius > 0.0 ? c->opts.outer_radius : 6.0;
   P.det = c->opts.deterministic;
+  P.selfc = c->opts.self_contact;
   P.armijo = c->opts.armijo;
   P.warm_start = c->opts.warm_start;
   P.gap0 = c->d_gap;

@@ -46,6 +46,8 @@ constexpr uint32_t kNoSlot10 = 1023;
 constexpr int kVF = 0;   // gel surface vertex  vs indenter triangle
 constexpr int kFV = 1;   // indenter vertex     vs gel surface triangle
 constexpr int kEE = 2;   // gel surface edge    vs indenter edge
+constexpr int kGVF = 3;  // gel surface vertex  vs gel surface triangle (self-contact)
+constexpr int kGEE = 4;  // gel surface edge    vs gel surface edge (self-contact)
 constexpr int kKindShift = 29;
 constexpr int kPrimMask = (1 << kKindShift) - 1;
 
@@ -197,6 +199,7 @@ struct StepParams {
   int ee_moll;                   // weight edge-edge barriers by the parallel-edge mollifier
   double outer_mult;             // coarse list margin beyond dhat, in multiples of dhat
   int det;                       // deterministic summation and list order
+  int selfc;                     // barriers between gel surface primitives too
   long long max_evals;           // energy + curvature passes per env per launch (<= 0: no limit)
   int warm_start;                // extrapolate the previous load step's displacement
   T2R_G double* gap0;            // [n_env] d_min at the start of the env's previous load step (0: unknown)

@@ -52,6 +52,8 @@ struct Shared {
   double bc[8];               // broadcast results
   int count, overflow, flag;
   int pad;
+  int rcount[3];              // self-contact region: surface vertices, triangles, edges
+  int pad2;
   double qb[7];               // the env's pose at the launch start (motion input)
   T2R_G double* vel;          // this env's velocities (dynamic form)
   double iw, dt;              // inertia weight density / dt^2 (0: quasi-static), time step
@@ -306,6 +308,7 @@ struct View {
   int mixed;
   int moll;              // edge-edge mollifier on
   int det;               // deterministic order: summing passes and list builds on one thread
+  int selfc;             // self-contact pairs (gel surface vs gel surface)
 };
 
 // Item loops of the passes that sum into shared per-vertex slots or append to
@@ -717,14 +720,24 @@ struct PairPts {
   int kind;
 };
 
-__device__ __forceinline__ int rec_kind(uint64_t r) { return (int)(r >> (4 * kRecBits)) & 3; }
+__device__ __forceinline__ int rec_kind(uint64_t r) { return (int)(r >> (4 * kRecBits)) & 7; }
 __device__ __forceinline__ int rec_slot(uint64_t r, int k) {
   return (int)(r >> (kRecBits * k)) & ((1 << kRecBits) - 1);
 }
 // Point k of a pair is a gel point: VF (gel vertex, indenter triangle),
-// FV (indenter vertex, gel triangle), EE (gel edge, indenter edge).
+// FV (indenter vertex, gel triangle), EE (gel edge, indenter edge); every point
+// of the self-contact kinds GVF (gel vertex, gel triangle) and GEE (two gel edges).
 __device__ __forceinline__ bool point_is_gel(int kind, int k) {
-  return kind == kVF ? k == 0 : (kind == kFV ? k > 0 : k < 2);
+  return kind >= kGVF ? true : (kind == kVF ? k == 0 : (kind == kFV ? k > 0 : k < 2));
+}
+
+// Bound on how fast a pair's distance can shrink when its gel points move with
+// squared speeds s[k] (0 for indenter points): the largest gel speed, or for a
+// self-contact pair, whose two primitives both move, the sum of each side's.
+__device__ __forceinline__ double closing_rate(int selfc, int kind, const double s[4]) {
+  if (selfc && kind == kGVF) return sqrt(s[0]) + sqrt(fmax(fmax(s[1], s[2]), s[3]));
+  if (selfc && kind == kGEE) return sqrt(fmax(s[0], s[1])) + sqrt(fmax(s[2], s[3]));
+  return sqrt(fmax(fmax(s[0], s[1]), fmax(s[2], s[3])));
 }
 
 // Vertex ids of the four points of pair `pr` (gel ids where point_is_gel).
@@ -737,9 +750,15 @@ __device__ __forceinline__ void pair_point_ids(const GelDev& G, const IndDev& I,
   } else if (kind == kFV) {
     id[0] = ip;
     id[1] = G.surf_f[gp]; id[2] = G.surf_f[G.n_sf + gp]; id[3] = G.surf_f[2 * G.n_sf + gp];
-  } else {
+  } else if (kind == kEE) {
     id[0] = G.surf_e[gp]; id[1] = G.surf_e[G.n_se + gp];
     id[2] = I.edge[ip]; id[3] = I.edge[I.n_e + ip];
+  } else if (kind == kGVF) {
+    id[0] = gp;
+    id[1] = G.surf_f[ip]; id[2] = G.surf_f[G.n_sf + ip]; id[3] = G.surf_f[2 * G.n_sf + ip];
+  } else {
+    id[0] = G.surf_e[gp]; id[1] = G.surf_e[G.n_se + gp];
+    id[2] = G.surf_e[ip]; id[3] = G.surf_e[G.n_se + ip];
   }
 }
 
@@ -796,7 +815,7 @@ __device__ __forceinline__ void get_pair(const View& V, const Shared& S, const T
 }
 
 __device__ __forceinline__ void classify(const PairPts& P, Feature& f) {
-  if (P.kind == kEE) classify_ee(P.z[0], P.z[1], P.z[2], P.z[3], f);
+  if (P.kind == kEE || P.kind == kGEE) classify_ee(P.z[0], P.z[1], P.z[2], P.z[3], f);
   else classify_pt(P.z[0], P.z[1], P.z[2], P.z[3], f);
 }
 
@@ -821,7 +840,7 @@ struct EdgeMoll {
 
 template <bool LDS>
 __device__ __forceinline__ bool edge_moll(const View& V, int2 pr, uint64_t rec, const PairPts& P, EdgeMoll& M) {
-  if (!V.moll || P.kind != kEE) return false;
+  if (!V.moll || (P.kind != kEE && P.kind != kGEE)) return false;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     M.a[c] = P.z[1][c] - P.z[0][c];
@@ -833,11 +852,12 @@ __device__ __forceinline__ bool edge_moll(const View& V, int2 pr, uint64_t rec, 
   const GelDev& G = *V.G;
   const IndDev& I = *V.I;
   int id[4];
+  const bool self = P.kind == kGEE;  // second edge on the gel too
   if constexpr (LDS) {
     id[0] = V.slot_v[rec_slot(rec, 0)];
     id[1] = V.slot_v[rec_slot(rec, 1)];
-    id[2] = V.islot_v[rec_slot(rec, 2)];
-    id[3] = V.islot_v[rec_slot(rec, 3)];
+    id[2] = self ? V.slot_v[rec_slot(rec, 2)] : V.islot_v[rec_slot(rec, 2)];
+    id[3] = self ? V.slot_v[rec_slot(rec, 3)] : V.islot_v[rec_slot(rec, 3)];
   } else {
     pair_point_ids(G, I, pr, id);
   }
@@ -845,7 +865,8 @@ __device__ __forceinline__ bool edge_moll(const View& V, int2 pr, uint64_t rec, 
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const double u = G.X[c * G.n_v + id[1]] - G.X[c * G.n_v + id[0]];
-    const double v = I.Y[c * I.n_v + id[3]] - I.Y[c * I.n_v + id[2]];
+    const double v = self ? G.X[c * G.n_v + id[3]] - G.X[c * G.n_v + id[2]]
+                          : I.Y[c * I.n_v + id[3]] - I.Y[c * I.n_v + id[2]];
     ar += u * u;
     br += v * v;
   }
@@ -932,26 +953,27 @@ __device__ __forceinline__ double pairs_eval(const View& V, const Shared& S, Til
     if constexpr (LDS) rec = V.pslot[i];
     else pr = V.pairs[i];
     if (alpha > 0.0) {
-      double l2 = 0.0;
+      double sk[4] = {0.0, 0.0, 0.0, 0.0};
+      int kind;
       if constexpr (LDS) {
-        const int kind = rec_kind(rec);
+        kind = rec_kind(rec);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-          if (point_is_gel(kind, k)) l2 = fmax(l2, T.pn[rec_slot(rec, k)]);
+          if (point_is_gel(kind, k)) sk[k] = T.pn[rec_slot(rec, k)];
       } else {
         int id[4];
         pair_point_ids(G, *V.I, pr, id);
-        const int kind = (int)((unsigned)pr.x >> kKindShift);
+        kind = (int)((unsigned)pr.x >> kKindShift);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           if (!point_is_gel(kind, k)) continue;
           double sq = 0.0;
 #pragma unroll
           for (int c = 0; c < 3; ++c) { const double pc = p[c * nv + id[k]]; sq += pc * pc; }
-          l2 = fmax(l2, sq);
+          sk[k] = sq;
         }
       }
-      const double lb = V.pd[i] - alpha * sqrt(l2);
+      const double lb = V.pd[i] - alpha * closing_rate(V.selfc, kind, sk);
       if (lb >= dh) { V.pd[i] = lb; continue; }
     }
     PairPts P;
@@ -1129,9 +1151,10 @@ __device__ __forceinline__ double pairs_ccd(const View& V, const Shared& S, cons
     else pr = V.pairs[i];
     const double d0 = V.pd[i];
     if (!(d0 > 0.0)) { tmin = 0.0; continue; }
-    double l2 = 0.0;
+    double sk[4] = {0.0, 0.0, 0.0, 0.0};
+    int kind;
     if constexpr (LDS) {
-      const int kind = rec_kind(rec);
+      kind = rec_kind(rec);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         if (!point_is_gel(kind, k)) continue;
@@ -1139,22 +1162,22 @@ __device__ __forceinline__ double pairs_ccd(const View& V, const Shared& S, cons
         double s = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) s += T.gq[c][q] * T.gq[c][q];
-        l2 = fmax(l2, s);
+        sk[k] = s;
       }
     } else {
       int id[4];
       pair_point_ids(G, *V.I, pr, id);
-      const int kind = (int)((unsigned)pr.x >> kKindShift);
+      kind = (int)((unsigned)pr.x >> kKindShift);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         if (!point_is_gel(kind, k)) continue;
         double s = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) { const double pc = p[c * nv + id[k]]; s += pc * pc; }
-        l2 = fmax(l2, s);
+        sk[k] = s;
       }
     }
-    const double l = sqrt(l2);
+    const double l = closing_rate(V.selfc, kind, sk);
     const double gap = kCcdGap * d0;
     if (l * amax <= d0 - gap) continue;
     double t = 0.0, d = d0;
@@ -1468,6 +1491,110 @@ __device__ __forceinline__ double cull(View& V, Shared& S, const double* x, doub
   return dmin;
 }
 
+// Self-contact candidates (option): pairs of gel surface primitives sharing no
+// vertex (vertex / triangle, edge / edge, each unordered edge pair once) whose
+// exact distance is below thr, appended to V.outer after the indenter pairs.
+// Searched among the surface primitives all of whose vertices are gel points of
+// the coarse list, i.e. within its margin of the indenter, where the gel
+// deforms, by pairwise box tests. The region's vertex, triangle and edge lists
+// are staged in the inner list's storage (rebuilt by the refilter that follows
+// every coarse build); a region beyond that storage sets S.overflow.
+__device__ __forceinline__ void cull_self(View& V, Shared& S, const double* x, double thr, int cap, int pair_cap) {
+  const GelDev& G = *V.G;
+  const IndDev& I = *V.I;
+  const int nv = G.n_v;
+  const int n0 = min(S.count, cap);
+  for (int i = threadIdx.x; i < n0; i += blockDim.x) {
+    const int2 pr = V.outer[i];
+    const int kind = (int)((unsigned)pr.x >> kKindShift);
+    int id[4];
+    pair_point_ids(G, I, pr, id);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (point_is_gel(kind, k)) V.vmap[id[k]] = -1;
+  }
+  if (threadIdx.x == 0) { S.rcount[0] = 0; S.rcount[1] = 0; S.rcount[2] = 0; }
+  __syncthreads();
+  T2R_G int* rv = reinterpret_cast<T2R_G int*>(V.pairs);  // 2 pair_cap ints
+  const int cap_v = min(kGelSlots, pair_cap / 2), cap_fe = (2 * pair_cap - cap_v) / 2;
+  T2R_G int* rf = rv + cap_v;
+  T2R_G int* re = rf + cap_fe;
+  for (int i = item_first(V); i < G.n_sv; i += item_step(V)) {
+    const int v = G.surf_v[i];
+    if (V.vmap[v] != -1) continue;
+    const int q = atomicAdd(&S.rcount[0], 1);
+    if (q < cap_v) rv[q] = v;
+    else S.overflow = 1;
+  }
+  for (int i = item_first(V); i < G.n_sf; i += item_step(V)) {
+    if (V.vmap[G.surf_f[i]] != -1 || V.vmap[G.surf_f[G.n_sf + i]] != -1 || V.vmap[G.surf_f[2 * G.n_sf + i]] != -1)
+      continue;
+    const int q = atomicAdd(&S.rcount[1], 1);
+    if (q < cap_fe) rf[q] = i;
+    else S.overflow = 1;
+  }
+  for (int i = item_first(V); i < G.n_se; i += item_step(V)) {
+    if (V.vmap[G.surf_e[i]] != -1 || V.vmap[G.surf_e[G.n_se + i]] != -1) continue;
+    const int q = atomicAdd(&S.rcount[2], 1);
+    if (q < cap_fe) re[q] = i;
+    else S.overflow = 1;
+  }
+  __syncthreads();
+  const int nrv = min(S.rcount[0], cap_v), nrf = min(S.rcount[1], cap_fe), nre = min(S.rcount[2], cap_fe);
+  auto near = [&](const double lo[3], const double hi[3], const double lo2[3], const double hi2[3]) {
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ok = ok && lo[c] - thr <= hi2[c] && lo2[c] - thr <= hi[c];
+    return ok;
+  };
+  auto append = [&](int kind, int a, int b) {
+    int2 pr;
+    pr.x = (kind << kKindShift) | a;
+    pr.y = b;
+    PairPts P;
+    load_pair(V, S, pr, x, nullptr, 0.0, P);
+    Feature f;
+    classify(P, f);
+    double r[3];
+    if (!(pair_distance(P, f, r) < thr)) return;
+    const int slot = atomicAdd(&S.count, 1);
+    if (slot < cap) V.outer[slot] = pr;
+    else S.overflow = 1;
+  };
+  const long long nvf = (long long)nrv * nrf;
+  for (long long k = item_first(V); k < nvf; k += item_step(V)) {
+    const int v = rv[k / nrf], f = rf[k % nrf];
+    const int t3[3] = {G.surf_f[f], G.surf_f[G.n_sf + f], G.surf_f[2 * G.n_sf + f]};
+    if (v == t3[0] || v == t3[1] || v == t3[2]) continue;
+    double lo[3], hi[3], pv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      pv[c] = x[c * nv + v];
+      lo[c] = fmin(fmin(x[c * nv + t3[0]], x[c * nv + t3[1]]), x[c * nv + t3[2]]);
+      hi[c] = fmax(fmax(x[c * nv + t3[0]], x[c * nv + t3[1]]), x[c * nv + t3[2]]);
+    }
+    if (near(pv, pv, lo, hi)) append(kGVF, v, f);
+  }
+  const long long nee = (long long)nre * nre;
+  for (long long k = item_first(V); k < nee; k += item_step(V)) {
+    const int ia = (int)(k / nre), ib = (int)(k % nre);
+    if (ia >= ib) continue;
+    const int ea = re[ia], eb = re[ib];
+    const int a0 = G.surf_e[ea], a1 = G.surf_e[G.n_se + ea], b0 = G.surf_e[eb], b1 = G.surf_e[G.n_se + eb];
+    if (a0 == b0 || a0 == b1 || a1 == b0 || a1 == b1) continue;
+    double lo[3], hi[3], lo2[3], hi2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = fmin(x[c * nv + a0], x[c * nv + a1]);
+      hi[c] = fmax(x[c * nv + a0], x[c * nv + a1]);
+      lo2[c] = fmin(x[c * nv + b0], x[c * nv + b1]);
+      hi2[c] = fmax(x[c * nv + b0], x[c * nv + b1]);
+    }
+    if (near(lo, hi, lo2, hi2)) append(kGEE, ea, eb);
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Vector passes over the 3 n_v DOFs of an env
 // ---------------------------------------------------------------------------
@@ -1553,7 +1680,7 @@ __device__ __forceinline__ double ind_motion(const double a[7], const double b[7
 // |(M - I)(y - g)| <= theta D, theta the rotation angle since the build; a
 // pair beyond the list radius r then stays beyond r - (motion + theta r), so
 // theta r is added to each list's figure.
-__device__ __forceinline__ void surf_motion(Solver& s, const double* x, const double* p, double out[3]) {
+__device__ __forceinline__ void surf_motion(Solver& s, const double* x, const double* p, double out[5]) {
   const GelDev& G = *s.V.G;
   const int nv = G.n_v, ns = G.n_sv;
   const Shared& S = *s.S;
@@ -1608,6 +1735,10 @@ __device__ __forceinline__ void surf_motion(Solver& s, const double* x, const do
   out[0] = sqrt(m[0]) + th[0] * (dh + s.buffer_out);
   out[1] = sqrt(m[1]) + th[1] * (dh + s.buffer);
   out[2] = sqrt(m[2]);
+  // deviation from the indenter's rigid motion alone: the distance of two gel
+  // points changes by at most twice it (a rigid motion keeps their distance)
+  out[3] = sqrt(m[0]);
+  out[4] = sqrt(m[1]);
 }
 
 __device__ __forceinline__ void snapshot(Solver& s, const double* x, double* dst) {
@@ -1718,6 +1849,7 @@ __device__ __forceinline__ bool rebuild_outer(Solver& s, const double* x) {
   View& V = s.V;
   const unsigned long long t0 = tick();
   cull(V, *s.S, x, V.E->dhat + s.buffer_out, s.outer_cap);
+  if (V.selfc) cull_self(V, *s.S, x, V.E->dhat + s.buffer_out, s.outer_cap, s.pair_cap);
   const int ov = s.S->overflow;
   const int cnt = s.S->count;
   __syncthreads();
@@ -1766,10 +1898,14 @@ __device__ __forceinline__ bool refilter(Solver& s, const double* x) {
 
 // Makes both lists valid at (x, current pose) for a coming motion of at most
 // `step` of any surface point. Returns false on a list overflow.
-__device__ __forceinline__ bool ensure_lists(Solver& s, const double* x, double step, const double m[2]) {
+__device__ __forceinline__ bool ensure_lists(Solver& s, const double* x, double step, const double m[5]) {
   const int vo = s.L->valid_o, vi = s.L->valid_i;
-  const double mo = vo ? m[0] : kInf;  // relative motions since the builds (surf_motion)
-  const double mi = vi ? m[1] : kInf;
+  double mo = vo ? m[0] : kInf;  // relative motions since the builds (surf_motion)
+  double mi = vi ? m[1] : kInf;
+  if (s.V.selfc) {  // gel-gel pairs: both points move, up to the deviation and the step each
+    mo = fmax(mo, vo ? 2.0 * m[3] + step : kInf);
+    mi = fmax(mi, vi ? 2.0 * m[4] + step : kInf);
+  }
   __syncthreads();
   if (!(mo + step <= s.buffer_out - s.buffer)) {
     if (!rebuild_outer(s, x)) return false;
@@ -1780,7 +1916,7 @@ __device__ __forceinline__ bool ensure_lists(Solver& s, const double* x, double 
 }
 
 __device__ __forceinline__ bool ensure_lists(Solver& s, const double* x, double step) {
-  double m[3];
+  double m[5];
   surf_motion(s, x, nullptr, m);
   return ensure_lists(s, x, step, m);
 }
@@ -1815,7 +1951,7 @@ __device__ __forceinline__ double lag_pass(Solver& s, const double* x, int mode,
     double r[3];
     const double d = pair_distance(P, f, r);
     dmin = fmin(dmin, d);
-    if (mode == 1 && d < V.E->dhat && d > 0.0) {
+    if (mode == 1 && P.kind < kGVF && d < V.E->dhat && d > 0.0) {  // self-contact pairs: no friction
       const int slot = atomicAdd(&S.count, 1);
       if (slot < s.fric_cap) {
         int id[4];
@@ -2010,7 +2146,7 @@ __device__ __forceinline__ int pncg(Solver& s, double tol, int max_iters, int& i
     const double a_bar = (curv > 0.0) ? -gp / curv : kInf;
     double alpha = fmin(a_up, a_bar);
     {
-      double m[3];
+      double m[5];
       surf_motion(s, x, V.p, m);
       if (!ensure_lists(s, x, alpha * m[2], m)) { status = kOverflow; break; }
     }
@@ -2136,6 +2272,7 @@ __device__ __forceinline__ void make_view(const StepParams& P, int e, View& V) {
   V.mixed = P.precision;
   V.moll = P.ee_moll;
   V.det = P.det;
+  V.selfc = P.selfc;
 }
 
 __device__ __forceinline__ void init_solver(Solver& s, const StepParams& P, Shared& S, Tile& T) {

@@ -32,7 +32,8 @@ class SolverOpts(C.Structure):
                 ("pair_capacity", C.c_int32), ("armijo", C.c_int32), ("block_size", C.c_int32),
                 ("warm_start", C.c_int32), ("dynamic", C.c_int32), ("dt", C.c_double),
                 ("density", C.c_double), ("max_evals", C.c_int32),
-                ("ee_mollifier", C.c_int32), ("outer_radius", C.c_double), ("deterministic", C.c_int32)]
+                ("ee_mollifier", C.c_int32), ("outer_radius", C.c_double), ("deterministic", C.c_int32),
+                ("self_contact", C.c_int32)]
 
 
 class EnvStats(C.Structure):
