@@ -286,6 +286,50 @@ def self_contact_press(depth: float = 0.3, n_steps: int = 3, xy=(-0.3, 0.0), gap
                     "1 env, two gel blocks with a gap, small sphere pressing next to the gap")
 
 
+def gripper_sensor_frames(w: float):
+    """Frames of two sensors facing each other across a parallel gripper: sensor
+    k's gel bottom centre sits at (-w, 0, 0) (k = 0) or (+w, 0, 0) (k = 1) of the
+    gripper frame, its gel normal (local +z) pointing at the gripper's centre.
+    Returns [(centre, unit quaternion)] for the two sensors."""
+    s = math.sqrt(0.5)
+    return [(np.array([-w, 0.0, 0.0]), np.array([s, 0.0, s, 0.0])),     # local z -> gripper +x
+            (np.array([w, 0.0, 0.0]), np.array([s, 0.0, -s, 0.0]))]     # local z -> gripper -x
+
+
+def object_in_sensor(obj_t, obj_q, centre, q_sensor) -> np.ndarray:
+    """The object's pose (t, q) relative to a sensor: the frame change
+    R_s^T (t - c), q_s^-1 q."""
+    qc = np.array([q_sensor[0], -q_sensor[1], -q_sensor[2], -q_sensor[3]])
+    t = rotation_matrix(q_sensor).T @ (np.asarray(obj_t, dtype=np.float64) - centre)
+    q = _qmul(qc, np.asarray(obj_q, dtype=np.float64))
+    return np.concatenate([t, q / np.linalg.norm(q)])
+
+
+def two_finger_grasp(n_steps: int = 3, squeeze: float = 0.12, obj_t=(0.04, 0.2, -0.15),
+                     obj_yaw_deg: float = 20.0, mu_f: float = 0.5) -> Workload:
+    """A parallel gripper with a sensor on each finger closing on one small
+    sphere (r = 0.6 mm) held off the gripper's centre (`obj_t`): one env per
+    sensor gel (the 32-vertex gel), each driven by the object's pose relative
+    to its own sensor as the fingers close until the gels are squeezed by about
+    `squeeze` mm. The sensors see different poses because of the offset."""
+    g = mesh_class("micro3")
+    ind = INDENTERS["sphere_small"]()
+    r = float(np.linalg.norm(ind.Y, axis=1).max())
+    q_obj = quat_from_axis_angle((1, 0, 0), math.radians(obj_yaw_deg))
+    w0 = g.thickness + r + 2.0 * DHAT + abs(obj_t[0])
+    w1 = g.thickness + r - squeeze
+    envs = []
+    for k in range(2):
+        poses = []
+        for i in range(n_steps + 1):
+            w = w0 + (w1 - w0) * i / n_steps
+            c, qs = gripper_sensor_frames(w)[k]
+            poses.append(object_in_sensor(obj_t, q_obj, c, qs))
+        envs.append(EnvSpec("micro3", "sphere_small", 0.3, NU, mu_f, np.array(poses)))
+    return Workload("two_finger_grasp", 0, {"micro3": g}, {"sphere_small": ind}, envs, "f64", 1e-6,
+                    "2 envs: the two finger sensors of a parallel gripper on one sphere")
+
+
 WORKLOADS = {
     "sphere_press_484v": sphere_press_484v,
     "peg_press_shear_12k": peg_press_shear_12k,
@@ -326,13 +370,6 @@ def protocol_poses(pose0, press=1.0, slide=1.0, rotate_deg=2.0, d_press=0.1, d_s
         p[3:] = _qmul(dq, p[3:])
         out.append(p)
     return np.stack(out)
-
-
-def _qmul(a, b):
-    w1, x1, y1, z1 = a
-    w2, x2, y2, z2 = b
-    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
-                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
 
 
 def _qmul(a, b):

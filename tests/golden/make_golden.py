@@ -19,7 +19,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle.sim import simulate  # noqa: E402
 from scenes.configs import (calibration_micro, micro_press, peg_press_484v, self_contact_press,  # noqa: E402
-                            sphere_press_484v)
+                            sphere_press_484v, two_finger_grasp)
 
 CALIB_THETA = (0.12, 0.45, 0.6)        # hidden (E MPa, nu, mu_f) of the calibration recordings
 CALIB_DYNAMIC = dict(density=2.5e-9, dt=2e-4)  # hidden density (t/mm^3) of the dynamic recordings
@@ -127,6 +127,21 @@ def self_contact_friction():
     print(f"self_contact_friction: {time.time() - t:.1f}s, active {r.n_active}, self {n_self}")
 
 
+def two_finger():
+    """The two finger sensors of a parallel gripper closing on one sphere held
+    off-centre, with friction: each sensor's env against the oracle's Newton."""
+    w = two_finger_grasp()
+    t = time.time()
+    xs, ms = [], []
+    for env in w.envs:
+        r = simulate(w.meshes["micro3"], w.indenters["sphere_small"], env, mode="newton", tol=1e-12)
+        xs.append(np.array(r.x))
+        ms.append(np.array(r.markers))
+    np.savez_compressed(os.path.join(HERE, "two_finger_grasp_newton.npz"), x=np.stack(xs), markers=np.stack(ms),
+                        poses=np.stack([e.poses for e in w.envs]))
+    print(f"two_finger: {time.time() - t:.1f}s")
+
+
 def calibration_targets():
     """Synthetic recordings for the calibration driver: the oracle's Newton
     marker fields of the calibration scene (two indenters, the recording
@@ -150,6 +165,6 @@ def calibration_targets():
 if __name__ == "__main__":
     which = sys.argv[1:] or ["micro_friction", "sphere_press", "peg_press_friction",
                              "peg_press_friction_unstructured", "calibration_targets", "peg_press_mollified",
-                             "self_contact_friction"]
+                             "self_contact_friction", "two_finger"]
     for name in which:
         globals()[name]()

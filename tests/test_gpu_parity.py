@@ -1086,3 +1086,24 @@ def test_benchmark_tolerance_result_is_an_equilibrium():
         xn, info = newton_solve(prob, x[s], tol=1e-12)
         assert info["converged"]
         assert np.abs(xn - x[s]).max() <= 1e-4
+
+
+def test_two_finger_grasp_matches_newton_oracle():
+    """A parallel gripper's two finger sensors closing on one sphere held off
+    the gripper's centre, with friction: the two sensors' envs, each driven by
+    the object's pose relative to its sensor, in one launch per step, against
+    the oracle's Newton solve of each (stored by tests/golden/make_golden.py)."""
+    t2r = _gpu()
+    from scenes.configs import two_finger_grasp
+    w = two_finger_grasp()
+    gold = np.load(os.path.join(HERE, "golden", "two_finger_grasp_newton.npz"))
+    sim = _build(t2r, w, tol=1e-11, substep_tol=1e-11, max_iters=400000)
+    poses = np.stack([e.poses for e in w.envs])
+    print("two-finger grasp, both sensors in one launch", flush=True)
+    for s in range(1, poses.shape[1]):
+        _, st = sim.step(poses[:, s], want_x=True)
+        torch.cuda.synchronize()
+        assert np.all(st.cpu().numpy() & 1)
+        xs = [a.cpu().numpy() for a in sim.split_x()]
+        for k in range(2):
+            assert np.abs(xs[k] - gold["x"][k][s - 1]).max() <= 1e-6, (s, k)

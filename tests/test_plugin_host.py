@@ -94,3 +94,28 @@ def test_plugin_checks_its_marker_grid_and_substeps():
         TactilePlugin(_FakeSim(2, 49))
     with pytest.raises(ValueError):
         TactilePlugin(_FakeSim(2, 63), substeps=0)
+
+
+def test_two_finger_sensor_poses_describe_one_object():
+    """The two finger sensors' envs of the grasp scene see one rigid object:
+    mapping each sensor's relative pose back through its frame gives the same
+    gripper-frame pose at every step, and the object centre's heights above
+    the two gels' bottoms add up to the finger gap 2 w."""
+    from scenes.configs import gripper_sensor_frames, two_finger_grasp
+    from scenes.indenters import rotation_matrix
+    w = two_finger_grasp(n_steps=4)
+    g = w.meshes["micro3"]
+    r = float(np.linalg.norm(w.indenters["sphere_small"].Y, axis=1).max())
+    w0 = g.thickness + r + 2 * 0.05 + 0.04
+    w1 = g.thickness + r - 0.12
+    for i in range(5):
+        wi = w0 + (w1 - w0) * i / 4
+        frames = gripper_sensor_frames(wi)
+        back = []
+        for (c, qs), env in zip(frames, w.envs):
+            t = rotation_matrix(qs) @ env.poses[i, :3] + c
+            Rg = rotation_matrix(qs) @ rotation_matrix(env.poses[i, 3:])
+            back.append((t, Rg))
+        assert np.allclose(back[0][0], back[1][0], atol=1e-12)
+        assert np.allclose(back[0][1], back[1][1], atol=1e-12)
+        assert w.envs[0].poses[i, 2] + w.envs[1].poses[i, 2] == pytest.approx(2 * wi, abs=1e-12)
