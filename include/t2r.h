@@ -55,7 +55,7 @@ enum {
   T2R_E_NOMEM = -2,        /* device allocation failed */
   T2R_E_HIP = -3,          /* HIP runtime error (no device, launch failure, ...) */
   T2R_E_STATE = -4,        /* call not valid in the context's current state */
-  T2R_E_UNSUPPORTED = -5   /* feature not available in this build */
+  T2R_E_UNSUPPORTED = -5   /* feature not available in the library as compiled */
 };
 
 /* Per-environment outcome bits written by t2r_step (d_status). */
