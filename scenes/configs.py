@@ -19,7 +19,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .indenters import (Indenter, end_on_peg, flat_plate, hex_nut, icosphere,
-                        quat_from_axis_angle, quat_mul, rotation_matrix)
+                        quat_from_axis_angle, quat_mul, rigid_set, rotation_matrix)
 from .mesh import GelMesh, hex_kuhn_gel, marker_grid, mesh_class
 
 DHAT = 0.05      # mm
@@ -68,6 +68,8 @@ INDENTERS = {
     "plate": lambda: flat_plate(2.0, 0.0, 3),
     "sphere_small": lambda: icosphere(0.6, 1),
     "sphere_sym": lambda: icosphere(0.6, 1, yaw=-np.pi / 4),
+    "two_pin": lambda: rigid_set([icosphere(0.5, 1), icosphere(0.5, 1, yaw=0.3)],
+                                 [(-0.75, -0.3, 0.0), (0.75, 0.35, 0.1)], name="two_pin"),
 }
 
 
@@ -284,6 +286,20 @@ def self_contact_press(depth: float = 0.3, n_steps: int = 3, xy=(-0.3, 0.0), gap
     env = EnvSpec("two_block", "sphere_small", 0.3, NU, mu_f, poses)
     return Workload("self_contact_press", 0, {"two_block": g}, {"sphere_small": ind}, [env], "f64", 1e-6,
                     "1 env, two gel blocks with a gap, small sphere pressing next to the gap")
+
+
+def two_pin_press(n_steps: int = 3, depth: float = 0.2, mu_f: float = 0.5, shear=(0.1, 0.05),
+                  n_shear: int = 2) -> Workload:
+    """Two small spheres held in one rigid fixture (one indenter made of two
+    closed meshes, the second 0.1 mm higher) pressed into the 32-vertex gel and
+    slid with friction: two separate contact patches that move together."""
+    g = mesh_class("micro3")
+    ind = INDENTERS["two_pin"]()
+    poses = press_schedule(ind, _yaw_tilt(0.2, 0.0), (0.0, 0.0), depth, g.thickness, n_steps, shear=shear,
+                           n_shear=n_shear)
+    env = EnvSpec("micro3", "two_pin", 0.3, NU, mu_f, poses)
+    return Workload("two_pin_press", 0, {"micro3": g}, {"two_pin": ind}, [env], "f64", 1e-6,
+                    "1 env, two pins of one rigid fixture on the 32-vertex gel")
 
 
 def gripper_sensor_frames(w: float):

@@ -31,6 +31,18 @@ class Indenter:
         return int(self.tris.shape[0])
 
 
+def rigid_set(parts, offsets, name: str = "") -> Indenter:
+    """Several closed meshes that move together as one rigid body (a fixture
+    with several pins, fingers of one tool): their union, part k shifted by
+    offsets[k] in the common local frame."""
+    Ys, Ts, n = [], [], 0
+    for ind, off in zip(parts, offsets):
+        Ys.append(np.asarray(ind.Y, dtype=np.float64) + np.asarray(off, dtype=np.float64))
+        Ts.append(np.asarray(ind.tris, dtype=np.int32) + n)
+        n += len(ind.Y)
+    return Indenter(Y=np.concatenate(Ys), tris=np.concatenate(Ts).astype(np.int32), name=name)
+
+
 def icosphere(radius: float = 3.0, level: int = 2, yaw: float = 0.0) -> Indenter:
     """Icosahedron subdivided `level` times, vertices projected to the sphere.
 

@@ -19,7 +19,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle.sim import simulate  # noqa: E402
 from scenes.configs import (calibration_micro, micro_press, peg_press_484v, self_contact_press,  # noqa: E402
-                            sphere_press_484v, two_finger_grasp)
+                            sphere_press_484v, two_finger_grasp, two_pin_press)
 
 CALIB_THETA = (0.12, 0.45, 0.6)        # hidden (E MPa, nu, mu_f) of the calibration recordings
 CALIB_DYNAMIC = dict(density=2.5e-9, dt=2e-4)  # hidden density (t/mm^3) of the dynamic recordings
@@ -142,6 +142,27 @@ def two_finger():
     print(f"two_finger: {time.time() - t:.1f}s")
 
 
+def two_pin():
+    """Two pins of one rigid fixture pressed and slid with friction on the
+    32-vertex gel; per step, the number of active pairs on each pin."""
+    from oracle.sim import build
+    w = two_pin_press()
+    env = w.envs[0]
+    t = time.time()
+    r = simulate(w.meshes["micro3"], w.indenters["two_pin"], env, mode="newton", tol=1e-12)
+    gel, ind, prob = build(w.meshes["micro3"], w.indenters["two_pin"], env)
+    half = len(ind.Y) // 2
+    per_pin = []
+    for s, x in enumerate(r.x):
+        prob.set_pose(env.poses[s + 1])
+        idx = prob.active(x)[0]["idx"]
+        ind_ids = idx[idx >= prob.nv] - prob.nv
+        per_pin.append([int(np.any(ind_ids < half)), int(np.any(ind_ids >= half))])
+    np.savez_compressed(os.path.join(HERE, "two_pin_press_newton.npz"), x=np.array(r.x),
+                        markers=np.array(r.markers), poses=env.poses, pins_in_contact=np.array(per_pin))
+    print(f"two_pin: {time.time() - t:.1f}s, pins in contact {per_pin}")
+
+
 def calibration_targets():
     """Synthetic recordings for the calibration driver: the oracle's Newton
     marker fields of the calibration scene (two indenters, the recording
@@ -165,6 +186,6 @@ def calibration_targets():
 if __name__ == "__main__":
     which = sys.argv[1:] or ["micro_friction", "sphere_press", "peg_press_friction",
                              "peg_press_friction_unstructured", "calibration_targets", "peg_press_mollified",
-                             "self_contact_friction", "two_finger"]
+                             "self_contact_friction", "two_finger", "two_pin"]
     for name in which:
         globals()[name]()

@@ -1114,3 +1114,21 @@ def test_two_finger_grasp_matches_newton_oracle():
         xs = [a.cpu().numpy() for a in sim.split_x()]
         for k in range(2):
             assert np.abs(xs[k] - gold["x"][k][s - 1]).max() <= 1e-6, (s, k)
+
+
+def test_two_pin_fixture_matches_newton_oracle():
+    """Two pins of one rigid fixture (one indenter made of two closed meshes)
+    pressed and slid with friction: both pins are in contact at every step, and
+    the GPU path equals the oracle's Newton path within 1e-6 mm."""
+    t2r = _gpu()
+    from scenes.configs import two_pin_press
+    w = two_pin_press()
+    gold = np.load(os.path.join(HERE, "golden", "two_pin_press_newton.npz"))
+    assert np.all(gold["pins_in_contact"] == 1)
+    sim = _build(t2r, w, tol=1e-11, substep_tol=1e-11, max_iters=400000)
+    poses = np.stack([e.poses for e in w.envs])
+    print("two-pin fixture press and slide", flush=True)
+    m, x, st = _run_steps(sim, poses, want_x=True)
+    assert np.all(st & 1), st
+    assert np.abs(x - gold["x"]).max() <= 1e-6
+    assert np.abs(m - gold["markers"]).max() <= 1e-6

@@ -119,3 +119,14 @@ def test_two_finger_sensor_poses_describe_one_object():
         assert np.allclose(back[0][0], back[1][0], atol=1e-12)
         assert np.allclose(back[0][1], back[1][1], atol=1e-12)
         assert w.envs[0].poses[i, 2] + w.envs[1].poses[i, 2] == pytest.approx(2 * wi, abs=1e-12)
+
+
+def test_rigid_set_is_the_union_of_its_parts():
+    """A fixture of several pins is one indenter: the union of the parts'
+    meshes, each shifted by its offset, triangle ids renumbered into the union."""
+    from scenes.indenters import icosphere, rigid_set
+    a, b = icosphere(0.5, 1), icosphere(0.4, 1, yaw=0.3)
+    u = rigid_set([a, b], [(-1.0, 0.0, 0.0), (1.0, 0.5, 0.2)])
+    na = len(a.Y)
+    assert np.allclose(u.Y[:na], a.Y + [-1.0, 0.0, 0.0]) and np.allclose(u.Y[na:], b.Y + [1.0, 0.5, 0.2])
+    assert np.array_equal(u.tris[:len(a.tris)], a.tris) and np.array_equal(u.tris[len(a.tris):], b.tris + na)
