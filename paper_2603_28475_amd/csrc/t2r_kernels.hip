@@ -990,10 +990,13 @@ __device__ __forceinline__ double pairs_eval(const View& V, const Shared& S, Til
     barrier3(d, dh, b, b1, b2);
     EdgeMoll M;
     const bool mol = edge_moll<LDS>(V, pr, rec, P, M);
-    double ga[3] = {0.0, 0.0, 0.0};
+    double ga[3] = {0.0, 0.0, 0.0}, gb[3] = {0.0, 0.0, 0.0};
     if (mol) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ga[c] = 2.0 * (M.bb * M.a[c] - M.ab * M.b[c]);
+      for (int c = 0; c < 3; ++c) {
+        ga[c] = 2.0 * (M.bb * M.a[c] - M.ab * M.b[c]);
+        gb[c] = 2.0 * (M.aa * M.b[c] - M.ab * M.a[c]);
+      }
     }
     energy += kap * (mol ? M.m * b : b);
     const double invd = 1.0 / d;
@@ -1023,9 +1026,9 @@ __device__ __forceinline__ double pairs_eval(const View& V, const Shared& S, Til
         // preconditioner diagonal: the pair's contribution clamped at zero (b' < 0
         // makes it negative in directions tangent to a close contact)
         double gval = kap * b1 * gi, hval = b2 * gi * gi + b1 * hdd;
-        if (mol) {  // gel points of an edge-edge pair: k = 0, 1
-          const double gc = k == 0 ? -ga[c] : ga[c];
-          const double hc = 2.0 * (M.bb - M.b[c] * M.b[c]);
+        if (mol) {  // gel points: the first edge (k = 0, 1), and for a gel-gel pair the second (2, 3)
+          const double gc = k == 0 ? -ga[c] : (k == 1 ? ga[c] : (k == 2 ? -gb[c] : gb[c]));
+          const double hc = k < 2 ? 2.0 * (M.bb - M.b[c] * M.b[c]) : 2.0 * (M.aa - M.a[c] * M.a[c]);
           gval = kap * (M.m * b1 * gi + M.m1 * b * gc);
           hval = M.m * hval + 2.0 * M.m1 * b1 * gi * gc + M.m2 * b * gc * gc + M.m1 * b * hc;
         }
@@ -1077,7 +1080,7 @@ __device__ __forceinline__ double pairs_curv(const View& V, const Shared& S, con
         D[w][c] = cw_of(f, 0, w) * P.z[0][c] + cw_of(f, 1, w) * P.z[1][c] + cw_of(f, 2, w) * P.z[2][c] + cw_of(f, 3, w) * P.z[3][c];
     double Mi[2][2];
     gram_inverse(D, f.k, Mi);
-    double q[3] = {0, 0, 0}, vv[2] = {0, 0}, da[3] = {0, 0, 0};
+    double q[3] = {0, 0, 0}, vv[2] = {0, 0}, da[3] = {0, 0, 0}, db[3] = {0, 0, 0};
     #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = P.gid[k];
@@ -1087,9 +1090,11 @@ __device__ __forceinline__ double pairs_curv(const View& V, const Shared& S, con
       for (int c = 0; c < 3; ++c) pk[c] = LDS ? T.gq[c][v] : p[c * nv + v];  // p = 0 on fixed vertices
       #pragma unroll
       for (int c = 0; c < 3; ++c) q[c] += f.c[k] * pk[c];
-      if (k < 2) {  // p_1 - p_0 of an edge-edge pair's gel edge
-        #pragma unroll
-        for (int c = 0; c < 3; ++c) da[c] += k == 0 ? -pk[c] : pk[c];
+      // p_1 - p_0 and p_3 - p_2 of an edge-edge pair (indenter points: p = 0)
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (k < 2) da[c] += k == 0 ? -pk[c] : pk[c];
+        else db[c] += k == 2 ? -pk[c] : pk[c];
       }
       const double rp = dot3(r, pk);
       #pragma unroll
@@ -1101,9 +1106,10 @@ __device__ __forceinline__ double pairs_curv(const View& V, const Shared& S, con
     double cv = b2 * nq * nq + b1 * pHp;
     EdgeMoll M;
     if (edge_moll<LDS>(V, pr, rec, P, M)) {
-      const double bd = dot3(M.b, da);
-      const double cp = 2.0 * (M.bb * dot3(M.a, da) - M.ab * bd);   // grad c . p
-      const double pHc = 2.0 * (M.bb * dot3(da, da) - bd * bd);      // p^T (d2c) p
+      const double ad = dot3(M.a, da), bd = dot3(M.b, da), ae = dot3(M.a, db), be = dot3(M.b, db);
+      const double cp = 2.0 * (M.bb * ad - M.ab * bd) + 2.0 * (M.aa * be - M.ab * ae);   // grad c . p
+      const double pHc = 2.0 * (M.bb * dot3(da, da) - bd * bd) + 2.0 * (M.aa * dot3(db, db) - ae * ae) +
+                         2.0 * (4.0 * ad * be - 2.0 * bd * ae - 2.0 * M.ab * dot3(da, db));   // p^T (d2c) p
       cv = M.m * cv + 2.0 * M.m1 * b1 * nq * cp + M.m2 * b * cp * cp + M.m1 * b * pHc;
     }
     curv += kap * cv;
@@ -2815,7 +2821,7 @@ __device__ __forceinline__ void pairs_hvp(const View& V, const Shared& S, Tile& 
         D[w][c] = cw_of(f, 0, w) * P.z[0][c] + cw_of(f, 1, w) * P.z[1][c] + cw_of(f, 2, w) * P.z[2][c] + cw_of(f, 3, w) * P.z[3][c];
     double Mi[2][2];
     gram_inverse(D, f.k, Mi);
-    double q[3] = {0, 0, 0}, vv[2] = {0, 0}, da[3] = {0, 0, 0};
+    double q[3] = {0, 0, 0}, vv[2] = {0, 0}, da[3] = {0, 0, 0}, db[3] = {0, 0, 0};
     #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int g = P.gid[k];
@@ -2825,9 +2831,11 @@ __device__ __forceinline__ void pairs_hvp(const View& V, const Shared& S, Tile& 
       for (int c = 0; c < 3; ++c) pk[c] = LDS ? T.gq[c][g] : v[c * nv + g];
       #pragma unroll
       for (int c = 0; c < 3; ++c) q[c] += f.c[k] * pk[c];
-      if (k < 2) {  // v_1 - v_0 of an edge-edge pair's gel edge
-        #pragma unroll
-        for (int c = 0; c < 3; ++c) da[c] += k == 0 ? -pk[c] : pk[c];
+      // v_1 - v_0 and v_3 - v_2 of an edge-edge pair (indenter points: v = 0)
+      #pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (k < 2) da[c] += k == 0 ? -pk[c] : pk[c];
+        else db[c] += k == 2 ? -pk[c] : pk[c];
       }
       const double rp = dot3(r, pk);
       #pragma unroll
@@ -2837,15 +2845,18 @@ __device__ __forceinline__ void pairs_hvp(const View& V, const Shared& S, Tile& 
     const double nq = dot3(n, q);
     EdgeMoll M;
     const bool mol = edge_moll<LDS>(V, pr, rec, P, M);
-    double ga[3] = {0, 0, 0}, hcv[3] = {0, 0, 0}, cp = 0.0;
+    // ga, gb: dc/da, dc/db; ha, hb: the a and b blocks of (d2c) (v_1 - v_0, v_3 - v_2)
+    double ga[3] = {0, 0, 0}, gb[3] = {0, 0, 0}, ha[3] = {0, 0, 0}, hbv[3] = {0, 0, 0}, cp = 0.0;
     if (mol) {
-      const double bd = dot3(M.b, da);
+      const double ad = dot3(M.a, da), bd = dot3(M.b, da), ae = dot3(M.a, db), be = dot3(M.b, db);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         ga[c] = 2.0 * (M.bb * M.a[c] - M.ab * M.b[c]);
-        hcv[c] = 2.0 * (M.bb * da[c] - M.b[c] * bd);   // (d2c/da2) (v_1 - v_0)
+        gb[c] = 2.0 * (M.aa * M.b[c] - M.ab * M.a[c]);
+        ha[c] = 2.0 * (M.bb * da[c] - M.b[c] * bd) + 4.0 * M.a[c] * be - 2.0 * M.b[c] * ae - 2.0 * M.ab * db[c];
+        hbv[c] = 2.0 * (M.aa * db[c] - M.a[c] * ae) + 4.0 * M.b[c] * ad - 2.0 * M.a[c] * bd - 2.0 * M.ab * da[c];
       }
-      cp = dot3(ga, da);
+      cp = dot3(ga, da) + dot3(gb, db);
     }
     #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -2860,10 +2871,10 @@ __device__ __forceinline__ void pairs_hvp(const View& V, const Shared& S, Tile& 
         for (int w = 0; w < 2; ++w)
           if (w < f.k) hv -= (cw_of(f, k, w) * r[c] + ci * D[w][c]) * wv[w];
         double hb = b2 * nq * ci * n[c] + b1 * hv * invd;
-        if (mol) {  // gel points of an edge-edge pair: k = 0, 1
-          const double sg = k == 0 ? -1.0 : 1.0;
-          hb = M.m * hb + M.m1 * b1 * (cp * ci * n[c] + nq * sg * ga[c]) + M.m2 * b * cp * sg * ga[c]
-               + M.m1 * b * sg * hcv[c];
+        if (mol) {  // gel points: the first edge (k = 0, 1), and for a gel-gel pair the second (2, 3)
+          const double sg = (k == 0 || k == 2) ? -1.0 : 1.0;
+          const double gc = sg * (k < 2 ? ga[c] : gb[c]), hc = sg * (k < 2 ? ha[c] : hbv[c]);
+          hb = M.m * hb + M.m1 * b1 * (cp * ci * n[c] + nq * gc) + M.m2 * b * cp * gc + M.m1 * b * hc;
         }
         const double o = kap * hb;
         if constexpr (LDS) atomicAdd(&T.gd[c][g], o);

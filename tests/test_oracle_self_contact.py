@@ -134,3 +134,35 @@ def test_self_contact_keeps_the_blocks_apart_where_plain_contact_lets_them_overl
     sel = np.isin(pairs["kind"], (GVF, GEE))
     d = prob.pair_geometry(r.x[-1], {"idx": pairs["idx"][sel], "kind": pairs["kind"][sel]})["d"]
     assert d.min() > 0.0 and np.sum(d < prob.dhat) > 0
+
+
+def test_self_contact_with_the_edge_mollifier_matches_differences():
+    """Both options on: the facing walls' parallel gel edges are mollified
+    edge-edge pairs (the threshold from both gel edges' rest lengths); the
+    energy's gradient and Hessian still match differences."""
+    from oracle.barrier import EDGE_MOLLIFIER_REL, edge_cross_derivatives
+    w = self_contact_press(depth=0.3, xy=(-0.45, 0.0), mu_f=0.0)
+    env = w.envs[0]
+    gel, ind, prob = build(w.meshes["two_block"], w.indenters["sphere_small"], env, self_contact=True,
+                           ee_mollifier=True)
+    plain = build(w.meshes["two_block"], w.indenters["sphere_small"], env, self_contact=True)[2]
+    for q in (prob, plain):
+        q.set_pose(env.poses[0])
+    rng = np.random.default_rng(8)
+    x = _squeezed(gel) + 2e-4 * rng.standard_normal(gel.X.shape) * (~gel.fixed.astype(bool))[:, None]
+    pairs, res = prob.active(x)
+    gee = np.nonzero(pairs["kind"] == GEE)[0]
+    idx = pairs["idx"][gee]
+    eps = EDGE_MOLLIFIER_REL * np.sum((gel.X[idx[:, 1]] - gel.X[idx[:, 0]]) ** 2, 1) * \
+        np.sum((gel.X[idx[:, 3]] - gel.X[idx[:, 2]]) ** 2, 1)
+    assert np.sum(edge_cross_derivatives(res["Z"][gee])[0] < eps) > 0
+    assert prob.energy(x) < plain.energy(x)
+    g = prob.gradient(x).ravel()
+    free = np.repeat(~gel.fixed.astype(bool), 3)
+    act = np.unique(idx)
+    h = 1e-7
+    for i in [3 * v + c for v in act[:6] for c in range(3) if free[3 * v + c]]:
+        e = np.zeros(x.size)
+        e[i] = h
+        xp, xm = x + e.reshape(x.shape), x - e.reshape(x.shape)
+        assert (prob.energy(xp) - prob.energy(xm)) / (2 * h) == pytest.approx(g[i], rel=1e-5, abs=1e-7)
