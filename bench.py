@@ -58,8 +58,10 @@ def parse():
     ap.add_argument("--density", type=float, default=1.1e-9,
                     help="mass density of the dynamic form (t/mm^3; 1.1e-9 = 1,100 kg/m^3)")
     ap.add_argument("--plain-envs", type=int, default=4, help="envs timed one launch each (0: skip)")
-    ap.add_argument("--launch", choices=["sequence", "per-step"], default="sequence",
-                    help="sequence: the K timed load steps of every env in one launch; per-step: one launch per load step")
+    ap.add_argument("--launch", choices=["sequence", "per-step", "graph"], default="sequence",
+                    help="sequence: the K timed load steps of every env in one launch; per-step: one launch per "
+                         "load step; graph: one replay of a captured HIP graph (env ordering and step kernel) "
+                         "per load step")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle budget (0: skip)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--outer-radius", type=float, default=0.0,
@@ -319,11 +321,13 @@ def main():
     opts = t2r.default_opts(tol=args.tol, precision=prec, block_size=args.block, dynamic=int(args.dynamic),
                             dt=args.dt, density=args.density, outer_radius=args.outer_radius)
     t_build = time.perf_counter()
-    sim = Sim.from_workload(workload, opts)
+    # graph replays need a stream of their own (capture is not allowed on the default one)
+    sim_stream = torch.cuda.Stream(device="cuda:0") if args.launch == "graph" else None
+    sim = Sim.from_workload(workload, opts, stream=sim_stream)
     poses = torch.as_tensor(np.stack([e.poses for e in workload.envs]), dtype=torch.float64,
                             device="cuda:0")
     log(args, f"built {args.envs} envs in {time.perf_counter() - t_build:.1f}s")
-    stream = torch.cuda.current_stream()
+    stream = sim.stream
     nv_env = np.array([workload.meshes[e.mesh].n_verts for e in workload.envs], dtype=np.float64)
     nt_env = np.array([workload.meshes[e.mesh].n_tets for e in workload.envs], dtype=np.float64)
     all_envs = list(range(args.envs))
@@ -337,9 +341,13 @@ def main():
         for _ in range(-(-W // K)):
             if args.launch == "sequence":
                 sm.step_sequence(seq(1, K + 1, envs))
+            elif args.launch == "graph":
+                for s in range(1, K + 1):  # the first call captures the graph
+                    sm.graph_step(poses[envs, s])
             else:
                 for s in range(1, K + 1):
                     sm.step(poses[envs, s].contiguous())
+            sm.stream.synchronize()
             sm.ctx.reset_envs(list(range(sm.n_env)))
         torch.cuda.synchronize()
 
@@ -381,8 +389,15 @@ def main():
         per_step = [pose_seq[k] for k in range(K)]
         for k in range(K):
             starts[k].record(stream)
-            sim.ctx.step(per_step[k], None, markers[k], None, status[k])
-            ends[k].record(stream)
+            if args.launch == "graph":
+                sim.graph_step(per_step[k])  # replay: pose copy, env ordering, step kernel
+                ends[k].record(stream)
+                with torch.cuda.stream(stream):
+                    markers[k].copy_(sim.markers)
+                    status[k].copy_(sim.status)
+            else:
+                sim.ctx.step(per_step[k], None, markers[k], None, status[k])
+                ends[k].record(stream)
             st = sim.stats()  # synchronises; needed for the per-launch iteration counts
             iters.append(np.array([x["iters"] for x in st], dtype=np.int64))
             log(args, f"step {k + 1}: {starts[k].elapsed_time(ends[k]):.1f} ms, iters/env mean "
@@ -419,13 +434,18 @@ def main():
     if args.plain_envs > 0:
         # unbatched: the same solver and launch mode, one env per context, on a sample of envs
         n = min(args.plain_envs, args.envs)
-        sims = [Sim.from_workload(workload, opts, envs=[i]) for i in range(n)]
+        sims = [Sim.from_workload(workload, opts, envs=[i],
+                                  stream=torch.cuda.Stream(device="cuda:0") if args.launch == "graph" else None)
+                for i in range(n)]
         for i_, sm in enumerate(sims):
             warmup(sm, slice(i_, i_ + 1))
         tp = time.perf_counter()
         for i_, sm in enumerate(sims):
             if args.launch == "sequence":
                 sm.step_sequence(seq(1, K + 1, slice(i_, i_ + 1)))
+            elif args.launch == "graph":
+                for s in range(1, K + 1):
+                    sm.graph_step(poses[i_:i_ + 1, s])
             else:
                 for s in range(1, K + 1):
                     sm.step(poses[i_:i_ + 1, s].contiguous())

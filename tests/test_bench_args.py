@@ -35,3 +35,17 @@ def test_driver_command_passes_argument_checks():
     if r.returncode == 0:
         return  # a GPU is present
     assert r.returncode == 1 and "needs a GPU" in r.stderr, r.stderr
+
+
+@pytest.mark.parametrize("launch", ["per-step", "graph"])
+def test_launch_modes_pass_argument_checks(launch):
+    # every launch mode is accepted; without a GPU the run stops at the device check
+    r = _run("--launch", launch, "--workload", "mixed_batch")
+    if r.returncode == 0:
+        return
+    assert r.returncode == 1 and "needs a GPU" in r.stderr, r.stderr
+
+
+def test_unknown_launch_mode_is_refused():
+    r = _run("--launch", "stream")
+    assert r.returncode == 2 and "invalid choice" in r.stderr
