@@ -33,6 +33,9 @@ constexpr double kEnergyGuard = 1e-13;     // x mu * total volume (energies are 
 constexpr double kDiagFloor = 1e-12;       // x mu * largest rest diagonal (mu = 1 part)
 constexpr double kYpMin = 1e-30;
 constexpr int kMaxHalvings = 30;
+// Entries of a per-vertex vector a thread loads per trip in the streaming passes
+// of the direction update.
+constexpr int kVecUnroll = 4;
 constexpr double kCcdGap = 0.1;            // keep every pair at >= 10% of its gap
 constexpr int kCcdMaxAdvance = 64;
 constexpr double kSqrt3 = 1.7320508075688772;
@@ -2196,31 +2199,65 @@ __device__ __forceinline__ int pncg(Solver& s, double tol, int max_iters, int& i
     nactive_out = nact;
     // dots: x += alpha p ; P1 ; y = g1 - g0
     double a[6] = {0, 0, 0, 0, 0, 0};  // gPy, yPy, yp, pg1, gPg | max|Pg1|
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      const double pj = V.p[j];
-      x[j] = fma(alpha, pj, x[j]);
-      const double P = 1.0 / fmax(V.diag[j], s.floor_d);
-      V.diag[j] = P;
-      const double gj = g1[j];
-      const double y = gj - g0[j];
-      const double Py = P * y;
-      a[0] += gj * Py;
-      a[1] += y * Py;
-      a[2] += y * pj;
-      a[3] += pj * gj;
-      a[4] += gj * P * gj;
-      a[5] = fmax(a[5], fabs(P * gj));
+    // kVecUnroll entries per thread per trip, all loads issued first (more bytes in
+    // flight per wave); each thread still visits j, j + B, j + 2B, ... in order, so
+    // its partial sums are the same as with one entry per trip
+    const int B = blockDim.x;
+    for (int j0 = threadIdx.x; j0 < n; j0 += kVecUnroll * B) {
+      double pv[kVecUnroll], xv[kVecUnroll], dv[kVecUnroll], g1v[kVecUnroll], g0v[kVecUnroll];
+#pragma unroll
+      for (int u = 0; u < kVecUnroll; ++u) {
+        const int j = min(j0 + u * B, n - 1);  // clamped: the loads issue unconditionally
+        pv[u] = V.p[j];
+        xv[u] = x[j];
+        dv[u] = V.diag[j];
+        g1v[u] = g1[j];
+        g0v[u] = g0[j];
+      }
+#pragma unroll
+      for (int u = 0; u < kVecUnroll; ++u) {
+        const int j = j0 + u * B;
+        if (j < n) {
+          const double pj = pv[u];
+          x[j] = fma(alpha, pj, xv[u]);
+          const double P = 1.0 / fmax(dv[u], s.floor_d);
+          V.diag[j] = P;
+          const double gj = g1v[u];
+          const double y = gj - g0v[u];
+          const double Py = P * y;
+          a[0] += gj * Py;
+          a[1] += y * Py;
+          a[2] += y * pj;
+          a[3] += pj * gj;
+          a[4] += gj * P * gj;
+          a[5] = fmax(a[5], fabs(P * gj));
+        }
+      }
     }
     block_reduce<5, 1>(a, *s.S);
     const double yp = a[2];
     double beta = 0.0;
     if (yp > kYpMin) beta = a[0] / yp - (a[1] / yp) * (a[3] / yp);
     double b2[2] = {0.0, 0.0};  // g.p_new | max |p_new|
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      const double pn = -V.diag[j] * g1[j] + beta * V.p[j];
-      V.p[j] = pn;
-      b2[0] += g1[j] * pn;
-      b2[1] = fmax(b2[1], fabs(pn));
+    for (int j0 = threadIdx.x; j0 < n; j0 += kVecUnroll * B) {
+      double dv[kVecUnroll], gv[kVecUnroll], pv[kVecUnroll];
+#pragma unroll
+      for (int u = 0; u < kVecUnroll; ++u) {
+        const int j = min(j0 + u * B, n - 1);
+        dv[u] = V.diag[j];
+        gv[u] = g1[j];
+        pv[u] = V.p[j];
+      }
+#pragma unroll
+      for (int u = 0; u < kVecUnroll; ++u) {
+        const int j = j0 + u * B;
+        if (j < n) {
+          const double pn = -dv[u] * gv[u] + beta * pv[u];
+          V.p[j] = pn;
+          b2[0] += gv[u] * pn;
+          b2[1] = fmax(b2[1], fabs(pn));
+        }
+      }
     }
     block_reduce<1, 1>(b2, *s.S);
     gp = b2[0];
@@ -3397,24 +3434,68 @@ __global__ void __launch_bounds__(BLOCK, (BLOCK == 256 ? 2 : 1)) t2r_backward_ke
     int it = 0;
     for (; it < P.max_iters && rn > P.cg_tol * r0 && r0 > 0.0; ++it) {
       hess_vec(s, xs, V.p, Ad);
+      // the three vector passes below load kVecUnroll entries per thread and trip
+      // before using them (same per-thread order of the sums as one per trip)
+      const int B = blockDim.x;
       double c1[1] = {0.0};
-      for (int j = threadIdx.x; j < n; j += blockDim.x) c1[0] += V.p[j] * Ad[j];
+      for (int j0 = threadIdx.x; j0 < n; j0 += kVecUnroll * B) {
+        double pv[kVecUnroll], av[kVecUnroll];
+#pragma unroll
+        for (int u = 0; u < kVecUnroll; ++u) {
+          const int j = min(j0 + u * B, n - 1);
+          pv[u] = V.p[j];
+          av[u] = Ad[j];
+        }
+#pragma unroll
+        for (int u = 0; u < kVecUnroll; ++u)
+          if (j0 + u * B < n) c1[0] += pv[u] * av[u];
+      }
       block_reduce<1, 0>(c1, S);
       if (!(c1[0] > 0.0)) { status |= kNonFinite; break; }
       const double alpha = rz / c1[0];
       double c2[2] = {0.0, 0.0};
-      for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        V.g0[j] = fma(alpha, V.p[j], V.g0[j]);
-        const double r = V.g1[j] - alpha * Ad[j];
-        V.g1[j] = r;
-        c2[0] += r * V.diag[j] * r;
-        c2[1] += r * r;
+      for (int j0 = threadIdx.x; j0 < n; j0 += kVecUnroll * B) {
+        double pv[kVecUnroll], xv[kVecUnroll], rv[kVecUnroll], av[kVecUnroll], dv[kVecUnroll];
+#pragma unroll
+        for (int u = 0; u < kVecUnroll; ++u) {
+          const int j = min(j0 + u * B, n - 1);
+          pv[u] = V.p[j];
+          xv[u] = V.g0[j];
+          rv[u] = V.g1[j];
+          av[u] = Ad[j];
+          dv[u] = V.diag[j];
+        }
+#pragma unroll
+        for (int u = 0; u < kVecUnroll; ++u) {
+          const int j = j0 + u * B;
+          if (j < n) {
+            V.g0[j] = fma(alpha, pv[u], xv[u]);
+            const double r = rv[u] - alpha * av[u];
+            V.g1[j] = r;
+            c2[0] += r * dv[u] * r;
+            c2[1] += r * r;
+          }
+        }
       }
       block_reduce<2, 0>(c2, S);
       const double beta = c2[0] / rz;
       rz = c2[0];
       rn = sqrt(c2[1]);
-      for (int j = threadIdx.x; j < n; j += blockDim.x) V.p[j] = fma(beta, V.p[j], V.diag[j] * V.g1[j]);
+      for (int j0 = threadIdx.x; j0 < n; j0 += kVecUnroll * B) {
+        double pv[kVecUnroll], dv[kVecUnroll], rv[kVecUnroll];
+#pragma unroll
+        for (int u = 0; u < kVecUnroll; ++u) {
+          const int j = min(j0 + u * B, n - 1);
+          pv[u] = V.p[j];
+          dv[u] = V.diag[j];
+          rv[u] = V.g1[j];
+        }
+#pragma unroll
+        for (int u = 0; u < kVecUnroll; ++u) {
+          const int j = j0 + u * B;
+          if (j < n) V.p[j] = fma(beta, pv[u], dv[u] * rv[u]);
+        }
+      }
       __syncthreads();
     }
     st.iters += it;
