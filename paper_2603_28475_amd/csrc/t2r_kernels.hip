@@ -2014,15 +2014,37 @@ __device__ __forceinline__ double inertia_eval(const View& V, const Shared& S, c
   const int nv = G.n_v, n = 3 * nv;
   double e = 0.0;
   __syncthreads();
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const int v = j >= 2 * nv ? j - 2 * nv : (j >= nv ? j - nv : j);
-    if (G.fixed[v]) continue;
-    const double w = S.iw * G.vmass[v];
-    const double xt = p ? fma(alpha, p[j], x[j]) : x[j];
-    const double r = xt - fma(S.dt, S.vel[j], V.xprev[j]);
-    g[j] += w * r;
-    dg[j] += w;
-    e += 0.5 * w * r * r;
+  const int B = blockDim.x;
+  const double* vel = S.vel;
+  // kVecUnroll entries per thread and trip, every load first (same per-thread order)
+  for (int j0 = threadIdx.x; j0 < n; j0 += kVecUnroll * B) {
+    bool fx[kVecUnroll];
+    double mv[kVecUnroll], xv[kVecUnroll], pv[kVecUnroll], vv[kVecUnroll], qv[kVecUnroll], gv[kVecUnroll],
+        dv[kVecUnroll];
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u) {
+      const int j = min(j0 + u * B, n - 1);  // clamped: the loads issue unconditionally
+      const int v = j >= 2 * nv ? j - 2 * nv : (j >= nv ? j - nv : j);
+      fx[u] = G.fixed[v];
+      mv[u] = G.vmass[v];
+      xv[u] = x[j];
+      pv[u] = p ? p[j] : 0.0;
+      vv[u] = vel[j];
+      qv[u] = V.xprev[j];
+      gv[u] = g[j];
+      dv[u] = dg[j];
+    }
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u) {
+      const int j = j0 + u * B;
+      if (j >= n || fx[u]) continue;
+      const double w = S.iw * mv[u];
+      const double xt = p ? fma(alpha, pv[u], xv[u]) : xv[u];
+      const double r = xt - fma(S.dt, vv[u], qv[u]);
+      g[j] = gv[u] + w * r;
+      dg[j] = dv[u] + w;
+      e += 0.5 * w * r * r;
+    }
   }
   return e;
 }
@@ -2032,10 +2054,21 @@ __device__ __forceinline__ double inertia_curv(const View& V, const Shared& S, c
   const GelDev& G = *V.G;
   const int nv = G.n_v, n = 3 * nv;
   double c = 0.0;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const int v = j >= 2 * nv ? j - 2 * nv : (j >= nv ? j - nv : j);
-    if (G.fixed[v]) continue;
-    c += S.iw * G.vmass[v] * p[j] * p[j];
+  const int B = blockDim.x;
+  for (int j0 = threadIdx.x; j0 < n; j0 += kVecUnroll * B) {
+    bool fx[kVecUnroll];
+    double mv[kVecUnroll], pv[kVecUnroll];
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u) {
+      const int j = min(j0 + u * B, n - 1);
+      const int v = j >= 2 * nv ? j - 2 * nv : (j >= nv ? j - nv : j);
+      fx[u] = G.fixed[v];
+      mv[u] = G.vmass[v];
+      pv[u] = p[j];
+    }
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u)
+      if (j0 + u * B < n && !fx[u]) c += S.iw * mv[u] * pv[u] * pv[u];
   }
   return c;
 }
