@@ -2016,13 +2016,14 @@ __device__ __forceinline__ double inertia_eval(const View& V, const Shared& S, c
   __syncthreads();
   const int B = blockDim.x;
   const double* vel = S.vel;
-  // kVecUnroll entries per thread and trip, every load first (same per-thread order)
-  for (int j0 = threadIdx.x; j0 < n; j0 += kVecUnroll * B) {
-    bool fx[kVecUnroll];
-    double mv[kVecUnroll], xv[kVecUnroll], pv[kVecUnroll], vv[kVecUnroll], qv[kVecUnroll], gv[kVecUnroll],
-        dv[kVecUnroll];
+  // two entries per thread and trip, every load first (same per-thread order; eight
+  // values per entry, so four would hold too many registers)
+  constexpr int U = 2;
+  for (int j0 = threadIdx.x; j0 < n; j0 += U * B) {
+    bool fx[U];
+    double mv[U], xv[U], pv[U], vv[U], qv[U], gv[U], dv[U];
 #pragma unroll
-    for (int u = 0; u < kVecUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int j = min(j0 + u * B, n - 1);  // clamped: the loads issue unconditionally
       const int v = j >= 2 * nv ? j - 2 * nv : (j >= nv ? j - nv : j);
       fx[u] = G.fixed[v];
@@ -2035,7 +2036,7 @@ __device__ __forceinline__ double inertia_eval(const View& V, const Shared& S, c
       dv[u] = dg[j];
     }
 #pragma unroll
-    for (int u = 0; u < kVecUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int j = j0 + u * B;
       if (j >= n || fx[u]) continue;
       const double w = S.iw * mv[u];
